@@ -1,0 +1,212 @@
+"""ctypes wrapper around the plain FP64 CPU oracle (``oracle.c``).
+
+TEST INFRASTRUCTURE ONLY: imported by ``tests/``, the package smoke check and the benchmark's
+CPU-baseline leg, never by the product path. It takes numpy arrays and plain Python values; it does not
+import the HIP package.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB = os.path.join(HERE, "liboracle.so")
+SOURCES = ["oracle.c"]
+
+FLUX = {"rusanov": 0, "hlle": 1}
+
+
+def build(verbose=False):
+    """Compile the oracle with gcc: no FMA contraction, no fast-math, OpenMP over blocks."""
+    srcs = [os.path.join(HERE, s) for s in SOURCES if os.path.exists(os.path.join(HERE, s))]
+    cmd = ["gcc", "-O2", "-fopenmp", "-ffp-contract=off", "-fno-fast-math", "-std=c11", "-Wall",
+           "-shared", "-fPIC", *srcs, "-o", LIB + ".tmp", "-lm"]
+    subprocess.run(cmd, check=True, capture_output=not verbose)
+    os.replace(LIB + ".tmp", LIB)
+    return LIB
+
+
+class _Sim(ctypes.Structure):
+    _fields_ = [("nroot", ctypes.c_int32 * 3), ("origin", ctypes.c_double * 3), ("dx0", ctypes.c_double),
+                ("bc", ctypes.c_int32 * 6), ("inflow_w", ctypes.c_double * 8),
+                ("body_c", ctypes.c_double * 3), ("body_r", ctypes.c_double)]
+
+
+class _Opts(ctypes.Structure):
+    _fields_ = [("flux", ctypes.c_int32), ("powell", ctypes.c_int32), ("n_table", ctypes.c_int32),
+                ("recompute_dt", ctypes.c_int32), ("alpha", ctypes.c_double * 2),
+                ("beta", ctypes.c_double * 2), ("cfl", ctypes.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB):
+            build()
+        L = ctypes.CDLL(LIB)
+        P = ctypes.POINTER
+        dp, ip = P(ctypes.c_double), P(ctypes.c_int32)
+        L.or_grid_create.restype = ctypes.c_void_p
+        L.or_grid_create.argtypes = [ctypes.c_int, ip, ip, ip, ctypes.c_int, P(_Sim)]
+        L.or_grid_free.argtypes = [ctypes.c_void_p]
+        L.or_neighbors.argtypes = [ctypes.c_void_p, ip]
+        L.or_set_state.argtypes = [ctypes.c_void_p, dp, dp]
+        L.or_fill_ghosts.argtypes = [ctypes.c_void_p, dp, dp]
+        L.or_dt.argtypes = [ctypes.c_void_p, dp, ctypes.c_double, dp]
+        L.or_advance.argtypes = [ctypes.c_void_p, dp, dp, dp, ctypes.c_int, P(_Opts), P(ctypes.c_long)]
+        L.or_advance.restype = ctypes.c_int
+        L.or_prim_to_cons.argtypes = [dp, dp]
+        L.or_cons_to_prim.argtypes = [dp, dp]
+        L.or_phys_flux.argtypes = [dp, ctypes.c_int, dp]
+        L.or_fast_speed.argtypes = [dp, ctypes.c_int]
+        L.or_fast_speed.restype = ctypes.c_double
+        L.or_num_flux.argtypes = [dp, dp, ctypes.c_int, ctypes.c_int, dp]
+        L.or_mc_slope.argtypes = [ctypes.c_double] * 3
+        L.or_mc_slope.restype = ctypes.c_double
+        L.or_restrict8.argtypes = [dp]
+        L.or_restrict8.restype = ctypes.c_double
+        L.or_prolong1.argtypes = [ctypes.c_double, dp, dp, ip]
+        L.or_prolong1.restype = ctypes.c_double
+        _lib = L
+    return _lib
+
+
+def _dp(a):
+    assert a.dtype == np.float64 and a.flags.c_contiguous
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _ip(a):
+    assert a.dtype == np.int32 and a.flags.c_contiguous
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+
+
+# ------------------------------------------------------------------------------------------------
+# point functions (used by the pins)
+
+def prim_to_cons(w):
+    w = np.ascontiguousarray(w, np.float64); u = np.empty(8)
+    lib().or_prim_to_cons(_dp(w), _dp(u)); return u
+
+
+def cons_to_prim(u):
+    u = np.ascontiguousarray(u, np.float64); w = np.empty(8)
+    lib().or_cons_to_prim(_dp(u), _dp(w)); return w
+
+
+def phys_flux(w, d):
+    w = np.ascontiguousarray(w, np.float64); f = np.empty(8)
+    lib().or_phys_flux(_dp(w), d, _dp(f)); return f
+
+
+def fast_speed(w, d):
+    w = np.ascontiguousarray(w, np.float64)
+    return lib().or_fast_speed(_dp(w), d)
+
+
+def num_flux(wl, wr, d, kind="rusanov"):
+    wl = np.ascontiguousarray(wl, np.float64); wr = np.ascontiguousarray(wr, np.float64); f = np.empty(8)
+    lib().or_num_flux(_dp(wl), _dp(wr), d, FLUX[kind], _dp(f)); return f
+
+
+def mc_slope(wm, w0, wp):
+    return lib().or_mc_slope(float(wm), float(w0), float(wp))
+
+
+def restrict8(c):
+    c = np.ascontiguousarray(c, np.float64)
+    return lib().or_restrict8(_dp(c))
+
+
+def prolong1(uc, cm, cp, s):
+    cm = np.ascontiguousarray(cm, np.float64); cp = np.ascontiguousarray(cp, np.float64)
+    s = np.ascontiguousarray(s, np.int32)
+    return lib().or_prolong1(float(uc), _dp(cm), _dp(cp), _ip(s))
+
+
+# ------------------------------------------------------------------------------------------------
+# grid-level driver
+
+class Grid:
+    """An oracle grid built from a block list (level, ijk, sim) and per-simulation descriptions
+    (objects with nroot, origin, dx0, bc, inflow_W, body_c, body_r attributes)."""
+
+    def __init__(self, level, ijk, sim, sims):
+        self.level = np.ascontiguousarray(level, np.int32)
+        self.ijk = np.ascontiguousarray(ijk, np.int32).reshape(-1, 3)
+        self.sim = np.ascontiguousarray(sim, np.int32)
+        self.nb = int(self.level.shape[0])
+        self.ns = len(sims)
+        arr = (_Sim * self.ns)()
+        for i, s in enumerate(sims):
+            arr[i].nroot[:] = [int(v) for v in s.nroot]
+            arr[i].origin[:] = [float(v) for v in s.origin]
+            arr[i].dx0 = float(s.dx0)
+            arr[i].bc[:] = [int(v) for v in s.bc]
+            arr[i].inflow_w[:] = [float(v) for v in s.inflow_W]
+            arr[i].body_c[:] = [float(v) for v in s.body_c]
+            arr[i].body_r = float(s.body_r)
+        self._sims = arr
+        h = lib().or_grid_create(self.nb, _ip(self.level), _ip(self.ijk), _ip(self.sim), self.ns, arr)
+        if not h:
+            raise ValueError("oracle: invalid grid")
+        self.h = h
+
+    @classmethod
+    def from_workload(cls, wl):
+        return cls(wl.level, wl.ijk, wl.sim, wl.sims)
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            lib().or_grid_free(self.h)
+            self.h = None
+
+    def neighbors(self):
+        out = np.empty((self.nb, 26, 5), np.int32)
+        lib().or_neighbors(self.h, _ip(out))
+        return out
+
+    def set_state(self, W):
+        W = np.ascontiguousarray(W, np.float64)
+        U = np.empty_like(W)
+        lib().or_set_state(self.h, _dp(W), _dp(U))
+        return U
+
+    def fill_ghosts(self, U):
+        U = np.ascontiguousarray(U, np.float64)
+        view = np.empty((8, self.nb, 12, 12, 12))
+        lib().or_fill_ghosts(self.h, _dp(U), _dp(view))
+        return view
+
+    def dt(self, U, cfl):
+        U = np.ascontiguousarray(U, np.float64)
+        out = np.empty(self.ns)
+        lib().or_dt(self.h, _dp(U), float(cfl), _dp(out))
+        return out
+
+    def advance(self, U0, U1, dt, n_stages, flux="rusanov", powell=False, cfl=0.8, recompute_dt=True,
+                alpha=(0.0, 0.5), beta=(1.0, 0.5)):
+        """Advance in place (U0, U1 updated; returns (dt, faults)). Heun by default."""
+        assert U0.flags.c_contiguous and U1.flags.c_contiguous
+        dt = np.ascontiguousarray(np.broadcast_to(np.asarray(dt, np.float64), (self.ns,))).copy()
+        o = _Opts(FLUX[flux], int(bool(powell)), 2, int(bool(recompute_dt)),
+                  (ctypes.c_double * 2)(*alpha), (ctypes.c_double * 2)(*beta), float(cfl))
+        faults = ctypes.c_long(0)
+        rc = lib().or_advance(self.h, _dp(U0), _dp(U1), _dp(dt), int(n_stages), ctypes.byref(o),
+                              ctypes.byref(faults))
+        if rc != 0:
+            raise RuntimeError(f"oracle advance failed ({rc})")
+        return dt, int(faults.value)
+
+    def run(self, W, n_steps, **kw):
+        """Convenience: conserved state after n_steps full steps from primitive W."""
+        U0 = self.set_state(W)
+        U1 = np.zeros_like(U0)
+        dt, faults = self.advance(U0, U1, np.zeros(self.ns), 2 * n_steps, **kw)
+        return U0, dt, faults

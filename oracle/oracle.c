@@ -1,0 +1,844 @@
+/*
+ * oracle.c -- plain, slow FP64 CPU oracle for the block-adaptive explicit ideal-MHD update.
+ *
+ * TEST INFRASTRUCTURE ONLY. Only the test suite, the package smoke check and the CPU-baseline leg of
+ * the benchmark load this library. It shares no code, header, table or constant generator with the
+ * HIP path, and it is built with contraction and fast-math off (-ffp-contract=off, no -ffast-math).
+ *
+ * What it computes, following the paper:
+ *   - storage: one padded array per block with two ghost layers on every side, variable index
+ *     fastest, in the spirit of State_VGB (Sec. 2; Sec. 4.1 sets the ghost width to 2);
+ *   - per block (Algorithm 1): face values, face fluxes, source, update; afterwards all ghost cells
+ *     are refilled ("exchange messages", Sec. 4.2: copy at equal resolution, restriction from a
+ *     finer sender, prolongation from a coarser sender, boundary conditions);
+ *   - the equations are ideal MHD in near-conservative form with the eight-wave Powell source
+ *     terms, total energy as in Eq. (5), mu0 = 1 (Eqs. 1-5);
+ *   - a two-stage time update with a CFL-limited global time step (Sec. 5.1 uses CFL 0.8; Sec. 5.2
+ *     contrasts one- and two-stage schemes).
+ * The paper leaves the limiter, reconstruction variables, flux formulas, wave-speed estimate, time-step
+ * formula, restriction/prolongation formulas and boundary details unstated; the readings implemented
+ * here are listed next to each function.
+ *
+ * External array layout (inputs and outputs): variable-major U[8][nB][8][8][8], i fastest, float64.
+ * Conserved order: rho, rho*ux, rho*uy, rho*uz, Bx, By, Bz, e.
+ * Primitive order: rho, ux, uy, uz, Bx, By, Bz, p.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define NC 8              /* cells per block and axis */
+#define NGH 2             /* ghost layers */
+#define NP (NC + 2 * NGH) /* padded extent: 12 */
+#define NV 8
+#define NPAD (NP * NP * NP)
+
+enum { BC_PERIODIC = 0, BC_OUTFLOW = 1, BC_INFLOW = 2 };
+enum { REL_SAME = 0, REL_COARSER = 1, REL_FINER = 2, REL_OUTFLOW = -1, REL_INFLOW = -2 };
+enum { FLUX_RUSANOV = 0, FLUX_HLLE = 1 };
+
+static const double GAM = 5.0 / 3.0;
+
+typedef struct {
+    int32_t nroot[3];
+    double origin[3];
+    double dx0;
+    int32_t bc[6];
+    double inflow_w[8];
+    double body_c[3];
+    double body_r;
+} or_sim;
+
+typedef struct {
+    int32_t flux;      /* FLUX_RUSANOV or FLUX_HLLE */
+    int32_t powell;    /* 0 / 1 */
+    int32_t n_table;   /* number of stages in the table (1 or 2) */
+    int32_t recompute_dt;
+    double alpha[2];
+    double beta[2];
+    double cfl;
+} or_opts;
+
+typedef struct {
+    int nb, ns;
+    int32_t *level, *ijk, *sim;
+    or_sim *sims;
+    int32_t **lut; /* lut[2*s + l]: block id at block coordinates of level l, or -1 */
+} or_grid;
+
+/* ------------------------------------------------------------------------------------------------ */
+/* state conversions (Eq. 5 with mu0 = 1)                                                            */
+
+void or_prim_to_cons(const double *w, double *u)
+{
+    double rho = w[0];
+    double u2 = w[1] * w[1] + w[2] * w[2] + w[3] * w[3];
+    double b2 = w[4] * w[4] + w[5] * w[5] + w[6] * w[6];
+    u[0] = rho;
+    u[1] = rho * w[1];
+    u[2] = rho * w[2];
+    u[3] = rho * w[3];
+    u[4] = w[4];
+    u[5] = w[5];
+    u[6] = w[6];
+    u[7] = w[7] / (GAM - 1.0) + 0.5 * rho * u2 + 0.5 * b2;
+}
+
+void or_cons_to_prim(const double *u, double *w)
+{
+    double rho = u[0];
+    double ux = u[1] / rho, uy = u[2] / rho, uz = u[3] / rho;
+    double u2 = ux * ux + uy * uy + uz * uz;
+    double b2 = u[4] * u[4] + u[5] * u[5] + u[6] * u[6];
+    w[0] = rho;
+    w[1] = ux;
+    w[2] = uy;
+    w[3] = uz;
+    w[4] = u[4];
+    w[5] = u[5];
+    w[6] = u[6];
+    w[7] = (GAM - 1.0) * (u[7] - 0.5 * rho * u2 - 0.5 * b2);
+}
+
+/* Physical flux along axis d of the conservation laws Eqs. (1)-(4) (left-hand sides). */
+void or_phys_flux(const double *w, int d, double *f)
+{
+    double rho = w[0], p = w[7];
+    const double *uv = w + 1, *bv = w + 4;
+    double un = uv[d], bn = bv[d];
+    double u2 = uv[0] * uv[0] + uv[1] * uv[1] + uv[2] * uv[2];
+    double b2 = bv[0] * bv[0] + bv[1] * bv[1] + bv[2] * bv[2];
+    double ub = uv[0] * bv[0] + uv[1] * bv[1] + uv[2] * bv[2];
+    double ptot = p + 0.5 * b2;
+    double e = p / (GAM - 1.0) + 0.5 * rho * u2 + 0.5 * b2;
+    f[0] = rho * un;
+    for (int a = 0; a < 3; a++) {
+        f[1 + a] = rho * uv[a] * un - bv[a] * bn;
+        if (a == d) f[1 + a] += ptot;
+        f[4 + a] = un * bv[a] - bn * uv[a];
+    }
+    f[7] = un * (e + ptot) - bn * ub;
+}
+
+/* Fast magnetosonic speed along axis d: the largest root of the ideal-MHD dispersion relation,
+ * c_f^2 = ((a^2 + b^2) + sqrt((a^2 + b^2)^2 - 4 a^2 b_n^2)) / 2 with a^2 = gamma p / rho,
+ * b^2 = |B|^2 / rho, b_n^2 = B_d^2 / rho. For k perpendicular to B it reduces to the paper's
+ * c_F = sqrt(c_s^2 + v_A^2) (Sec. 5.1). */
+double or_fast_speed(const double *w, int d)
+{
+    double rho = w[0];
+    double a2 = GAM * w[7] / rho;
+    double b2 = (w[4] * w[4] + w[5] * w[5] + w[6] * w[6]) / rho;
+    double bn2 = w[4 + d] * w[4 + d] / rho;
+    double s = a2 + b2;
+    double disc = s * s - 4.0 * a2 * bn2;
+    if (disc < 0.0) disc = 0.0;
+    return sqrt(0.5 * (s + sqrt(disc)));
+}
+
+/* Numerical flux from primitive face states (reading: Rusanov with the larger of the two |u_n|+c_f;
+ * HLLE with Davis-type min/max signal speeds; every component, B_n included, gets the same
+ * dissipation). */
+void or_num_flux(const double *wl, const double *wr, int d, int kind, double *f)
+{
+    double ul[8], ur[8], fl[8], fr[8];
+    or_prim_to_cons(wl, ul);
+    or_prim_to_cons(wr, ur);
+    or_phys_flux(wl, d, fl);
+    or_phys_flux(wr, d, fr);
+    double cl = or_fast_speed(wl, d), cr = or_fast_speed(wr, d);
+    double unl = wl[1 + d], unr = wr[1 + d];
+    if (kind == FLUX_RUSANOV) {
+        double cmax = fmax(fabs(unl) + cl, fabs(unr) + cr);
+        for (int v = 0; v < 8; v++) f[v] = 0.5 * (fl[v] + fr[v]) - 0.5 * cmax * (ur[v] - ul[v]);
+    } else {
+        double sl = fmin(unl - cl, unr - cr);
+        double sr = fmax(unl + cl, unr + cr);
+        if (sl >= 0.0) {
+            for (int v = 0; v < 8; v++) f[v] = fl[v];
+        } else if (sr <= 0.0) {
+            for (int v = 0; v < 8; v++) f[v] = fr[v];
+        } else {
+            for (int v = 0; v < 8; v++)
+                f[v] = (sr * fl[v] - sl * fr[v] + sl * sr * (ur[v] - ul[v])) / (sr - sl);
+        }
+    }
+}
+
+/* ------------------------------------------------------------------------------------------------ */
+/* limiters                                                                                         */
+
+static double minmod3(double a, double b, double c)
+{
+    if (a > 0.0 && b > 0.0 && c > 0.0) return fmin(a, fmin(b, c));
+    if (a < 0.0 && b < 0.0 && c < 0.0) return fmax(a, fmax(b, c));
+    return 0.0;
+}
+
+static double minmod2(double a, double b)
+{
+    if (a > 0.0 && b > 0.0) return fmin(a, b);
+    if (a < 0.0 && b < 0.0) return fmax(a, b);
+    return 0.0;
+}
+
+/* Monotonized-central limited slope of the middle value (the paper's "second-order scheme" leaves the
+ * limiter open; MC is the reading): minmod(2 D-, (D- + D+)/2, 2 D+). */
+double or_mc_slope(double wm, double w0, double wp)
+{
+    double dm = w0 - wm, dp = wp - w0;
+    return minmod3(2.0 * dm, 0.5 * (dm + dp), 2.0 * dp);
+}
+
+/* Restriction: pairwise-tree mean of the 8 fine children c[z][y][x] (x fastest). */
+double or_restrict8(const double *c)
+{
+    return (((c[0] + c[1]) + (c[2] + c[3])) + ((c[4] + c[5]) + (c[6] + c[7]))) * 0.125;
+}
+
+/* Prolongation of one variable: coarse value plus a quarter of the minmod slope per axis, with the sign
+ * of the fine cell's half, added in the order x, y, z. cm/cp are the coarse neighbours. */
+double or_prolong1(double uc, const double *cm, const double *cp, const int *s)
+{
+    double v = uc;
+    for (int d = 0; d < 3; d++) {
+        double sig = minmod2(uc - cm[d], cp[d] - uc);
+        v = v + 0.25 * (double)s[d] * sig;
+    }
+    return v;
+}
+
+/* ------------------------------------------------------------------------------------------------ */
+/* grid                                                                                             */
+
+static long nblk_axis(const or_sim *s, int l, int a) { return (long)s->nroot[a] << l; }
+static long ncell_axis(const or_sim *s, int l, int a) { return nblk_axis(s, l, a) * NC; }
+
+static int lut_get(const or_grid *g, int s, int l, const long bb[3])
+{
+    const or_sim *sm = &g->sims[s];
+    long nx = nblk_axis(sm, l, 0), ny = nblk_axis(sm, l, 1), nz = nblk_axis(sm, l, 2);
+    if (bb[0] < 0 || bb[1] < 0 || bb[2] < 0 || bb[0] >= nx || bb[1] >= ny || bb[2] >= nz) return -1;
+    return g->lut[2 * s + l][(bb[2] * ny + bb[1]) * nx + bb[0]];
+}
+
+void or_grid_free(or_grid *g)
+{
+    if (!g) return;
+    if (g->lut)
+        for (int i = 0; i < 2 * g->ns; i++) free(g->lut[i]);
+    free(g->lut);
+    free(g->level);
+    free(g->ijk);
+    free(g->sim);
+    free(g->sims);
+    free(g);
+}
+
+/* Returns NULL on an invalid grid: levels outside {0,1}, blocks outside the root box, overlaps, or a
+ * root region that is neither one level-0 block nor fully covered by its 8 level-1 children. */
+or_grid *or_grid_create(int nb, const int32_t *level, const int32_t *ijk, const int32_t *sim, int ns,
+                        const or_sim *sims)
+{
+    or_grid *g = calloc(1, sizeof(or_grid));
+    g->nb = nb;
+    g->ns = ns;
+    g->level = malloc(sizeof(int32_t) * (size_t)nb);
+    g->ijk = malloc(sizeof(int32_t) * 3 * (size_t)nb);
+    g->sim = malloc(sizeof(int32_t) * (size_t)nb);
+    g->sims = malloc(sizeof(or_sim) * (size_t)ns);
+    memcpy(g->level, level, sizeof(int32_t) * (size_t)nb);
+    memcpy(g->ijk, ijk, sizeof(int32_t) * 3 * (size_t)nb);
+    memcpy(g->sim, sim, sizeof(int32_t) * (size_t)nb);
+    memcpy(g->sims, sims, sizeof(or_sim) * (size_t)ns);
+    g->lut = calloc(2 * (size_t)ns, sizeof(int32_t *));
+    for (int s = 0; s < ns; s++)
+        for (int l = 0; l < 2; l++) {
+            long n = nblk_axis(&sims[s], l, 0) * nblk_axis(&sims[s], l, 1) * nblk_axis(&sims[s], l, 2);
+            g->lut[2 * s + l] = malloc(sizeof(int32_t) * (size_t)n);
+            for (long i = 0; i < n; i++) g->lut[2 * s + l][i] = -1;
+        }
+    for (int b = 0; b < nb; b++) {
+        int s = sim[b], l = level[b];
+        if (s < 0 || s >= ns || l < 0 || l > 1) goto bad;
+        const or_sim *sm = &sims[s];
+        long nx = nblk_axis(sm, l, 0), ny = nblk_axis(sm, l, 1), nz = nblk_axis(sm, l, 2);
+        long i = ijk[3 * b], j = ijk[3 * b + 1], k = ijk[3 * b + 2];
+        if (i < 0 || j < 0 || k < 0 || i >= nx || j >= ny || k >= nz) goto bad;
+        int32_t *slot = &g->lut[2 * s + l][(k * ny + j) * nx + i];
+        if (*slot != -1) goto bad;
+        *slot = b;
+    }
+    /* coverage: each root is a leaf or has all 8 children */
+    for (int s = 0; s < ns; s++) {
+        const or_sim *sm = &sims[s];
+        for (long k = 0; k < sm->nroot[2]; k++)
+            for (long j = 0; j < sm->nroot[1]; j++)
+                for (long i = 0; i < sm->nroot[0]; i++) {
+                    long r[3] = {i, j, k};
+                    int leaf = lut_get(g, s, 0, r) >= 0;
+                    int nch = 0;
+                    for (int c = 0; c < 8; c++) {
+                        long cc[3] = {2 * i + (c & 1), 2 * j + ((c >> 1) & 1), 2 * k + ((c >> 2) & 1)};
+                        nch += lut_get(g, s, 1, cc) >= 0;
+                    }
+                    if (!((leaf && nch == 0) || (!leaf && nch == 8))) goto bad;
+                }
+    }
+    return g;
+bad:
+    or_grid_free(g);
+    return NULL;
+}
+
+/* Neighbour table: for block b and direction index n (dx, dy, dz in {-1,0,1}^3 minus 0, enumerated
+ * with dx fastest, the zero vector skipped), five ints {relation, id0..id3}. Relation: 0 same level,
+ * 1 coarser, 2 finer (the finer blocks touching b, enumerated x fastest over the free sub-positions),
+ * -1 outflow / -2 inflow when the direction leaves the domain through a non-periodic face (the first
+ * such axis in the order x, y, z decides). Unused ids are -1. */
+void or_neighbors(const or_grid *g, int32_t *out)
+{
+    for (int b = 0; b < g->nb; b++) {
+        int s = g->sim[b], l = g->level[b];
+        const or_sim *sm = &g->sims[s];
+        int n = 0;
+        for (int dz = -1; dz <= 1; dz++)
+            for (int dy = -1; dy <= 1; dy++)
+                for (int dx = -1; dx <= 1; dx++) {
+                    if (dx == 0 && dy == 0 && dz == 0) continue;
+                    int32_t *e = out + ((size_t)b * 26 + n) * 5;
+                    n++;
+                    for (int q = 0; q < 5; q++) e[q] = -1;
+                    int dd[3] = {dx, dy, dz};
+                    long nbk[3];
+                    int boundary = 0;
+                    for (int a = 0; a < 3 && !boundary; a++) {
+                        long N = nblk_axis(sm, l, a);
+                        long c = g->ijk[3 * b + a] + dd[a];
+                        if (c < 0 || c >= N) {
+                            int t = sm->bc[2 * a + (c < 0 ? 0 : 1)];
+                            if (t == BC_PERIODIC) c = (c + N) % N;
+                            else {
+                                e[0] = t == BC_OUTFLOW ? REL_OUTFLOW : REL_INFLOW;
+                                boundary = 1;
+                            }
+                        }
+                        nbk[a] = c;
+                    }
+                    if (boundary) continue;
+                    int id = lut_get(g, s, l, nbk);
+                    if (id >= 0) {
+                        e[0] = REL_SAME;
+                        e[1] = id;
+                        continue;
+                    }
+                    if (l == 1) {
+                        long cb[3] = {nbk[0] / 2, nbk[1] / 2, nbk[2] / 2};
+                        id = lut_get(g, s, 0, cb);
+                        if (id >= 0) {
+                            e[0] = REL_COARSER;
+                            e[1] = id;
+                        }
+                        continue;
+                    }
+                    e[0] = REL_FINER;
+                    int m = 1;
+                    for (int sz = 0; sz < 2; sz++)
+                        for (int sy = 0; sy < 2; sy++)
+                            for (int sx = 0; sx < 2; sx++) {
+                                int sub[3] = {sx, sy, sz};
+                                int ok = 1;
+                                for (int a = 0; a < 3; a++) {
+                                    if (dd[a] == 1 && sub[a] != 0) ok = 0;
+                                    if (dd[a] == -1 && sub[a] != 1) ok = 0;
+                                }
+                                if (!ok) continue;
+                                long fb[3] = {2 * nbk[0] + sx, 2 * nbk[1] + sy, 2 * nbk[2] + sz};
+                                e[m++] = lut_get(g, s, 1, fb);
+                            }
+                }
+    }
+}
+
+/* ------------------------------------------------------------------------------------------------ */
+/* padded block storage: st[b][k][j][i][v], i, j, k in [0, 12), interior at [2, 10)                  */
+
+#define PIDX(i, j, k) ((((size_t)(k)) * NP + (size_t)(j)) * NP + (size_t)(i))
+
+static double *pad_alloc(int nb) { return calloc((size_t)nb * NPAD * NV, sizeof(double)); }
+
+static double *pcell(double *st, int b, int i, int j, int k) /* i,j,k in block coordinates [-2,10) */
+{
+    return st + ((size_t)b * NPAD + PIDX(i + NGH, j + NGH, k + NGH)) * NV;
+}
+
+static void pad_from_ext(const or_grid *g, const double *U, double *st)
+{
+    size_t nbc = (size_t)g->nb * 512;
+    for (int b = 0; b < g->nb; b++)
+        for (int k = 0; k < NC; k++)
+            for (int j = 0; j < NC; j++)
+                for (int i = 0; i < NC; i++) {
+                    double *c = pcell(st, b, i, j, k);
+                    for (int v = 0; v < NV; v++) c[v] = U[v * nbc + (size_t)b * 512 + (k * 8 + j) * 8 + i];
+                }
+}
+
+static void pad_to_ext(const or_grid *g, double *st, double *U)
+{
+    size_t nbc = (size_t)g->nb * 512;
+    for (int b = 0; b < g->nb; b++)
+        for (int k = 0; k < NC; k++)
+            for (int j = 0; j < NC; j++)
+                for (int i = 0; i < NC; i++) {
+                    double *c = pcell(st, b, i, j, k);
+                    for (int v = 0; v < NV; v++) U[v * nbc + (size_t)b * 512 + (k * 8 + j) * 8 + i] = c[v];
+                }
+}
+
+/* ------------------------------------------------------------------------------------------------ */
+/* ghost values (exchange of messages between blocks, Sec. 4.2)                                     */
+
+/* Boundary handling of a level-l global cell index, axis by axis in the order x, y, z: periodic wraps,
+ * outflow clamps to the nearest interior cell along the normal, inflow returns 1. */
+static int apply_bc(const or_grid *g, int s, int l, long G[3])
+{
+    const or_sim *sm = &g->sims[s];
+    for (int a = 0; a < 3; a++) {
+        long N = ncell_axis(sm, l, a);
+        if (G[a] >= 0 && G[a] < N) continue;
+        int side = G[a] < 0 ? 0 : 1;
+        int t = sm->bc[2 * a + side];
+        if (t == BC_PERIODIC) G[a] = ((G[a] % N) + N) % N;
+        else if (t == BC_OUTFLOW) G[a] = side ? N - 1 : 0;
+        else return 1;
+    }
+    return 0;
+}
+
+static void inflow_cons(const or_grid *g, int s, double *u) { or_prim_to_cons(g->sims[s].inflow_w, u); }
+
+/* interior value of the leaf that holds level-l cell G (in-domain), for levels where a leaf exists */
+static int leaf_value(const or_grid *g, const double *st, int s, int l, const long G[3], double *u)
+{
+    long bb[3] = {G[0] / NC, G[1] / NC, G[2] / NC};
+    int b = lut_get(g, s, l, bb);
+    if (b < 0) return 0;
+    const double *c = pcell((double *)st, b, (int)(G[0] % NC), (int)(G[1] % NC), (int)(G[2] % NC));
+    memcpy(u, c, sizeof(double) * NV);
+    return 1;
+}
+
+/* Restriction of level-0 cell G from the 8 level-1 cells 2G + {0,1}^3. */
+static int restricted_value(const or_grid *g, const double *st, int s, const long G[3], double *u)
+{
+    double c[8][NV];
+    for (int q = 0; q < 8; q++) {
+        long F[3] = {2 * G[0] + (q & 1), 2 * G[1] + ((q >> 1) & 1), 2 * G[2] + ((q >> 2) & 1)};
+        if (!leaf_value(g, st, s, 1, F, c[q])) return 0;
+    }
+    for (int v = 0; v < NV; v++) {
+        double cv[8];
+        for (int q = 0; q < 8; q++) cv[q] = c[q][v];
+        u[v] = (((cv[0] + cv[1]) + (cv[2] + cv[3])) + ((cv[4] + cv[5]) + (cv[6] + cv[7]))) * 0.125;
+    }
+    return 1;
+}
+
+/* Level-0 ("pass-1") value at a possibly out-of-domain level-0 index: boundary rule, then a level-0
+ * leaf's interior, else restriction from level 1. */
+static void coarse_value(const or_grid *g, const double *st, int s, long G[3], double *u)
+{
+    if (apply_bc(g, s, 0, G)) {
+        inflow_cons(g, s, u);
+        return;
+    }
+    if (leaf_value(g, st, s, 0, G, u)) return;
+    if (restricted_value(g, st, s, G, u)) return;
+    fprintf(stderr, "oracle: uncovered coarse cell\n");
+    abort();
+}
+
+/* Ghost value of a level-l cell at global index G (may be outside the domain). */
+static void ghost_value(const or_grid *g, const double *st, int s, int l, const long G0[3], double *u)
+{
+    long G[3] = {G0[0], G0[1], G0[2]};
+    if (apply_bc(g, s, l, G)) {
+        inflow_cons(g, s, u);
+        return;
+    }
+    if (leaf_value(g, st, s, l, G, u)) return;
+    if (l == 0) {
+        if (restricted_value(g, st, s, G, u)) return;
+    } else {
+        /* prolongation from the coarse cell C = floor(G / 2) */
+        long C[3] = {G[0] / 2, G[1] / 2, G[2] / 2};
+        double uc[NV], um[3][NV], up[3][NV];
+        if (!leaf_value(g, st, s, 0, C, uc)) {
+            fprintf(stderr, "oracle: prolongation source missing\n");
+            abort();
+        }
+        for (int d = 0; d < 3; d++) {
+            long Cm[3] = {C[0], C[1], C[2]}, Cp[3] = {C[0], C[1], C[2]};
+            Cm[d] -= 1;
+            Cp[d] += 1;
+            coarse_value(g, st, s, Cm, um[d]);
+            coarse_value(g, st, s, Cp, up[d]);
+        }
+        int sg[3];
+        for (int d = 0; d < 3; d++) sg[d] = (G[d] & 1) ? 1 : -1;
+        for (int v = 0; v < NV; v++) {
+            double cm[3] = {um[0][v], um[1][v], um[2][v]};
+            double cp[3] = {up[0][v], up[1][v], up[2][v]};
+            u[v] = or_prolong1(uc[v], cm, cp, sg);
+        }
+        return;
+    }
+    fprintf(stderr, "oracle: uncovered cell\n");
+    abort();
+}
+
+/* Fill every ghost cell of every block (faces, edges and corners). */
+static void exchange_messages(const or_grid *g, double *st)
+{
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int b = 0; b < g->nb; b++) {
+        int s = g->sim[b], l = g->level[b];
+        for (int k = -NGH; k < NC + NGH; k++)
+            for (int j = -NGH; j < NC + NGH; j++)
+                for (int i = -NGH; i < NC + NGH; i++) {
+                    if (i >= 0 && i < NC && j >= 0 && j < NC && k >= 0 && k < NC) continue;
+                    long G[3] = {(long)g->ijk[3 * b] * NC + i, (long)g->ijk[3 * b + 1] * NC + j,
+                                 (long)g->ijk[3 * b + 2] * NC + k};
+                    ghost_value(g, st, s, l, G, pcell(st, b, i, j, k));
+                }
+    }
+}
+
+/* ------------------------------------------------------------------------------------------------ */
+/* body mask: a cell belongs to the body when its centre lies strictly inside the sphere             */
+
+static double cell_dx(const or_grid *g, int b) { return g->sims[g->sim[b]].dx0 / (double)(1 << g->level[b]); }
+
+static int is_body(const or_grid *g, int b, int i, int j, int k)
+{
+    const or_sim *sm = &g->sims[g->sim[b]];
+    if (!(sm->body_r > 0.0)) return 0;
+    double dx = cell_dx(g, b);
+    int ii[3] = {i, j, k};
+    double r2 = 0.0;
+    for (int a = 0; a < 3; a++) {
+        long G = (long)g->ijk[3 * b + a] * NC + ii[a];
+        double x = sm->origin[a] + ((double)G + 0.5) * dx;
+        double t = x - sm->body_c[a];
+        r2 = r2 + t * t;
+    }
+    return r2 < sm->body_r * sm->body_r;
+}
+
+/* ------------------------------------------------------------------------------------------------ */
+/* time step                                                                                        */
+
+/* dt = CFL * min over fluid cells of 1 / sum_d ((|u_d| + c_f,d) / dx_d), per simulation. */
+static void compute_dt(const or_grid *g, double *st, double cfl, double *dt)
+{
+    for (int s = 0; s < g->ns; s++) dt[s] = INFINITY;
+    for (int b = 0; b < g->nb; b++) {
+        int s = g->sim[b];
+        double dx = cell_dx(g, b);
+        for (int k = 0; k < NC; k++)
+            for (int j = 0; j < NC; j++)
+                for (int i = 0; i < NC; i++) {
+                    if (is_body(g, b, i, j, k)) continue;
+                    double w[NV];
+                    or_cons_to_prim(pcell(st, b, i, j, k), w);
+                    double lam = 0.0;
+                    for (int d = 0; d < 3; d++) lam = lam + (fabs(w[1 + d]) + or_fast_speed(w, d)) / dx;
+                    double t = cfl * (1.0 / lam);
+                    if (t < dt[s]) dt[s] = t;
+                }
+    }
+}
+
+/* ------------------------------------------------------------------------------------------------ */
+/* one stage on one block (Algorithm 1, body of the block loop)                                     */
+
+typedef struct {
+    double f[3][NC + 1][NC][NC][NV]; /* face fluxes: [axis][face index along axis][t2][t1][v] */
+    double bbar[3][NC + 1][NC][NC];  /* average normal B at the face */
+} or_faces;
+
+static void face_cell(int d, int f, int t1, int t2, int *ijk)
+{
+    /* cell with index f along axis d and transverse indices (t1, t2) along the other axes in order */
+    int a1 = d == 0 ? 1 : 0, a2 = d == 2 ? 1 : 2;
+    ijk[d] = f;
+    ijk[a1] = t1;
+    ijk[a2] = t2;
+}
+
+static void calc_face_values_and_fluxes(const or_grid *g, int b, double *st, const or_opts *o, or_faces *F)
+{
+    for (int d = 0; d < 3; d++)
+        for (int t2 = 0; t2 < NC; t2++)
+            for (int t1 = 0; t1 < NC; t1++)
+                for (int f = 0; f <= NC; f++) {
+                    /* face f lies between cells f-1 (left) and f (right) along axis d */
+                    int c[4][3];
+                    for (int q = 0; q < 4; q++) face_cell(d, f - 2 + q, t1, t2, c[q]);
+                    double w[4][NV];
+                    int body[4];
+                    for (int q = 0; q < 4; q++) {
+                        or_cons_to_prim(pcell(st, b, c[q][0], c[q][1], c[q][2]), w[q]);
+                        body[q] = is_body(g, b, c[q][0], c[q][1], c[q][2]);
+                    }
+                    double wl[NV], wr[NV], *fv = F->f[d][f][t2][t1];
+                    if (body[1] && body[2]) {
+                        for (int v = 0; v < NV; v++) fv[v] = 0.0;
+                        F->bbar[d][f][t2][t1] = 0.0;
+                        continue;
+                    }
+                    if (body[2]) { /* reflecting wall on the right: mirror of the first-order left state */
+                        memcpy(wl, w[1], sizeof wl);
+                        memcpy(wr, wl, sizeof wr);
+                        wr[1 + d] = -wl[1 + d];
+                    } else if (body[1]) {
+                        memcpy(wr, w[2], sizeof wr);
+                        memcpy(wl, wr, sizeof wl);
+                        wl[1 + d] = -wr[1 + d];
+                    } else {
+                        for (int v = 0; v < NV; v++) {
+                            double sl = (body[0] || body[2]) ? 0.0 : or_mc_slope(w[0][v], w[1][v], w[2][v]);
+                            double sr = (body[1] || body[3]) ? 0.0 : or_mc_slope(w[1][v], w[2][v], w[3][v]);
+                            wl[v] = w[1][v] + 0.5 * sl;
+                            wr[v] = w[2][v] - 0.5 * sr;
+                        }
+                    }
+                    or_num_flux(wl, wr, d, o->flux, fv);
+                    F->bbar[d][f][t2][t1] = 0.5 * (wl[4 + d] + wr[4 + d]);
+                }
+}
+
+/* Source (Powell terms, right-hand sides of Eqs. 2-4) and update of the physical cells.
+ * out = alpha * u0 + (1 - alpha) * in + beta * dt * (-sum_d dF_d / dx + S). Body cells are copied. */
+static void calc_source_and_update(const or_grid *g, int b, double *in, double *u0, double *out, double dt,
+                                   double alpha, double beta, const or_opts *o, const or_faces *F)
+{
+    double dx = cell_dx(g, b);
+    for (int k = 0; k < NC; k++)
+        for (int j = 0; j < NC; j++)
+            for (int i = 0; i < NC; i++) {
+                double *ci = pcell(in, b, i, j, k), *c0 = pcell(u0, b, i, j, k), *co = pcell(out, b, i, j, k);
+                if (is_body(g, b, i, j, k)) {
+                    for (int v = 0; v < NV; v++) co[v] = ci[v];
+                    continue;
+                }
+                int ii[3] = {i, j, k};
+                double rhs[NV] = {0};
+                double divb = 0.0;
+                for (int d = 0; d < 3; d++) {
+                    int a1 = d == 0 ? 1 : 0, a2 = d == 2 ? 1 : 2;
+                    int f = ii[d], t1 = ii[a1], t2 = ii[a2];
+                    for (int v = 0; v < NV; v++)
+                        rhs[v] = rhs[v] - (F->f[d][f + 1][t2][t1][v] - F->f[d][f][t2][t1][v]) / dx;
+                    divb = divb + (F->bbar[d][f + 1][t2][t1] - F->bbar[d][f][t2][t1]) / dx;
+                }
+                if (o->powell) {
+                    double w[NV];
+                    or_cons_to_prim(ci, w);
+                    double ub = w[1] * w[4] + w[2] * w[5] + w[3] * w[6];
+                    for (int a = 0; a < 3; a++) {
+                        rhs[1 + a] = rhs[1 + a] - divb * w[4 + a];
+                        rhs[4 + a] = rhs[4 + a] - divb * w[1 + a];
+                    }
+                    rhs[7] = rhs[7] - divb * ub;
+                }
+                for (int v = 0; v < NV; v++)
+                    co[v] = alpha * c0[v] + (1.0 - alpha) * ci[v] + beta * dt * rhs[v];
+            }
+}
+
+/* ------------------------------------------------------------------------------------------------ */
+/* flux correction at resolution changes: the coarse cell next to a coarse-fine face replaces its     */
+/* coarse flux by the pairwise mean of the four fine fluxes covering that face                      */
+
+static int find_fine_faces(const or_grid *g, int s, int bc, int d, int side, int fine_ids[4])
+{
+    /* the four level-1 blocks across face (d, side) of level-0 block bc, ordered by (t1, t2) with t1
+     * fastest, where t1 < t2 are the two axes other than d */
+    const or_sim *sm = &g->sims[s];
+    long nb[3];
+    for (int a = 0; a < 3; a++) nb[a] = g->ijk[3 * bc + a];
+    nb[d] += side ? 1 : -1;
+    long N = nblk_axis(sm, 0, d);
+    if (nb[d] < 0 || nb[d] >= N) {
+        if (sm->bc[2 * d + side] != BC_PERIODIC) return 0;
+        nb[d] = (nb[d] + N) % N;
+    }
+    if (lut_get(g, s, 0, nb) >= 0) return 0;
+    int a1 = d == 0 ? 1 : 0, a2 = d == 2 ? 1 : 2;
+    int q = 0;
+    for (int s2 = 0; s2 < 2; s2++)
+        for (int s1 = 0; s1 < 2; s1++) {
+            long fb[3];
+            fb[d] = 2 * nb[d] + (side ? 0 : 1);
+            fb[a1] = 2 * nb[a1] + s1;
+            fb[a2] = 2 * nb[a2] + s2;
+            fine_ids[q++] = lut_get(g, s, 1, fb);
+        }
+    return 1;
+}
+
+static void flux_correction(const or_grid *g, or_faces **faces, double *out, const double *dt, double beta)
+{
+    for (int b = 0; b < g->nb; b++) {
+        if (g->level[b] != 0 || !faces[b]) continue;
+        int s = g->sim[b];
+        double dxc = cell_dx(g, b);
+        for (int d = 0; d < 3; d++)
+            for (int side = 0; side < 2; side++) {
+                int fid[4];
+                if (!find_fine_faces(g, s, b, d, side, fid)) continue;
+                int fc = side ? NC : 0;         /* coarse face index along d */
+                int ff = side ? 0 : NC;         /* the same face seen from the fine blocks */
+                double sgn = side ? 1.0 : -1.0;
+                for (int t2 = 0; t2 < NC; t2++)
+                    for (int t1 = 0; t1 < NC; t1++) {
+                        /* fine block covering this coarse face cell, and its first fine face index */
+                        int q = (t1 / 4) + 2 * (t2 / 4);
+                        const or_faces *Ff = faces[fid[q]];
+                        int f1 = 2 * (t1 % 4), f2 = 2 * (t2 % 4);
+                        int ci[3];
+                        face_cell(d, side ? NC - 1 : 0, t1, t2, ci);
+                        double *co = pcell(out, b, ci[0], ci[1], ci[2]);
+                        if (is_body(g, b, ci[0], ci[1], ci[2])) continue;
+                        for (int v = 0; v < NV; v++) {
+                            double a = Ff->f[d][ff][f2][f1][v], bq = Ff->f[d][ff][f2][f1 + 1][v];
+                            double c = Ff->f[d][ff][f2 + 1][f1][v], e = Ff->f[d][ff][f2 + 1][f1 + 1][v];
+                            double fmean = ((a + bq) + (c + e)) * 0.25;
+                            double fcv = faces[b]->f[d][fc][t2][t1][v];
+                            co[v] = co[v] + beta * dt[s] * sgn * (fcv - fmean) / dxc;
+                        }
+                    }
+            }
+    }
+}
+
+static int has_level_change(const or_grid *g, int b)
+{
+    int s = g->sim[b], l = g->level[b];
+    const or_sim *sm = &g->sims[s];
+    for (int d = 0; d < 3; d++)
+        for (int side = 0; side < 2; side++) {
+            long nb[3];
+            for (int a = 0; a < 3; a++) nb[a] = g->ijk[3 * b + a];
+            nb[d] += side ? 1 : -1;
+            long N = nblk_axis(sm, l, d);
+            if (nb[d] < 0 || nb[d] >= N) {
+                if (sm->bc[2 * d + side] != BC_PERIODIC) continue;
+                nb[d] = (nb[d] + N) % N;
+            }
+            if (lut_get(g, s, l, nb) < 0) return 1;
+        }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------------------------------ */
+/* public driver                                                                                     */
+
+/* Primitive to conserved over all interior cells (external layout). */
+void or_set_state(const or_grid *g, const double *W, double *U)
+{
+    size_t nc = (size_t)g->nb * 512;
+    for (size_t c = 0; c < nc; c++) {
+        double w[NV], u[NV];
+        for (int v = 0; v < NV; v++) w[v] = W[v * nc + c];
+        or_prim_to_cons(w, u);
+        for (int v = 0; v < NV; v++) U[v * nc + c] = u[v];
+    }
+}
+
+/* Every ghost cell of every block into view[8][nB][12][12][12] (interior copied too). */
+void or_fill_ghosts(const or_grid *g, const double *U, double *view)
+{
+    double *st = pad_alloc(g->nb);
+    pad_from_ext(g, U, st);
+    exchange_messages(g, st);
+    size_t nbp = (size_t)g->nb * NPAD;
+    for (int b = 0; b < g->nb; b++)
+        for (size_t c = 0; c < NPAD; c++)
+            for (int v = 0; v < NV; v++) view[v * nbp + (size_t)b * NPAD + c] = st[((size_t)b * NPAD + c) * NV + v];
+    free(st);
+}
+
+void or_dt(const or_grid *g, const double *U, double cfl, double *dt)
+{
+    double *st = pad_alloc(g->nb);
+    pad_from_ext(g, U, st);
+    compute_dt(g, st, cfl, dt);
+    free(st);
+}
+
+/* Count of fluid cells whose density or pressure is not positive (or not finite). */
+static long count_faults(const or_grid *g, double *st)
+{
+    long n = 0;
+    for (int b = 0; b < g->nb; b++)
+        for (int k = 0; k < NC; k++)
+            for (int j = 0; j < NC; j++)
+                for (int i = 0; i < NC; i++) {
+                    if (is_body(g, b, i, j, k)) continue;
+                    double w[NV];
+                    or_cons_to_prim(pcell(st, b, i, j, k), w);
+                    if (!(w[0] > 0.0) || !(w[7] > 0.0)) n++;
+                }
+    return n;
+}
+
+/* Advance n_stages stages. Stage s uses table entry s % n_table; even stages read U0 and write U1,
+ * odd stages read U1 (and U0 as the step's starting state) and overwrite U0. With recompute_dt, dt is
+ * recomputed from U0 at the start of every step; otherwise dt[] is used as given. On return dt[] holds
+ * the last step's dt and *faults the number of non-positive cells after the last stage. */
+int or_advance(const or_grid *g, double *U0, double *U1, double *dt, int n_stages, const or_opts *o, long *faults)
+{
+    if (o->n_table != 2) return -1;
+    double *s0 = pad_alloc(g->nb), *s1 = pad_alloc(g->nb);
+    pad_from_ext(g, U0, s0);
+    pad_from_ext(g, U1, s1);
+    or_faces **faces = calloc((size_t)g->nb, sizeof(or_faces *));
+    int any_change = 0;
+    for (int b = 0; b < g->nb; b++)
+        if (has_level_change(g, b)) {
+            faces[b] = malloc(sizeof(or_faces));
+            any_change = 1;
+        }
+    for (int st = 0; st < n_stages; st++) {
+        int e = st % 2;
+        double alpha = o->alpha[e], beta = o->beta[e];
+        double *in = e ? s1 : s0, *out = e ? s0 : s1;
+        if (e == 0 && o->recompute_dt) compute_dt(g, s0, o->cfl, dt);
+        exchange_messages(g, in);
+#pragma omp parallel
+        {
+            or_faces *tmp = malloc(sizeof(or_faces));
+#pragma omp for schedule(dynamic, 4)
+            for (int b = 0; b < g->nb; b++) {
+                or_faces *F = faces[b] ? faces[b] : tmp;
+                calc_face_values_and_fluxes(g, b, in, o, F);
+                calc_source_and_update(g, b, in, s0, out, dt[g->sim[b]], alpha, beta, o, F);
+            }
+            free(tmp);
+        }
+        if (any_change) flux_correction(g, faces, out, dt, beta);
+    }
+    if (faults) *faults = count_faults(g, (n_stages % 2) ? s1 : s0);
+    pad_to_ext(g, s0, U0);
+    pad_to_ext(g, s1, U1);
+    for (int b = 0; b < g->nb; b++) free(faces[b]);
+    free(faces);
+    free(s0);
+    free(s1);
+    return 0;
+}

@@ -1,0 +1,494 @@
+"""Pins of the CPU oracle against facts fixed by the paper and by mathematics (CPU only).
+
+Each test ties one part of the oracle to something other than its own code: numbers printed in the
+paper, closed forms of the ideal-MHD eigen-structure, exact invariants of a conservative finite-volume
+update, symmetries, numpy library routines that reproduce a definition, and the convergence order
+against an exact nonlinear solution.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+from paper_2501_06717_amd import workloads as wk
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+GAMMA = 5.0 / 3.0
+
+
+# ------------------------------------------------------------------------------------------------
+# helpers that assemble a single-level simulation into one global array (numpy only)
+
+def to_global(wl, U):
+    nx, ny, nz = wl.sims[0].nroot
+    G = np.zeros((U.shape[0], nz * 8, ny * 8, nx * 8))
+    for b in range(wl.n_blocks):
+        i, j, k = wl.ijk[b]
+        G[:, k * 8:(k + 1) * 8, j * 8:(j + 1) * 8, i * 8:(i + 1) * 8] = U[:, b]
+    return G
+
+
+def from_global(wl, G):
+    U = np.zeros((G.shape[0], wl.n_blocks, 8, 8, 8))
+    for b in range(wl.n_blocks):
+        i, j, k = wl.ijk[b]
+        U[:, b] = G[:, k * 8:(k + 1) * 8, j * 8:(j + 1) * 8, i * 8:(i + 1) * 8]
+    return U
+
+
+def total(wl, U):
+    """sum over cells of U * cell volume, per variable, with exact summation"""
+    dx = wl.sims[0].dx0 / (2.0 ** wl.level)
+    vol = dx ** 3
+    return np.array([math.fsum((U[v] * vol[:, None, None, None]).ravel()) for v in range(8)])
+
+
+# ------------------------------------------------------------------------------------------------
+# wave speeds: numbers printed with the paper's fast-wave setup
+
+def test_fast_speed_matches_paper_printed_values(oracle_mod):
+    g = json.load(open(os.path.join(GOLDEN, "fast_wave_speeds.json")))
+    W0 = np.array(g["V0"])
+    # gamma p / rho = c_s^2 and |B|^2 / rho = c_A^2 for the printed background state
+    assert math.isclose(math.sqrt(GAMMA * W0[7] / W0[0]), g["c_s"], rel_tol=1e-12)
+    assert math.isclose(abs(W0[5]) / math.sqrt(W0[0]), g["c_A"], rel_tol=1e-12)
+    # k along x is perpendicular to B0 (along y): the fast speed is the printed c_F
+    assert math.isclose(oracle_mod.fast_speed(W0, 0), g["c_F"], rel_tol=1e-15)
+    assert math.isclose(oracle_mod.fast_speed(W0, 2), g["c_F"], rel_tol=1e-15)
+    # along B0 the fast speed is the larger of the sound and Alfven speeds
+    assert math.isclose(oracle_mod.fast_speed(W0, 1), max(g["c_s"], g["c_A"]), rel_tol=1e-12)
+
+
+def _jacobian(oracle_mod, U, d, h=1e-6):
+    J = np.zeros((8, 8))
+    for c in range(8):
+        step = h * max(1.0, abs(U[c]))
+        Up, Um = U.copy(), U.copy()
+        Up[c] += step
+        Um[c] -= step
+        fp = oracle_mod.phys_flux(oracle_mod.cons_to_prim(Up), d)
+        fm = oracle_mod.phys_flux(oracle_mod.cons_to_prim(Um), d)
+        J[:, c] = (fp - fm) / (2 * step)
+    return J
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_flux_jacobian_eigenstructure(oracle_mod, seed):
+    """The eigenvalues of dF/dU of ideal MHD (with F_Bn = 0) are 0, u_n, u_n +- c_A, u_n +- c_s and
+    u_n +- c_f; c_A^2 = B_n^2/rho, and c_f^2, c_s^2 are the roots of x^2 - (a^2+b^2) x + a^2 b_n^2.
+    A sign, index or missing term in the flux or in the fast speed breaks this."""
+    rng = np.random.default_rng(seed)
+    W = np.array([rng.uniform(0.5, 2), *rng.uniform(-1, 1, 3), *rng.uniform(-1.5, 1.5, 3),
+                  rng.uniform(0.3, 2)])
+    U = oracle_mod.prim_to_cons(W)
+    for d in range(3):
+        lam = np.sort(np.linalg.eigvals(_jacobian(oracle_mod, U, d)).real)
+        un = W[1 + d]
+        rel = lam - un
+        cf = oracle_mod.fast_speed(W, d)
+        a2 = GAMMA * W[7] / W[0]
+        b2 = (W[4:7] ** 2).sum() / W[0]
+        bn2 = W[4 + d] ** 2 / W[0]
+        # Vieta for the fast/slow pair
+        cs2 = a2 * bn2 / cf ** 2
+        assert math.isclose(cf ** 2 + cs2, a2 + b2, rel_tol=1e-12)
+        expect = np.sort(np.array([-un, 0.0, -cf, cf, -math.sqrt(bn2), math.sqrt(bn2),
+                                   -math.sqrt(cs2), math.sqrt(cs2)]))
+        assert np.allclose(np.sort(rel), expect, atol=2e-6), (d, rel, expect)
+        assert math.isclose(rel.max(), cf, rel_tol=1e-6)
+
+
+# ------------------------------------------------------------------------------------------------
+# numerical flux properties
+
+@pytest.mark.parametrize("seed", range(8))
+def test_numerical_flux_consistency(oracle_mod, seed):
+    rng = np.random.default_rng(100 + seed)
+    W = np.array([rng.uniform(0.5, 2), *rng.uniform(-1, 1, 3), *rng.uniform(-1, 1, 3), rng.uniform(0.3, 2)])
+    for d in range(3):
+        F = oracle_mod.phys_flux(W, d)
+        assert np.array_equal(oracle_mod.num_flux(W, W, d, "rusanov"), F)
+        Fh = oracle_mod.num_flux(W, W, d, "hlle")
+        assert np.all(np.abs(Fh - F) <= 4 * np.spacing(np.maximum(np.abs(F), 1e-300)) + 1e-300), (Fh - F)
+
+
+def test_hlle_upwinds_supersonic_states(oracle_mod):
+    WL = np.array([1.0, 5.0, 0.1, 0.0, 0.3, 0.2, 0.1, 0.5])
+    WR = np.array([0.8, 4.5, -0.2, 0.1, 0.3, -0.1, 0.2, 0.4])
+    for d, sign in ((0, 1.0),):
+        assert np.array_equal(oracle_mod.num_flux(WL, WR, d, "hlle"), oracle_mod.phys_flux(WL, d))
+    WL2, WR2 = WL.copy(), WR.copy()
+    WL2[1] *= -1
+    WR2[1] *= -1
+    assert np.array_equal(oracle_mod.num_flux(WL2, WR2, 0, "hlle"), oracle_mod.phys_flux(WR2, 0))
+
+
+def test_numerical_flux_mirror_symmetry(oracle_mod):
+    """Reflecting x -> -x swaps the states, flips u_x and B_x, and flips the sign of every flux
+    component except those odd in the normal direction."""
+    rng = np.random.default_rng(7)
+    for _ in range(5):
+        WL = np.array([rng.uniform(0.5, 2), *rng.uniform(-1, 1, 3), *rng.uniform(-1, 1, 3), rng.uniform(0.3, 2)])
+        WR = np.array([rng.uniform(0.5, 2), *rng.uniform(-1, 1, 3), *rng.uniform(-1, 1, 3), rng.uniform(0.3, 2)])
+        flip = np.array([1, -1, 1, 1, -1, 1, 1, 1.0])
+        for kind in ("rusanov", "hlle"):
+            F = oracle_mod.num_flux(WL, WR, 0, kind)
+            Fm = oracle_mod.num_flux(WR * flip, WL * flip, 0, kind)
+            # mass, transverse momentum, transverse B, energy fluxes change sign; normal momentum and
+            # normal-B fluxes keep it
+            parity = np.array([-1, 1, -1, -1, 1, -1, -1, -1.0])
+            assert np.allclose(Fm, parity * F, rtol=1e-13, atol=1e-13)
+
+
+# ------------------------------------------------------------------------------------------------
+# limiter and inter-level transfer
+
+def test_mc_slope_closed_forms(oracle_mod):
+    mc = oracle_mod.mc_slope
+    assert mc(0.0, 1.0, 2.0) == 1.0          # linear data: exact slope
+    assert mc(0.0, 1.0, 1.0) == 0.0          # flat on one side
+    assert mc(1.0, 0.0, 1.0) == 0.0          # extremum
+    assert mc(0.0, 0.1, 1.0) == 0.2          # 2 * smaller one-sided difference
+    assert mc(0.0, 1.0, 1.5) == 0.75         # central difference
+    assert mc(2.0, 1.0, 0.0) == -1.0
+
+
+def test_mc_face_values_bounded_by_neighbours(oracle_mod):
+    rng = np.random.default_rng(1)
+    for _ in range(2000):
+        wm, w0, wp = rng.normal(size=3)
+        s = oracle_mod.mc_slope(wm, w0, wp)
+        lo, hi = min(wm, w0, wp), max(wm, w0, wp)
+        # exact up to the one rounding of w0 + s/2 (at the MC bound w0 + (wp - w0) may land 1 ulp out)
+        tol = 2 * np.spacing(max(abs(lo), abs(hi), abs(w0)))
+        assert lo - tol <= w0 + 0.5 * s <= hi + tol and lo - tol <= w0 - 0.5 * s <= hi + tol
+
+
+def test_restriction_of_prolongation_is_identity(oracle_mod):
+    rng = np.random.default_rng(2)
+    for _ in range(200):
+        uc = rng.normal()
+        cm, cp = rng.normal(size=3), rng.normal(size=3)
+        kids = []
+        for q in range(8):
+            s = np.array([1 if (q >> a) & 1 else -1 for a in range(3)], np.int32)
+            kids.append(oracle_mod.prolong1(uc, cm, cp, s))
+        r = oracle_mod.restrict8(np.array(kids))
+        assert abs(r - uc) <= 2 * np.spacing(abs(uc)) + 4 * np.spacing(max(abs(k) for k in kids))
+
+
+def test_prolongation_of_linear_data_is_exact(oracle_mod):
+    b = np.array([1.0, -2.0, 3.0])
+    uc = 5.0
+    for q in range(8):
+        s = np.array([1 if (q >> a) & 1 else -1 for a in range(3)], np.int32)
+        v = oracle_mod.prolong1(uc, uc - b, uc + b, s)
+        assert v == uc + 0.25 * float((b * s).sum())
+
+
+# ------------------------------------------------------------------------------------------------
+# neighbour tables written by hand
+
+def dir_index(dx, dy, dz):
+    n = (dz + 1) * 9 + (dy + 1) * 3 + (dx + 1)
+    return n if n < 13 else n - 1
+
+
+def test_neighbors_single_block_periodic(oracle_mod):
+    wl = wk.uniform_state((1, 1, 1))
+    nb = oracle_mod.Grid.from_workload(wl).neighbors()
+    assert nb.shape == (1, 26, 5)
+    assert np.all(nb[0, :, 0] == 0) and np.all(nb[0, :, 1] == 0) and np.all(nb[0, :, 2:] == -1)
+
+
+def test_neighbors_boundaries_and_two_blocks(oracle_mod):
+    wl = wk.uniform_state((2, 1, 1), bc=(1, 2, 0, 0, 1, 1))
+    nb = oracle_mod.Grid.from_workload(wl).neighbors()
+    assert tuple(nb[0, dir_index(1, 0, 0)]) == (0, 1, -1, -1, -1)
+    assert nb[0, dir_index(-1, 0, 0), 0] == -1           # outflow at x-min
+    assert nb[1, dir_index(1, 0, 0), 0] == -2            # inflow at x-max
+    assert tuple(nb[1, dir_index(0, 1, 0)]) == (0, 1, -1, -1, -1)   # periodic y onto itself
+    assert nb[1, dir_index(1, 1, 1), 0] == -2            # x decides first
+    assert nb[0, dir_index(0, 1, 1), 0] == -1            # z outflow
+
+
+def test_neighbors_two_level_hand_table(oracle_mod):
+    mask = np.zeros((1, 1, 2), bool)
+    mask[0, 0, 1] = True
+    lv, ijk, sid = wk.two_level_blocks((2, 1, 1), mask)
+    sim = wk.Sim((2, 1, 1), (0, 0, 0), 1.0)
+    nb = oracle_mod.Grid(lv, ijk, sid, [sim]).neighbors()
+    # children of root 1 are blocks 1..8 with child index cx + 2 cy + 4 cz
+    assert tuple(nb[0, dir_index(1, 0, 0)]) == (2, 1, 3, 5, 7)
+    assert tuple(nb[0, dir_index(-1, 0, 0)]) == (2, 2, 4, 6, 8)
+    assert tuple(nb[0, dir_index(1, 1, 0)]) == (2, 1, 5, -1, -1)   # sub-positions (0,0,z): cy = 0
+    assert tuple(nb[0, dir_index(1, 1, 1)]) == (2, 1, -1, -1, -1)
+    assert tuple(nb[1, dir_index(-1, 0, 0)]) == (1, 0, -1, -1, -1)
+    assert tuple(nb[1, dir_index(1, 0, 0)]) == (0, 2, -1, -1, -1)
+    assert tuple(nb[1, dir_index(0, -1, 0)]) == (0, 3, -1, -1, -1)
+
+
+def test_invalid_grids_rejected(oracle_mod):
+    sim = wk.Sim((2, 1, 1), (0, 0, 0), 1.0)
+    with pytest.raises(ValueError):   # overlap
+        oracle_mod.Grid([0, 0], [[0, 0, 0], [0, 0, 0]], [0, 0], [sim])
+    with pytest.raises(ValueError):   # missing root
+        oracle_mod.Grid([0], [[0, 0, 0]], [0], [sim])
+    with pytest.raises(ValueError):   # partial refinement
+        oracle_mod.Grid([0, 1], [[0, 0, 0], [2, 0, 0]], [0, 0], [sim])
+
+
+# ------------------------------------------------------------------------------------------------
+# ghost fill against numpy padding (uniform grids) and against linear fields (two levels)
+
+@pytest.mark.parametrize("nroot,bc", [((1, 1, 1), (0,) * 6), ((2, 1, 1), (0,) * 6),
+                                      ((3, 2, 1), (1, 1, 0, 0, 1, 1)), ((2, 2, 2), (1, 2, 0, 0, 2, 1))])
+def test_ghost_fill_uniform_equals_numpy_pad(oracle_mod, nroot, bc):
+    wl = wk.uniform_state(nroot, bc=bc)
+    U = wk.unique_id_field(wl)
+    view = oracle_mod.Grid.from_workload(wl).fill_ghosts(U)
+    uin = oracle_mod.prim_to_cons(wl.sims[0].inflow_W)
+    G = to_global(wl, U)
+    for v in range(8):
+        A = G[v]
+        for axis_np, a in ((2, 0), (1, 1), (0, 2)):   # pad x, then y, then z
+            lo, hi = bc[2 * a], bc[2 * a + 1]
+            parts = []
+            widths = [(0, 0)] * 3
+            if lo == 0:
+                w = list(widths); w[axis_np] = (2, 2)
+                A = np.pad(A, w, mode="wrap")
+                continue
+            for side, t in ((0, lo), (1, hi)):
+                w = list(widths); w[axis_np] = (2, 0) if side == 0 else (0, 2)
+                if t == 1:
+                    A = np.pad(A, w, mode="edge")
+                else:
+                    A = np.pad(A, w, mode="constant", constant_values=uin[v])
+        for b in range(wl.n_blocks):
+            i, j, k = wl.ijk[b]
+            ref = A[k * 8:k * 8 + 12, j * 8:j * 8 + 12, i * 8:i * 8 + 12]
+            assert np.array_equal(view[v, b], ref), (v, b)
+
+
+def _linear_field(wl, coef):
+    sim = wl.sims[0]
+    x, y, z = wk.cell_centres(sim, wl.level, wl.ijk)
+    U = np.empty((8, wl.n_blocks, 8, 8, 8))
+    for v in range(8):
+        a, bx, by, bz = coef[v]
+        U[v] = a + bx * x + by * y + bz * z
+    return U
+
+
+def test_ghost_fill_two_level_linear_field_exact(oracle_mod):
+    """Copy, restriction (mean of 8) and minmod prolongation all reproduce a linear field exactly at the
+    ghost-cell centres (dyadic values, no rounding)."""
+    nroot = (4, 4, 4)
+    mask = np.zeros((4, 4, 4), bool)
+    for (i, j, k) in ((1, 1, 1), (2, 1, 1), (1, 2, 2)):
+        mask[k, j, i] = True
+    lv, ijk, sid = wk.two_level_blocks(nroot, mask)
+    sim = wk.Sim(nroot, (0.0, 0.0, 0.0), 1.0, (1,) * 6)
+    wl = wk.Workload("lin", lv, ijk, sid, [sim], np.zeros((8, len(lv), 8, 8, 8)))
+    coef = [(1.0 + v, (v % 3) + 1.0, -2.0 + v * 0.5, 3.0 - v) for v in range(8)]
+    U = _linear_field(wl, coef)
+    view = oracle_mod.Grid.from_workload(wl).fill_ghosts(U)
+    n_checked = 0
+    for b in range(wl.n_blocks):
+        dx = 1.0 / 2 ** lv[b]
+        g = (np.arange(12) - 2 + 0.5)
+        xs = (ijk[b, 0] * 8 + g) * dx
+        ys = (ijk[b, 1] * 8 + g) * dx
+        zs = (ijk[b, 2] * 8 + g) * dx
+        Z, Y, X = np.meshgrid(zs, ys, xs, indexing="ij")
+        inside = (X > 3) & (X < 29) & (Y > 3) & (Y < 29) & (Z > 3) & (Z < 29)
+        for v in range(8):
+            a, bx, by, bz = coef[v]
+            ref = a + bx * X + by * Y + bz * Z
+            assert np.array_equal(view[v, b][inside], ref[inside]), (b, v)
+        n_checked += int(inside.sum())
+    assert n_checked > 50000
+
+
+def test_ghost_fill_uniform_two_level(oracle_mod):
+    wl = wk.two_level_box(bc=(1, 2, 0, 0, 1, 1))
+    W0 = np.array([1.3, 0.2, -0.1, 0.4, 0.5, -0.3, 0.2, 0.9])
+    U = np.empty((8, wl.n_blocks, 8, 8, 8))
+    u0 = oracle_mod.prim_to_cons(W0)
+    for v in range(8):
+        U[v] = u0[v]
+    sim = wl.sims[0]
+    import dataclasses
+    wl2 = dataclasses.replace(wl, sims=[dataclasses.replace(sim, inflow_W=tuple(W0))])
+    view = oracle_mod.Grid.from_workload(wl2).fill_ghosts(U)
+    for v in range(8):
+        assert np.all(view[v] == u0[v])
+
+
+# ------------------------------------------------------------------------------------------------
+# invariants of the full update
+
+def _run(oracle_mod, wl, W, steps, **kw):
+    g = oracle_mod.Grid.from_workload(wl)
+    U0 = g.set_state(W)
+    U1 = np.zeros_like(U0)
+    dt, faults = g.advance(U0, U1, np.zeros(len(wl.sims)), 2 * steps, **kw)
+    return U0, dt, faults
+
+
+@pytest.mark.parametrize("case", ["periodic", "two_level", "powell_body", "outflow_hlle"])
+def test_uniform_state_preserved_bitwise(oracle_mod, case):
+    if case == "periodic":
+        wl = wk.uniform_state((2, 2, 1))
+        kw = dict(flux="rusanov", powell=False)
+    elif case == "two_level":
+        wl = wk.uniform_state((3, 2, 2), levels=np.array([[[0, 1, 0], [0, 0, 1]], [[1, 0, 0], [0, 0, 0]]], bool))
+        kw = dict(flux="hlle", powell=True)
+    elif case == "powell_body":
+        wl = wk.uniform_state((2, 2, 2), W0=(1.0, 0.0, 0.0, 0.0, 0.5, -0.4, 0.3, 0.7), body_r=3.0)
+        kw = dict(flux="hlle", powell=True)
+    else:
+        W0 = (1.0, 0.3, 0.1, -0.2, 0.5, -0.4, 0.3, 0.7)
+        wl = wk.uniform_state((2, 1, 2), W0=W0, bc=(1, 2, 1, 1, 2, 1))
+        kw = dict(flux="hlle", powell=True)
+    g = oracle_mod.Grid.from_workload(wl)
+    U0 = g.set_state(wl.W)
+    ref = U0.copy()
+    U, _, faults = _run(oracle_mod, wl, wl.W, 3, **kw)
+    assert faults == 0
+    assert np.array_equal(U, ref)
+
+
+@pytest.mark.parametrize("flux", ["rusanov", "hlle"])
+@pytest.mark.parametrize("two_level", [False, True])
+def test_conservation_periodic(oracle_mod, flux, two_level):
+    wl = wk.two_level_box() if two_level else wk.uniform_state((2, 2, 2))
+    W = wk.random_positive_state(wl, seed=11)
+    g = oracle_mod.Grid.from_workload(wl)
+    U0 = g.set_state(W)
+    t0 = total(wl, U0)
+    scale = np.array([math.fsum((np.abs(U0[v]) * (1.0 / 2 ** wl.level)[:, None, None, None] ** 3).ravel())
+                      for v in range(8)])
+    U, _, faults = _run(oracle_mod, wl, W, 3, flux=flux, powell=False)
+    assert faults == 0
+    t1 = total(wl, U)
+    assert np.all(np.abs(t1 - t0) <= 1e-14 * scale), (t1 - t0) / scale
+    assert not np.array_equal(U, U0)
+
+
+def test_powell_breaks_conservation_only_through_divB(oracle_mod):
+    """With the Powell source on, mass is still conserved exactly; with a divergence-free field the
+    whole update stays conservative."""
+    wl = wk.uniform_state((2, 2, 1))
+    W = wk.random_positive_state(wl, seed=4)
+    g = oracle_mod.Grid.from_workload(wl)
+    U0 = g.set_state(W)
+    t0 = total(wl, U0)
+    U, _, _ = _run(oracle_mod, wl, W, 2, flux="hlle", powell=True)
+    t1 = total(wl, U)
+    assert abs(t1[0] - t0[0]) <= 1e-14 * abs(t0[0])
+    assert np.any(np.abs(t1[1:] - t0[1:]) > 1e-12 * np.abs(t0[1:]).max())
+
+
+def _permute(wl, U):
+    """Cyclic axis permutation x->y->z->x of a global single-level field and of vector components."""
+    G = to_global(wl, U)
+    Gp = np.moveaxis(G, 1, 3)
+    out = Gp.copy()
+    out[1], out[2], out[3] = Gp[3], Gp[1], Gp[2]
+    out[4], out[5], out[6] = Gp[6], Gp[4], Gp[5]
+    return out
+
+
+@pytest.mark.parametrize("flux,powell", [("rusanov", False), ("hlle", True)])
+def test_axis_permutation_symmetry(oracle_mod, flux, powell):
+    wl = wk.uniform_state((2, 2, 2))
+    W = wk.random_positive_state(wl, seed=21)
+    Wp = from_global(wl, _permute(wl, W))
+    U, dt, _ = _run(oracle_mod, wl, W, 2, flux=flux, powell=powell)
+    Up, dtp, _ = _run(oracle_mod, wl, Wp, 2, flux=flux, powell=powell)
+    assert math.isclose(dt[0], dtp[0], rel_tol=1e-14)
+    ref = _permute(wl, U)
+    got = to_global(wl, Up)
+    scale = np.abs(ref).max(axis=(1, 2, 3))
+    assert np.all(np.abs(got - ref).max(axis=(1, 2, 3)) <= 1e-13 * scale)
+
+
+def test_body_mirror_symmetry(oracle_mod):
+    """A state symmetric under y -> -y about a centred body stays symmetric (reflecting wall)."""
+    wl = wk.magnetosphere_cut(16, n_steps=2)
+    W = wl.W.copy()
+    G = to_global(wl, W)
+    Gs = 0.5 * (G + G[:, :, ::-1, :] * np.array([1, 1, -1, 1, -1, 1, -1, 1.0])[:, None, None, None])
+    Gs = Gs * 1.0
+    Gs[2] = 0.5 * (G[2] - G[2][:, ::-1, :])
+    Gs[4] = 0.5 * (G[4] - G[4][:, ::-1, :])
+    Gs[6] = 0.5 * (G[6] - G[6][:, ::-1, :])
+    Ws = from_global(wl, Gs)
+    U, _, faults = _run(oracle_mod, wl, Ws, 2, flux="hlle", powell=True)
+    assert faults == 0
+    R = to_global(wl, U)
+    Rm = R[:, :, ::-1, :] * np.array([1, 1, -1, 1, 1, -1, 1, 1.0])[:, None, None, None]
+    scale = np.abs(R).max(axis=(1, 2, 3)) + 1e-300
+    assert np.all(np.abs(R - Rm).max(axis=(1, 2, 3)) <= 1e-11 * scale)
+
+
+# ------------------------------------------------------------------------------------------------
+# accuracy against exact solutions
+
+def _cp_error(oracle_mod, n):
+    wl = wk.cp_alfven(n)
+    g = oracle_mod.Grid.from_workload(wl)
+    U0 = g.set_state(wl.W)
+    T = 1.0 / math.sqrt(2.0)
+    dt_cfl = g.dt(U0, 0.8)[0]
+    nsteps = int(math.ceil(T / dt_cfl))
+    U1 = np.zeros_like(U0)
+    g.advance(U0, U1, [T / nsteps], 2 * nsteps, flux="rusanov", recompute_dt=False)
+    exact = wk.cp_alfven_field(wl.sims[0], wl.level, wl.ijk, 0.0)
+    return float(np.mean(np.abs(U0[4:7] - exact[4:7])))
+
+
+def test_cp_alfven_second_order(oracle_mod):
+    """L1 order between 16^3 and 32^3. MC clipping at the wave's extrema keeps the observed order below
+    2 at these resolutions (the same limiter and Heun scheme on 1-D linear advection of a sine give 1.69
+    from 32 to 64 cells and 1.85 from 64 to 128); a first-order mistake would give about 1."""
+    e16 = _cp_error(oracle_mod, 16)
+    e32 = _cp_error(oracle_mod, 32)
+    order = math.log2(e16 / e32)
+    assert order >= 1.6, (e16, e32, order)
+
+
+@pytest.mark.slow
+def test_cp_alfven_second_order_finer(oracle_mod):
+    e32 = _cp_error(oracle_mod, 32)
+    e64 = _cp_error(oracle_mod, 64)
+    order = math.log2(e32 / e64)
+    assert order >= 1.65, (e32, e64, order)
+
+
+def test_paper_fast_wave_phase_speed(oracle_mod):
+    """A small-amplitude version of the paper's fast wave (Eq. 6) travels along x at c_F = 0.05."""
+    g_ = json.load(open(os.path.join(GOLDEN, "fast_wave_speeds.json")))
+    wl = wk.fast_wave(nroot=(8, 1, 1))
+    V0, V1 = np.array(g_["V0"]), np.array(g_["V1"]) * 0.01
+    x, _, _ = wk.cell_centres(wl.sims[0], wl.level, wl.ijk)
+    k = g_["k"][0]
+    W = np.stack([V0[v] + V1[v] * np.cos(k * x) for v in range(8)])
+    g = oracle_mod.Grid.from_workload(wl)
+    U0 = g.set_state(W)
+    t_end = 320.0
+    dt_cfl = g.dt(U0, 0.8)[0]
+    nsteps = int(math.ceil(t_end / dt_cfl))
+    U1 = np.zeros_like(U0)
+    g.advance(U0, U1, [t_end / nsteps], 2 * nsteps, flux="hlle", powell=True, recompute_dt=False)
+    rho = to_global(wl, U0)[0][0, 0, :]
+    xs = (np.arange(64) + 0.5) - 32.0
+    ph0 = np.angle(np.sum((V0[0] + V1[0] * np.cos(k * xs)) * np.exp(-1j * k * xs)))
+    ph1 = np.angle(np.sum(rho * np.exp(-1j * k * xs)))
+    shift = (ph0 - ph1) % (2 * math.pi)
+    speed = shift / k / t_end
+    assert abs(speed - g_["c_F"]) < 0.02 * g_["c_F"], speed
