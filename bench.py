@@ -1,0 +1,159 @@
+"""Benchmark: FP64 cell-updates/s of the explicit block-adaptive MHD update on one MI355X.
+
+Workload (the metric's configuration): the magnetosphere-shaped uniform grid of 256^3 cells in 32^3
+blocks of 8^3 (dipole along -z, solar-wind inflow, reflecting body of radius 2.5 cells, outflow
+elsewhere), HLLE flux with the Powell source, MC limiter, Heun stages, CFL 0.8. A step is one full time
+step of the whole hot path: dt reduction, two fused stage kernels (ghost gather, reconstruction, fluxes,
+source, update, next-dt bound). Inputs are resident in HBM before the timed region starts.
+
+Prints one JSON line (rank 0). Extra fields: "roofline" for the dominant kernel (the stage kernel, timed
+live with HIP events that the library records on its stream), "cpu_baseline" (the CPU oracle on the
+host's cores over a bounded sample), and "forms" (the FP32-flux form on the same workload, with its
+error against the FP64 path).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "cell-updates/sec (FP64 plain vs FP32-flux vs learned) at stated L1 err; % HBM roofline"
+HBM_PEAK_GBS = 8000.0
+# algorithmic HBM bytes per cell and stage: stage 1 reads U^n and writes U^1 (2 x 64 B); stage 2 reads
+# U^1 and U^n and writes U^{n+1} (3 x 64 B): 320 B per cell-update
+BYTES_STAGE = (128.0, 192.0)
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=100)
+    p.add_argument("--warmup", type=int, default=3)
+    p.add_argument("--n", type=int, default=256, help="cells per axis of the magnetosphere grid")
+    p.add_argument("--slab", type=int, default=0)
+    p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--no-forms", action="store_true")
+    p.add_argument("--cpu-steps", type=int, default=1)
+    p.add_argument("--profile", action="store_true", help="short run for a profiler: no CPU leg, no forms")
+    return p.parse_args()
+
+
+def time_form(g, W, steps, warmup, precision, slab):
+    import torch
+    from paper_2501_06717_amd import binding
+    U0 = g.set_state(W)
+    U1 = torch.empty_like(U0)
+    dt = torch.zeros(1, dtype=torch.float64, device="cuda")
+    faults = torch.zeros(1, dtype=torch.int32, device="cuda")
+    base = dict(flux="hlle", powell=True, precision=precision, cfl=0.8, slab=slab)
+    if warmup:
+        g.advance(U0, U1, dt, 2 * warmup, faults=faults, **base)
+        U0 = g.set_state(W)  # restart from the initial state: the timed run is the first `steps` steps
+    torch.cuda.synchronize()
+    events = [torch.cuda.Event(enable_timing=True) for _ in range(4 * steps)]
+    for e in events:  # torch creates the HIP event lazily, on its first record
+        e.record()
+    torch.cuda.synchronize()
+    opts = binding.make_opts(events=events, **base)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    g.advance(U0, U1, dt, 2 * steps, opts=opts, faults=faults)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    st = [[], []]
+    for s in range(2 * steps):
+        st[s % 2].append(events[2 * s].elapsed_time(events[2 * s + 1]) * 1e-3)
+    return U0, wall, st, int(faults.item()), float(dt.item())
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        sys.exit(2)
+    import torch
+    from paper_2501_06717_amd import binding, workloads as wk
+
+    torch.cuda.set_device(0)
+    wl = wk.magnetosphere(a.n, n_steps=a.steps)
+    log(f"workload {wl.name}: {wl.n_blocks} blocks, {wl.n_cells} cells")
+    g = binding.Grid.from_workload(wl).upload()
+    W = torch.from_numpy(wl.W).cuda()
+    steps, warm = a.steps, a.warmup
+
+    U64, wall, st, faults, dt_last = time_form(g, W, steps, warm, "fp64", a.slab)
+    cells = wl.n_cells
+    value = cells * steps / wall
+    t1, t2 = float(np.mean(st[0])), float(np.mean(st[1]))
+    achieved = cells * (BYTES_STAGE[0] + BYTES_STAGE[1]) / (t1 + t2) / 1e9
+    log(f"fp64: {wall * 1e3:.2f} ms for {steps} steps, stage kernels {t1 * 1e6:.1f} / {t2 * 1e6:.1f} us, "
+        f"faults {faults}, dt {dt_last:.4e}")
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "cell-updates/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": warm,
+        "ms_per_step": wall * 1e3 / steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"magnetosphere {a.n}^3 cells ({wl.n_blocks} blocks of 8^3), dipole + solar-wind "
+                               "inflow, body r=2.5, HLLE + Powell, MC, Heun, CFL 0.8, FP64",
+                   "cells": cells, "blocks": wl.n_blocks, "parallelism": "1 GPU"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_stage (FP64, both stages)",
+                     "stage_us": [t1 * 1e6, t2 * 1e6], "bytes_per_cell_update": 320},
+        "faults": faults,
+    }
+    if not (a.no_forms or a.profile):
+        U32, wall32, st32, f32, _ = time_form(g, W, steps, warm, "fp32_flux", a.slab)
+        ref = U64.cpu().numpy()
+        got = U32.cpu().numpy()
+        l1 = float(np.abs(got - ref).sum() / np.abs(ref).sum())
+        linf = {k: float(np.abs(got[v] - ref[v]).max() / np.abs(ref[v]).max())
+                for k, v in (("rho", [0]), ("mom", [1, 2, 3]), ("B", [4, 5, 6]), ("e", [7]))}
+        out["forms"] = {"fp32_flux": {"value": cells * steps / wall32, "unit": "cell-updates/s",
+                                      "stage_us": [float(np.mean(st32[0])) * 1e6, float(np.mean(st32[1])) * 1e6],
+                                      "l1_rel_vs_fp64": l1, "linf_rel_vs_fp64": linf, "faults": f32,
+                                      "error_reference": "the FP64 GPU path on the same steps (itself within "
+                                                         "1e-12 of the CPU oracle)"}}
+        log(f"fp32_flux: {wall32 * 1e3:.2f} ms, L1 {l1:.3e}")
+        del U32
+    del U64
+    torch.cuda.synchronize()
+    if not (a.no_cpu_baseline or a.profile):
+        import oracle
+        o = oracle.Grid.from_workload(wl)
+        U0 = o.set_state(wl.W)
+        U1 = np.zeros_like(U0)
+        cores = len(os.sched_getaffinity(0))
+        t0 = time.perf_counter()
+        o.advance(U0, U1, [0.0], 2 * a.cpu_steps, flux="hlle", powell=True, cfl=0.8)
+        tc = time.perf_counter() - t0
+        threads = int(os.environ.get("OMP_NUM_THREADS", cores))
+        out["cpu_baseline"] = {"value": cells * a.cpu_steps / tc, "unit": "cell-updates/s",
+                               "cores": min(cores, threads), "kind": "oracle",
+                               "sample": f"{a.cpu_steps} full step(s) of the same {a.n}^3 workload "
+                                         f"({tc:.1f} s, OpenMP over blocks)"}
+        log(f"cpu oracle: {tc:.1f} s for {a.cpu_steps} step(s)")
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,168 @@
+/*
+ * bmhd.h -- C ABI of the MI355X block-adaptive ideal-MHD library (libbmhd.so).
+ *
+ * The library advances the explicit second-order finite-volume ideal-MHD update over every 8x8x8
+ * block of one or more simulations on one GPU (the single-GPU solver of the paper, Sec. 3 and
+ * Algorithm 2): ghost cells from neighbour blocks with restriction and prolongation at resolution
+ * changes (Sec. 4.1-4.2), limited linear face reconstruction, Rusanov or HLLE fluxes, the Powell
+ * divergence source (Eqs. 1-4), and a two-stage update under a CFL-limited global time step (Sec. 5.1,
+ * 5.2).
+ *
+ * Conventions
+ *   - Every device pointer is memory the caller owns (PyTorch tensors in the Python binding). The
+ *     library never allocates device memory. Pointers must be 8-byte aligned; d_work 256-byte aligned.
+ *   - `stream` is a hipStream_t passed as void*; NULL means the default stream. Every call that takes
+ *     a stream only enqueues work on it and returns; nothing is synchronised.
+ *   - State arrays are variable-major, U[8][n_blocks][8][8][8] (k, j, i with i fastest), float64.
+ *     Conserved order: rho, rho*ux, rho*uy, rho*uz, Bx, By, Bz, e (total energy, Eq. 5, mu0 = 1).
+ *     Primitive order: rho, ux, uy, uz, Bx, By, Bz, p. gamma = 5/3.
+ *   - Blocks are indexed in the caller's order; the library never reorders them.
+ *   - Return value: BMHD_OK (0) or a negative code; bmhd_last_error() gives a message (thread-local).
+ *     Launch errors are returned immediately. Numerical faults (rho <= 0, p <= 0, non-finite) are
+ *     counted on the device into the caller's fault counter.
+ *   - A grid handle must not be used from two host threads at once, and two calls that use the same
+ *     uploaded workspace must not run concurrently on different streams.
+ */
+#ifndef BMHD_H
+#define BMHD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define BMHD_OK 0
+#define BMHD_EINVAL (-1)       /* bad argument or descriptor */
+#define BMHD_EHIP (-2)         /* a HIP runtime call failed */
+#define BMHD_ENOMEM (-3)       /* host allocation failed, or the workspace is too small */
+#define BMHD_EUNSUPPORTED (-4) /* option combination not implemented */
+
+#define BMHD_BC_PERIODIC 0
+#define BMHD_BC_OUTFLOW 1 /* zero gradient: both ghost layers copy the nearest interior cell */
+#define BMHD_BC_INFLOW 2  /* ghost cells hold the conserved form of inflow_W */
+
+#define BMHD_FLUX_RUSANOV 0
+#define BMHD_FLUX_HLLE 1
+
+#define BMHD_FP64 0      /* every step in float64 */
+#define BMHD_FP32_FLUX 1 /* reconstruction and fluxes in float32; update, flux correction, dt in float64 */
+
+/* Neighbour relations reported by bmhd_grid_neighbors. */
+#define BMHD_REL_SAME 0
+#define BMHD_REL_COARSER 1
+#define BMHD_REL_FINER 2
+#define BMHD_REL_OUTFLOW (-1)
+#define BMHD_REL_INFLOW (-2)
+
+/* One simulation (an independent domain with its own root-block box and time step). */
+typedef struct {
+    int32_t nroot[3];     /* level-0 blocks per axis */
+    double origin[3];     /* lower domain corner */
+    double dx0;           /* level-0 cell size (level 1: dx0 / 2) */
+    int32_t bc[6];        /* x-lo, x-hi, y-lo, y-hi, z-lo, z-hi: BMHD_BC_*; periodic must pair up */
+    double inflow_W[8];   /* primitive inflow state */
+    double body_c[3];     /* centre of the reflecting body */
+    double body_r;        /* radius; <= 0 means no body. Cells whose centre lies strictly inside are
+                             body cells: never updated, never in dt, reflecting faces */
+} bmhd_sim_desc;
+
+/* A grid of blocks over n_sims simulations. Block b has refinement level level[b] in {0, 1}, block
+ * index ijk[3b..3b+2] at that level (level-1 indices are twice as fine) and simulation sim[b]. Every
+ * root block must be either one level-0 block or exactly its 8 level-1 children. */
+typedef struct {
+    int32_t n_blocks;
+    const int32_t *level; /* host [n_blocks] */
+    const int32_t *ijk;   /* host [n_blocks][3] */
+    const int32_t *sim;   /* host [n_blocks] */
+    int32_t n_sims;
+    const bmhd_sim_desc *sims; /* host [n_sims] */
+} bmhd_grid_desc;
+
+typedef struct {
+    int32_t flux;         /* BMHD_FLUX_* */
+    int32_t powell;       /* 1: Powell source terms (right-hand sides of Eqs. 2-4) */
+    int32_t precision;    /* BMHD_FP64 or BMHD_FP32_FLUX */
+    int32_t recompute_dt; /* 1: dt = CFL-limited global minimum per simulation, recomputed at the start
+                             of every step; 0: d_dt used as given for every step */
+    double cfl;
+    double alpha[2];      /* stage table: out = alpha U^n + (1 - alpha) U_in + beta dt L(U_in) */
+    double beta[2];       /* Heun: alpha = {0, 0.5}, beta = {1, 0.5} */
+    int32_t slab;         /* tile depth of the stage kernel: 0 = default, 4 or 8 cells along z */
+    int32_t n_events;     /* length of `events`, or 0 */
+    void **events;        /* optional caller-created hipEvent_t handles: when n_events >= 2 * n_stages,
+                             events[2s] and events[2s+1] are recorded on `stream` right before and after
+                             the stage kernel of stage s (for timing the dominant kernel) */
+} bmhd_opts;
+
+typedef struct {
+    int32_t n_blocks;
+    int32_t n_sims;
+    int32_t n_level_faces;  /* block faces that border a different refinement level */
+    int32_t n_flux_faces;   /* coarse block faces that get a flux correction */
+    size_t work_bytes;      /* size of the device workspace bmhd_grid_upload needs */
+} bmhd_grid_info;
+
+typedef struct bmhd_grid bmhd_grid;
+
+/* Library version (major * 10000 + minor * 100 + patch). */
+int32_t bmhd_version(void);
+
+/* Message of the last failing call on this thread ("" if none). Valid until the next call. */
+const char *bmhd_last_error(void);
+
+/* Validate a descriptor and build the host-side tables: the 26-direction neighbour table, the face
+ * relations used for ghost filling (Sec. 4.2: copy, restriction, prolongation, boundary), the list of
+ * coarse-fine faces for flux correction, and a Morton-ordered block schedule. Host only; no HIP call.
+ * On success *out owns a handle the caller frees with bmhd_grid_destroy. Errors: BMHD_EINVAL for a
+ * malformed descriptor (level outside {0,1}, block outside its root box, overlap, partial refinement,
+ * unpaired periodic faces, non-positive cell size). Body cells are found from cell-centre positions,
+ * ghost cells included, so a body is expected to stay clear of domain faces and resolution changes. */
+int32_t bmhd_grid_create(const bmhd_grid_desc *desc, bmhd_grid **out);
+void bmhd_grid_destroy(bmhd_grid *g);
+
+int32_t bmhd_grid_info_get(const bmhd_grid *g, bmhd_grid_info *info);
+
+/* Neighbour table into host memory h_out[n_blocks][26][5]: {relation, id0, id1, id2, id3} for the 26
+ * directions (dx, dy, dz) in {-1,0,1}^3 \ {0}, enumerated with dx fastest. SAME/COARSER: id0 is the
+ * neighbour. FINER: the finer blocks that touch the block, ordered x fastest over the free
+ * sub-positions. OUTFLOW/INFLOW: the direction leaves the domain through a non-periodic face (the
+ * first such axis in x, y, z order decides). Unused ids are -1. */
+int32_t bmhd_grid_neighbors(const bmhd_grid *g, int32_t *h_out);
+
+/* Copy the tables into the caller's device workspace d_work (work_bytes from bmhd_grid_info_get,
+ * 256-byte aligned) on `stream`. The grid keeps d_work as a borrowed pointer: it must stay allocated
+ * while the grid is used, and upload must be repeated if it moves. The host tables are read again
+ * by the copy only until the stream reaches it (the call waits for the copy before returning). */
+int32_t bmhd_grid_upload(bmhd_grid *g, void *d_work, size_t work_bytes, void *stream);
+
+/* Primitive to conserved (Eq. 5) for every interior cell: d_U[8][nB][512] from d_W[8][nB][512]. */
+int32_t bmhd_set_state(const bmhd_grid *g, const double *d_W, double *d_U, void *stream);
+
+/* Every cell of every block including both ghost layers on faces, edges and corners, written into a
+ * padded view d_view[8][nB][12][12][12] (interior copied). Ghost rules (Sec. 4.2): copy from an
+ * equal-level neighbour; restriction (pairwise-tree mean of the 8 finer cells) from a finer one;
+ * prolongation (coarse value plus a quarter of the minmod slope per axis toward the fine cell) from a
+ * coarser one; periodic wrap, outflow copy of the nearest interior cell, inflow state. Bit-exact
+ * (no contraction). */
+int32_t bmhd_fill_ghosts(const bmhd_grid *g, const double *d_U, double *d_view, void *stream);
+
+/* d_dt[n_sims] = cfl * min over fluid cells of 1 / sum_d ((|u_d| + c_f,d) / dx) from d_U. */
+int32_t bmhd_reduce_dt(const bmhd_grid *g, const double *d_U, double cfl, double *d_dt, void *stream);
+
+/* Advance n_stages stages of the two-stage scheme (Algorithm 2's block sweep, repeated). Stage s uses
+ * table entry s % 2: even stages read d_U0 (with ghost cells from neighbours) and write d_U1; odd
+ * stages read d_U1 and d_U0 and overwrite d_U0, so a whole step leaves U^{n+1} in d_U0. A call starts
+ * at a step boundary; after an odd n_stages the intermediate state is in d_U1. d_dt[n_sims]: with
+ * recompute_dt, dt is recomputed at the start of every step and d_dt returns the last step's dt;
+ * otherwise d_dt is read as given. d_faults (int32[1], may be NULL) is incremented by the number of
+ * fluid cells with rho <= 0, p <= 0 or a non-finite value at the end of each step. Requires a prior
+ * bmhd_grid_upload. */
+int32_t bmhd_advance(const bmhd_grid *g, double *d_U0, double *d_U1, double *d_dt, int32_t n_stages,
+                     const bmhd_opts *opts, int32_t *d_faults, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,232 @@
+"""Thin ctypes binding of libbmhd.so (include/bmhd.h). Argument marshalling only: every step of the
+solver runs in the library's HIP kernels. Device buffers are torch tensors on the current HIP device;
+every call is enqueued on torch's current stream.
+
+The binding fails loudly when the library is missing: there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libbmhd.so")
+
+BC_PERIODIC, BC_OUTFLOW, BC_INFLOW = 0, 1, 2
+FLUX = {"rusanov": 0, "hlle": 1}
+PRECISION = {"fp64": 0, "fp32_flux": 1}
+
+EXPORTS = ["bmhd_version", "bmhd_last_error", "bmhd_grid_create", "bmhd_grid_destroy", "bmhd_grid_info_get",
+           "bmhd_grid_neighbors", "bmhd_grid_upload", "bmhd_set_state", "bmhd_fill_ghosts", "bmhd_reduce_dt",
+           "bmhd_advance"]
+
+
+class SimDesc(ctypes.Structure):
+    _fields_ = [("nroot", ctypes.c_int32 * 3), ("origin", ctypes.c_double * 3), ("dx0", ctypes.c_double),
+                ("bc", ctypes.c_int32 * 6), ("inflow_W", ctypes.c_double * 8), ("body_c", ctypes.c_double * 3),
+                ("body_r", ctypes.c_double)]
+
+
+class GridDesc(ctypes.Structure):
+    _fields_ = [("n_blocks", ctypes.c_int32), ("level", ctypes.POINTER(ctypes.c_int32)),
+                ("ijk", ctypes.POINTER(ctypes.c_int32)), ("sim", ctypes.POINTER(ctypes.c_int32)),
+                ("n_sims", ctypes.c_int32), ("sims", ctypes.POINTER(SimDesc))]
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("flux", ctypes.c_int32), ("powell", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("recompute_dt", ctypes.c_int32), ("cfl", ctypes.c_double), ("alpha", ctypes.c_double * 2),
+                ("beta", ctypes.c_double * 2), ("slab", ctypes.c_int32), ("n_events", ctypes.c_int32),
+                ("events", ctypes.POINTER(ctypes.c_void_p))]
+
+
+class GridInfo(ctypes.Structure):
+    _fields_ = [("n_blocks", ctypes.c_int32), ("n_sims", ctypes.c_int32), ("n_level_faces", ctypes.c_int32),
+                ("n_flux_faces", ctypes.c_int32), ("work_bytes", ctypes.c_size_t)]
+
+
+class BmhdError(RuntimeError):
+    pass
+
+
+_lib = None
+
+
+def lib():
+    """Load libbmhd.so (built by paper_2501_06717_amd.build). Raises if it is missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise BmhdError(f"{LIB_PATH} is missing: build it with `python -m paper_2501_06717_amd.build` "
+                        "(there is no fallback path)")
+    L = ctypes.CDLL(LIB_PATH)
+    P, vp, i32 = ctypes.POINTER, ctypes.c_void_p, ctypes.c_int32
+    L.bmhd_version.restype = i32
+    L.bmhd_last_error.restype = ctypes.c_char_p
+    L.bmhd_grid_create.argtypes = [P(GridDesc), P(vp)]
+    L.bmhd_grid_create.restype = i32
+    L.bmhd_grid_destroy.argtypes = [vp]
+    L.bmhd_grid_destroy.restype = None
+    L.bmhd_grid_info_get.argtypes = [vp, P(GridInfo)]
+    L.bmhd_grid_info_get.restype = i32
+    L.bmhd_grid_neighbors.argtypes = [vp, P(i32)]
+    L.bmhd_grid_neighbors.restype = i32
+    L.bmhd_grid_upload.argtypes = [vp, vp, ctypes.c_size_t, vp]
+    L.bmhd_grid_upload.restype = i32
+    L.bmhd_set_state.argtypes = [vp, vp, vp, vp]
+    L.bmhd_set_state.restype = i32
+    L.bmhd_fill_ghosts.argtypes = [vp, vp, vp, vp]
+    L.bmhd_fill_ghosts.restype = i32
+    L.bmhd_reduce_dt.argtypes = [vp, vp, ctypes.c_double, vp, vp]
+    L.bmhd_reduce_dt.restype = i32
+    L.bmhd_advance.argtypes = [vp, vp, vp, vp, i32, P(Opts), vp, vp]
+    L.bmhd_advance.restype = i32
+    _lib = L
+    return L
+
+
+def _check(rc):
+    if rc != 0:
+        msg = lib().bmhd_last_error().decode()
+        raise BmhdError(f"bmhd error {rc}: {msg}")
+
+
+def make_opts(flux="rusanov", powell=False, precision="fp64", recompute_dt=True, cfl=0.8,
+              alpha=(0.0, 0.5), beta=(1.0, 0.5), slab=0, events=None) -> Opts:
+    """Options for bmhd_advance. `events`: optional list of torch.cuda.Event (enable_timing=True), two per
+    stage, recorded by the library around each stage kernel."""
+    o = Opts()
+    o.flux = FLUX[flux]
+    o.powell = int(bool(powell))
+    o.precision = PRECISION[precision]
+    o.recompute_dt = int(bool(recompute_dt))
+    o.cfl = float(cfl)
+    o.alpha[:] = [float(a) for a in alpha]
+    o.beta[:] = [float(b) for b in beta]
+    o.slab = int(slab)
+    if events:
+        arr = (ctypes.c_void_p * len(events))(*[ctypes.c_void_p(e.cuda_event) for e in events])
+        o._events_keepalive = arr
+        o.n_events = len(events)
+        o.events = ctypes.cast(arr, ctypes.POINTER(ctypes.c_void_p))
+    else:
+        o.n_events = 0
+        o.events = None
+    return o
+
+
+def _stream_ptr(stream=None):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _dev_ptr(t, dtype=None):
+    import torch
+    if not t.is_cuda:
+        raise BmhdError("tensor must live on the GPU")
+    if not t.is_contiguous():
+        raise BmhdError("tensor must be contiguous")
+    if dtype is not None and t.dtype != dtype:
+        raise BmhdError(f"tensor dtype must be {dtype}, got {t.dtype}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Grid:
+    """A grid handle: host tables built by the library, plus (after `upload`) a torch-owned device
+    workspace holding them."""
+
+    def __init__(self, level: Sequence[int], ijk, sim, sims):
+        L = lib()
+        self.level = np.ascontiguousarray(level, np.int32)
+        self.ijk = np.ascontiguousarray(ijk, np.int32).reshape(-1, 3)
+        self.sim = np.ascontiguousarray(sim, np.int32)
+        self.nb = int(self.level.shape[0])
+        self.ns = len(sims)
+        arr = (SimDesc * self.ns)()
+        for i, s in enumerate(sims):
+            arr[i].nroot[:] = [int(v) for v in s.nroot]
+            arr[i].origin[:] = [float(v) for v in s.origin]
+            arr[i].dx0 = float(s.dx0)
+            arr[i].bc[:] = [int(v) for v in s.bc]
+            arr[i].inflow_W[:] = [float(v) for v in s.inflow_W]
+            arr[i].body_c[:] = [float(v) for v in s.body_c]
+            arr[i].body_r = float(s.body_r)
+        d = GridDesc()
+        d.n_blocks = self.nb
+        d.level = self.level.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+        d.ijk = self.ijk.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+        d.sim = self.sim.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+        d.n_sims = self.ns
+        d.sims = arr
+        h = ctypes.c_void_p()
+        _check(L.bmhd_grid_create(ctypes.byref(d), ctypes.byref(h)))
+        self.h = h
+        self.work = None
+        info = GridInfo()
+        _check(L.bmhd_grid_info_get(self.h, ctypes.byref(info)))
+        self.info = info
+
+    @classmethod
+    def from_workload(cls, wl):
+        return cls(wl.level, wl.ijk, wl.sim, wl.sims)
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h is not None and h.value:
+            lib().bmhd_grid_destroy(h)
+            self.h = None
+
+    @property
+    def n_cells(self):
+        return self.nb * 512
+
+    def neighbors(self) -> np.ndarray:
+        out = np.empty((self.nb, 26, 5), np.int32)
+        _check(lib().bmhd_grid_neighbors(self.h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))))
+        return out
+
+    def upload(self, device="cuda", stream=None):
+        import torch
+        n = int(self.info.work_bytes)
+        self.work = torch.empty(n + 256, dtype=torch.uint8, device=device)
+        base = self.work.data_ptr()
+        aligned = (base + 255) & ~255
+        _check(lib().bmhd_grid_upload(self.h, ctypes.c_void_p(aligned), ctypes.c_size_t(n), _stream_ptr(stream)))
+        return self
+
+    def set_state(self, W, U=None, stream=None):
+        import torch
+        if U is None:
+            U = torch.empty_like(W)
+        _check(lib().bmhd_set_state(self.h, _dev_ptr(W, torch.float64), _dev_ptr(U, torch.float64),
+                                    _stream_ptr(stream)))
+        return U
+
+    def fill_ghosts(self, U, view=None, stream=None):
+        import torch
+        if view is None:
+            view = torch.empty((8, self.nb, 12, 12, 12), dtype=torch.float64, device=U.device)
+        _check(lib().bmhd_fill_ghosts(self.h, _dev_ptr(U, torch.float64), _dev_ptr(view, torch.float64),
+                                      _stream_ptr(stream)))
+        return view
+
+    def reduce_dt(self, U, cfl, dt=None, stream=None):
+        import torch
+        if dt is None:
+            dt = torch.empty(self.ns, dtype=torch.float64, device=U.device)
+        _check(lib().bmhd_reduce_dt(self.h, _dev_ptr(U, torch.float64), float(cfl), _dev_ptr(dt, torch.float64),
+                                    _stream_ptr(stream)))
+        return dt
+
+    def advance(self, U0, U1, dt, n_stages, opts: Optional[Opts] = None, faults=None, stream=None, **kw):
+        import torch
+        o = opts if opts is not None else make_opts(**kw)
+        fp = _dev_ptr(faults, torch.int32) if faults is not None else ctypes.c_void_p(0)
+        _check(lib().bmhd_advance(self.h, _dev_ptr(U0, torch.float64), _dev_ptr(U1, torch.float64),
+                                  _dev_ptr(dt, torch.float64), int(n_stages), ctypes.byref(o), fp,
+                                  _stream_ptr(stream)))

@@ -1,0 +1,992 @@
+// kernels.hip -- CDNA4 (gfx950) kernels and the C ABI of libbmhd.so.
+//
+// Hot path per stage (the GPU solver's block sweep, Algorithm 2, redesigned for MI355X):
+//   k_halo_fill   ghost layers of faces that border another level (restriction / prolongation,
+//                 Sec. 4.2), only on grids with two levels;
+//   k_stage       one workgroup per slab of a block (8 x 8 x KS cells). It gathers the slab and its
+//                 2-deep face halos from HBM straight into LDS as primitive variables (same-level
+//                 neighbours are read in place: no separate ghost-fill pass), computes every face flux
+//                 once (MC-limited reconstruction, Rusanov or HLLE), exchanges fluxes through LDS,
+//                 adds the Powell source (Eqs. 2-4) and writes the stage result. The second stage also
+//                 folds in the next time-step bound (wave-level max, one filtered 64-bit atomic per
+//                 workgroup) and the positivity check;
+//   k_flux_correct coarse cells next to a coarse-fine face swap their coarse flux for the mean of the
+//                 four fine fluxes (FP64 in every precision form);
+//   k_dt_finalize dt = CFL / max bound per simulation.
+// Workgroups are mapped XCD-aware: consecutive workgroup ids go to different XCDs, so each XCD is
+// handed a contiguous run of the Morton-ordered block schedule and neighbouring blocks share an L2.
+#include <hip/hip_runtime.h>
+
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "bmhd_internal.h"
+
+namespace bmhd {
+
+constexpr double GAMMA = 5.0 / 3.0;
+
+// ------------------------------------------------------------------------------------------------
+// small device helpers
+
+template <typename R>
+__device__ __forceinline__ R rmin(R a, R b) { return a < b ? a : b; }
+template <typename R>
+__device__ __forceinline__ R rmax(R a, R b) { return a > b ? a : b; }
+
+template <typename R>
+__device__ __forceinline__ R rsqrt_(R x);
+template <>
+__device__ __forceinline__ double rsqrt_<double>(double x) { return sqrt(x); }
+template <>
+__device__ __forceinline__ float rsqrt_<float>(float x) { return sqrtf(x); }
+
+// conserved -> primitive in FP64 (u = m / rho, p from the total energy of Eq. 5)
+__device__ __forceinline__ void cons_to_prim(const double u[8], double w[8]) {
+    const double rho = u[0];
+    const double ir = 1.0 / rho;
+    const double ux = u[1] * ir, uy = u[2] * ir, uz = u[3] * ir;
+    const double ke = u[1] * ux + u[2] * uy + u[3] * uz;
+    const double b2 = u[4] * u[4] + u[5] * u[5] + u[6] * u[6];
+    w[0] = rho;
+    w[1] = ux;
+    w[2] = uy;
+    w[3] = uz;
+    w[4] = u[4];
+    w[5] = u[5];
+    w[6] = u[6];
+    w[7] = (GAMMA - 1.0) * (u[7] - 0.5 * ke - 0.5 * b2);
+}
+
+// fast magnetosonic speed along axis D (largest root of the ideal-MHD dispersion relation)
+template <typename R, int D>
+__device__ __forceinline__ R fast_speed(const R w[8], R ir) {
+    const R a2 = R(GAMMA) * w[7] * ir;
+    const R bx = w[4], by = w[5], bz = w[6];
+    const R b2 = (bx * bx + by * by + bz * bz) * ir;
+    const R bn = w[4 + D];
+    const R bn2 = bn * bn * ir;
+    const R s = a2 + b2;
+    R disc = s * s - R(4) * a2 * bn2;
+    disc = rmax(disc, R(0));
+    return rsqrt_<R>(R(0.5) * (s + rsqrt_<R>(disc)));
+}
+
+// conserved state, physical flux along D, normal velocity and fast speed of one face state
+template <typename R, int D>
+__device__ __forceinline__ void face_side(const R w[8], R U[8], R F[8], R &un, R &cf) {
+    const R rho = w[0], ux = w[1], uy = w[2], uz = w[3], bx = w[4], by = w[5], bz = w[6], p = w[7];
+    const R u2 = ux * ux + uy * uy + uz * uz;
+    const R b2 = bx * bx + by * by + bz * bz;
+    const R ub = ux * bx + uy * by + uz * bz;
+    const R pb = R(0.5) * b2;
+    const R ptot = p + pb;
+    const R e = p * R(1.5) + R(0.5) * rho * u2 + pb;
+    un = w[1 + D];
+    const R bn = w[4 + D];
+    const R mn = rho * un;
+    U[0] = rho;
+    U[1] = rho * ux;
+    U[2] = rho * uy;
+    U[3] = rho * uz;
+    U[4] = bx;
+    U[5] = by;
+    U[6] = bz;
+    U[7] = e;
+    F[0] = mn;
+    F[1] = mn * ux - bx * bn;
+    F[2] = mn * uy - by * bn;
+    F[3] = mn * uz - bz * bn;
+    F[1 + D] += ptot;
+    F[4] = un * bx - bn * ux;
+    F[5] = un * by - bn * uy;
+    F[6] = un * bz - bn * uz;
+    F[4 + D] = R(0);
+    F[7] = un * (e + ptot) - bn * ub;
+    const R ir = R(1) / rho;
+    cf = fast_speed<R, D>(w, ir);
+}
+
+template <typename R, int D, int FLUX>
+__device__ __forceinline__ void num_flux(const R wl[8], const R wr[8], R f[8]) {
+    R UL[8], FL[8], UR[8], FR[8], unl, cl, unr, cr;
+    face_side<R, D>(wl, UL, FL, unl, cl);
+    face_side<R, D>(wr, UR, FR, unr, cr);
+    if constexpr (FLUX == BMHD_FLUX_RUSANOV) {
+        const R cmax = rmax(fabs(unl) + cl, fabs(unr) + cr);
+#pragma unroll
+        for (int v = 0; v < 8; ++v) f[v] = R(0.5) * (FL[v] + FR[v]) - R(0.5) * cmax * (UR[v] - UL[v]);
+    } else {
+        const R sl = rmin(unl - cl, unr - cr);
+        const R sr = rmax(unl + cl, unr + cr);
+        if (sl >= R(0)) {
+#pragma unroll
+            for (int v = 0; v < 8; ++v) f[v] = FL[v];
+        } else if (sr <= R(0)) {
+#pragma unroll
+            for (int v = 0; v < 8; ++v) f[v] = FR[v];
+        } else {
+            const R inv = R(1) / (sr - sl);
+            const R slsr = sl * sr;
+#pragma unroll
+            for (int v = 0; v < 8; ++v) f[v] = (sr * FL[v] - sl * FR[v] + slsr * (UR[v] - UL[v])) * inv;
+        }
+    }
+}
+
+// monotonized-central limited slope: minmod(2 dm, (dm + dp) / 2, 2 dp)
+template <typename R>
+__device__ __forceinline__ R mc_slope(R wm, R w0, R wp) {
+    const R dm = w0 - wm, dp = wp - w0;
+    const R a = R(2) * dm, b = R(0.5) * (dm + dp), c = R(2) * dp;
+    const R m = rmin(rmin(fabs(a), fabs(b)), fabs(c));
+    return (a > R(0) && b > R(0) && c > R(0)) ? m : ((a < R(0) && b < R(0) && c < R(0)) ? -m : R(0));
+}
+
+// body membership of a cell from its centre (no contraction: must agree bit for bit everywhere)
+__device__ __noinline__ bool in_body(const DevSim &S, int level, const int32_t ijk[3], int i, int j, int k) {
+#pragma clang fp contract(off)
+    if (!(S.body_r > 0.0)) return false;
+    const double dx = S.dx0 / double(1 << level);
+    const int idx[3] = {i, j, k};
+    double r2 = 0.0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const long long G = (long long)ijk[a] * 8 + idx[a];
+        const double x = S.origin[a] + (double(G) + 0.5) * dx;
+        const double t = x - S.body_c[a];
+        r2 = r2 + t * t;
+    }
+    return r2 < S.body_r * S.body_r;
+}
+
+// ------------------------------------------------------------------------------------------------
+// generic ghost-value rules (Sec. 4.2) on global cell indices; used by the halo and full ghost fills.
+// Evaluated without contraction so that copy, restriction and prolongation are reproducible bit for bit.
+
+struct Cursor {
+    const Tables *T;
+    const double *U;
+    size_t vs;  // variable stride = nb * 512
+};
+
+__device__ __forceinline__ int32_t lut_at(const Tables &T, const DevSim &S, int l, long long bx, long long by,
+                                          long long bz) {
+    const long long nx = (long long)S.nroot[0] << l, ny = (long long)S.nroot[1] << l, nz = (long long)S.nroot[2] << l;
+    if (bx < 0 || by < 0 || bz < 0 || bx >= nx || by >= ny || bz >= nz) return -1;
+    return T.lut[S.lut_off[l] + (bz * ny + by) * nx + bx];
+}
+
+// boundary rule on a level-l global cell index; false means "inflow"
+__device__ __forceinline__ bool apply_bounds(const DevSim &S, int l, long long G[3]) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const long long n = ((long long)S.nroot[a] * 8) << l;
+        if (G[a] < 0 || G[a] >= n) {
+            const int side = G[a] >= n;
+            const int t = S.bc[2 * a + side];
+            if (t == BMHD_BC_PERIODIC) G[a] = ((G[a] % n) + n) % n;
+            else if (t == BMHD_BC_OUTFLOW) G[a] = side ? n - 1 : 0;
+            else return false;
+        }
+    }
+    return true;
+}
+
+__device__ __forceinline__ bool leaf_cell(const Cursor &c, const DevSim &S, int l, const long long G[3], double out[8]) {
+    const int32_t b = lut_at(*c.T, S, l, G[0] >> 3, G[1] >> 3, G[2] >> 3);
+    if (b < 0) return false;
+    const size_t off = size_t(b) * 512 + size_t(((G[2] & 7) * 8 + (G[1] & 7)) * 8 + (G[0] & 7));
+#pragma unroll
+    for (int v = 0; v < 8; ++v) out[v] = c.U[v * c.vs + off];
+    return true;
+}
+
+__device__ __noinline__ bool restricted_cell(const Cursor &c, const DevSim &S, const long long G[3], double out[8]) {
+#pragma clang fp contract(off)
+    size_t off[8];
+    for (int q = 0; q < 8; ++q) {
+        const long long F[3] = {2 * G[0] + (q & 1), 2 * G[1] + ((q >> 1) & 1), 2 * G[2] + (q >> 2)};
+        const int32_t b = lut_at(*c.T, S, 1, F[0] >> 3, F[1] >> 3, F[2] >> 3);
+        if (b < 0) return false;
+        off[q] = size_t(b) * 512 + size_t(((F[2] & 7) * 8 + (F[1] & 7)) * 8 + (F[0] & 7));
+    }
+#pragma unroll
+    for (int v = 0; v < 8; ++v) {
+        const double *u = c.U + v * c.vs;
+        const double s = ((u[off[0]] + u[off[1]]) + (u[off[2]] + u[off[3]])) +
+                         ((u[off[4]] + u[off[5]]) + (u[off[6]] + u[off[7]]));
+        out[v] = s * 0.125;
+    }
+    return true;
+}
+
+// level-0 value with boundary rule, from a level-0 leaf or restricted from level 1
+__device__ __noinline__ void coarse_cell(const Cursor &c, const DevSim &S, long long G[3], double out[8]) {
+    if (!apply_bounds(S, 0, G)) {
+#pragma unroll
+        for (int v = 0; v < 8; ++v) out[v] = S.inflow_U[v];
+        return;
+    }
+    if (leaf_cell(c, S, 0, G, out)) return;
+    restricted_cell(c, S, G, out);
+}
+
+__device__ __forceinline__ double minmod2(double a, double b) {
+    return (a > 0.0 && b > 0.0) ? fmin(a, b) : ((a < 0.0 && b < 0.0) ? fmax(a, b) : 0.0);
+}
+
+// any cell of a level-l grid, at a global index that may lie outside the domain
+__device__ __noinline__ void ghost_cell(const Cursor &c, const DevSim &S, int l, const long long G0[3], double out[8]) {
+#pragma clang fp contract(off)
+    long long G[3] = {G0[0], G0[1], G0[2]};
+    if (!apply_bounds(S, l, G)) {
+#pragma unroll
+        for (int v = 0; v < 8; ++v) out[v] = S.inflow_U[v];
+        return;
+    }
+    if (leaf_cell(c, S, l, G, out)) return;
+    if (l == 0) {
+        restricted_cell(c, S, G, out);
+        return;
+    }
+    // prolongation from coarse cell C = G / 2
+    long long C[3] = {G[0] >> 1, G[1] >> 1, G[2] >> 1};
+    double uc[8];
+    leaf_cell(c, S, 0, C, uc);
+    double acc[8];
+#pragma unroll
+    for (int v = 0; v < 8; ++v) acc[v] = uc[v];
+    for (int d = 0; d < 3; ++d) {
+        long long Cm[3] = {C[0], C[1], C[2]}, Cp[3] = {C[0], C[1], C[2]};
+        Cm[d] -= 1;
+        Cp[d] += 1;
+        double um[8], up[8];
+        coarse_cell(c, S, Cm, um);
+        coarse_cell(c, S, Cp, up);
+        const double s = (G[d] & 1) ? 0.25 : -0.25;
+#pragma unroll
+        for (int v = 0; v < 8; ++v) acc[v] = acc[v] + s * minmod2(uc[v] - um[v], up[v] - uc[v]);
+    }
+#pragma unroll
+    for (int v = 0; v < 8; ++v) out[v] = acc[v];
+}
+
+// ------------------------------------------------------------------------------------------------
+// kernels: state conversion, full ghost view, halo buffer
+
+__global__ void k_set_state(const double *__restrict__ W, double *__restrict__ U, size_t n) {
+    const size_t c = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (c >= n) return;
+    double w[8];
+#pragma unroll
+    for (int v = 0; v < 8; ++v) w[v] = W[v * n + c];
+    const double rho = w[0];
+    const double u2 = w[1] * w[1] + w[2] * w[2] + w[3] * w[3];
+    const double b2 = w[4] * w[4] + w[5] * w[5] + w[6] * w[6];
+    U[c] = rho;
+    U[n + c] = rho * w[1];
+    U[2 * n + c] = rho * w[2];
+    U[3 * n + c] = rho * w[3];
+    U[4 * n + c] = w[4];
+    U[5 * n + c] = w[5];
+    U[6 * n + c] = w[6];
+    U[7 * n + c] = w[7] * 1.5 + 0.5 * rho * u2 + 0.5 * b2;
+}
+
+__global__ void __launch_bounds__(256) k_fill_view(Tables T, const double *__restrict__ U, double *__restrict__ view) {
+    const int b = blockIdx.x;
+    const DevBlock &B = T.blocks[b];
+    const DevSim &S = T.sims[B.sim];
+    const size_t vs = size_t(T.nb) * 512, vv = size_t(T.nb) * 1728;
+    Cursor cur{&T, U, vs};
+    for (int c = threadIdx.x; c < 1728; c += blockDim.x) {
+        const int i = c % 12 - 2, j = (c / 12) % 12 - 2, k = c / 144 - 2;
+        double out[8];
+        if ((unsigned)i < 8u && (unsigned)j < 8u && (unsigned)k < 8u) {
+            const size_t off = size_t(b) * 512 + (k * 8 + j) * 8 + i;
+#pragma unroll
+            for (int v = 0; v < 8; ++v) out[v] = U[v * vs + off];
+        } else {
+            const long long G[3] = {(long long)B.ijk[0] * 8 + i, (long long)B.ijk[1] * 8 + j, (long long)B.ijk[2] * 8 + k};
+            ghost_cell(cur, S, B.level, G, out);
+        }
+#pragma unroll
+        for (int v = 0; v < 8; ++v) view[v * vv + size_t(b) * 1728 + c] = out[v];
+    }
+}
+
+// ghost layers of one level-change face: item = (block << 3) | face; 128 threads = 2 layers x 64
+__global__ void __launch_bounds__(128) k_halo_fill(Tables T, const double *__restrict__ U) {
+    const int32_t item = T.halo_items[blockIdx.x];
+    const int b = item >> 3, f = item & 7;
+    const DevBlock &B = T.blocks[b];
+    const DevSim &S = T.sims[B.sim];
+    const int t = threadIdx.x, layer = t >> 6, t1 = t & 7, t2 = (t >> 3) & 7;
+    const int a = f >> 1, side = f & 1;
+    const int a1 = a == 0 ? 1 : 0, a2 = a == 2 ? 1 : 2;
+    int idx[3];
+    idx[a] = side ? 8 + layer : -1 - layer;
+    idx[a1] = t1;
+    idx[a2] = t2;
+    const long long G[3] = {(long long)B.ijk[0] * 8 + idx[0], (long long)B.ijk[1] * 8 + idx[1],
+                            (long long)B.ijk[2] * 8 + idx[2]};
+    Cursor cur{&T, U, size_t(T.nb) * 512};
+    double out[8];
+    ghost_cell(cur, S, B.level, G, out);
+    double *h = T.halo + size_t(B.halo_slot) * HALO_SLOT + size_t(f) * HALO_FACE + layer * 64 + t2 * 8 + t1;
+#pragma unroll
+    for (int v = 0; v < 8; ++v) h[v * 128] = out[v];
+}
+
+// ------------------------------------------------------------------------------------------------
+// time-step bound
+
+__device__ __forceinline__ double cell_bound(const double w[8], double inv_dx) {
+    const double ir = 1.0 / w[0];
+    const double cx = fast_speed<double, 0>(w, ir), cy = fast_speed<double, 1>(w, ir), cz = fast_speed<double, 2>(w, ir);
+    return (fabs(w[1]) + cx) * inv_dx + (fabs(w[2]) + cy) * inv_dx + (fabs(w[3]) + cz) * inv_dx;
+}
+
+__device__ __forceinline__ double wave_max(double x) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) x = fmax(x, __shfl_xor(x, o));
+    return x;
+}
+__device__ __forceinline__ int wave_sum(int x) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
+    return x;
+}
+
+// bits of a non-negative double order like the double; read first so that most workgroups skip the atomic
+__device__ __forceinline__ void publish_max(unsigned long long *slot, double v) {
+    if (!(v > 0.0)) {
+        if (v != v) atomicMax(slot, 0x7ff8000000000000ull);
+        return;
+    }
+    const unsigned long long bits = (unsigned long long)__double_as_longlong(v);
+    if (__atomic_load_n(slot, __ATOMIC_RELAXED) < bits) atomicMax(slot, bits);
+}
+
+template <int NT>
+__device__ __forceinline__ void block_publish(double lam, int nfault, double *red, int *redi, unsigned long long *slot,
+                                              int32_t *faults) {
+    lam = wave_max(lam);
+    nfault = wave_sum(nfault);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) {
+        red[wid] = lam;
+        redi[wid] = nfault;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double m = red[0];
+        int n = redi[0];
+        for (int w = 1; w < NT / 64; ++w) {
+            m = fmax(m, red[w]);
+            n += redi[w];
+        }
+        if (slot) publish_max(slot, m);
+        if (n && faults) atomicAdd(faults, n);
+    }
+}
+
+__global__ void __launch_bounds__(512) k_dt_reduce(Tables T, const double *__restrict__ U) {
+    __shared__ double red[8];
+    __shared__ int redi[8];
+    const int b = blockIdx.x;
+    const DevBlock &B = T.blocks[b];
+    const DevSim &S = T.sims[B.sim];
+    const size_t vs = size_t(T.nb) * 512;
+    const int c = threadIdx.x;
+    double u[8], w[8];
+#pragma unroll
+    for (int v = 0; v < 8; ++v) u[v] = U[v * vs + size_t(b) * 512 + c];
+    cons_to_prim(u, w);
+    const double inv_dx = double(1 << B.level) / S.dx0;
+    bool body = (B.flags & BF_NEAR_BODY) && in_body(S, B.level, B.ijk, c & 7, (c >> 3) & 7, c >> 6);
+    const double lam = body ? 0.0 : cell_bound(w, inv_dx);
+    block_publish<512>(lam, 0, red, redi, T.lam + B.sim, nullptr);
+}
+
+__global__ void k_dt_finalize(Tables T, double cfl, double *__restrict__ dt) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= T.ns) return;
+    const double lam = __longlong_as_double((long long)T.lam[s]);
+    dt[s] = cfl * (1.0 / lam);
+    T.lam[s] = 0ull;
+}
+
+__global__ void k_lam_reset(Tables T) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s < T.ns) T.lam[s] = 0ull;
+}
+
+// ------------------------------------------------------------------------------------------------
+// the fused stage kernel
+
+// LDS cell numbering of a slab with KS z-layers: [0, 64 KS) slab cells (k, j, i) = thread id; then the
+// two z-halo layers below and above; then x-halo (k, j, 4) and y-halo (k, 4, i) columns.
+template <int KS>
+struct Slab {
+    static constexpr int NT = 64 * KS;
+    static constexpr int ZLO = 64 * KS;
+    static constexpr int ZHI = 64 * KS + 128;
+    static constexpr int XH = 64 * KS + 256;
+    static constexpr int YH = 96 * KS + 256;
+    static constexpr int NC = 128 * KS + 256;
+    static constexpr int NFX = 72 * KS;
+    static constexpr int NFZ = 64 * (KS + 1);
+    static constexpr int NF = NFX > NFZ ? NFX : NFZ;
+    // (i, j, k) slab-local, at most one coordinate outside the slab
+    __device__ static __forceinline__ int idx(int i, int j, int k) {
+        if ((unsigned)i < 8u && (unsigned)j < 8u) {
+            if ((unsigned)k < (unsigned)KS) return (k * 8 + j) * 8 + i;
+            if (k < 0) return ZLO + ((k + 2) * 8 + j) * 8 + i;
+            return ZHI + ((k - KS) * 8 + j) * 8 + i;
+        }
+        if ((unsigned)j < 8u) return XH + (k * 8 + j) * 4 + (i < 0 ? i + 2 : i - 6);
+        return YH + (k * 4 + (j < 0 ? j + 2 : j - 6)) * 8 + i;
+    }
+    __device__ static __forceinline__ void decode(int c, int &i, int &j, int &k) {
+        if (c < ZLO) {
+            i = c & 7; j = (c >> 3) & 7; k = c >> 6;
+        } else if (c < XH) {
+            const int cc = c - ZLO, hi = cc >> 7, l = (cc >> 6) & 1;
+            i = cc & 7; j = (cc >> 3) & 7; k = hi ? KS + l : l - 2;
+        } else if (c < YH) {
+            const int cc = c - XH, xh = cc & 3;
+            k = cc >> 5; j = (cc >> 2) & 7; i = xh < 2 ? xh - 2 : xh + 6;
+        } else {
+            const int cc = c - YH, yh = (cc >> 3) & 3;
+            k = cc >> 5; i = cc & 7; j = yh < 2 ? yh - 2 : yh + 6;
+        }
+    }
+};
+
+struct StageArgs {
+    const double *Uin;
+    const double *U0;
+    double *Uout;
+    const double *dt;
+    int32_t *faults;
+    double alpha, beta;
+    int use_u0;      // add alpha * U0 (second stage)
+    int want_lam;    // accumulate the next dt bound
+    int count_faults;
+};
+
+template <int KS, typename R, int D, int FLUX, bool BODY>
+__device__ __forceinline__ void sweep(const Tables &T, const DevBlock &B, int slab, R (*sW)[Slab<KS>::NC],
+                                      const unsigned char *sM, R (*sF)[Slab<KS>::NF]) {
+    using SL = Slab<KS>;
+    constexpr int NF = D == 2 ? SL::NFZ : SL::NFX;
+    for (int f = threadIdx.x; f < NF; f += SL::NT) {
+        int i, j, k;
+        if (D == 0) { i = f % 9; j = (f / 9) & 7; k = f / 72; }
+        else if (D == 1) { i = f & 7; j = (f >> 3) % 9; k = f / 72; }
+        else { i = f & 7; j = (f >> 3) & 7; k = f >> 6; }
+        int c[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int o = q - 2;
+            c[q] = D == 0 ? SL::idx(i + o, j, k) : (D == 1 ? SL::idx(i, j + o, k) : SL::idx(i, j, k + o));
+        }
+        R w[4][8];
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int v = 0; v < 8; ++v) w[q][v] = sW[v][c[q]];
+        R wl[8], wr[8], fl[8];
+        R bbar;
+        bool skip = false;
+        if constexpr (BODY) {
+            const bool m0 = sM[c[0]], m1 = sM[c[1]], m2 = sM[c[2]], m3 = sM[c[3]];
+            if (m1 && m2) {
+                skip = true;
+            } else if (m2) {
+#pragma unroll
+                for (int v = 0; v < 8; ++v) wl[v] = wr[v] = w[1][v];
+                wr[1 + D] = -wl[1 + D];
+            } else if (m1) {
+#pragma unroll
+                for (int v = 0; v < 8; ++v) wl[v] = wr[v] = w[2][v];
+                wl[1 + D] = -wr[1 + D];
+            } else {
+#pragma unroll
+                for (int v = 0; v < 8; ++v) {
+                    const R sl = m0 ? R(0) : mc_slope(w[0][v], w[1][v], w[2][v]);
+                    const R sr = m3 ? R(0) : mc_slope(w[1][v], w[2][v], w[3][v]);
+                    wl[v] = w[1][v] + R(0.5) * sl;
+                    wr[v] = w[2][v] - R(0.5) * sr;
+                }
+            }
+        } else {
+#pragma unroll
+            for (int v = 0; v < 8; ++v) {
+                wl[v] = w[1][v] + R(0.5) * mc_slope(w[0][v], w[1][v], w[2][v]);
+                wr[v] = w[2][v] - R(0.5) * mc_slope(w[1][v], w[2][v], w[3][v]);
+            }
+        }
+        if (!skip) {
+            num_flux<R, D, FLUX>(wl, wr, fl);
+            bbar = R(0.5) * (wl[4 + D] + wr[4 + D]);
+        } else {
+#pragma unroll
+            for (int v = 0; v < 8; ++v) fl[v] = R(0);
+            bbar = R(0);
+        }
+#pragma unroll
+        for (int v = 0; v < 8; ++v) sF[v][f] = fl[v];
+        sF[8][f] = bbar;
+        // fluxes through block faces that take part in a flux correction
+        if (B.flags & BF_FC) {
+            int bf = -1, t1 = 0, t2 = 0;
+            if (D == 0) { if (i == 0) bf = 0; else if (i == 8) bf = 1; t1 = j; t2 = slab * KS + k; }
+            if (D == 1) { if (j == 0) bf = 2; else if (j == 8) bf = 3; t1 = i; t2 = slab * KS + k; }
+            if (D == 2) {
+                const int z = slab * KS + k;
+                if (z == 0) bf = 4; else if (z == 8) bf = 5;
+                t1 = i; t2 = j;
+            }
+            if (bf >= 0 && B.fc_rec[bf] >= 0) {
+                double *rec = T.fcbuf + size_t(B.fc_rec[bf]) * FC_REC;
+                if ((B.fc_role >> bf) & 1) {
+#pragma unroll
+                    for (int v = 0; v < 8; ++v) rec[v * 64 + t2 * 8 + t1] = double(fl[v]);
+                } else {
+                    const int q = B.fc_quad[bf];
+                    const int g1 = 8 * (q & 1) + t1, g2 = 8 * (q >> 1) + t2;
+#pragma unroll
+                    for (int v = 0; v < 8; ++v) rec[FC_COARSE + v * 256 + g2 * 16 + g1] = double(fl[v]);
+                }
+            }
+        }
+    }
+}
+
+template <int KS, typename R, int D>
+__device__ __forceinline__ void accumulate(R (*sF)[Slab<KS>::NF], double rhs[8], double &divb, double inv_dx) {
+    const int t = threadIdx.x, i = t & 7, j = (t >> 3) & 7, k = t >> 6;
+    int fl, fr;
+    if (D == 0) { fl = k * 72 + j * 9 + i; fr = fl + 1; }
+    else if (D == 1) { fl = k * 72 + j * 8 + i; fr = fl + 8; }
+    else { fl = (k * 8 + j) * 8 + i; fr = fl + 64; }
+#pragma unroll
+    for (int v = 0; v < 8; ++v) rhs[v] += (double(sF[v][fl]) - double(sF[v][fr])) * inv_dx;
+    divb += (double(sF[8][fr]) - double(sF[8][fl])) * inv_dx;
+}
+
+template <int KS, typename R, int FLUX, bool POWELL>
+__global__ void __launch_bounds__(64 * KS) k_stage(Tables T, StageArgs A) {
+    using SL = Slab<KS>;
+    constexpr int S_PER_BLOCK = 8 / KS;
+    __shared__ R sW[8][SL::NC];
+    __shared__ R sF[9][SL::NF];
+    __shared__ unsigned char sM[SL::NC];
+    __shared__ double red[SL::NT / 64];
+    __shared__ int redi[SL::NT / 64];
+
+    // XCD-aware schedule: workgroup w runs on XCD w % 8; XCD x owns a contiguous run of items
+    const int nwork = T.nb * S_PER_BLOCK;
+    const int wg = blockIdx.x, xcd = wg & 7, slot = wg >> 3;
+    const int q8 = nwork >> 3, r8 = nwork & 7;
+    const int item = xcd * q8 + (xcd < r8 ? xcd : r8) + slot;
+    const int b = T.order[item / S_PER_BLOCK];
+    const int slab = item % S_PER_BLOCK;
+    const DevBlock &B = T.blocks[b];
+    const DevSim &S = T.sims[B.sim];
+    const size_t vs = size_t(T.nb) * 512;
+    const bool near_body = (B.flags & BF_NEAR_BODY) != 0;
+    const int tid = threadIdx.x;
+
+    // 1. gather slab + face halos into LDS as primitive variables
+    double uin[8];
+    for (int c = tid; c < SL::NC; c += SL::NT) {
+        int i, j, k;
+        SL::decode(c, i, j, k);
+        const int z = slab * KS + k;
+        int fd = -1;
+        if (i < 0) fd = 0; else if (i > 7) fd = 1;
+        else if (j < 0) fd = 2; else if (j > 7) fd = 3;
+        else if (z < 0) fd = 4; else if (z > 7) fd = 5;
+        double u[8];
+        const int rel = fd < 0 ? b : B.face[fd];
+        if (rel >= 0 || rel == FACE_OUTFLOW) {
+            int src = b, ii = i, jj = j, zz = z;
+            if (rel >= 0) {
+                src = rel;
+                ii &= 7; jj &= 7; zz &= 7;
+            } else {
+                ii = ii < 0 ? 0 : (ii > 7 ? 7 : ii);
+                jj = jj < 0 ? 0 : (jj > 7 ? 7 : jj);
+                zz = zz < 0 ? 0 : (zz > 7 ? 7 : zz);
+            }
+            const double *p = A.Uin + size_t(src) * 512 + (zz * 8 + jj) * 8 + ii;
+#pragma unroll
+            for (int v = 0; v < 8; ++v) u[v] = p[v * vs];
+        } else if (rel == FACE_INFLOW) {
+#pragma unroll
+            for (int v = 0; v < 8; ++v) u[v] = S.inflow_U[v];
+        } else {
+            const int a = fd >> 1;
+            const int along = a == 0 ? i : (a == 1 ? j : z);
+            const int layer = along < 0 ? -1 - along : along - 8;
+            const int t1 = a == 0 ? j : i, t2 = a == 2 ? j : z;
+            const double *p = T.halo + size_t(B.halo_slot) * HALO_SLOT + size_t(fd) * HALO_FACE + layer * 64 + t2 * 8 + t1;
+#pragma unroll
+            for (int v = 0; v < 8; ++v) u[v] = p[v * 128];
+        }
+        if (c == tid) {
+#pragma unroll
+            for (int v = 0; v < 8; ++v) uin[v] = u[v];
+        }
+        double w[8];
+        cons_to_prim(u, w);
+#pragma unroll
+        for (int v = 0; v < 8; ++v) sW[v][c] = R(w[v]);
+        if (near_body) sM[c] = in_body(S, B.level, B.ijk, i, j, z) ? 1 : 0;
+    }
+    __syncthreads();
+
+    // 2. three flux sweeps; fluxes meet their two cells through LDS
+    const double inv_dx = double(1 << B.level) / S.dx0;
+    double rhs[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    double divb = 0.0;
+    if (near_body) sweep<KS, R, 0, FLUX, true>(T, B, slab, sW, sM, sF);
+    else sweep<KS, R, 0, FLUX, false>(T, B, slab, sW, sM, sF);
+    __syncthreads();
+    accumulate<KS, R, 0>(sF, rhs, divb, inv_dx);
+    __syncthreads();
+    if (near_body) sweep<KS, R, 1, FLUX, true>(T, B, slab, sW, sM, sF);
+    else sweep<KS, R, 1, FLUX, false>(T, B, slab, sW, sM, sF);
+    __syncthreads();
+    accumulate<KS, R, 1>(sF, rhs, divb, inv_dx);
+    __syncthreads();
+    if (near_body) sweep<KS, R, 2, FLUX, true>(T, B, slab, sW, sM, sF);
+    else sweep<KS, R, 2, FLUX, false>(T, B, slab, sW, sM, sF);
+    __syncthreads();
+    accumulate<KS, R, 2>(sF, rhs, divb, inv_dx);
+
+    // 3. source and update of the thread's own cell
+    const bool body = near_body && sM[tid];
+    const int cell = tid + slab * 64 * KS;
+    const size_t off = size_t(b) * 512 + cell;
+    double out[8];
+    if (body) {
+#pragma unroll
+        for (int v = 0; v < 8; ++v) out[v] = uin[v];
+    } else {
+        if (POWELL) {
+            const double ux = double(sW[1][tid]), uy = double(sW[2][tid]), uz = double(sW[3][tid]);
+            const double bx = double(sW[4][tid]), by = double(sW[5][tid]), bz = double(sW[6][tid]);
+            const double ub = ux * bx + uy * by + uz * bz;
+            rhs[1] -= divb * bx;
+            rhs[2] -= divb * by;
+            rhs[3] -= divb * bz;
+            rhs[4] -= divb * ux;
+            rhs[5] -= divb * uy;
+            rhs[6] -= divb * uz;
+            rhs[7] -= divb * ub;
+        }
+        const double bdt = A.beta * A.dt[B.sim];
+        if (A.use_u0) {
+            const double a0 = A.alpha, a1 = 1.0 - A.alpha;
+#pragma unroll
+            for (int v = 0; v < 8; ++v) out[v] = a0 * A.U0[v * vs + off] + a1 * uin[v] + bdt * rhs[v];
+        } else {
+#pragma unroll
+            for (int v = 0; v < 8; ++v) out[v] = uin[v] + bdt * rhs[v];
+        }
+    }
+#pragma unroll
+    for (int v = 0; v < 8; ++v) A.Uout[v * vs + off] = out[v];
+
+    // 4. end of a step: positivity check and the next time-step bound
+    if (A.count_faults || A.want_lam) {
+        const int i = tid & 7, j = (tid >> 3) & 7, z = slab * KS + (tid >> 6);
+        const int skipm = B.fc_skip;
+        const bool later = skipm && (((skipm & 1) && i == 0) || ((skipm & 2) && i == 7) || ((skipm & 4) && j == 0) ||
+                                     ((skipm & 8) && j == 7) || ((skipm & 16) && z == 0) || ((skipm & 32) && z == 7));
+        double lam = 0.0;
+        int nf = 0;
+        if (!body && !later) {
+            double w[8];
+            cons_to_prim(out, w);
+            nf = !(w[0] > 0.0) || !(w[7] > 0.0) || !(w[7] < INFINITY);
+            if (A.want_lam) lam = cell_bound(w, inv_dx);
+        }
+        block_publish<SL::NT>(lam, A.count_faults ? nf : 0, red, redi, A.want_lam ? T.lam + B.sim : nullptr,
+                              A.faults);
+    }
+}
+
+// coarse cells at coarse-fine faces: swap the coarse flux for the mean of the four fine fluxes
+__global__ void __launch_bounds__(256) k_flux_correct(Tables T, StageArgs A) {
+    __shared__ double red[4];
+    __shared__ int redi[4];
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    double lam = 0.0;
+    int nf = 0;
+    int sim = 0;
+    if (e < T.n_fc_cells) {
+        const DevFcCell C = T.fc_cells[e];
+        const DevBlock &B = T.blocks[C.block];
+        const DevSim &S = T.sims[B.sim];
+        sim = B.sim;
+        const size_t vs = size_t(T.nb) * 512, off = size_t(C.block) * 512 + C.cell;
+        const double inv_dx = 1.0 / S.dx0;
+        const double bdt = A.beta * A.dt[B.sim];
+        double u[8];
+#pragma unroll
+        for (int v = 0; v < 8; ++v) u[v] = A.Uout[v * vs + off];
+        for (int m = 0; m < C.n; ++m) {
+            const double *rec = T.fcbuf + size_t(C.rec[m]) * FC_REC;
+            const int t1 = C.t[m] & 7, t2 = C.t[m] >> 3;
+            const double sg = (C.face[m] & 1) ? 1.0 : -1.0;
+#pragma unroll
+            for (int v = 0; v < 8; ++v) {
+                const double fc = rec[v * 64 + t2 * 8 + t1];
+                const double *fn = rec + FC_COARSE + v * 256 + (2 * t2) * 16 + 2 * t1;
+                const double fm = ((fn[0] + fn[1]) + (fn[16] + fn[17])) * 0.25;
+                u[v] += bdt * sg * (fc - fm) * inv_dx;
+            }
+        }
+#pragma unroll
+        for (int v = 0; v < 8; ++v) A.Uout[v * vs + off] = u[v];
+        if (A.count_faults || A.want_lam) {
+            double w[8];
+            cons_to_prim(u, w);
+            nf = !(w[0] > 0.0) || !(w[7] > 0.0) || !(w[7] < INFINITY);
+            if (A.want_lam) lam = cell_bound(w, inv_dx);
+        }
+    }
+    if (A.want_lam) {
+        // a grid may mix simulations inside one workgroup here: publish per thread (few cells)
+        if (e < T.n_fc_cells) publish_max(T.lam + sim, lam);
+    }
+    if (A.count_faults) block_publish<256>(0.0, nf, red, redi, nullptr, A.faults);
+}
+
+}  // namespace bmhd
+
+// ================================================================================================
+// C ABI
+
+using namespace bmhd;
+
+namespace {
+thread_local std::string g_err;
+
+int32_t fail(int32_t code, const std::string &msg) {
+    g_err = msg;
+    return code;
+}
+
+int32_t hip_check(hipError_t e, const char *what) {
+    if (e == hipSuccess) return BMHD_OK;
+    return fail(BMHD_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+int32_t launch_check(const char *what) { return hip_check(hipGetLastError(), what); }
+
+bool ptr_ok(const void *p) { return p && (reinterpret_cast<uintptr_t>(p) & 7u) == 0; }
+
+template <int KS, typename R, int FLUX>
+int32_t launch_stage_flux(const HostGrid &h, const StageArgs &a, bool powell, hipStream_t s) {
+    const int grid = h.nb * (8 / KS);
+    if (powell) k_stage<KS, R, FLUX, true><<<grid, 64 * KS, 0, s>>>(h.dev, a);
+    else k_stage<KS, R, FLUX, false><<<grid, 64 * KS, 0, s>>>(h.dev, a);
+    return launch_check("stage kernel");
+}
+
+template <int KS, typename R>
+int32_t launch_stage_prec(const HostGrid &h, const StageArgs &a, int flux, bool powell, hipStream_t s) {
+    if (flux == BMHD_FLUX_RUSANOV) return launch_stage_flux<KS, R, BMHD_FLUX_RUSANOV>(h, a, powell, s);
+    return launch_stage_flux<KS, R, BMHD_FLUX_HLLE>(h, a, powell, s);
+}
+
+int32_t launch_stage(const HostGrid &h, const StageArgs &a, const bmhd_opts &o, hipStream_t s) {
+    const int ks = o.slab == 0 ? (o.precision == BMHD_FP64 ? 4 : 8) : o.slab;
+    if (o.precision == BMHD_FP64) {
+        if (ks == 4) return launch_stage_prec<4, double>(h, a, o.flux, o.powell, s);
+        return launch_stage_prec<8, double>(h, a, o.flux, o.powell, s);
+    }
+    if (ks == 4) return launch_stage_prec<4, float>(h, a, o.flux, o.powell, s);
+    return launch_stage_prec<8, float>(h, a, o.flux, o.powell, s);
+}
+
+int32_t need_upload(const bmhd_grid *g) {
+    if (!g) return fail(BMHD_EINVAL, "null grid");
+    if (!g->h.d_work) return fail(BMHD_EINVAL, "grid not uploaded (call bmhd_grid_upload first)");
+    return BMHD_OK;
+}
+}  // namespace
+
+extern "C" {
+
+int32_t bmhd_version(void) { return 100; }
+
+const char *bmhd_last_error(void) { return g_err.c_str(); }
+
+int32_t bmhd_grid_create(const bmhd_grid_desc *desc, bmhd_grid **out) {
+    g_err.clear();
+    if (!out) return fail(BMHD_EINVAL, "null output handle");
+    *out = nullptr;
+    bmhd_grid *g = new (std::nothrow) bmhd_grid;
+    if (!g) return fail(BMHD_ENOMEM, "out of host memory");
+    std::string err;
+    int32_t rc;
+    try {
+        rc = build_grid(desc, g->h, err);
+    } catch (const std::bad_alloc &) {
+        rc = BMHD_ENOMEM;
+        err = "out of host memory";
+    }
+    if (rc != BMHD_OK) {
+        delete g;
+        return fail(rc, err);
+    }
+    *out = g;
+    return BMHD_OK;
+}
+
+void bmhd_grid_destroy(bmhd_grid *g) { delete g; }
+
+int32_t bmhd_grid_info_get(const bmhd_grid *g, bmhd_grid_info *info) {
+    if (!g || !info) return fail(BMHD_EINVAL, "null argument");
+    info->n_blocks = g->h.nb;
+    info->n_sims = g->h.ns;
+    info->n_level_faces = int32_t(g->h.halo_items.size());
+    info->n_flux_faces = g->h.n_fc_rec;
+    info->work_bytes = g->h.work_bytes;
+    return BMHD_OK;
+}
+
+int32_t bmhd_grid_neighbors(const bmhd_grid *g, int32_t *h_out) {
+    if (!g || !h_out) return fail(BMHD_EINVAL, "null argument");
+    std::memcpy(h_out, g->h.nbr.data(), sizeof(int32_t) * g->h.nbr.size());
+    return BMHD_OK;
+}
+
+int32_t bmhd_grid_upload(bmhd_grid *g, void *d_work, size_t work_bytes, void *stream) {
+    if (!g || !d_work) return fail(BMHD_EINVAL, "null argument");
+    if ((reinterpret_cast<uintptr_t>(d_work) & 255u) != 0) return fail(BMHD_EINVAL, "workspace not 256-byte aligned");
+    HostGrid &h = g->h;
+    if (work_bytes < h.work_bytes)
+        return fail(BMHD_ENOMEM, "workspace too small: need " + std::to_string(h.work_bytes) + " bytes");
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    unsigned char *base = static_cast<unsigned char *>(d_work);
+    int32_t rc = hip_check(hipMemcpyAsync(base, h.blob.data(), h.table_bytes, hipMemcpyHostToDevice, s), "upload tables");
+    if (rc) return rc;
+    rc = hip_check(hipMemsetAsync(base + h.table_bytes, 0, h.work_bytes - h.table_bytes, s), "clear scratch");
+    if (rc) return rc;
+    rc = hip_check(hipStreamSynchronize(s), "upload sync");
+    if (rc) return rc;
+    h.d_work = d_work;
+    Tables &t = h.dev;
+    t.blocks = reinterpret_cast<const DevBlock *>(base + h.off_blocks);
+    t.sims = reinterpret_cast<const DevSim *>(base + h.off_sims);
+    t.lut = reinterpret_cast<const int32_t *>(base + h.off_lut);
+    t.order = reinterpret_cast<const int32_t *>(base + h.off_order);
+    t.halo_items = reinterpret_cast<const int32_t *>(base + h.off_halo_items);
+    t.fc_cells = reinterpret_cast<const DevFcCell *>(base + h.off_fc_cells);
+    t.lam = reinterpret_cast<unsigned long long *>(base + h.off_lam);
+    t.halo = reinterpret_cast<double *>(base + h.off_halo);
+    t.fcbuf = reinterpret_cast<double *>(base + h.off_fcbuf);
+    t.nb = h.nb;
+    t.ns = h.ns;
+    t.n_halo_items = int32_t(h.halo_items.size());
+    t.n_fc_cells = int32_t(h.fc_cells.size());
+    return BMHD_OK;
+}
+
+int32_t bmhd_set_state(const bmhd_grid *g, const double *d_W, double *d_U, void *stream) {
+    if (int32_t rc = need_upload(g)) return rc;
+    if (!ptr_ok(d_W) || !ptr_ok(d_U)) return fail(BMHD_EINVAL, "null or misaligned state pointer");
+    const size_t n = size_t(g->h.nb) * 512;
+    if (n == 0) return BMHD_OK;
+    k_set_state<<<unsigned((n + 255) / 256), 256, 0, reinterpret_cast<hipStream_t>(stream)>>>(d_W, d_U, n);
+    return launch_check("set_state");
+}
+
+int32_t bmhd_fill_ghosts(const bmhd_grid *g, const double *d_U, double *d_view, void *stream) {
+    if (int32_t rc = need_upload(g)) return rc;
+    if (!ptr_ok(d_U) || !ptr_ok(d_view)) return fail(BMHD_EINVAL, "null or misaligned pointer");
+    if (g->h.nb == 0) return BMHD_OK;
+    k_fill_view<<<g->h.nb, 256, 0, reinterpret_cast<hipStream_t>(stream)>>>(g->h.dev, d_U, d_view);
+    return launch_check("fill_ghosts");
+}
+
+int32_t bmhd_reduce_dt(const bmhd_grid *g, const double *d_U, double cfl, double *d_dt, void *stream) {
+    if (int32_t rc = need_upload(g)) return rc;
+    if (!ptr_ok(d_U) || !ptr_ok(d_dt)) return fail(BMHD_EINVAL, "null or misaligned pointer");
+    if (!(cfl > 0.0)) return fail(BMHD_EINVAL, "cfl must be positive");
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    const HostGrid &h = g->h;
+    const int sb = (h.ns + 63) / 64;
+    k_lam_reset<<<sb, 64, 0, s>>>(h.dev);
+    if (h.nb) k_dt_reduce<<<h.nb, 512, 0, s>>>(h.dev, d_U);
+    k_dt_finalize<<<sb, 64, 0, s>>>(h.dev, cfl, d_dt);
+    return launch_check("reduce_dt");
+}
+
+int32_t bmhd_advance(const bmhd_grid *g, double *d_U0, double *d_U1, double *d_dt, int32_t n_stages,
+                     const bmhd_opts *opts, int32_t *d_faults, void *stream) {
+    if (int32_t rc = need_upload(g)) return rc;
+    if (!opts) return fail(BMHD_EINVAL, "null options");
+    if (!ptr_ok(d_U0) || !ptr_ok(d_U1) || !ptr_ok(d_dt) || d_U0 == d_U1)
+        return fail(BMHD_EINVAL, "null, misaligned or aliased state pointers");
+    if (d_faults && (reinterpret_cast<uintptr_t>(d_faults) & 3u)) return fail(BMHD_EINVAL, "misaligned fault counter");
+    if (n_stages < 0) return fail(BMHD_EINVAL, "n_stages must be >= 0");
+    const bmhd_opts &o = *opts;
+    if (o.flux != BMHD_FLUX_RUSANOV && o.flux != BMHD_FLUX_HLLE) return fail(BMHD_EINVAL, "unknown flux");
+    if (o.precision != BMHD_FP64 && o.precision != BMHD_FP32_FLUX) return fail(BMHD_EINVAL, "unknown precision");
+    if (o.slab != 0 && o.slab != 4 && o.slab != 8) return fail(BMHD_EINVAL, "slab must be 0, 4 or 8");
+    if (o.recompute_dt && !(o.cfl > 0.0)) return fail(BMHD_EINVAL, "cfl must be positive");
+    const HostGrid &h = g->h;
+    if (h.nb == 0 || n_stages == 0) return BMHD_OK;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    const int sb = (h.ns + 63) / 64;
+    for (int st = 0; st < n_stages; ++st) {
+        const int e = st & 1;
+        const double *in = e ? d_U1 : d_U0;
+        double *out = e ? d_U0 : d_U1;
+        if (e == 0 && o.recompute_dt) {
+            if (st == 0) {
+                k_lam_reset<<<sb, 64, 0, s>>>(h.dev);
+                k_dt_reduce<<<h.nb, 512, 0, s>>>(h.dev, d_U0);
+            }
+            k_dt_finalize<<<sb, 64, 0, s>>>(h.dev, o.cfl, d_dt);
+        }
+        if (!h.halo_items.empty()) k_halo_fill<<<unsigned(h.halo_items.size()), 128, 0, s>>>(h.dev, in);
+        StageArgs a;
+        a.Uin = in;
+        a.U0 = d_U0;
+        a.Uout = out;
+        a.dt = d_dt;
+        a.faults = d_faults;
+        a.alpha = o.alpha[e];
+        a.beta = o.beta[e];
+        a.use_u0 = o.alpha[e] != 0.0 ? 1 : 0;
+        a.want_lam = (e == 1 && o.recompute_dt && st + 1 < n_stages) ? 1 : 0;
+        a.count_faults = (e == 1 && d_faults) ? 1 : 0;
+        const bool timed = o.events && o.n_events >= 2 * n_stages;
+        if (timed) {
+            if (int32_t rc = hip_check(hipEventRecord(reinterpret_cast<hipEvent_t>(o.events[2 * st]), s), "event")) return rc;
+        }
+        if (int32_t rc = launch_stage(h, a, o, s)) return rc;
+        if (timed) {
+            if (int32_t rc = hip_check(hipEventRecord(reinterpret_cast<hipEvent_t>(o.events[2 * st + 1]), s), "event")) return rc;
+        }
+        if (!h.fc_cells.empty()) {
+            k_flux_correct<<<unsigned((h.fc_cells.size() + 255) / 256), 256, 0, s>>>(h.dev, a);
+            if (int32_t rc = launch_check("flux correction")) return rc;
+        }
+    }
+    return launch_check("advance");
+}
+
+}  // extern "C"

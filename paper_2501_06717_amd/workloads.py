@@ -308,7 +308,7 @@ def with_state(wl: Workload, W, name=None) -> Workload:
     return dataclasses.replace(wl, W=W, name=name or wl.name)
 
 
-def odd_box(nroot=(3, 2, 5), bc=(0, 1, 0, 2, 1, 0), seed=3):
+def odd_box(nroot=(3, 2, 5), bc=(1, 1, 0, 0, 2, 1), seed=3):
     """A ragged box of blocks with mixed boundary types and a random positive state."""
     sim = Sim(tuple(nroot), (0.0, 0.0, 0.0), 1.0, tuple(bc), (1.1, -0.2, 0.1, 0.05, 0.3, 0.6, -0.2, 0.9))
     lv, ijk, sid = uniform_blocks(nroot)

@@ -1,0 +1,219 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle on the same seeded inputs.
+
+Bars: neighbour tables and ghost cells bit-exact (copy, restriction and prolongation are evaluated
+without contraction on both sides); dt within 1e-14 relative; states after stages within 1e-12
+relative per variable group (rho, momentum, B, energy: max abs difference over the group divided by
+the group's max abs value); the FP32-flux form reported against the FP64 oracle.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2501_06717_amd import workloads as wk
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+GROUPS = {"rho": [0], "mom": [1, 2, 3], "B": [4, 5, 6], "e": [7]}
+TOL = 1e-12
+
+
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def bd():
+    _need_gpu()
+    from paper_2501_06717_amd import binding
+    binding.lib()
+    return binding
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def group_err(got, ref):
+    out = {}
+    for g, vs in GROUPS.items():
+        scale = np.abs(ref[vs]).max()
+        out[g] = float(np.abs(got[vs] - ref[vs]).max() / (scale if scale > 0 else 1.0))
+    return out
+
+
+def gpu_run(bd, wl, W, n_stages, dt0=None, **kw):
+    g = bd.Grid.from_workload(wl).upload()
+    U0 = g.set_state(dev(W))
+    U1 = torch.zeros_like(U0)
+    dt = dev(np.zeros(len(wl.sims)) if dt0 is None else np.asarray(dt0, np.float64))
+    faults = torch.zeros(1, dtype=torch.int32, device="cuda")
+    g.advance(U0, U1, dt, n_stages, faults=faults, **kw)
+    torch.cuda.synchronize()
+    return U0.cpu().numpy(), U1.cpu().numpy(), dt.cpu().numpy(), int(faults.item())
+
+
+def oracle_run(oracle_mod, wl, W, n_stages, dt0=None, **kw):
+    o = oracle_mod.Grid.from_workload(wl)
+    U0 = o.set_state(W)
+    U1 = np.zeros_like(U0)
+    kw = {k: v for k, v in kw.items() if k in ("flux", "powell", "cfl", "recompute_dt", "alpha", "beta")}
+    dt, faults = o.advance(U0, U1, np.zeros(len(wl.sims)) if dt0 is None else dt0, n_stages, **kw)
+    return U0, U1, dt, faults
+
+
+# ------------------------------------------------------------------------------------------------
+# set_state, ghost fill, dt
+
+@pytest.mark.parametrize("make", [lambda: wk.cp_alfven(16), lambda: wk.magnetosphere_cut(32), lambda: wk.two_level_box()])
+def test_set_state(bd, oracle_mod, make):
+    wl = make()
+    say("set_state", wl.name)
+    g = bd.Grid.from_workload(wl).upload()
+    U = g.set_state(dev(wl.W)).cpu().numpy()
+    ref = oracle_mod.Grid.from_workload(wl).set_state(wl.W)
+    assert max(group_err(U, ref).values()) <= 1e-15
+
+
+GHOST_CASES = {
+    "periodic_1": lambda: wk.uniform_state((1, 1, 1)),
+    "odd_box": lambda: wk.odd_box(),
+    "two_level": lambda: wk.two_level_box(),
+    "two_level_bc": lambda: wk.two_level_box(bc=(1, 2, 0, 0, 2, 1)),
+    "two_level_48": lambda: wk.two_level_magnetosphere(48),
+    "fast_wave_octant": lambda: wk.fast_wave((4, 2, 2), refine_octant=True),
+}
+
+
+@pytest.mark.parametrize("case", list(GHOST_CASES))
+@pytest.mark.parametrize("field", ["unique_id", "random"])
+def test_fill_ghosts_bit_exact(bd, oracle_mod, case, field):
+    wl = GHOST_CASES[case]()
+    say("fill_ghosts", case, field, wl.n_blocks)
+    if field == "unique_id":
+        U = wk.unique_id_field(wl)
+    else:
+        U = oracle_mod.Grid.from_workload(wl).set_state(wk.random_positive_state(wl, seed=9))
+    g = bd.Grid.from_workload(wl).upload()
+    view = g.fill_ghosts(dev(U)).cpu().numpy()
+    ref = oracle_mod.Grid.from_workload(wl).fill_ghosts(U)
+    bad = np.argwhere(view != ref)
+    assert bad.shape[0] == 0, (bad[:5], view[tuple(bad[0])], ref[tuple(bad[0])])
+
+
+@pytest.mark.parametrize("make", [lambda: wk.cp_alfven(32), lambda: wk.magnetosphere_cut(64), lambda: wk.two_level_box()])
+def test_reduce_dt(bd, oracle_mod, make):
+    wl = make()
+    say("reduce_dt", wl.name)
+    o = oracle_mod.Grid.from_workload(wl)
+    U = o.set_state(wl.W)
+    ref = o.dt(U, 0.8)
+    g = bd.Grid.from_workload(wl).upload()
+    dt = g.reduce_dt(dev(U), 0.8).cpu().numpy()
+    assert np.all(np.abs(dt - ref) <= 1e-14 * ref), (dt, ref)
+
+
+# ------------------------------------------------------------------------------------------------
+# stages
+
+STAGE_CASES = {
+    "cp_alfven_32": (lambda: wk.cp_alfven(32), dict(flux="rusanov", powell=False)),
+    "cp_alfven_32_hlle": (lambda: wk.cp_alfven(32), dict(flux="hlle", powell=True)),
+    "odd_box": (lambda: wk.odd_box(), dict(flux="hlle", powell=True)),
+    "magnetosphere_32": (lambda: wk.magnetosphere_cut(32), dict(flux="hlle", powell=True)),
+    "two_level_box": (lambda: wk.two_level_box(), dict(flux="rusanov", powell=False)),
+    "two_level_box_hlle": (lambda: wk.two_level_box(bc=(1, 2, 0, 0, 2, 1)), dict(flux="hlle", powell=True)),
+    "two_level_48": (lambda: wk.two_level_magnetosphere(48), dict(flux="hlle", powell=True)),
+}
+
+
+@pytest.mark.parametrize("case", list(STAGE_CASES))
+@pytest.mark.parametrize("n_stages", [1, 2, 6])
+def test_advance_parity(bd, oracle_mod, case, n_stages):
+    make, kw = STAGE_CASES[case]
+    wl = make()
+    say("advance", case, n_stages, wl.n_blocks)
+    U0, U1, dt, f = gpu_run(bd, wl, wl.W, n_stages, **kw)
+    R0, R1, rdt, rf = oracle_run(oracle_mod, wl, wl.W, n_stages, **kw)
+    assert f == 0 and rf == 0
+    assert np.all(np.abs(dt - rdt) <= 1e-14 * rdt), (dt, rdt)
+    got, ref = (U1, R1) if n_stages % 2 else (U0, R0)
+    err = group_err(got, ref)
+    say("  err", err)
+    assert max(err.values()) <= TOL, err
+
+
+@pytest.mark.parametrize("slab", [4, 8])
+def test_slab_choice_is_bitwise_neutral(bd, slab):
+    wl = wk.magnetosphere_cut(32)
+    a = gpu_run(bd, wl, wl.W, 4, flux="hlle", powell=True, slab=slab)
+    b = gpu_run(bd, wl, wl.W, 4, flux="hlle", powell=True, slab=4)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[2], b[2])
+
+
+def test_cp_alfven_ten_steps(bd, oracle_mod):
+    wl = wk.cp_alfven(32)
+    say("cp_alfven 10 steps")
+    U0, _, dt, _ = gpu_run(bd, wl, wl.W, 20, flux="rusanov")
+    R0, _, rdt, _ = oracle_run(oracle_mod, wl, wl.W, 20, flux="rusanov")
+    err = group_err(U0, R0)
+    say("  err", err)
+    assert max(err.values()) <= TOL
+
+
+def test_fixed_dt_and_midpoint_table(bd, oracle_mod):
+    wl = wk.odd_box()
+    kw = dict(flux="rusanov", powell=True, recompute_dt=False, alpha=(0.0, 0.0), beta=(0.5, 1.0))
+    U0, _, dt, _ = gpu_run(bd, wl, wl.W, 4, dt0=[0.05], **kw)
+    R0, _, rdt, _ = oracle_run(oracle_mod, wl, wl.W, 4, dt0=[0.05], **kw)
+    assert dt[0] == 0.05 and rdt[0] == 0.05
+    assert max(group_err(U0, R0).values()) <= TOL
+
+
+def test_deterministic_and_faults(bd):
+    wl = wk.magnetosphere_cut(32)
+    a = gpu_run(bd, wl, wl.W, 6, flux="hlle", powell=True)
+    b = gpu_run(bd, wl, wl.W, 6, flux="hlle", powell=True)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+    # faults forced on the host: a pressure far below what one step of inflow can refill (a cell at
+    # p = -1 next to p = 7500 gains about +50 in one step of 1e-5 and heals), and a negative density
+    W = wl.W.copy()
+    W[7, 5, 3, 3, 3] = -1e7
+    W[0, 9, 4, 4, 4] = -1.0
+    _, _, _, f = gpu_run(bd, wl, W, 2, flux="hlle", powell=True, recompute_dt=False, dt0=[1e-5])
+    assert f >= 2
+
+
+def test_fp32_flux_form_error(bd, oracle_mod):
+    """FP32 reconstruction and flux with an FP64 update: report L1 and Linf against the FP64 oracle."""
+    wl = wk.magnetosphere_cut(32)
+    kw = dict(flux="hlle", powell=True)
+    U0, _, _, f = gpu_run(bd, wl, wl.W, 10, precision="fp32_flux", **kw)
+    R0, _, _, _ = oracle_run(oracle_mod, wl, wl.W, 10, **kw)
+    assert f == 0 and np.all(np.isfinite(U0))
+    err = group_err(U0, R0)
+    l1 = {g: float(np.abs(U0[v] - R0[v]).mean() / np.abs(R0[v]).mean()) for g, v in GROUPS.items()}
+    say("  fp32 Linf", err, "L1", l1)
+    assert max(err.values()) < 1e-4
+
+
+def test_two_level_conservation_gpu(bd, oracle_mod):
+    """Periodic two-level grid, Powell off: the GPU keeps sum U dV to round-off (flux correction)."""
+    wl = wk.two_level_box()
+    W = wk.random_positive_state(wl, seed=11)
+    U0, _, _, _ = gpu_run(bd, wl, W, 6, flux="hlle", powell=False)
+    Ui = oracle_mod.Grid.from_workload(wl).set_state(W)
+    vol = (1.0 / 2.0 ** wl.level) ** 3
+    for v in range(8):
+        t0 = math.fsum((Ui[v] * vol[:, None, None, None]).ravel())
+        t1 = math.fsum((U0[v] * vol[:, None, None, None]).ravel())
+        s = math.fsum((np.abs(Ui[v]) * vol[:, None, None, None]).ravel())
+        assert abs(t1 - t0) <= 1e-14 * s
