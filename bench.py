@@ -42,21 +42,24 @@ def parse():
     p.add_argument("--warmup", type=int, default=3)
     p.add_argument("--n", type=int, default=256, help="cells per axis of the magnetosphere grid")
     p.add_argument("--slab", type=int, default=0)
+    p.add_argument("--persist", type=int, default=0, help="persistent grid size of the stage kernel (0: off)")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-forms", action="store_true")
     p.add_argument("--cpu-steps", type=int, default=1)
     p.add_argument("--profile", action="store_true", help="short run for a profiler: no CPU leg, no forms")
+    p.add_argument("--calib", action="store_true",
+                   help="also run a plain 256 MiB device copy (scales the HBM byte counters of a profiler run)")
     return p.parse_args()
 
 
-def time_form(g, W, steps, warmup, precision, slab):
+def time_form(g, W, steps, warmup, precision, slab, persist=0):
     import torch
     from paper_2501_06717_amd import binding
     U0 = g.set_state(W)
     U1 = torch.empty_like(U0)
     dt = torch.zeros(1, dtype=torch.float64, device="cuda")
     faults = torch.zeros(1, dtype=torch.int32, device="cuda")
-    base = dict(flux="hlle", powell=True, precision=precision, cfl=0.8, slab=slab)
+    base = dict(flux="hlle", powell=True, precision=precision, cfl=0.8, slab=slab, persist_wgs=persist)
     if warmup:
         g.advance(U0, U1, dt, 2 * warmup, faults=faults, **base)
         U0 = g.set_state(W)  # restart from the initial state: the timed run is the first `steps` steps
@@ -92,7 +95,7 @@ def main():
     W = torch.from_numpy(wl.W).cuda()
     steps, warm = a.steps, a.warmup
 
-    U64, wall, st, faults, dt_last = time_form(g, W, steps, warm, "fp64", a.slab)
+    U64, wall, st, faults, dt_last = time_form(g, W, steps, warm, "fp64", a.slab, a.persist)
     cells = wl.n_cells
     value = cells * steps / wall
     t1, t2 = float(np.mean(st[0])), float(np.mean(st[1]))
@@ -121,8 +124,15 @@ def main():
                      "stage_us": [t1 * 1e6, t2 * 1e6], "bytes_per_cell_update": 320},
         "faults": faults,
     }
+    if a.calib:
+        src = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     if not (a.no_forms or a.profile):
-        U32, wall32, st32, f32, _ = time_form(g, W, steps, warm, "fp32_flux", a.slab)
+        U32, wall32, st32, f32, _ = time_form(g, W, steps, warm, "fp32_flux", a.slab, a.persist)
         ref = U64.cpu().numpy()
         got = U32.cpu().numpy()
         l1 = float(np.abs(got - ref).sum() / np.abs(ref).sum())

@@ -90,6 +90,10 @@ typedef struct {
     double alpha[2];      /* stage table: out = alpha U^n + (1 - alpha) U_in + beta dt L(U_in) */
     double beta[2];       /* Heun: alpha = {0, 0.5}, beta = {1, 0.5} */
     int32_t slab;         /* tile depth of the stage kernel: 0 = default, 4 or 8 cells along z */
+    int32_t persist_wgs;  /* 0: one workgroup per tile; > 0: a persistent grid of this many workgroups
+                             (rounded up to a multiple of 8), each looping over tiles */
+    int32_t use_graph;    /* 1: steps after the first replay one captured HIP graph of a whole step
+                             (n_stages must be even; `events` are ignored) */
     int32_t n_events;     /* length of `events`, or 0 */
     void **events;        /* optional caller-created hipEvent_t handles: when n_events >= 2 * n_stages,
                              events[2s] and events[2s+1] are recorded on `stream` right before and after
@@ -161,6 +165,14 @@ int32_t bmhd_reduce_dt(const bmhd_grid *g, const double *d_U, double cfl, double
  * bmhd_grid_upload. */
 int32_t bmhd_advance(const bmhd_grid *g, double *d_U0, double *d_U1, double *d_dt, int32_t n_stages,
                      const bmhd_opts *opts, int32_t *d_faults, void *stream);
+
+/* Autotuner: time every launch shape of the stage kernel (tile depth 4 or 8 cells, one workgroup per
+ * tile or a persistent grid of 2 or 4 workgroups per compute unit) for n_steps steps each with `base`'s
+ * other options, on the caller's buffers (they are advanced: pass scratch copies), and write `base` with
+ * the fastest shape into *best. h_ms (host, may be NULL) receives the milliseconds of the 6 candidates
+ * in the order (4,0) (4,2/CU) (4,4/CU) (8,0) (8,2/CU) (8,4/CU). Blocking: synchronises `stream`. */
+int32_t bmhd_autotune(const bmhd_grid *g, double *d_U0, double *d_U1, double *d_dt, const bmhd_opts *base,
+                      int32_t n_steps, bmhd_opts *best, float *h_ms, void *stream);
 
 #ifdef __cplusplus
 }

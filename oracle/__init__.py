@@ -14,7 +14,7 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB = os.path.join(HERE, "liboracle.so")
-SOURCES = ["oracle.c"]
+SOURCES = ["oracle.c", "mlp.c"]
 
 FLUX = {"rusanov": 0, "hlle": 1}
 
@@ -73,6 +73,13 @@ def lib():
         L.or_restrict8.restype = ctypes.c_double
         L.or_prolong1.argtypes = [ctypes.c_double, dp, dp, ip]
         L.or_prolong1.restype = ctypes.c_double
+        L.mlp_n_params.argtypes = [ctypes.c_int]
+        L.mlp_n_params.restype = ctypes.c_long
+        L.mlp_forward.argtypes = [dp, ctypes.c_int, ctypes.c_int, dp, dp]
+        L.mlp_loss_grad.argtypes = [dp, ctypes.c_int, ctypes.c_int, dp, dp, dp]
+        L.mlp_loss_grad.restype = ctypes.c_double
+        L.mlp_adam.argtypes = [dp, dp, dp, dp, ctypes.c_long, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                               ctypes.c_double, ctypes.c_int]
         _lib = L
     return _lib
 
@@ -210,3 +217,31 @@ class Grid:
         U1 = np.zeros_like(U0)
         dt, faults = self.advance(U0, U1, np.zeros(self.ns), 2 * n_steps, **kw)
         return U0, dt, faults
+
+
+# ------------------------------------------------------------------------------------------------
+# MLP of the learned flux correction (32 inputs, three SiLU hidden layers of width H, 8 outputs)
+
+def mlp_n_params(H):
+    return int(lib().mlp_n_params(int(H)))
+
+
+def mlp_forward(params, H, x):
+    params = np.ascontiguousarray(params, np.float64); x = np.ascontiguousarray(x, np.float64)
+    N = x.shape[0]
+    y = np.empty((N, 8))
+    lib().mlp_forward(_dp(params), int(H), N, _dp(x), _dp(y))
+    return y
+
+
+def mlp_loss_grad(params, H, x, t):
+    params = np.ascontiguousarray(params, np.float64); x = np.ascontiguousarray(x, np.float64)
+    t = np.ascontiguousarray(t, np.float64)
+    g = np.empty_like(params)
+    loss = lib().mlp_loss_grad(_dp(params), int(H), x.shape[0], _dp(x), _dp(t), _dp(g))
+    return loss, g
+
+
+def mlp_adam(p, m, v, g, lr, t, b1=0.9, b2=0.999, eps=1e-8):
+    """In place on float64 arrays p, m, v."""
+    lib().mlp_adam(_dp(p), _dp(m), _dp(v), _dp(np.ascontiguousarray(g, np.float64)), p.size, lr, b1, b2, eps, int(t))

@@ -21,7 +21,7 @@ PRECISION = {"fp64": 0, "fp32_flux": 1}
 
 EXPORTS = ["bmhd_version", "bmhd_last_error", "bmhd_grid_create", "bmhd_grid_destroy", "bmhd_grid_info_get",
            "bmhd_grid_neighbors", "bmhd_grid_upload", "bmhd_set_state", "bmhd_fill_ghosts", "bmhd_reduce_dt",
-           "bmhd_advance"]
+           "bmhd_advance", "bmhd_autotune"]
 
 
 class SimDesc(ctypes.Structure):
@@ -39,7 +39,8 @@ class GridDesc(ctypes.Structure):
 class Opts(ctypes.Structure):
     _fields_ = [("flux", ctypes.c_int32), ("powell", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("recompute_dt", ctypes.c_int32), ("cfl", ctypes.c_double), ("alpha", ctypes.c_double * 2),
-                ("beta", ctypes.c_double * 2), ("slab", ctypes.c_int32), ("n_events", ctypes.c_int32),
+                ("beta", ctypes.c_double * 2), ("slab", ctypes.c_int32), ("persist_wgs", ctypes.c_int32),
+                ("use_graph", ctypes.c_int32), ("n_events", ctypes.c_int32),
                 ("events", ctypes.POINTER(ctypes.c_void_p))]
 
 
@@ -85,6 +86,8 @@ def lib():
     L.bmhd_reduce_dt.restype = i32
     L.bmhd_advance.argtypes = [vp, vp, vp, vp, i32, P(Opts), vp, vp]
     L.bmhd_advance.restype = i32
+    L.bmhd_autotune.argtypes = [vp, vp, vp, vp, P(Opts), i32, P(Opts), P(ctypes.c_float), vp]
+    L.bmhd_autotune.restype = i32
     _lib = L
     return L
 
@@ -96,7 +99,7 @@ def _check(rc):
 
 
 def make_opts(flux="rusanov", powell=False, precision="fp64", recompute_dt=True, cfl=0.8,
-              alpha=(0.0, 0.5), beta=(1.0, 0.5), slab=0, events=None) -> Opts:
+              alpha=(0.0, 0.5), beta=(1.0, 0.5), slab=0, persist_wgs=0, use_graph=False, events=None) -> Opts:
     """Options for bmhd_advance. `events`: optional list of torch.cuda.Event (enable_timing=True), two per
     stage, recorded by the library around each stage kernel."""
     o = Opts()
@@ -108,6 +111,8 @@ def make_opts(flux="rusanov", powell=False, precision="fp64", recompute_dt=True,
     o.alpha[:] = [float(a) for a in alpha]
     o.beta[:] = [float(b) for b in beta]
     o.slab = int(slab)
+    o.persist_wgs = int(persist_wgs)
+    o.use_graph = int(bool(use_graph))
     if events:
         arr = (ctypes.c_void_p * len(events))(*[ctypes.c_void_p(e.cuda_event) for e in events])
         o._events_keepalive = arr
@@ -230,3 +235,15 @@ class Grid:
         _check(lib().bmhd_advance(self.h, _dev_ptr(U0, torch.float64), _dev_ptr(U1, torch.float64),
                                   _dev_ptr(dt, torch.float64), int(n_stages), ctypes.byref(o), fp,
                                   _stream_ptr(stream)))
+
+    def autotune(self, U0, U1, dt, n_steps=3, stream=None, **kw):
+        """Time the stage kernel's launch shapes on (scratch) buffers; returns (best Opts, {shape: ms})."""
+        import torch
+        base = make_opts(**kw)
+        best = Opts()
+        ms = (ctypes.c_float * 6)()
+        _check(lib().bmhd_autotune(self.h, _dev_ptr(U0, torch.float64), _dev_ptr(U1, torch.float64),
+                                   _dev_ptr(dt, torch.float64), ctypes.byref(base), int(n_steps), ctypes.byref(best),
+                                   ms, _stream_ptr(stream)))
+        names = ["slab4", "slab4_persist2", "slab4_persist4", "slab8", "slab8_persist2", "slab8_persist4"]
+        return best, dict(zip(names, list(ms)))

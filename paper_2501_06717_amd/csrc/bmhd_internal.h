@@ -106,6 +106,9 @@ struct HostGrid {
     std::vector<unsigned char> blob;  // packed tables (first table_bytes of the workspace)
     void *d_work = nullptr;
     Tables dev{};
+    // cached HIP graph of one step (opaque hipGraph_t / hipGraphExec_t / hipStream_t) and its key
+    void *graph = nullptr, *graph_exec = nullptr, *capture_stream = nullptr;
+    std::vector<unsigned char> graph_key;
 };
 
 int32_t build_grid(const bmhd_grid_desc *d, HostGrid &g, std::string &err);
@@ -115,4 +118,5 @@ void prim_to_cons_host(const double *w, double *u);
 
 struct bmhd_grid {
     bmhd::HostGrid h;
+    ~bmhd_grid();
 };

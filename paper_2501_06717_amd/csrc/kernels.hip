@@ -31,21 +31,41 @@ constexpr double GAMMA = 5.0 / 3.0;
 // small device helpers
 
 template <typename R>
-__device__ __forceinline__ R rmin(R a, R b) { return a < b ? a : b; }
+__device__ __forceinline__ R rmin(R a, R b) { return fmin(a, b); }
 template <typename R>
-__device__ __forceinline__ R rmax(R a, R b) { return a > b ? a : b; }
+__device__ __forceinline__ R rmax(R a, R b) { return fmax(a, b); }
 
-template <typename R>
-__device__ __forceinline__ R rsqrt_(R x);
-template <>
-__device__ __forceinline__ double rsqrt_<double>(double x) { return sqrt(x); }
-template <>
-__device__ __forceinline__ float rsqrt_<float>(float x) { return sqrtf(x); }
+// Reciprocal and square root from the hardware approximations (about 26 correct bits) refined by
+// Newton steps: two steps for 1/x, two corrections for sqrt. Inputs are positive normal numbers
+// (densities, squared wave speeds, signal-speed spans); sqrt(0) returns 0.
+__device__ __forceinline__ double frcp(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-x, r, 1.0);
+    return fma(r, e, r);
+}
+__device__ __forceinline__ float frcp(float x) {
+    float r = __builtin_amdgcn_rcpf(x);
+    return fmaf(r, fmaf(-x, r, 1.0f), r);
+}
+__device__ __forceinline__ double fsqrt(double x) {
+    const double r = __builtin_amdgcn_rsq(fmax(x, 1e-300));
+    double g = x * r, h = 0.5 * r;
+    const double t = fma(-g, h, 0.5);
+    g = fma(g, t, g);
+    h = fma(h, t, h);
+    double d = fma(-g, g, x);
+    g = fma(d, h, g);
+    d = fma(-g, g, x);
+    return fma(d, h, g);
+}
+__device__ __forceinline__ float fsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
 
 // conserved -> primitive in FP64 (u = m / rho, p from the total energy of Eq. 5)
 __device__ __forceinline__ void cons_to_prim(const double u[8], double w[8]) {
     const double rho = u[0];
-    const double ir = 1.0 / rho;
+    const double ir = frcp(rho);
     const double ux = u[1] * ir, uy = u[2] * ir, uz = u[3] * ir;
     const double ke = u[1] * ux + u[2] * uy + u[3] * uz;
     const double b2 = u[4] * u[4] + u[5] * u[5] + u[6] * u[6];
@@ -70,7 +90,7 @@ __device__ __forceinline__ R fast_speed(const R w[8], R ir) {
     const R s = a2 + b2;
     R disc = s * s - R(4) * a2 * bn2;
     disc = rmax(disc, R(0));
-    return rsqrt_<R>(R(0.5) * (s + rsqrt_<R>(disc)));
+    return fsqrt(R(0.5) * (s + fsqrt(disc)));
 }
 
 // conserved state, physical flux along D, normal velocity and fast speed of one face state
@@ -104,7 +124,7 @@ __device__ __forceinline__ void face_side(const R w[8], R U[8], R F[8], R &un, R
     F[6] = un * bz - bn * uz;
     F[4 + D] = R(0);
     F[7] = un * (e + ptot) - bn * ub;
-    const R ir = R(1) / rho;
+    const R ir = frcp(rho);
     cf = fast_speed<R, D>(w, ir);
 }
 
@@ -118,30 +138,25 @@ __device__ __forceinline__ void num_flux(const R wl[8], const R wr[8], R f[8]) {
 #pragma unroll
         for (int v = 0; v < 8; ++v) f[v] = R(0.5) * (FL[v] + FR[v]) - R(0.5) * cmax * (UR[v] - UL[v]);
     } else {
-        const R sl = rmin(unl - cl, unr - cr);
-        const R sr = rmax(unl + cl, unr + cr);
-        if (sl >= R(0)) {
+        // with sl' = min(sl, 0) and sr' = max(sr, 0) the single formula covers the three cases
+        const R sl = rmin(rmin(unl - cl, unr - cr), R(0));
+        const R sr = rmax(rmax(unl + cl, unr + cr), R(0));
+        const R inv = frcp(sr - sl);
+        const R a = sr * inv, b = -sl * inv, c = sl * a;
 #pragma unroll
-            for (int v = 0; v < 8; ++v) f[v] = FL[v];
-        } else if (sr <= R(0)) {
-#pragma unroll
-            for (int v = 0; v < 8; ++v) f[v] = FR[v];
-        } else {
-            const R inv = R(1) / (sr - sl);
-            const R slsr = sl * sr;
-#pragma unroll
-            for (int v = 0; v < 8; ++v) f[v] = (sr * FL[v] - sl * FR[v] + slsr * (UR[v] - UL[v])) * inv;
-        }
+        for (int v = 0; v < 8; ++v) f[v] = fma(a, FL[v], fma(b, FR[v], c * (UR[v] - UL[v])));
     }
 }
 
-// monotonized-central limited slope: minmod(2 dm, (dm + dp) / 2, 2 dp)
+// Half of the monotonized-central limited slope, minmod(2 dm, (dm + dp) / 2, 2 dp) / 2, from the two
+// one-sided differences. With s = sign(dm + dp) it is s * max(0, min(|dm + dp| / 4, s dm, s dp)): the
+// same value bit for bit (every scaling is by a power of two), without branches.
 template <typename R>
-__device__ __forceinline__ R mc_slope(R wm, R w0, R wp) {
-    const R dm = w0 - wm, dp = wp - w0;
-    const R a = R(2) * dm, b = R(0.5) * (dm + dp), c = R(2) * dp;
-    const R m = rmin(rmin(fabs(a), fabs(b)), fabs(c));
-    return (a > R(0) && b > R(0) && c > R(0)) ? m : ((a < R(0) && b < R(0) && c < R(0)) ? -m : R(0));
+__device__ __forceinline__ R mc_half(R dm, R dp) {
+    const R c = dm + dp;
+    const R s = copysign(R(1), c);
+    const R q = rmax(R(0), rmin(rmin(R(0.25) * fabs(c), s * dm), s * dp));
+    return s * q;
 }
 
 // body membership of a cell from its centre (no contraction: must agree bit for bit everywhere)
@@ -344,7 +359,7 @@ __global__ void __launch_bounds__(128) k_halo_fill(Tables T, const double *__res
 // time-step bound
 
 __device__ __forceinline__ double cell_bound(const double w[8], double inv_dx) {
-    const double ir = 1.0 / w[0];
+    const double ir = frcp(w[0]);
     const double cx = fast_speed<double, 0>(w, ir), cy = fast_speed<double, 1>(w, ir), cz = fast_speed<double, 2>(w, ir);
     return (fabs(w[1]) + cx) * inv_dx + (fabs(w[2]) + cy) * inv_dx + (fabs(w[3]) + cz) * inv_dx;
 }
@@ -431,15 +446,18 @@ __global__ void k_lam_reset(Tables T) {
 // two z-halo layers below and above; then x-halo (k, j, 4) and y-halo (k, 4, i) columns.
 template <int KS>
 struct Slab {
-    static constexpr int NT = 64 * KS;
+    static constexpr int NCELLS = 64 * KS;  // cells of the slab, owned one per thread
+    static constexpr int NFX = 72 * KS;
+    static constexpr int NFZ = 64 * (KS + 1);
+    static constexpr int NF = NFX > NFZ ? NFX : NFZ;
+    // one face per thread in every sweep: 320 threads for KS = 4, 576 for KS = 8
+    static constexpr int NT = (NF + 63) / 64 * 64;
     static constexpr int ZLO = 64 * KS;
     static constexpr int ZHI = 64 * KS + 128;
     static constexpr int XH = 64 * KS + 256;
     static constexpr int YH = 96 * KS + 256;
     static constexpr int NC = 128 * KS + 256;
-    static constexpr int NFX = 72 * KS;
-    static constexpr int NFZ = 64 * (KS + 1);
-    static constexpr int NF = NFX > NFZ ? NFX : NFZ;
+    static constexpr int NPT = (NC + NT - 1) / NT;  // gathered cells per thread
     // (i, j, k) slab-local, at most one coordinate outside the slab
     __device__ static __forceinline__ int idx(int i, int j, int k) {
         if ((unsigned)i < 8u && (unsigned)j < 8u) {
@@ -478,90 +496,97 @@ struct StageArgs {
     int count_faults;
 };
 
+// The thread index, laundered through an empty asm statement so that index arithmetic derived from it
+// is recomputed where it is used instead of being hoisted out of the persistent loop (where it would
+// stay live across the whole slab computation and double the register footprint).
+__device__ __forceinline__ int lane_tid() {
+    int t = threadIdx.x;
+    asm volatile("" : "+v"(t));
+    return t;
+}
+
 template <int KS, typename R, int D, int FLUX, bool BODY>
 __device__ __forceinline__ void sweep(const Tables &T, const DevBlock &B, int slab, R (*sW)[Slab<KS>::NC],
                                       const unsigned char *sM, R (*sF)[Slab<KS>::NF]) {
     using SL = Slab<KS>;
     constexpr int NF = D == 2 ? SL::NFZ : SL::NFX;
-    for (int f = threadIdx.x; f < NF; f += SL::NT) {
-        int i, j, k;
-        if (D == 0) { i = f % 9; j = (f / 9) & 7; k = f / 72; }
-        else if (D == 1) { i = f & 7; j = (f >> 3) % 9; k = f / 72; }
-        else { i = f & 7; j = (f >> 3) & 7; k = f >> 6; }
-        int c[4];
+    const int f = lane_tid();
+    if (f >= NF) return;
+    int i, j, k;
+    if (D == 0) { i = f % 9; j = (f / 9) & 7; k = f / 72; }
+    else if (D == 1) { i = f & 7; j = (f >> 3) % 9; k = f / 72; }
+    else { i = f & 7; j = (f >> 3) & 7; k = f >> 6; }
+    int c[4];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int o = q - 2;
-            c[q] = D == 0 ? SL::idx(i + o, j, k) : (D == 1 ? SL::idx(i, j + o, k) : SL::idx(i, j, k + o));
-        }
-        R w[4][8];
+    for (int q = 0; q < 4; ++q) {
+        const int o = q - 2;
+        c[q] = D == 0 ? SL::idx(i + o, j, k) : (D == 1 ? SL::idx(i, j + o, k) : SL::idx(i, j, k + o));
+    }
+    // face values: W_L = W_{i-1} + slope/2, W_R = W_i - slope/2 (monotonized central)
+    R wl[8], wr[8], fl[8];
+    bool m0 = false, m1 = false, m2 = false, m3 = false;
+    if constexpr (BODY) {
+        m0 = sM[c[0]]; m1 = sM[c[1]]; m2 = sM[c[2]]; m3 = sM[c[3]];
+    }
 #pragma unroll
-        for (int q = 0; q < 4; ++q)
-#pragma unroll
-            for (int v = 0; v < 8; ++v) w[q][v] = sW[v][c[q]];
-        R wl[8], wr[8], fl[8];
-        R bbar;
-        bool skip = false;
+    for (int v = 0; v < 8; ++v) {
+        const R a = sW[v][c[0]], b = sW[v][c[1]], cc = sW[v][c[2]], d = sW[v][c[3]];
+        const R d0 = b - a, d1 = cc - b, d2 = d - cc;
+        R hl = mc_half(d0, d1), hr = mc_half(d1, d2);
         if constexpr (BODY) {
-            const bool m0 = sM[c[0]], m1 = sM[c[1]], m2 = sM[c[2]], m3 = sM[c[3]];
-            if (m1 && m2) {
-                skip = true;
-            } else if (m2) {
-#pragma unroll
-                for (int v = 0; v < 8; ++v) wl[v] = wr[v] = w[1][v];
-                wr[1 + D] = -wl[1 + D];
-            } else if (m1) {
-#pragma unroll
-                for (int v = 0; v < 8; ++v) wl[v] = wr[v] = w[2][v];
-                wl[1 + D] = -wr[1 + D];
-            } else {
-#pragma unroll
-                for (int v = 0; v < 8; ++v) {
-                    const R sl = m0 ? R(0) : mc_slope(w[0][v], w[1][v], w[2][v]);
-                    const R sr = m3 ? R(0) : mc_slope(w[1][v], w[2][v], w[3][v]);
-                    wl[v] = w[1][v] + R(0.5) * sl;
-                    wr[v] = w[2][v] - R(0.5) * sr;
-                }
-            }
-        } else {
-#pragma unroll
-            for (int v = 0; v < 8; ++v) {
-                wl[v] = w[1][v] + R(0.5) * mc_slope(w[0][v], w[1][v], w[2][v]);
-                wr[v] = w[2][v] - R(0.5) * mc_slope(w[1][v], w[2][v], w[3][v]);
-            }
+            hl = (m0 || m2) ? R(0) : hl;
+            hr = (m1 || m3) ? R(0) : hr;
         }
-        if (!skip) {
-            num_flux<R, D, FLUX>(wl, wr, fl);
-            bbar = R(0.5) * (wl[4 + D] + wr[4 + D]);
-        } else {
+        wl[v] = b + hl;
+        wr[v] = cc - hr;
+    }
+    bool skip = false;
+    if constexpr (BODY) {
+        // a face between a fluid and a body cell reflects the first-order fluid state
+        if (m1 && m2) {
+            skip = true;
+        } else if (m2) {
+#pragma unroll
+            for (int v = 0; v < 8; ++v) wr[v] = wl[v];
+            wr[1 + D] = -wl[1 + D];
+        } else if (m1) {
+#pragma unroll
+            for (int v = 0; v < 8; ++v) wl[v] = wr[v];
+            wl[1 + D] = -wr[1 + D];
+        }
+    }
+    num_flux<R, D, FLUX>(wl, wr, fl);
+    R bbar = R(0.5) * (wl[4 + D] + wr[4 + D]);
+    if constexpr (BODY) {
+        if (skip) {
 #pragma unroll
             for (int v = 0; v < 8; ++v) fl[v] = R(0);
             bbar = R(0);
         }
+    }
 #pragma unroll
-        for (int v = 0; v < 8; ++v) sF[v][f] = fl[v];
-        sF[8][f] = bbar;
-        // fluxes through block faces that take part in a flux correction
-        if (B.flags & BF_FC) {
-            int bf = -1, t1 = 0, t2 = 0;
-            if (D == 0) { if (i == 0) bf = 0; else if (i == 8) bf = 1; t1 = j; t2 = slab * KS + k; }
-            if (D == 1) { if (j == 0) bf = 2; else if (j == 8) bf = 3; t1 = i; t2 = slab * KS + k; }
-            if (D == 2) {
-                const int z = slab * KS + k;
-                if (z == 0) bf = 4; else if (z == 8) bf = 5;
-                t1 = i; t2 = j;
-            }
-            if (bf >= 0 && B.fc_rec[bf] >= 0) {
-                double *rec = T.fcbuf + size_t(B.fc_rec[bf]) * FC_REC;
-                if ((B.fc_role >> bf) & 1) {
+    for (int v = 0; v < 8; ++v) sF[v][f] = fl[v];
+    sF[8][f] = bbar;
+    // fluxes through block faces that take part in a flux correction
+    if (B.flags & BF_FC) {
+        int bf = -1, t1 = 0, t2 = 0;
+        if (D == 0) { if (i == 0) bf = 0; else if (i == 8) bf = 1; t1 = j; t2 = slab * KS + k; }
+        if (D == 1) { if (j == 0) bf = 2; else if (j == 8) bf = 3; t1 = i; t2 = slab * KS + k; }
+        if (D == 2) {
+            const int z = slab * KS + k;
+            if (z == 0) bf = 4; else if (z == 8) bf = 5;
+            t1 = i; t2 = j;
+        }
+        if (bf >= 0 && B.fc_rec[bf] >= 0) {
+            double *rec = T.fcbuf + size_t(B.fc_rec[bf]) * FC_REC;
+            if ((B.fc_role >> bf) & 1) {
 #pragma unroll
-                    for (int v = 0; v < 8; ++v) rec[v * 64 + t2 * 8 + t1] = double(fl[v]);
-                } else {
-                    const int q = B.fc_quad[bf];
-                    const int g1 = 8 * (q & 1) + t1, g2 = 8 * (q >> 1) + t2;
+                for (int v = 0; v < 8; ++v) rec[v * 64 + t2 * 8 + t1] = double(fl[v]);
+            } else {
+                const int q = B.fc_quad[bf];
+                const int g1 = 8 * (q & 1) + t1, g2 = 8 * (q >> 1) + t2;
 #pragma unroll
-                    for (int v = 0; v < 8; ++v) rec[FC_COARSE + v * 256 + g2 * 16 + g1] = double(fl[v]);
-                }
+                for (int v = 0; v < 8; ++v) rec[FC_COARSE + v * 256 + g2 * 16 + g1] = double(fl[v]);
             }
         }
     }
@@ -569,7 +594,7 @@ __device__ __forceinline__ void sweep(const Tables &T, const DevBlock &B, int sl
 
 template <int KS, typename R, int D>
 __device__ __forceinline__ void accumulate(R (*sF)[Slab<KS>::NF], double rhs[8], double &divb, double inv_dx) {
-    const int t = threadIdx.x, i = t & 7, j = (t >> 3) & 7, k = t >> 6;
+    const int t = lane_tid(), i = t & 7, j = (t >> 3) & 7, k = t >> 6;
     int fl, fr;
     if (D == 0) { fl = k * 72 + j * 9 + i; fr = fl + 1; }
     else if (D == 1) { fl = k * 72 + j * 8 + i; fr = fl + 8; }
@@ -579,32 +604,19 @@ __device__ __forceinline__ void accumulate(R (*sF)[Slab<KS>::NF], double rhs[8],
     divb += (double(sF[8][fr]) - double(sF[8][fl])) * inv_dx;
 }
 
-template <int KS, typename R, int FLUX, bool POWELL>
-__global__ void __launch_bounds__(64 * KS) k_stage(Tables T, StageArgs A) {
+// Issue the global loads of one slab and its face halos (cells tid, tid + NT, ...) into registers.
+template <int KS>
+__device__ __forceinline__ void gather_issue(const Tables &T, const StageArgs &A, int b, int slab,
+                                             double (&u)[Slab<KS>::NPT][8]) {
     using SL = Slab<KS>;
-    constexpr int S_PER_BLOCK = 8 / KS;
-    __shared__ R sW[8][SL::NC];
-    __shared__ R sF[9][SL::NF];
-    __shared__ unsigned char sM[SL::NC];
-    __shared__ double red[SL::NT / 64];
-    __shared__ int redi[SL::NT / 64];
-
-    // XCD-aware schedule: workgroup w runs on XCD w % 8; XCD x owns a contiguous run of items
-    const int nwork = T.nb * S_PER_BLOCK;
-    const int wg = blockIdx.x, xcd = wg & 7, slot = wg >> 3;
-    const int q8 = nwork >> 3, r8 = nwork & 7;
-    const int item = xcd * q8 + (xcd < r8 ? xcd : r8) + slot;
-    const int b = T.order[item / S_PER_BLOCK];
-    const int slab = item % S_PER_BLOCK;
     const DevBlock &B = T.blocks[b];
     const DevSim &S = T.sims[B.sim];
     const size_t vs = size_t(T.nb) * 512;
-    const bool near_body = (B.flags & BF_NEAR_BODY) != 0;
-    const int tid = threadIdx.x;
-
-    // 1. gather slab + face halos into LDS as primitive variables
-    double uin[8];
-    for (int c = tid; c < SL::NC; c += SL::NT) {
+    const int tid = lane_tid();
+#pragma unroll
+    for (int m = 0; m < SL::NPT; ++m) {
+        const int c = tid + m * SL::NT;
+        if (c >= SL::NC) break;
         int i, j, k;
         SL::decode(c, i, j, k);
         const int z = slab * KS + k;
@@ -612,8 +624,9 @@ __global__ void __launch_bounds__(64 * KS) k_stage(Tables T, StageArgs A) {
         if (i < 0) fd = 0; else if (i > 7) fd = 1;
         else if (j < 0) fd = 2; else if (j > 7) fd = 3;
         else if (z < 0) fd = 4; else if (z > 7) fd = 5;
-        double u[8];
         const int rel = fd < 0 ? b : B.face[fd];
+        const double *p;
+        size_t stride;
         if (rel >= 0 || rel == FACE_OUTFLOW) {
             int src = b, ii = i, jj = j, zz = z;
             if (rel >= 0) {
@@ -624,102 +637,186 @@ __global__ void __launch_bounds__(64 * KS) k_stage(Tables T, StageArgs A) {
                 jj = jj < 0 ? 0 : (jj > 7 ? 7 : jj);
                 zz = zz < 0 ? 0 : (zz > 7 ? 7 : zz);
             }
-            const double *p = A.Uin + size_t(src) * 512 + (zz * 8 + jj) * 8 + ii;
-#pragma unroll
-            for (int v = 0; v < 8; ++v) u[v] = p[v * vs];
+            p = A.Uin + size_t(src) * 512 + (zz * 8 + jj) * 8 + ii;
+            stride = vs;
         } else if (rel == FACE_INFLOW) {
-#pragma unroll
-            for (int v = 0; v < 8; ++v) u[v] = S.inflow_U[v];
+            p = S.inflow_U;
+            stride = 1;
         } else {
             const int a = fd >> 1;
             const int along = a == 0 ? i : (a == 1 ? j : z);
             const int layer = along < 0 ? -1 - along : along - 8;
             const int t1 = a == 0 ? j : i, t2 = a == 2 ? j : z;
-            const double *p = T.halo + size_t(B.halo_slot) * HALO_SLOT + size_t(fd) * HALO_FACE + layer * 64 + t2 * 8 + t1;
-#pragma unroll
-            for (int v = 0; v < 8; ++v) u[v] = p[v * 128];
+            p = T.halo + size_t(B.halo_slot) * HALO_SLOT + size_t(fd) * HALO_FACE + layer * 64 + t2 * 8 + t1;
+            stride = 128;
         }
-        if (c == tid) {
 #pragma unroll
-            for (int v = 0; v < 8; ++v) uin[v] = u[v];
-        }
+        for (int v = 0; v < 8; ++v) u[m][v] = p[v * stride];
+    }
+}
+
+// Convert the gathered conserved values to primitives in LDS (and the body mask near a body).
+template <int KS, typename R>
+__device__ __forceinline__ void gather_store(const Tables &T, int b, int slab, const double (&u)[Slab<KS>::NPT][8],
+                                             R (*sW)[Slab<KS>::NC], unsigned char *sM) {
+    using SL = Slab<KS>;
+    const DevBlock &B = T.blocks[b];
+    const bool near_body = (B.flags & BF_NEAR_BODY) != 0;
+    const int tid = lane_tid();
+#pragma unroll
+    for (int m = 0; m < SL::NPT; ++m) {
+        const int c = tid + m * SL::NT;
+        if (c >= SL::NC) break;
         double w[8];
-        cons_to_prim(u, w);
+        cons_to_prim(u[m], w);
 #pragma unroll
         for (int v = 0; v < 8; ++v) sW[v][c] = R(w[v]);
-        if (near_body) sM[c] = in_body(S, B.level, B.ijk, i, j, z) ? 1 : 0;
+        if (near_body) {
+            int i, j, k;
+            SL::decode(c, i, j, k);
+            sM[c] = in_body(T.sims[B.sim], B.level, B.ijk, i, j, slab * KS + k) ? 1 : 0;
+        }
     }
-    __syncthreads();
+}
 
-    // 2. three flux sweeps; fluxes meet their two cells through LDS
+// Sweeps, source, update and end-of-step bookkeeping for one slab whose primitives are in LDS.
+template <int KS, typename R, int FLUX, bool POWELL>
+__device__ __forceinline__ void slab_compute(const Tables &T, const StageArgs &A, int b, int slab, const double (&uin)[8],
+                                             R (*sW)[Slab<KS>::NC], unsigned char *sM, R (*sF)[Slab<KS>::NF],
+                                             double *red, int *redi) {
+    using SL = Slab<KS>;
+    const DevBlock &B = T.blocks[b];
+    const DevSim &S = T.sims[B.sim];
+    const size_t vs = size_t(T.nb) * 512;
+    const bool near_body = (B.flags & BF_NEAR_BODY) != 0;
+    const int tid = lane_tid();
+    const bool owner = tid < SL::NCELLS;
+
+    // three flux sweeps, one face per thread; fluxes meet their two cells through LDS
     const double inv_dx = double(1 << B.level) / S.dx0;
     double rhs[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     double divb = 0.0;
     if (near_body) sweep<KS, R, 0, FLUX, true>(T, B, slab, sW, sM, sF);
     else sweep<KS, R, 0, FLUX, false>(T, B, slab, sW, sM, sF);
     __syncthreads();
-    accumulate<KS, R, 0>(sF, rhs, divb, inv_dx);
+    if (owner) accumulate<KS, R, 0>(sF, rhs, divb, inv_dx);
     __syncthreads();
     if (near_body) sweep<KS, R, 1, FLUX, true>(T, B, slab, sW, sM, sF);
     else sweep<KS, R, 1, FLUX, false>(T, B, slab, sW, sM, sF);
     __syncthreads();
-    accumulate<KS, R, 1>(sF, rhs, divb, inv_dx);
+    if (owner) accumulate<KS, R, 1>(sF, rhs, divb, inv_dx);
     __syncthreads();
     if (near_body) sweep<KS, R, 2, FLUX, true>(T, B, slab, sW, sM, sF);
     else sweep<KS, R, 2, FLUX, false>(T, B, slab, sW, sM, sF);
     __syncthreads();
-    accumulate<KS, R, 2>(sF, rhs, divb, inv_dx);
+    if (owner) accumulate<KS, R, 2>(sF, rhs, divb, inv_dx);
 
-    // 3. source and update of the thread's own cell
-    const bool body = near_body && sM[tid];
+    // source and update of the thread's own cell
+    const bool body = owner && near_body && sM[tid];
     const int cell = tid + slab * 64 * KS;
     const size_t off = size_t(b) * 512 + cell;
     double out[8];
-    if (body) {
+    if (owner) {
+        if (body) {
 #pragma unroll
-        for (int v = 0; v < 8; ++v) out[v] = uin[v];
-    } else {
-        if (POWELL) {
-            const double ux = double(sW[1][tid]), uy = double(sW[2][tid]), uz = double(sW[3][tid]);
-            const double bx = double(sW[4][tid]), by = double(sW[5][tid]), bz = double(sW[6][tid]);
-            const double ub = ux * bx + uy * by + uz * bz;
-            rhs[1] -= divb * bx;
-            rhs[2] -= divb * by;
-            rhs[3] -= divb * bz;
-            rhs[4] -= divb * ux;
-            rhs[5] -= divb * uy;
-            rhs[6] -= divb * uz;
-            rhs[7] -= divb * ub;
-        }
-        const double bdt = A.beta * A.dt[B.sim];
-        if (A.use_u0) {
-            const double a0 = A.alpha, a1 = 1.0 - A.alpha;
-#pragma unroll
-            for (int v = 0; v < 8; ++v) out[v] = a0 * A.U0[v * vs + off] + a1 * uin[v] + bdt * rhs[v];
+            for (int v = 0; v < 8; ++v) out[v] = uin[v];
         } else {
+            if (POWELL) {
+                const double ux = double(sW[1][tid]), uy = double(sW[2][tid]), uz = double(sW[3][tid]);
+                const double bx = double(sW[4][tid]), by = double(sW[5][tid]), bz = double(sW[6][tid]);
+                const double ub = ux * bx + uy * by + uz * bz;
+                rhs[1] -= divb * bx;
+                rhs[2] -= divb * by;
+                rhs[3] -= divb * bz;
+                rhs[4] -= divb * ux;
+                rhs[5] -= divb * uy;
+                rhs[6] -= divb * uz;
+                rhs[7] -= divb * ub;
+            }
+            const double bdt = A.beta * A.dt[B.sim];
+            if (A.use_u0) {
+                const double a0 = A.alpha, a1 = 1.0 - A.alpha;
 #pragma unroll
-            for (int v = 0; v < 8; ++v) out[v] = uin[v] + bdt * rhs[v];
+                for (int v = 0; v < 8; ++v) out[v] = a0 * A.U0[v * vs + off] + a1 * uin[v] + bdt * rhs[v];
+            } else {
+#pragma unroll
+                for (int v = 0; v < 8; ++v) out[v] = uin[v] + bdt * rhs[v];
+            }
         }
-    }
 #pragma unroll
-    for (int v = 0; v < 8; ++v) A.Uout[v * vs + off] = out[v];
+        for (int v = 0; v < 8; ++v) A.Uout[v * vs + off] = out[v];
+    }
 
-    // 4. end of a step: positivity check and the next time-step bound
+    // end of a step: positivity check and the next time-step bound
     if (A.count_faults || A.want_lam) {
-        const int i = tid & 7, j = (tid >> 3) & 7, z = slab * KS + (tid >> 6);
-        const int skipm = B.fc_skip;
-        const bool later = skipm && (((skipm & 1) && i == 0) || ((skipm & 2) && i == 7) || ((skipm & 4) && j == 0) ||
-                                     ((skipm & 8) && j == 7) || ((skipm & 16) && z == 0) || ((skipm & 32) && z == 7));
         double lam = 0.0;
         int nf = 0;
-        if (!body && !later) {
-            double w[8];
-            cons_to_prim(out, w);
-            nf = !(w[0] > 0.0) || !(w[7] > 0.0) || !(w[7] < INFINITY);
-            if (A.want_lam) lam = cell_bound(w, inv_dx);
+        if (owner && !body) {
+            const int i = tid & 7, j = (tid >> 3) & 7, z = slab * KS + (tid >> 6);
+            const int skipm = B.fc_skip;
+            const bool later = skipm && (((skipm & 1) && i == 0) || ((skipm & 2) && i == 7) || ((skipm & 4) && j == 0) ||
+                                         ((skipm & 8) && j == 7) || ((skipm & 16) && z == 0) || ((skipm & 32) && z == 7));
+            if (!later) {
+                double w[8];
+                cons_to_prim(out, w);
+                nf = !(w[0] > 0.0) || !(w[7] > 0.0) || !(w[7] < INFINITY);
+                if (A.want_lam) lam = cell_bound(w, inv_dx);
+            }
         }
         block_publish<SL::NT>(lam, A.count_faults ? nf : 0, red, redi, A.want_lam ? T.lam + B.sim : nullptr,
                               A.faults);
+    }
+}
+
+// Work item -> (block, slab). Items are the slabs of the Morton-ordered block list. XCD x (workgroups
+// w with w % 8 == x) owns the contiguous item range [first(x), first(x) + count(x)).
+__device__ __forceinline__ int xcd_first(int nwork, int x) {
+    const int q = nwork >> 3, r = nwork & 7;
+    return x * q + (x < r ? x : r);
+}
+__device__ __forceinline__ int xcd_count(int nwork, int x) { return (nwork >> 3) + (x < (nwork & 7) ? 1 : 0); }
+
+// One workgroup per slab (PERSIST = false: the grid has one workgroup per item) or a persistent grid
+// (PERSIST = true: gridDim.x workgroups, a multiple of 8, each looping over the items of its XCD). The
+// gather of a slab is issued at the top of its iteration: holding the next slab's 24 values per thread
+// in registers across the flux sweeps would double the register footprint and halve occupancy, while
+// two co-resident workgroups per CU already overlap one's gather with the other's sweeps.
+template <int KS, typename R, int FLUX, bool POWELL, bool PERSIST>
+__global__ void __launch_bounds__(Slab<KS>::NT) k_stage(Tables T, StageArgs A) {
+    using SL = Slab<KS>;
+    constexpr int S_PER_BLOCK = 8 / KS;
+    __shared__ R sW[8][SL::NC];
+    __shared__ R sF[9][SL::NF];
+    __shared__ unsigned char sM[SL::NC];
+    __shared__ double red[SL::NT / 64];
+    __shared__ int redi[SL::NT / 64];
+
+    const int nwork = T.nb * S_PER_BLOCK;
+    const int wg = blockIdx.x, xcd = wg & 7, slot = wg >> 3;
+    const int first = xcd_first(nwork, xcd), count = xcd_count(nwork, xcd);
+    if constexpr (!PERSIST) {
+        const int item = first + slot;
+        const int b = T.order[item / S_PER_BLOCK], slab = item % S_PER_BLOCK;
+        double u[SL::NPT][8];
+        gather_issue<KS>(T, A, b, slab, u);
+        gather_store<KS, R>(T, b, slab, u, sW, sM);
+        __syncthreads();
+        slab_compute<KS, R, FLUX, POWELL>(T, A, b, slab, u[0], sW, sM, sF, red, redi);
+    } else {
+        const int step = int(gridDim.x >> 3);
+#pragma nounroll
+        for (int it = slot; it < count; it += step) {
+            const int item = first + it;
+            const int b = T.order[item / S_PER_BLOCK], slab = item % S_PER_BLOCK;
+            double u[SL::NPT][8];
+            gather_issue<KS>(T, A, b, slab, u);
+            gather_store<KS, R>(T, b, slab, u, sW, sM);
+            __syncthreads();
+            slab_compute<KS, R, FLUX, POWELL>(T, A, b, slab, u[0], sW, sM, sF, red, redi);
+            __syncthreads();
+            // keep the scheduler from overlapping iterations (that would hold two slabs' values live)
+            __builtin_amdgcn_sched_barrier(0);
+        }
     }
 }
 
@@ -777,6 +874,12 @@ __global__ void __launch_bounds__(256) k_flux_correct(Tables T, StageArgs A) {
 
 using namespace bmhd;
 
+bmhd_grid::~bmhd_grid() {
+    if (h.graph_exec) (void)hipGraphExecDestroy(reinterpret_cast<hipGraphExec_t>(h.graph_exec));
+    if (h.graph) (void)hipGraphDestroy(reinterpret_cast<hipGraph_t>(h.graph));
+    if (h.capture_stream) (void)hipStreamDestroy(reinterpret_cast<hipStream_t>(h.capture_stream));
+}
+
 namespace {
 thread_local std::string g_err;
 
@@ -794,28 +897,131 @@ int32_t launch_check(const char *what) { return hip_check(hipGetLastError(), wha
 
 bool ptr_ok(const void *p) { return p && (reinterpret_cast<uintptr_t>(p) & 7u) == 0; }
 
-template <int KS, typename R, int FLUX>
-int32_t launch_stage_flux(const HostGrid &h, const StageArgs &a, bool powell, hipStream_t s) {
-    const int grid = h.nb * (8 / KS);
-    if (powell) k_stage<KS, R, FLUX, true><<<grid, 64 * KS, 0, s>>>(h.dev, a);
-    else k_stage<KS, R, FLUX, false><<<grid, 64 * KS, 0, s>>>(h.dev, a);
+// Launch shape of the stage kernel: tile depth (4 or 8 cells) and persistent grid size (0: one
+// workgroup per slab).
+struct Shape {
+    int ks;
+    int persist_wgs;
+};
+
+template <int KS, typename R, int FLUX, bool POWELL>
+int32_t launch_stage_shape(const HostGrid &h, const StageArgs &a, int persist_wgs, hipStream_t s) {
+    constexpr int nt = Slab<KS>::NT;
+    const int items = h.nb * (8 / KS);
+    if (persist_wgs > 0) {
+        int grid = persist_wgs < items ? persist_wgs : items;
+        grid = (grid + 7) & ~7;
+        k_stage<KS, R, FLUX, POWELL, true><<<grid, nt, 0, s>>>(h.dev, a);
+    } else {
+        k_stage<KS, R, FLUX, POWELL, false><<<items, nt, 0, s>>>(h.dev, a);
+    }
     return launch_check("stage kernel");
 }
 
 template <int KS, typename R>
-int32_t launch_stage_prec(const HostGrid &h, const StageArgs &a, int flux, bool powell, hipStream_t s) {
-    if (flux == BMHD_FLUX_RUSANOV) return launch_stage_flux<KS, R, BMHD_FLUX_RUSANOV>(h, a, powell, s);
-    return launch_stage_flux<KS, R, BMHD_FLUX_HLLE>(h, a, powell, s);
+int32_t launch_stage_prec(const HostGrid &h, const StageArgs &a, int flux, bool powell, int pw, hipStream_t s) {
+    if (flux == BMHD_FLUX_RUSANOV) {
+        if (powell) return launch_stage_shape<KS, R, BMHD_FLUX_RUSANOV, true>(h, a, pw, s);
+        return launch_stage_shape<KS, R, BMHD_FLUX_RUSANOV, false>(h, a, pw, s);
+    }
+    if (powell) return launch_stage_shape<KS, R, BMHD_FLUX_HLLE, true>(h, a, pw, s);
+    return launch_stage_shape<KS, R, BMHD_FLUX_HLLE, false>(h, a, pw, s);
+}
+
+Shape pick_shape(const bmhd_opts &o) {
+    Shape sh;
+    sh.ks = o.slab == 0 ? (o.precision == BMHD_FP64 ? 4 : 8) : o.slab;
+    sh.persist_wgs = o.persist_wgs;
+    return sh;
 }
 
 int32_t launch_stage(const HostGrid &h, const StageArgs &a, const bmhd_opts &o, hipStream_t s) {
-    const int ks = o.slab == 0 ? (o.precision == BMHD_FP64 ? 4 : 8) : o.slab;
+    const Shape sh = pick_shape(o);
     if (o.precision == BMHD_FP64) {
-        if (ks == 4) return launch_stage_prec<4, double>(h, a, o.flux, o.powell, s);
-        return launch_stage_prec<8, double>(h, a, o.flux, o.powell, s);
+        if (sh.ks == 4) return launch_stage_prec<4, double>(h, a, o.flux, o.powell, sh.persist_wgs, s);
+        return launch_stage_prec<8, double>(h, a, o.flux, o.powell, sh.persist_wgs, s);
     }
-    if (ks == 4) return launch_stage_prec<4, float>(h, a, o.flux, o.powell, s);
-    return launch_stage_prec<8, float>(h, a, o.flux, o.powell, s);
+    if (sh.ks == 4) return launch_stage_prec<4, float>(h, a, o.flux, o.powell, sh.persist_wgs, s);
+    return launch_stage_prec<8, float>(h, a, o.flux, o.powell, sh.persist_wgs, s);
+}
+
+int32_t check_opts(const bmhd_opts &o) {
+    if (o.flux != BMHD_FLUX_RUSANOV && o.flux != BMHD_FLUX_HLLE) return fail(BMHD_EINVAL, "unknown flux");
+    if (o.precision != BMHD_FP64 && o.precision != BMHD_FP32_FLUX) return fail(BMHD_EINVAL, "unknown precision");
+    if (o.slab != 0 && o.slab != 4 && o.slab != 8) return fail(BMHD_EINVAL, "slab must be 0, 4 or 8");
+    if (o.persist_wgs < 0 || o.persist_wgs > (1 << 20)) return fail(BMHD_EINVAL, "persist_wgs out of range");
+    if (o.recompute_dt && !(o.cfl > 0.0)) return fail(BMHD_EINVAL, "cfl must be positive");
+    return BMHD_OK;
+}
+
+// One stage: level-change halos, the stage kernel (optionally bracketed by events), flux correction.
+int32_t enqueue_stage(const HostGrid &h, const bmhd_opts &o, int e, double *d_U0, double *d_U1, double *d_dt,
+                      int32_t *d_faults, bool want_lam, void *ev0, void *ev1, hipStream_t s) {
+    const double *in = e ? d_U1 : d_U0;
+    double *out = e ? d_U0 : d_U1;
+    if (!h.halo_items.empty()) k_halo_fill<<<unsigned(h.halo_items.size()), 128, 0, s>>>(h.dev, in);
+    StageArgs a;
+    a.Uin = in;
+    a.U0 = d_U0;
+    a.Uout = out;
+    a.dt = d_dt;
+    a.faults = d_faults;
+    a.alpha = o.alpha[e];
+    a.beta = o.beta[e];
+    a.use_u0 = o.alpha[e] != 0.0 ? 1 : 0;
+    a.want_lam = want_lam ? 1 : 0;
+    a.count_faults = (e == 1 && d_faults) ? 1 : 0;
+    if (ev0)
+        if (int32_t rc = hip_check(hipEventRecord(reinterpret_cast<hipEvent_t>(ev0), s), "event")) return rc;
+    if (int32_t rc = launch_stage(h, a, o, s)) return rc;
+    if (ev1)
+        if (int32_t rc = hip_check(hipEventRecord(reinterpret_cast<hipEvent_t>(ev1), s), "event")) return rc;
+    if (!h.fc_cells.empty()) {
+        k_flux_correct<<<unsigned((h.fc_cells.size() + 255) / 256), 256, 0, s>>>(h.dev, a);
+        if (int32_t rc = launch_check("flux correction")) return rc;
+    }
+    return BMHD_OK;
+}
+
+// Capture (once per buffer set and options) a graph of one whole step after the first: dt from the
+// previous step's bound, both stages, the next bound. Kernels only: no memset or copy nodes.
+int32_t ensure_step_graph(HostGrid &h, const bmhd_opts &o, double *d_U0, double *d_U1, double *d_dt,
+                          int32_t *d_faults) {
+    bmhd_opts ko = o;
+    ko.events = nullptr;
+    ko.n_events = 0;
+    std::vector<unsigned char> key(sizeof(ko) + 4 * sizeof(void *));
+    std::memcpy(key.data(), &ko, sizeof(ko));
+    void *ptrs[4] = {d_U0, d_U1, d_dt, d_faults};
+    std::memcpy(key.data() + sizeof(ko), ptrs, sizeof(ptrs));
+    if (h.graph_exec && key == h.graph_key) return BMHD_OK;
+    if (h.graph_exec) (void)hipGraphExecDestroy(reinterpret_cast<hipGraphExec_t>(h.graph_exec));
+    if (h.graph) (void)hipGraphDestroy(reinterpret_cast<hipGraph_t>(h.graph));
+    h.graph_exec = h.graph = nullptr;
+    if (!h.capture_stream) {
+        hipStream_t cs;
+        if (int32_t rc = hip_check(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking), "capture stream")) return rc;
+        h.capture_stream = cs;
+    }
+    hipStream_t cs = reinterpret_cast<hipStream_t>(h.capture_stream);
+    if (int32_t rc = hip_check(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal), "begin capture")) return rc;
+    int32_t rc = BMHD_OK;
+    if (o.recompute_dt) k_dt_finalize<<<(h.ns + 63) / 64, 64, 0, cs>>>(h.dev, o.cfl, d_dt);
+    for (int e = 0; e < 2 && rc == BMHD_OK; ++e)
+        rc = enqueue_stage(h, ko, e, d_U0, d_U1, d_dt, d_faults, e == 1 && o.recompute_dt, nullptr, nullptr, cs);
+    hipGraph_t graph = nullptr;
+    const int32_t rc2 = hip_check(hipStreamEndCapture(cs, &graph), "end capture");
+    if (rc) return rc;
+    if (rc2) return rc2;
+    hipGraphExec_t ex = nullptr;
+    if (int32_t rc3 = hip_check(hipGraphInstantiate(&ex, graph, nullptr, nullptr, 0), "instantiate")) {
+        (void)hipGraphDestroy(graph);
+        return rc3;
+    }
+    h.graph = graph;
+    h.graph_exec = ex;
+    h.graph_key = key;
+    return BMHD_OK;
 }
 
 int32_t need_upload(const bmhd_grid *g) {
@@ -942,51 +1148,83 @@ int32_t bmhd_advance(const bmhd_grid *g, double *d_U0, double *d_U1, double *d_d
     if (d_faults && (reinterpret_cast<uintptr_t>(d_faults) & 3u)) return fail(BMHD_EINVAL, "misaligned fault counter");
     if (n_stages < 0) return fail(BMHD_EINVAL, "n_stages must be >= 0");
     const bmhd_opts &o = *opts;
-    if (o.flux != BMHD_FLUX_RUSANOV && o.flux != BMHD_FLUX_HLLE) return fail(BMHD_EINVAL, "unknown flux");
-    if (o.precision != BMHD_FP64 && o.precision != BMHD_FP32_FLUX) return fail(BMHD_EINVAL, "unknown precision");
-    if (o.slab != 0 && o.slab != 4 && o.slab != 8) return fail(BMHD_EINVAL, "slab must be 0, 4 or 8");
-    if (o.recompute_dt && !(o.cfl > 0.0)) return fail(BMHD_EINVAL, "cfl must be positive");
-    const HostGrid &h = g->h;
+    if (int32_t rc = check_opts(o)) return rc;
+    if (o.use_graph && (n_stages & 1)) return fail(BMHD_EINVAL, "use_graph needs whole steps (even n_stages)");
+    HostGrid &h = const_cast<bmhd_grid *>(g)->h;
     if (h.nb == 0 || n_stages == 0) return BMHD_OK;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    const int sb = (h.ns + 63) / 64;
-    for (int st = 0; st < n_stages; ++st) {
-        const int e = st & 1;
-        const double *in = e ? d_U1 : d_U0;
-        double *out = e ? d_U0 : d_U1;
-        if (e == 0 && o.recompute_dt) {
-            if (st == 0) {
-                k_lam_reset<<<sb, 64, 0, s>>>(h.dev);
-                k_dt_reduce<<<h.nb, 512, 0, s>>>(h.dev, d_U0);
+    const int n_steps = (n_stages + 1) / 2;
+    const bool timed = !o.use_graph && o.events && o.n_events >= 2 * n_stages;
+    // the first step (and every step without a graph) is launched directly
+    const int direct_steps = o.use_graph ? 1 : n_steps;
+    for (int step = 0; step < direct_steps; ++step) {
+        for (int e = 0; e < 2; ++e) {
+            const int st = 2 * step + e;
+            if (st >= n_stages) break;
+            if (e == 0 && o.recompute_dt) {
+                const int sb = (h.ns + 63) / 64;
+                if (st == 0) {
+                    k_lam_reset<<<sb, 64, 0, s>>>(h.dev);
+                    k_dt_reduce<<<h.nb, 512, 0, s>>>(h.dev, d_U0);
+                }
+                k_dt_finalize<<<sb, 64, 0, s>>>(h.dev, o.cfl, d_dt);
             }
-            k_dt_finalize<<<sb, 64, 0, s>>>(h.dev, o.cfl, d_dt);
-        }
-        if (!h.halo_items.empty()) k_halo_fill<<<unsigned(h.halo_items.size()), 128, 0, s>>>(h.dev, in);
-        StageArgs a;
-        a.Uin = in;
-        a.U0 = d_U0;
-        a.Uout = out;
-        a.dt = d_dt;
-        a.faults = d_faults;
-        a.alpha = o.alpha[e];
-        a.beta = o.beta[e];
-        a.use_u0 = o.alpha[e] != 0.0 ? 1 : 0;
-        a.want_lam = (e == 1 && o.recompute_dt && st + 1 < n_stages) ? 1 : 0;
-        a.count_faults = (e == 1 && d_faults) ? 1 : 0;
-        const bool timed = o.events && o.n_events >= 2 * n_stages;
-        if (timed) {
-            if (int32_t rc = hip_check(hipEventRecord(reinterpret_cast<hipEvent_t>(o.events[2 * st]), s), "event")) return rc;
-        }
-        if (int32_t rc = launch_stage(h, a, o, s)) return rc;
-        if (timed) {
-            if (int32_t rc = hip_check(hipEventRecord(reinterpret_cast<hipEvent_t>(o.events[2 * st + 1]), s), "event")) return rc;
-        }
-        if (!h.fc_cells.empty()) {
-            k_flux_correct<<<unsigned((h.fc_cells.size() + 255) / 256), 256, 0, s>>>(h.dev, a);
-            if (int32_t rc = launch_check("flux correction")) return rc;
+            void *ev0 = timed ? o.events[2 * st] : nullptr, *ev1 = timed ? o.events[2 * st + 1] : nullptr;
+            const bool want_lam = e == 1 && o.recompute_dt && st + 1 < n_stages;
+            if (int32_t rc = enqueue_stage(h, o, e, d_U0, d_U1, d_dt, d_faults, want_lam, ev0, ev1, s)) return rc;
         }
     }
+    if (o.use_graph && n_steps > 1) {
+        if (int32_t rc = ensure_step_graph(h, o, d_U0, d_U1, d_dt, d_faults)) return rc;
+        hipGraphExec_t ex = reinterpret_cast<hipGraphExec_t>(h.graph_exec);
+        for (int step = 1; step < n_steps; ++step)
+            if (int32_t rc = hip_check(hipGraphLaunch(ex, s), "graph launch")) return rc;
+    }
     return launch_check("advance");
+}
+
+int32_t bmhd_autotune(const bmhd_grid *g, double *d_U0, double *d_U1, double *d_dt, const bmhd_opts *base,
+                      int32_t n_steps, bmhd_opts *best, float *h_ms, void *stream) {
+    if (int32_t rc = need_upload(g)) return rc;
+    if (!base || !best || n_steps <= 0) return fail(BMHD_EINVAL, "bad autotune arguments");
+    if (int32_t rc = check_opts(*base)) return rc;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    int dev = 0, cus = 0;
+    if (int32_t rc = hip_check(hipGetDevice(&dev), "device")) return rc;
+    if (int32_t rc = hip_check(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev), "attr")) return rc;
+    hipEvent_t e0, e1;
+    if (int32_t rc = hip_check(hipEventCreate(&e0), "event")) return rc;
+    if (int32_t rc = hip_check(hipEventCreate(&e1), "event")) return rc;
+    const int shapes[6][2] = {{4, 0}, {4, 2}, {4, 4}, {8, 0}, {8, 2}, {8, 4}};
+    float best_ms = 1e30f;
+    int32_t rc = BMHD_OK;
+    *best = *base;
+    for (int c = 0; c < 6 && rc == BMHD_OK; ++c) {
+        bmhd_opts o = *base;
+        o.slab = shapes[c][0];
+        o.persist_wgs = shapes[c][1] * cus;
+        o.events = nullptr;
+        o.n_events = 0;
+        rc = bmhd_advance(g, d_U0, d_U1, d_dt, 2, &o, nullptr, stream);  // warm-up
+        if (rc) break;
+        rc = hip_check(hipEventRecord(e0, s), "event");
+        if (!rc) rc = bmhd_advance(g, d_U0, d_U1, d_dt, 2 * n_steps, &o, nullptr, stream);
+        if (!rc) rc = hip_check(hipEventRecord(e1, s), "event");
+        if (!rc) rc = hip_check(hipEventSynchronize(e1), "event sync");
+        float ms = 0.f;
+        if (!rc) rc = hip_check(hipEventElapsedTime(&ms, e0, e1), "elapsed");
+        if (rc) break;
+        if (h_ms) h_ms[c] = ms;
+        if (ms < best_ms) {
+            best_ms = ms;
+            *best = o;
+            best->events = base->events;
+            best->n_events = base->n_events;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return rc;
 }
 
 }  // extern "C"

@@ -326,3 +326,86 @@ def two_level_box(nroot=(4, 3, 2), refine=((1, 1, 0), (2, 1, 0), (1, 0, 1)), bc=
     lv, ijk, sid = two_level_blocks(nroot, mask)
     wl = Workload("two_level_box", lv, ijk, sid, [sim], _empty_W(len(lv)), flux="hlle", powell=True)
     return with_state(wl, random_positive_state(wl, seed))
+
+
+# --------------------------------------------------------------------------------------------------
+# batched simulations of superposed linear MHD waves
+
+def _primitive_jacobian(rho, p, B, n):
+    """Matrix A of the linearised primitive ideal-MHD system W_t + A W_s = 0 along unit vector n, about
+    rest (u = 0) with density rho, pressure p and field B. Used only to shape initial perturbations."""
+    A = np.zeros((8, 8))
+    bn = float(np.dot(B, n))
+    for d in range(3):
+        A[0, 1 + d] = rho * n[d]
+        A[7, 1 + d] = GAMMA * p * n[d]
+        A[1 + d, 7] = n[d] / rho
+        for m in range(3):
+            A[1 + d, 4 + m] = (n[d] * B[m] - (bn if d == m else 0.0)) / rho
+            A[4 + d, 1 + m] = B[d] * n[m] - (bn if d == m else 0.0)
+    return A
+
+
+WAVE_FAMILIES = ("fast-", "alfven-", "slow-", "entropy", "slow+", "alfven+", "fast+")
+
+
+def wave_eigenvector(rho, p, B, n, family):
+    """Right eigenvector of the linearised system for one wave family, normalised to max-norm 1."""
+    A = _primitive_jacobian(rho, p, np.asarray(B, float), np.asarray(n, float))
+    lam, R = np.linalg.eig(A)
+    lam, R = lam.real, R.real
+    if family == "entropy":
+        r = np.zeros(8); r[0] = 1.0
+        return r
+    order = np.argsort(lam)           # -cf, -ca, -cs, 0, 0, cs, ca, cf
+    pick = {"fast-": 0, "alfven-": 1, "slow-": 2, "slow+": 5, "alfven+": 6, "fast+": 7}[family]
+    r = R[:, order[pick]]
+    return r / np.abs(r).max()
+
+
+def batched_waves(n_sims=64, seed=4, n_waves=8, amp_max=0.05, n_lo=64, n_hi=4096, n_steps=100):
+    """Many independent periodic simulations on one grid. Block counts are drawn log-uniformly in
+    [n_lo, n_hi] and factorised into a box (bz = floor(N^(1/3)), by = floor(sqrt(N / bz)),
+    bx = floor(N / (bz by))); cell size 1. Background rho = 1, p = 1, u = 0, |B| = 1 along a random
+    direction; each simulation superposes n_waves linear waves (family uniform, integer wave-number
+    vector in [-2, 2]^3 without 0, amplitude uniform in [0, amp_max], phase uniform)."""
+    rng = np.random.default_rng(seed)
+    counts = np.rint(np.exp(rng.uniform(math.log(n_lo), math.log(n_hi), n_sims))).astype(int)
+    sims, lv, ijk, sid = [], [], [], []
+    for s, N in enumerate(counts):
+        bz = int(math.floor(N ** (1.0 / 3.0) + 1e-9))
+        by = int(math.floor(math.sqrt(N / bz) + 1e-9))
+        bx = int(N // (bz * by))
+        sims.append(Sim((bx, by, bz), (0.0, 0.0, 0.0), 1.0))
+        l, c, _ = uniform_blocks((bx, by, bz))
+        lv.append(l); ijk.append(c); sid.append(np.full(len(l), s, np.int32))
+    level = np.concatenate(lv); ijk = np.concatenate(ijk); sim = np.concatenate(sid)
+    W = _empty_W(len(level))
+    W[0] = 1.0
+    W[7] = 1.0
+    for s, sd in enumerate(sims):
+        sel = sim == s
+        v = rng.normal(size=3); Bhat = v / np.linalg.norm(v)
+        x, y, z = cell_centres(sd, level[sel], ijk[sel])
+        L = np.array(sd.nroot) * NX * sd.dx0
+        Ws = np.zeros((8,) + x.shape)
+        Ws[0] = 1.0; Ws[7] = 1.0
+        for m in range(3):
+            Ws[4 + m] = Bhat[m]
+        for _ in range(n_waves):
+            fam = WAVE_FAMILIES[rng.integers(len(WAVE_FAMILIES))]
+            while True:
+                nv = rng.integers(-2, 3, size=3)
+                if np.any(nv != 0):
+                    break
+            a = rng.uniform(0.0, amp_max)
+            ph = rng.uniform(0.0, 2 * math.pi)
+            kvec = 2 * math.pi * nv / L
+            khat = kvec / np.linalg.norm(kvec)
+            r = wave_eigenvector(1.0, 1.0, Bhat, khat, fam)
+            cph = np.cos(kvec[0] * x + kvec[1] * y + kvec[2] * z + ph)
+            for q in range(8):
+                Ws[q] += a * r[q] * cph
+        W[:, sel] = Ws
+    return Workload(f"batched_{n_sims}", level, ijk, sim, sims, W, flux="rusanov", powell=False, cfl=0.8,
+                    n_steps=n_steps)

@@ -159,6 +159,15 @@ def test_slab_choice_is_bitwise_neutral(bd, slab):
     assert np.array_equal(a[0], b[0]) and np.array_equal(a[2], b[2])
 
 
+@pytest.mark.parametrize("slab,persist", [(4, 8), (4, 256), (8, 24), (4, 1024)])
+def test_persistent_form_is_bitwise_identical(bd, slab, persist):
+    wl = wk.two_level_magnetosphere(48)
+    kw = dict(flux="hlle", powell=True)
+    a = gpu_run(bd, wl, wl.W, 4, slab=slab, persist_wgs=persist, **kw)
+    b = gpu_run(bd, wl, wl.W, 4, slab=4, **kw)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]) and np.array_equal(a[2], b[2])
+
+
 def test_cp_alfven_ten_steps(bd, oracle_mod):
     wl = wk.cp_alfven(32)
     say("cp_alfven 10 steps")
@@ -217,3 +226,65 @@ def test_two_level_conservation_gpu(bd, oracle_mod):
         t1 = math.fsum((U0[v] * vol[:, None, None, None]).ravel())
         s = math.fsum((np.abs(Ui[v]) * vol[:, None, None, None]).ravel())
         assert abs(t1 - t0) <= 1e-14 * s
+
+
+# ------------------------------------------------------------------------------------------------
+# batched simulations, graph replay, autotuner
+
+def small_batch():
+    return wk.batched_waves(n_sims=5, seed=7, n_lo=8, n_hi=60)
+
+
+def test_batched_parity_fp64(bd, oracle_mod):
+    wl = small_batch()
+    say("batched", wl.n_blocks, len(wl.sims))
+    U0, _, dt, f = gpu_run(bd, wl, wl.W, 6, flux="rusanov")
+    R0, _, rdt, rf = oracle_run(oracle_mod, wl, wl.W, 6, flux="rusanov")
+    assert f == 0 and rf == 0
+    assert np.all(np.abs(dt - rdt) <= 1e-14 * rdt)
+    assert max(group_err(U0, R0).values()) <= TOL
+
+
+def test_batched_member_equals_alone(bd):
+    """Every simulation of a batch advances exactly as it does alone (its own dt, no coupling)."""
+    import dataclasses
+    wl = small_batch()
+    U0, _, dt, _ = gpu_run(bd, wl, wl.W, 4, flux="rusanov", precision="fp32_flux")
+    for s in (0, 3):
+        sel = wl.sim == s
+        alone = dataclasses.replace(wl, level=wl.level[sel], ijk=wl.ijk[sel], sim=np.zeros(sel.sum(), np.int32),
+                                    sims=[wl.sims[s]], W=np.ascontiguousarray(wl.W[:, sel]))
+        A0, _, adt, _ = gpu_run(bd, alone, alone.W, 4, flux="rusanov", precision="fp32_flux")
+        assert adt[0] == dt[s]
+        assert np.array_equal(A0, U0[:, sel])
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_flux"])
+def test_graph_replay_matches_eager(bd, precision):
+    """Graph replays interleaved with eager work and synchronisations, each checked bitwise."""
+    wl = small_batch()
+    g = bd.Grid.from_workload(wl).upload()
+    kw = dict(flux="rusanov", precision=precision, persist_wgs=64)
+    Ue = g.set_state(dev(wl.W)); U1e = torch.zeros_like(Ue); dte = torch.zeros(len(wl.sims), dtype=torch.float64, device="cuda")
+    Ug = g.set_state(dev(wl.W)); U1g = torch.zeros_like(Ug); dtg = torch.zeros_like(dte)
+    fe = torch.zeros(1, dtype=torch.int32, device="cuda"); fg = torch.zeros_like(fe)
+    for rep in range(3):
+        g.advance(Ue, U1e, dte, 8, faults=fe, **kw)
+        torch.cuda.synchronize()
+        g.advance(Ug, U1g, dtg, 8, faults=fg, use_graph=True, **kw)
+        torch.cuda.synchronize()
+        _ = (Ue * 2.0).sum().item()   # unrelated eager work between replays
+        assert torch.equal(Ue, Ug) and torch.equal(U1e, U1g) and torch.equal(dte, dtg), rep
+    assert fe.item() == 0 and fg.item() == 0
+
+
+def test_autotune_picks_a_valid_shape(bd):
+    wl = small_batch()
+    g = bd.Grid.from_workload(wl).upload()
+    U0 = g.set_state(dev(wl.W)); U1 = torch.zeros_like(U0)
+    dt = torch.zeros(len(wl.sims), dtype=torch.float64, device="cuda")
+    best, ms = g.autotune(U0, U1, dt, n_steps=2, flux="rusanov", precision="fp32_flux")
+    say("autotune", ms, best.slab, best.persist_wgs)
+    assert best.slab in (4, 8) and best.persist_wgs >= 0
+    assert all(v > 0 for v in ms.values())
+    assert min(ms.values()) == pytest.approx(ms[min(ms, key=ms.get)])
