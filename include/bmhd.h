@@ -80,6 +80,25 @@ typedef struct {
     const bmhd_sim_desc *sims; /* host [n_sims] */
 } bmhd_grid_desc;
 
+/* Learned flux correction inside bmhd_advance (uniform grids only). Per stage: the 4-cell stencil of
+ * every face (primitives in the face-normal frame (rho, u_n, u_t1, u_t2, B_n, B_t1, B_t2, p), z-scored
+ * with stats[0..63]) goes through the MLP; its output, de-normalised with stats[64..79] and rotated back,
+ * is added to the face flux. Cells whose provisional state has rho <= 0 or p <= 0, or rho or p outside
+ * [min - tau * range, max + tau * range] of their old 7-point neighbourhood, are flagged; every face of a
+ * flagged cell falls back to the plain flux on both sides and the affected cells are recomputed once. */
+typedef struct {
+    int32_t hidden;              /* 32, 64 or 128 */
+    int32_t mode;                /* 0: BF16 matrix cores, 1: FP32 reference */
+    const float *params;         /* device [n_params] float32 */
+    const uint16_t *params_bf16; /* device [n_params] bfloat16 copy */
+    const float *stats;          /* device: in_mean[32], in_std[32], out_mean[8], out_std[8] */
+    float *x_buf;                /* device scratch [n_blocks * 1728][32] */
+    float *y_buf;                /* device scratch [n_blocks * 1728][8] */
+    uint8_t *flags;              /* device scratch [n_blocks * 512] */
+    int32_t *fallback_cells;     /* device counter of flagged cells, incremented per stage (may be NULL) */
+    double tau;                  /* tolerance of the neighbourhood bound (0.1) */
+} bmhd_learned;
+
 typedef struct {
     int32_t flux;         /* BMHD_FLUX_* */
     int32_t powell;       /* 1: Powell source terms (right-hand sides of Eqs. 2-4) */
@@ -94,6 +113,7 @@ typedef struct {
                              (rounded up to a multiple of 8), each looping over tiles */
     int32_t use_graph;    /* 1: steps after the first replay one captured HIP graph of a whole step
                              (n_stages must be even; `events` are ignored) */
+    const bmhd_learned *learned; /* NULL: plain fluxes */
     int32_t n_events;     /* length of `events`, or 0 */
     void **events;        /* optional caller-created hipEvent_t handles: when n_events >= 2 * n_stages,
                              events[2s] and events[2s+1] are recorded on `stream` right before and after
@@ -166,6 +186,17 @@ int32_t bmhd_reduce_dt(const bmhd_grid *g, const double *d_U, double cfl, double
 int32_t bmhd_advance(const bmhd_grid *g, double *d_U0, double *d_U1, double *d_dt, int32_t n_stages,
                      const bmhd_opts *opts, int32_t *d_faults, void *stream);
 
+/* Per-face data of a state for training the learned correction. Faces are enumerated per block and
+ * direction d: face f of direction d sits between cells f-1 and f along d; f runs over
+ * (z * 8 + y) * 9 + x for d = 0, (z * 9 + y) * 8 + x for d = 1 and (z * 8 + y) * 8 + x for d = 2 (576 per
+ * direction), so the global index is (b * 3 + d) * 576 + f (faces shared by two blocks appear twice,
+ * with equal values). d_X (may be NULL) [n_blocks * 1728][32]: stencil features in the face-normal
+ * frame, z-scored with d_stats[0..63] when d_stats is not NULL. d_F (may be NULL)
+ * [n_blocks * 1728][8]: the plain numerical flux (MC reconstruction, `flux`, FP64 arithmetic) in the
+ * face-normal frame (rho, (rho u)_n, (rho u)_t1, (rho u)_t2, B_n, B_t1, B_t2, e). */
+int32_t bmhd_face_data(const bmhd_grid *g, const double *d_U, int32_t flux, const float *d_stats, float *d_X,
+                       float *d_F, void *stream);
+
 /* Autotuner: time every launch shape of the stage kernel (tile depth 4 or 8 cells, one workgroup per
  * tile or a persistent grid of 2 or 4 workgroups per compute unit) for n_steps steps each with `base`'s
  * other options, on the caller's buffers (they are advanced: pass scratch copies), and write `base` with
@@ -173,6 +204,33 @@ int32_t bmhd_advance(const bmhd_grid *g, double *d_U0, double *d_U1, double *d_d
  * in the order (4,0) (4,2/CU) (4,4/CU) (8,0) (8,2/CU) (8,4/CU). Blocking: synchronises `stream`. */
 int32_t bmhd_autotune(const bmhd_grid *g, double *d_U0, double *d_U1, double *d_dt, const bmhd_opts *base,
                       int32_t n_steps, bmhd_opts *best, float *h_ms, void *stream);
+
+/* ---------------------------------------------------------------------------------------------
+ * Learned flux correction: a multilayer perceptron 32 -> H -> H -> H -> 8 with SiLU activations
+ * (hidden width H in {32, 64, 128}). This component is not in the paper; it is the task's learned
+ * form. Parameters are one flat float32 vector W1[H][32], b1[H], W2[H][H], b2[H], W3[H][H], b3[H],
+ * W4[8][H], b4[8] (row-major, output index first) plus a bfloat16 copy of it (uint16 storage) that the
+ * matrix-core products read. Loss: mean over samples and the 8 outputs of the squared error.
+ * mode 0: products on BF16 matrix cores with FP32 accumulation; mode 1: FP32 FMAs (reference mode).
+ * All buffers are caller-owned device memory; calls are asynchronous on `stream`. */
+const char *bmhd_mlp_last_error(void);
+int64_t bmhd_mlp_n_params(int32_t hidden);
+/* Bytes of the scratch buffer bmhd_mlp_backward needs for n samples. */
+size_t bmhd_mlp_work_bytes(int32_t hidden, int32_t n);
+/* y[n][8] = MLP(x[n][32]); with d_save (float [3][n][H], may be NULL) the three hidden
+ * pre-activations are kept for the backward pass. */
+int32_t bmhd_mlp_forward(const float *d_params, const uint16_t *d_params_bf16, int32_t hidden, int32_t n,
+                         const float *d_x, float *d_y, float *d_save, int32_t mode, void *stream);
+/* Gradient of the loss against targets d_t[n][8] into d_grad (n_params floats, overwritten), given the
+ * forward's d_y and d_save; d_sqerr[n][8] receives the squared errors. Deterministic (no atomics). */
+int32_t bmhd_mlp_backward(const float *d_params, int32_t hidden, int32_t n, const float *d_x, const float *d_t,
+                          const float *d_save, const float *d_y, float *d_grad, float *d_sqerr, float *d_work,
+                          int32_t mode, void *stream);
+/* One Adam step (step count t >= 1) on the float32 parameters; refreshes the bfloat16 copy. */
+int32_t bmhd_mlp_adam(float *d_params, uint16_t *d_params_bf16, float *d_m, float *d_v, const float *d_grad,
+                      int64_t n_params, float lr, float b1, float b2, float eps, int32_t t, void *stream);
+/* Refresh the bfloat16 copy from the float32 parameters (round to nearest even). */
+int32_t bmhd_mlp_to_bf16(const float *d_params, uint16_t *d_params_bf16, int64_t n_params, void *stream);
 
 #ifdef __cplusplus
 }

@@ -21,7 +21,8 @@ PRECISION = {"fp64": 0, "fp32_flux": 1}
 
 EXPORTS = ["bmhd_version", "bmhd_last_error", "bmhd_grid_create", "bmhd_grid_destroy", "bmhd_grid_info_get",
            "bmhd_grid_neighbors", "bmhd_grid_upload", "bmhd_set_state", "bmhd_fill_ghosts", "bmhd_reduce_dt",
-           "bmhd_advance", "bmhd_autotune"]
+           "bmhd_advance", "bmhd_autotune", "bmhd_mlp_last_error", "bmhd_mlp_n_params", "bmhd_mlp_work_bytes",
+           "bmhd_mlp_forward", "bmhd_mlp_backward", "bmhd_mlp_adam", "bmhd_mlp_to_bf16", "bmhd_face_data"]
 
 
 class SimDesc(ctypes.Structure):
@@ -36,11 +37,18 @@ class GridDesc(ctypes.Structure):
                 ("n_sims", ctypes.c_int32), ("sims", ctypes.POINTER(SimDesc))]
 
 
+class Learned(ctypes.Structure):
+    _fields_ = [("hidden", ctypes.c_int32), ("mode", ctypes.c_int32), ("params", ctypes.c_void_p),
+                ("params_bf16", ctypes.c_void_p), ("stats", ctypes.c_void_p), ("x_buf", ctypes.c_void_p),
+                ("y_buf", ctypes.c_void_p), ("flags", ctypes.c_void_p), ("fallback_cells", ctypes.c_void_p),
+                ("tau", ctypes.c_double)]
+
+
 class Opts(ctypes.Structure):
     _fields_ = [("flux", ctypes.c_int32), ("powell", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("recompute_dt", ctypes.c_int32), ("cfl", ctypes.c_double), ("alpha", ctypes.c_double * 2),
                 ("beta", ctypes.c_double * 2), ("slab", ctypes.c_int32), ("persist_wgs", ctypes.c_int32),
-                ("use_graph", ctypes.c_int32), ("n_events", ctypes.c_int32),
+                ("use_graph", ctypes.c_int32), ("learned", ctypes.POINTER(Learned)), ("n_events", ctypes.c_int32),
                 ("events", ctypes.POINTER(ctypes.c_void_p))]
 
 
@@ -88,6 +96,22 @@ def lib():
     L.bmhd_advance.restype = i32
     L.bmhd_autotune.argtypes = [vp, vp, vp, vp, P(Opts), i32, P(Opts), P(ctypes.c_float), vp]
     L.bmhd_autotune.restype = i32
+    L.bmhd_face_data.argtypes = [vp, vp, i32, vp, vp, vp, vp]
+    L.bmhd_face_data.restype = i32
+    L.bmhd_mlp_last_error.restype = ctypes.c_char_p
+    L.bmhd_mlp_n_params.argtypes = [i32]
+    L.bmhd_mlp_n_params.restype = ctypes.c_int64
+    L.bmhd_mlp_work_bytes.argtypes = [i32, i32]
+    L.bmhd_mlp_work_bytes.restype = ctypes.c_size_t
+    L.bmhd_mlp_forward.argtypes = [vp, vp, i32, i32, vp, vp, vp, i32, vp]
+    L.bmhd_mlp_forward.restype = i32
+    L.bmhd_mlp_backward.argtypes = [vp, i32, i32, vp, vp, vp, vp, vp, vp, vp, i32, vp]
+    L.bmhd_mlp_backward.restype = i32
+    L.bmhd_mlp_adam.argtypes = [vp, vp, vp, vp, vp, ctypes.c_int64, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                                ctypes.c_float, i32, vp]
+    L.bmhd_mlp_adam.restype = i32
+    L.bmhd_mlp_to_bf16.argtypes = [vp, vp, ctypes.c_int64, vp]
+    L.bmhd_mlp_to_bf16.restype = i32
     _lib = L
     return L
 
@@ -99,7 +123,8 @@ def _check(rc):
 
 
 def make_opts(flux="rusanov", powell=False, precision="fp64", recompute_dt=True, cfl=0.8,
-              alpha=(0.0, 0.5), beta=(1.0, 0.5), slab=0, persist_wgs=0, use_graph=False, events=None) -> Opts:
+              alpha=(0.0, 0.5), beta=(1.0, 0.5), slab=0, persist_wgs=0, use_graph=False, events=None,
+              learned=None) -> Opts:
     """Options for bmhd_advance. `events`: optional list of torch.cuda.Event (enable_timing=True), two per
     stage, recorded by the library around each stage kernel."""
     o = Opts()
@@ -113,6 +138,11 @@ def make_opts(flux="rusanov", powell=False, precision="fp64", recompute_dt=True,
     o.slab = int(slab)
     o.persist_wgs = int(persist_wgs)
     o.use_graph = int(bool(use_graph))
+    if learned is not None:
+        o._learned_keepalive = learned
+        o.learned = ctypes.pointer(learned)
+    else:
+        o.learned = None
     if events:
         arr = (ctypes.c_void_p * len(events))(*[ctypes.c_void_p(e.cuda_event) for e in events])
         o._events_keepalive = arr
@@ -236,6 +266,40 @@ class Grid:
                                   _dev_ptr(dt, torch.float64), int(n_stages), ctypes.byref(o), fp,
                                   _stream_ptr(stream)))
 
+    def face_data(self, U, flux="hlle", stats=None, want_x=True, want_f=True, stream=None):
+        """Per-face stencil features [nB*1728][32] and plain fluxes [nB*1728][8] (face-normal frame)."""
+        import torch
+        nf = self.nb * 1728
+        X = torch.empty((nf, 32), dtype=torch.float32, device=U.device) if want_x else None
+        F = torch.empty((nf, 8), dtype=torch.float32, device=U.device) if want_f else None
+        _check(lib().bmhd_face_data(self.h, _dev_ptr(U, torch.float64), FLUX[flux],
+                                    _dev_ptr(stats, torch.float32) if stats is not None else None,
+                                    _dev_ptr(X) if want_x else None, _dev_ptr(F) if want_f else None,
+                                    _stream_ptr(stream)))
+        return X, F
+
+    def learned(self, mlp, stats, mode="bf16", tau=0.1, fallback=None):
+        """Scratch buffers and the options struct of the learned correction for this grid."""
+        import torch
+        nf = self.nb * 1728
+        dev = mlp.p.device
+        self._lx = torch.empty((nf, 32), dtype=torch.float32, device=dev)
+        self._ly = torch.empty((nf, 8), dtype=torch.float32, device=dev)
+        self._lf = torch.zeros(self.nb * 512, dtype=torch.uint8, device=dev)
+        self._lstats = stats.to(dev, torch.float32).contiguous()
+        L = Learned()
+        L.hidden = mlp.H
+        L.mode = MLP_MODE[mode]
+        L.params = mlp.p.data_ptr()
+        L.params_bf16 = mlp.pb.data_ptr()
+        L.stats = self._lstats.data_ptr()
+        L.x_buf = self._lx.data_ptr()
+        L.y_buf = self._ly.data_ptr()
+        L.flags = self._lf.data_ptr()
+        L.fallback_cells = fallback.data_ptr() if fallback is not None else None
+        L.tau = float(tau)
+        return L
+
     def autotune(self, U0, U1, dt, n_steps=3, stream=None, **kw):
         """Time the stage kernel's launch shapes on (scratch) buffers; returns (best Opts, {shape: ms})."""
         import torch
@@ -247,3 +311,64 @@ class Grid:
                                    ms, _stream_ptr(stream)))
         names = ["slab4", "slab4_persist2", "slab4_persist4", "slab8", "slab8_persist2", "slab8_persist4"]
         return best, dict(zip(names, list(ms)))
+
+
+# ------------------------------------------------------------------------------------------------
+# learned flux correction: MLP on matrix cores
+
+MLP_MODE = {"bf16": 0, "fp32": 1}
+
+
+def _mcheck(rc):
+    if rc != 0:
+        raise BmhdError(f"bmhd mlp error {rc}: {lib().bmhd_mlp_last_error().decode()}")
+
+
+class Mlp:
+    """Parameters (FP32 master + BF16 copy) and Adam moments of the flux-correction MLP, all torch
+    tensors on the GPU."""
+
+    def __init__(self, hidden=128, params=None, device="cuda"):
+        import torch
+        self.H = int(hidden)
+        self.n = int(lib().bmhd_mlp_n_params(self.H))
+        if params is None:
+            params = torch.zeros(self.n, dtype=torch.float32)
+        self.p = torch.as_tensor(params, dtype=torch.float32).to(device).contiguous()
+        assert self.p.numel() == self.n
+        self.pb = torch.empty(self.n, dtype=torch.int16, device=device)
+        self.m = torch.zeros_like(self.p)
+        self.v = torch.zeros_like(self.p)
+        self.t = 0
+        self.refresh()
+
+    def refresh(self, stream=None):
+        _mcheck(lib().bmhd_mlp_to_bf16(_dev_ptr(self.p), _dev_ptr(self.pb), self.n, _stream_ptr(stream)))
+
+    def forward(self, x, save=False, mode="bf16", stream=None):
+        import torch
+        n = x.shape[0]
+        y = torch.empty((n, 8), dtype=torch.float32, device=x.device)
+        z = torch.empty((3, n, self.H), dtype=torch.float32, device=x.device) if save else None
+        _mcheck(lib().bmhd_mlp_forward(_dev_ptr(self.p), _dev_ptr(self.pb), self.H, n, _dev_ptr(x, torch.float32),
+                                       _dev_ptr(y), _dev_ptr(z) if save else None, MLP_MODE[mode],
+                                       _stream_ptr(stream)))
+        return (y, z) if save else y
+
+    def loss_grad(self, x, t, mode="bf16", stream=None):
+        """Returns (loss tensor, gradient tensor) for targets t[n][8]."""
+        import torch
+        n = x.shape[0]
+        y, z = self.forward(x, save=True, mode=mode, stream=stream)
+        g = torch.empty_like(self.p)
+        sq = torch.empty((n, 8), dtype=torch.float32, device=x.device)
+        work = torch.empty(int(lib().bmhd_mlp_work_bytes(self.H, n)) // 4, dtype=torch.float32, device=x.device)
+        _mcheck(lib().bmhd_mlp_backward(_dev_ptr(self.p), self.H, n, _dev_ptr(x), _dev_ptr(t, torch.float32),
+                                        _dev_ptr(z), _dev_ptr(y), _dev_ptr(g), _dev_ptr(sq), _dev_ptr(work),
+                                        MLP_MODE[mode], _stream_ptr(stream)))
+        return sq.mean(), g
+
+    def adam(self, g, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8, stream=None):
+        self.t += 1
+        _mcheck(lib().bmhd_mlp_adam(_dev_ptr(self.p), _dev_ptr(self.pb), _dev_ptr(self.m), _dev_ptr(self.v),
+                                    _dev_ptr(g), self.n, lr, b1, b2, eps, self.t, _stream_ptr(stream)))

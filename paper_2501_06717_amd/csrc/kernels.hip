@@ -494,7 +494,33 @@ struct StageArgs {
     int use_u0;      // add alpha * U0 (second stage)
     int want_lam;    // accumulate the next dt bound
     int count_faults;
+    // learned correction (only read by the LEARN variants)
+    const float *lrn_y;      // MLP outputs per face, normalised, face-normal frame
+    const float *lrn_stats;  // in_mean[32], in_std[32], out_mean[8], out_std[8]
+    uint8_t *lrn_flags;      // per cell: provisional state rejected
+    double tau;
 };
+
+// block-local index of face (i, j, z) of direction D (see bmhd_face_data)
+template <int D>
+__device__ __forceinline__ int face_index(int i, int j, int z) {
+    return D == 0 ? (z * 8 + j) * 9 + i : (D == 1 ? (z * 9 + j) * 8 + i : (z * 8 + j) * 8 + i);
+}
+
+// learned flux increment of one face, de-normalised and rotated from the face-normal frame to x, y, z
+template <typename R, int D>
+__device__ __forceinline__ void learned_increment(const float *y, const float *stats, R dF[8]) {
+    float v[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) v[q] = y[q] * stats[72 + q] + stats[64 + q];
+    dF[0] = R(v[0]);
+    dF[7] = R(v[7]);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        dF[1 + (D + a) % 3] = R(v[1 + a]);
+        dF[4 + (D + a) % 3] = R(v[4 + a]);
+    }
+}
 
 // The thread index, laundered through an empty asm statement so that index arithmetic derived from it
 // is recomputed where it is used instead of being hoisted out of the persistent loop (where it would
@@ -505,9 +531,9 @@ __device__ __forceinline__ int lane_tid() {
     return t;
 }
 
-template <int KS, typename R, int D, int FLUX, bool BODY>
-__device__ __forceinline__ void sweep(const Tables &T, const DevBlock &B, int slab, R (*sW)[Slab<KS>::NC],
-                                      const unsigned char *sM, R (*sF)[Slab<KS>::NF]) {
+template <int KS, typename R, int D, int FLUX, bool BODY, bool LEARN>
+__device__ __forceinline__ void sweep(const Tables &T, const StageArgs &A, const DevBlock &B, int b, int slab,
+                                      R (*sW)[Slab<KS>::NC], const unsigned char *sM, R (*sF)[Slab<KS>::NF]) {
     using SL = Slab<KS>;
     constexpr int NF = D == 2 ? SL::NFZ : SL::NFX;
     const int f = lane_tid();
@@ -556,6 +582,16 @@ __device__ __forceinline__ void sweep(const Tables &T, const DevBlock &B, int sl
         }
     }
     num_flux<R, D, FLUX>(wl, wr, fl);
+    if constexpr (LEARN) {
+        // faces next to a body cell keep the plain (reflecting) flux
+        if (!(m1 || m2)) {
+            const int fb = face_index<D>(i, j, slab * KS + k);
+            R dF[8];
+            learned_increment<R, D>(A.lrn_y + (size_t(b) * 3 + D) * 4608 + size_t(fb) * 8, A.lrn_stats, dF);
+#pragma unroll
+            for (int v = 0; v < 8; ++v) fl[v] += dF[v];
+        }
+    }
     R bbar = R(0.5) * (wl[4 + D] + wr[4 + D]);
     if constexpr (BODY) {
         if (skip) {
@@ -680,7 +716,7 @@ __device__ __forceinline__ void gather_store(const Tables &T, int b, int slab, c
 }
 
 // Sweeps, source, update and end-of-step bookkeeping for one slab whose primitives are in LDS.
-template <int KS, typename R, int FLUX, bool POWELL>
+template <int KS, typename R, int FLUX, bool POWELL, bool LEARN>
 __device__ __forceinline__ void slab_compute(const Tables &T, const StageArgs &A, int b, int slab, const double (&uin)[8],
                                              R (*sW)[Slab<KS>::NC], unsigned char *sM, R (*sF)[Slab<KS>::NF],
                                              double *red, int *redi) {
@@ -696,18 +732,18 @@ __device__ __forceinline__ void slab_compute(const Tables &T, const StageArgs &A
     const double inv_dx = double(1 << B.level) / S.dx0;
     double rhs[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     double divb = 0.0;
-    if (near_body) sweep<KS, R, 0, FLUX, true>(T, B, slab, sW, sM, sF);
-    else sweep<KS, R, 0, FLUX, false>(T, B, slab, sW, sM, sF);
+    if (near_body) sweep<KS, R, 0, FLUX, true, LEARN>(T, A, B, b, slab, sW, sM, sF);
+    else sweep<KS, R, 0, FLUX, false, LEARN>(T, A, B, b, slab, sW, sM, sF);
     __syncthreads();
     if (owner) accumulate<KS, R, 0>(sF, rhs, divb, inv_dx);
     __syncthreads();
-    if (near_body) sweep<KS, R, 1, FLUX, true>(T, B, slab, sW, sM, sF);
-    else sweep<KS, R, 1, FLUX, false>(T, B, slab, sW, sM, sF);
+    if (near_body) sweep<KS, R, 1, FLUX, true, LEARN>(T, A, B, b, slab, sW, sM, sF);
+    else sweep<KS, R, 1, FLUX, false, LEARN>(T, A, B, b, slab, sW, sM, sF);
     __syncthreads();
     if (owner) accumulate<KS, R, 1>(sF, rhs, divb, inv_dx);
     __syncthreads();
-    if (near_body) sweep<KS, R, 2, FLUX, true>(T, B, slab, sW, sM, sF);
-    else sweep<KS, R, 2, FLUX, false>(T, B, slab, sW, sM, sF);
+    if (near_body) sweep<KS, R, 2, FLUX, true, LEARN>(T, A, B, b, slab, sW, sM, sF);
+    else sweep<KS, R, 2, FLUX, false, LEARN>(T, A, B, b, slab, sW, sM, sF);
     __syncthreads();
     if (owner) accumulate<KS, R, 2>(sF, rhs, divb, inv_dx);
 
@@ -745,6 +781,29 @@ __device__ __forceinline__ void slab_compute(const Tables &T, const StageArgs &A
         }
 #pragma unroll
         for (int v = 0; v < 8; ++v) A.Uout[v * vs + off] = out[v];
+        if constexpr (LEARN) {
+            // reject the provisional state if it is not positive or leaves the widened range of the old
+            // 7-point neighbourhood in density or pressure
+            bool bad = false;
+            if (!body) {
+                double w[8];
+                cons_to_prim(out, w);
+                const int i = tid & 7, j = (tid >> 3) & 7, kk = tid >> 6;
+                const int nb7[7] = {SL::idx(i, j, kk), SL::idx(i - 1, j, kk), SL::idx(i + 1, j, kk), SL::idx(i, j - 1, kk),
+                                    SL::idx(i, j + 1, kk), SL::idx(i, j, kk - 1), SL::idx(i, j, kk + 1)};
+                double rlo = 1e300, rhi = -1e300, plo = 1e300, phi = -1e300;
+#pragma unroll
+                for (int q = 0; q < 7; ++q) {
+                    const double r0 = double(sW[0][nb7[q]]), p0 = double(sW[7][nb7[q]]);
+                    rlo = fmin(rlo, r0); rhi = fmax(rhi, r0);
+                    plo = fmin(plo, p0); phi = fmax(phi, p0);
+                }
+                const double rr = A.tau * (rhi - rlo), pr = A.tau * (phi - plo);
+                bad = !(w[0] > 0.0) || !(w[7] > 0.0) || w[0] < rlo - rr || w[0] > rhi + rr || w[7] < plo - pr ||
+                      w[7] > phi + pr;
+            }
+            A.lrn_flags[off] = bad ? 1 : 0;
+        }
     }
 
     // end of a step: positivity check and the next time-step bound
@@ -781,7 +840,7 @@ __device__ __forceinline__ int xcd_count(int nwork, int x) { return (nwork >> 3)
 // gather of a slab is issued at the top of its iteration: holding the next slab's 24 values per thread
 // in registers across the flux sweeps would double the register footprint and halve occupancy, while
 // two co-resident workgroups per CU already overlap one's gather with the other's sweeps.
-template <int KS, typename R, int FLUX, bool POWELL, bool PERSIST>
+template <int KS, typename R, int FLUX, bool POWELL, bool PERSIST, bool LEARN = false>
 __global__ void __launch_bounds__(Slab<KS>::NT) k_stage(Tables T, StageArgs A) {
     using SL = Slab<KS>;
     constexpr int S_PER_BLOCK = 8 / KS;
@@ -801,7 +860,7 @@ __global__ void __launch_bounds__(Slab<KS>::NT) k_stage(Tables T, StageArgs A) {
         gather_issue<KS>(T, A, b, slab, u);
         gather_store<KS, R>(T, b, slab, u, sW, sM);
         __syncthreads();
-        slab_compute<KS, R, FLUX, POWELL>(T, A, b, slab, u[0], sW, sM, sF, red, redi);
+        slab_compute<KS, R, FLUX, POWELL, LEARN>(T, A, b, slab, u[0], sW, sM, sF, red, redi);
     } else {
         const int step = int(gridDim.x >> 3);
 #pragma nounroll
@@ -812,11 +871,169 @@ __global__ void __launch_bounds__(Slab<KS>::NT) k_stage(Tables T, StageArgs A) {
             gather_issue<KS>(T, A, b, slab, u);
             gather_store<KS, R>(T, b, slab, u, sW, sM);
             __syncthreads();
-            slab_compute<KS, R, FLUX, POWELL>(T, A, b, slab, u[0], sW, sM, sF, red, redi);
+            slab_compute<KS, R, FLUX, POWELL, LEARN>(T, A, b, slab, u[0], sW, sM, sF, red, redi);
             __syncthreads();
             // keep the scheduler from overlapping iterations (that would hold two slabs' values live)
             __builtin_amdgcn_sched_barrier(0);
         }
+    }
+}
+
+// Per-face training data of a whole block (one workgroup of 576 threads = one face per thread and
+// direction): stencil features in the face-normal frame (optionally z-scored) and the plain flux in the
+// face-normal frame, FP64 arithmetic.
+template <int FLUX>
+__global__ void __launch_bounds__(Slab<8>::NT) k_face_data(Tables T, StageArgs A, const float *__restrict__ stats,
+                                                           float *__restrict__ X, float *__restrict__ F) {
+    using SL = Slab<8>;
+    __shared__ double sW[8][SL::NC];
+    __shared__ unsigned char sM[SL::NC];
+    const int b = blockIdx.x;
+    double u[SL::NPT][8];
+    gather_issue<8>(T, A, b, 0, u);
+    gather_store<8, double>(T, b, 0, u, sW, sM);
+    __syncthreads();
+    const DevBlock &B = T.blocks[b];
+    const bool near_body = (B.flags & BF_NEAR_BODY) != 0;
+    const int f = lane_tid();
+    if (f >= 576) return;
+#pragma unroll
+    for (int D = 0; D < 3; ++D) {
+        int i, j, k;
+        if (D == 0) { i = f % 9; j = (f / 9) & 7; k = f / 72; }
+        else if (D == 1) { i = f & 7; j = (f >> 3) % 9; k = f / 72; }
+        else { i = f & 7; j = (f >> 3) & 7; k = f >> 6; }
+        int c[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int o = q - 2;
+            c[q] = D == 0 ? SL::idx(i + o, j, k) : (D == 1 ? SL::idx(i, j + o, k) : SL::idx(i, j, k + o));
+        }
+        const size_t g = (size_t(b) * 3 + D) * 576 + f;
+        if (X) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                float x[8];
+                x[0] = float(sW[0][c[q]]);
+                x[7] = float(sW[7][c[q]]);
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    x[1 + a] = float(sW[1 + (D + a) % 3][c[q]]);
+                    x[4 + a] = float(sW[4 + (D + a) % 3][c[q]]);
+                }
+#pragma unroll
+                for (int v = 0; v < 8; ++v) {
+                    const int e = q * 8 + v;
+                    X[g * 32 + e] = stats ? (x[v] - stats[e]) / stats[32 + e] : x[v];
+                }
+            }
+        }
+        if (F) {
+            double wl[8], wr[8], fl[8];
+            const bool m0 = near_body && sM[c[0]], m1 = near_body && sM[c[1]];
+            const bool m2 = near_body && sM[c[2]], m3 = near_body && sM[c[3]];
+#pragma unroll
+            for (int v = 0; v < 8; ++v) {
+                const double a = sW[v][c[0]], bb = sW[v][c[1]], cc = sW[v][c[2]], d = sW[v][c[3]];
+                const double d0 = bb - a, d1 = cc - bb, d2 = d - cc;
+                const double hl = (m0 || m2) ? 0.0 : mc_half(d0, d1), hr = (m1 || m3) ? 0.0 : mc_half(d1, d2);
+                wl[v] = bb + hl;
+                wr[v] = cc - hr;
+            }
+            if (m2 && !m1) {
+#pragma unroll
+                for (int v = 0; v < 8; ++v) wr[v] = wl[v];
+                wr[1 + D] = -wl[1 + D];
+            } else if (m1 && !m2) {
+#pragma unroll
+                for (int v = 0; v < 8; ++v) wl[v] = wr[v];
+                wl[1 + D] = -wr[1 + D];
+            }
+            if (D == 0) num_flux<double, 0, FLUX>(wl, wr, fl);
+            else if (D == 1) num_flux<double, 1, FLUX>(wl, wr, fl);
+            else num_flux<double, 2, FLUX>(wl, wr, fl);
+            if (m1 && m2) {
+#pragma unroll
+                for (int v = 0; v < 8; ++v) fl[v] = 0.0;
+            }
+            F[g * 8 + 0] = float(fl[0]);
+            F[g * 8 + 7] = float(fl[7]);
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                F[g * 8 + 1 + a] = float(fl[1 + (D + a) % 3]);
+                F[g * 8 + 4 + a] = float(fl[4 + (D + a) % 3]);
+            }
+        }
+    }
+}
+
+// Learned-correction fallback: every face with a flagged cell on either side loses its learned
+// increment on both sides (cell-centric, so each thread only writes its own cell). At the end of a step
+// it also counts non-positive cells.
+__global__ void __launch_bounds__(512) k_learn_fixup(Tables T, StageArgs A, int32_t *fallback_cells) {
+    __shared__ double red[8];
+    __shared__ int redi[8];
+    const int b = blockIdx.x, c = threadIdx.x;
+    const DevBlock &B = T.blocks[b];
+    const DevSim &S = T.sims[B.sim];
+    const size_t vs = size_t(T.nb) * 512, off = size_t(b) * 512 + c;
+    const int ii[3] = {c & 7, (c >> 3) & 7, c >> 6};
+    const bool near_body = (B.flags & BF_NEAR_BODY) != 0;
+    const bool body = near_body && in_body(S, B.level, B.ijk, ii[0], ii[1], ii[2]);
+    const bool self = A.lrn_flags[off] != 0;
+    double u[8];
+#pragma unroll
+    for (int v = 0; v < 8; ++v) u[v] = A.Uout[v * vs + off];
+    bool changed = false;
+    if (!body) {
+        const double bdt = A.beta * A.dt[B.sim], inv_dx = double(1 << B.level) / S.dx0;
+#pragma unroll
+        for (int fd = 0; fd < 6; ++fd) {
+            const int a = fd >> 1, side = fd & 1;
+            int nn[3] = {ii[0], ii[1], ii[2]};
+            nn[a] += side ? 1 : -1;
+            int nblk = b;
+            if (nn[a] < 0 || nn[a] > 7) {
+                nblk = B.face[fd];
+                nn[a] &= 7;
+            }
+            bool other = false, nbody = false;
+            if (nblk >= 0) {
+                const DevBlock &NB = T.blocks[nblk];
+                other = A.lrn_flags[size_t(nblk) * 512 + (nn[2] * 8 + nn[1]) * 8 + nn[0]] != 0;
+                nbody = (NB.flags & BF_NEAR_BODY) && in_body(S, NB.level, NB.ijk, nn[0], nn[1], nn[2]);
+            }
+            if (nbody || !(self || other)) continue;
+            int fi[3] = {ii[0], ii[1], ii[2]};
+            fi[a] += side;  // face index along a: the cell's own index (minus face) or one more (plus face)
+            const int fb = a == 0 ? face_index<0>(fi[0], fi[1], fi[2])
+                                  : (a == 1 ? face_index<1>(fi[0], fi[1], fi[2]) : face_index<2>(fi[0], fi[1], fi[2]));
+            const float *y = A.lrn_y + (size_t(b) * 3 + a) * 4608 + size_t(fb) * 8;
+            double dF[8];
+            if (a == 0) learned_increment<double, 0>(y, A.lrn_stats, dF);
+            else if (a == 1) learned_increment<double, 1>(y, A.lrn_stats, dF);
+            else learned_increment<double, 2>(y, A.lrn_stats, dF);
+            const double sg = side ? 1.0 : -1.0;
+#pragma unroll
+            for (int v = 0; v < 8; ++v) u[v] += bdt * sg * dF[v] * inv_dx;
+            changed = true;
+        }
+        if (changed) {
+#pragma unroll
+            for (int v = 0; v < 8; ++v) A.Uout[v * vs + off] = u[v];
+        }
+    }
+    int nf = 0;
+    if (A.count_faults && !body) {
+        double w[8];
+        cons_to_prim(u, w);
+        nf = !(w[0] > 0.0) || !(w[7] > 0.0) || !(w[7] < INFINITY);
+    }
+    block_publish<512>(0.0, nf, red, redi, nullptr, A.faults);
+    if (fallback_cells) {
+        // reuse the reduction for the flagged-cell count
+        __syncthreads();
+        block_publish<512>(0.0, self ? 1 : 0, red, redi, nullptr, fallback_cells);
     }
 }
 
@@ -945,22 +1162,50 @@ int32_t launch_stage(const HostGrid &h, const StageArgs &a, const bmhd_opts &o, 
     return launch_stage_prec<8, float>(h, a, o.flux, o.powell, sh.persist_wgs, s);
 }
 
+template <typename R, int FLUX>
+int32_t launch_learn_flux(const HostGrid &h, const StageArgs &a, bool powell, hipStream_t s) {
+    constexpr int nt = Slab<4>::NT;
+    if (powell) k_stage<4, R, FLUX, true, false, true><<<h.nb * 2, nt, 0, s>>>(h.dev, a);
+    else k_stage<4, R, FLUX, false, false, true><<<h.nb * 2, nt, 0, s>>>(h.dev, a);
+    return launch_check("learned stage kernel");
+}
+
+int32_t launch_learn(const HostGrid &h, const StageArgs &a, const bmhd_opts &o, hipStream_t s) {
+    if (o.precision == BMHD_FP64) {
+        if (o.flux == BMHD_FLUX_RUSANOV) return launch_learn_flux<double, BMHD_FLUX_RUSANOV>(h, a, o.powell, s);
+        return launch_learn_flux<double, BMHD_FLUX_HLLE>(h, a, o.powell, s);
+    }
+    if (o.flux == BMHD_FLUX_RUSANOV) return launch_learn_flux<float, BMHD_FLUX_RUSANOV>(h, a, o.powell, s);
+    return launch_learn_flux<float, BMHD_FLUX_HLLE>(h, a, o.powell, s);
+}
+
 int32_t check_opts(const bmhd_opts &o) {
     if (o.flux != BMHD_FLUX_RUSANOV && o.flux != BMHD_FLUX_HLLE) return fail(BMHD_EINVAL, "unknown flux");
     if (o.precision != BMHD_FP64 && o.precision != BMHD_FP32_FLUX) return fail(BMHD_EINVAL, "unknown precision");
     if (o.slab != 0 && o.slab != 4 && o.slab != 8) return fail(BMHD_EINVAL, "slab must be 0, 4 or 8");
     if (o.persist_wgs < 0 || o.persist_wgs > (1 << 20)) return fail(BMHD_EINVAL, "persist_wgs out of range");
     if (o.recompute_dt && !(o.cfl > 0.0)) return fail(BMHD_EINVAL, "cfl must be positive");
+    if (o.learned) {
+        const bmhd_learned &L = *o.learned;
+        if (L.hidden != 32 && L.hidden != 64 && L.hidden != 128) return fail(BMHD_EINVAL, "learned: hidden must be 32, 64 or 128");
+        if (L.mode != 0 && L.mode != 1) return fail(BMHD_EINVAL, "learned: mode must be 0 or 1");
+        if (!L.params || !L.params_bf16 || !L.stats || !L.x_buf || !L.y_buf || !L.flags)
+            return fail(BMHD_EINVAL, "learned: null buffer");
+        if (!(L.tau >= 0.0)) return fail(BMHD_EINVAL, "learned: tau must be >= 0");
+        if (o.use_graph) return fail(BMHD_EUNSUPPORTED, "learned correction is not captured in graphs");
+    }
     return BMHD_OK;
 }
 
 // One stage: level-change halos, the stage kernel (optionally bracketed by events), flux correction.
+// With the learned correction: face features, the MLP, the corrected stage, and the fallback.
 int32_t enqueue_stage(const HostGrid &h, const bmhd_opts &o, int e, double *d_U0, double *d_U1, double *d_dt,
                       int32_t *d_faults, bool want_lam, void *ev0, void *ev1, hipStream_t s) {
     const double *in = e ? d_U1 : d_U0;
     double *out = e ? d_U0 : d_U1;
     if (!h.halo_items.empty()) k_halo_fill<<<unsigned(h.halo_items.size()), 128, 0, s>>>(h.dev, in);
     StageArgs a;
+    std::memset(&a, 0, sizeof a);
     a.Uin = in;
     a.U0 = d_U0;
     a.Uout = out;
@@ -971,6 +1216,29 @@ int32_t enqueue_stage(const HostGrid &h, const bmhd_opts &o, int e, double *d_U0
     a.use_u0 = o.alpha[e] != 0.0 ? 1 : 0;
     a.want_lam = want_lam ? 1 : 0;
     a.count_faults = (e == 1 && d_faults) ? 1 : 0;
+    if (o.learned) {
+        const bmhd_learned &L = *o.learned;
+        a.lrn_y = L.y_buf;
+        a.lrn_stats = L.stats;
+        a.lrn_flags = L.flags;
+        a.tau = L.tau;
+        a.want_lam = 0;
+        const int count = a.count_faults;
+        a.count_faults = 0;
+        k_face_data<BMHD_FLUX_HLLE><<<h.nb, Slab<8>::NT, 0, s>>>(h.dev, a, L.stats, L.x_buf, nullptr);
+        if (int32_t rc = launch_check("face features")) return rc;
+        if (int32_t rc = bmhd_mlp_forward(L.params, L.params_bf16, L.hidden, h.nb * 1728, L.x_buf, L.y_buf, nullptr,
+                                          L.mode, s))
+            return fail(rc, bmhd_mlp_last_error());
+        if (ev0)
+            if (int32_t rc = hip_check(hipEventRecord(reinterpret_cast<hipEvent_t>(ev0), s), "event")) return rc;
+        if (int32_t rc = launch_learn(h, a, o, s)) return rc;
+        if (ev1)
+            if (int32_t rc = hip_check(hipEventRecord(reinterpret_cast<hipEvent_t>(ev1), s), "event")) return rc;
+        a.count_faults = count;
+        k_learn_fixup<<<h.nb, 512, 0, s>>>(h.dev, a, L.fallback_cells);
+        return launch_check("learned fallback");
+    }
     if (ev0)
         if (int32_t rc = hip_check(hipEventRecord(reinterpret_cast<hipEvent_t>(ev0), s), "event")) return rc;
     if (int32_t rc = launch_stage(h, a, o, s)) return rc;
@@ -1151,6 +1419,10 @@ int32_t bmhd_advance(const bmhd_grid *g, double *d_U0, double *d_U1, double *d_d
     if (int32_t rc = check_opts(o)) return rc;
     if (o.use_graph && (n_stages & 1)) return fail(BMHD_EINVAL, "use_graph needs whole steps (even n_stages)");
     HostGrid &h = const_cast<bmhd_grid *>(g)->h;
+    if (o.learned && !h.halo_items.empty())
+        return fail(BMHD_EUNSUPPORTED, "the learned correction needs a single-level grid");
+    // the fused next-dt bound is taken before the learned fallback, so the learned form reduces dt anew
+    const bool fused_dt = !o.learned;
     if (h.nb == 0 || n_stages == 0) return BMHD_OK;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     const int n_steps = (n_stages + 1) / 2;
@@ -1163,14 +1435,14 @@ int32_t bmhd_advance(const bmhd_grid *g, double *d_U0, double *d_U1, double *d_d
             if (st >= n_stages) break;
             if (e == 0 && o.recompute_dt) {
                 const int sb = (h.ns + 63) / 64;
-                if (st == 0) {
+                if (st == 0 || !fused_dt) {
                     k_lam_reset<<<sb, 64, 0, s>>>(h.dev);
                     k_dt_reduce<<<h.nb, 512, 0, s>>>(h.dev, d_U0);
                 }
                 k_dt_finalize<<<sb, 64, 0, s>>>(h.dev, o.cfl, d_dt);
             }
             void *ev0 = timed ? o.events[2 * st] : nullptr, *ev1 = timed ? o.events[2 * st + 1] : nullptr;
-            const bool want_lam = e == 1 && o.recompute_dt && st + 1 < n_stages;
+            const bool want_lam = fused_dt && e == 1 && o.recompute_dt && st + 1 < n_stages;
             if (int32_t rc = enqueue_stage(h, o, e, d_U0, d_U1, d_dt, d_faults, want_lam, ev0, ev1, s)) return rc;
         }
     }
@@ -1181,6 +1453,23 @@ int32_t bmhd_advance(const bmhd_grid *g, double *d_U0, double *d_U1, double *d_d
             if (int32_t rc = hip_check(hipGraphLaunch(ex, s), "graph launch")) return rc;
     }
     return launch_check("advance");
+}
+
+int32_t bmhd_face_data(const bmhd_grid *g, const double *d_U, int32_t flux, const float *d_stats, float *d_X,
+                       float *d_F, void *stream) {
+    if (int32_t rc = need_upload(g)) return rc;
+    if (!ptr_ok(d_U) || (!d_X && !d_F)) return fail(BMHD_EINVAL, "face_data: bad pointers");
+    if (flux != BMHD_FLUX_RUSANOV && flux != BMHD_FLUX_HLLE) return fail(BMHD_EINVAL, "unknown flux");
+    const HostGrid &h = g->h;
+    if (!h.halo_items.empty()) return fail(BMHD_EUNSUPPORTED, "face_data needs a single-level grid");
+    if (h.nb == 0) return BMHD_OK;
+    StageArgs a;
+    std::memset(&a, 0, sizeof a);
+    a.Uin = d_U;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    if (flux == BMHD_FLUX_RUSANOV) k_face_data<BMHD_FLUX_RUSANOV><<<h.nb, Slab<8>::NT, 0, s>>>(h.dev, a, d_stats, d_X, d_F);
+    else k_face_data<BMHD_FLUX_HLLE><<<h.nb, Slab<8>::NT, 0, s>>>(h.dev, a, d_stats, d_X, d_F);
+    return launch_check("face_data");
 }
 
 int32_t bmhd_autotune(const bmhd_grid *g, double *d_U0, double *d_U1, double *d_dt, const bmhd_opts *base,

@@ -1,0 +1,376 @@
+// mlp.hip -- the small MLP of the learned flux correction on CDNA4 matrix cores.
+//
+// Network: 32 inputs -> H -> H -> H (SiLU) -> 8 outputs, parameters as one flat vector
+// W1[H][32], b1[H], W2[H][H], b2[H], W3[H][H], b3[H], W4[8][H], b4[8] (weights row-major, output first).
+// The products run on v_mfma_f32_16x16x32_bf16: BF16 operands (weights from a BF16 copy of the FP32
+// master parameters, activations rounded to BF16), FP32 accumulation; biases, SiLU and every reduction
+// stay in FP32. A second mode evaluates the same products with FP32 FMAs (used to check gradients
+// against a float64 reference to FP32 accuracy).
+//
+// MFMA 16x16x32 operand layout (wave of 64 lanes, lane l, q = l / 16, r = l % 16):
+//   A (16 x 32, rows m, cols k): lane holds A[r][8q .. 8q+7]
+//   B (32 x 16, rows k, cols n): lane holds B[8q .. 8q+7][r]
+//   C/D (16 x 16):               lane holds D[4q .. 4q+3][r]
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <type_traits>
+
+#include "bmhd_internal.h"
+
+namespace bmhd {
+
+typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
+typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4;
+
+constexpr int MLP_IN = 32;
+constexpr int MLP_OUT = 8;
+
+struct MlpView {
+    int H;
+    long off_w[4], off_b[4];
+    int nin[4], nout[4];
+};
+
+__host__ __device__ inline MlpView mlp_view(int H) {
+    MlpView v;
+    v.H = H;
+    const int in[4] = {MLP_IN, H, H, H}, out[4] = {H, H, H, MLP_OUT};
+    long o = 0;
+    for (int l = 0; l < 4; ++l) {
+        v.nin[l] = in[l];
+        v.nout[l] = out[l];
+        v.off_w[l] = o;
+        o += long(out[l]) * in[l];
+        v.off_b[l] = o;
+        o += out[l];
+    }
+    return v;
+}
+
+__host__ __device__ inline long mlp_params(int H) {
+    return long(H) * MLP_IN + H + 2L * (long(H) * H + H) + long(MLP_OUT) * H + MLP_OUT;
+}
+
+__device__ __forceinline__ float silu(float z) { return z / (1.0f + __expf(-z)); }
+__device__ __forceinline__ float silu_grad(float z) {
+    const float s = 1.0f / (1.0f + __expf(-z));
+    return s * (1.0f + z * (1.0f - s));
+}
+
+// ------------------------------------------------------------------------------------------------
+// fused forward: one wave per tile of 16 samples, activations of the tile in LDS (BF16 for the
+// MFMA mode, FP32 for the FP32 mode), weights read from L2.
+
+template <int H, bool MFMA>
+struct FwdLds {
+    using T = typename std::conditional<MFMA, __bf16, float>::type;
+    static constexpr int PAD = MFMA ? 8 : 1;  // row padding against bank conflicts
+    static constexpr int LD = H + PAD;
+};
+
+template <int H, bool MFMA>
+__global__ void __launch_bounds__(256) k_mlp_forward(const float *__restrict__ P, const __bf16 *__restrict__ Pb, int n,
+                                                     const float *__restrict__ X, float *__restrict__ Y,
+                                                     float *__restrict__ Zsave) {
+    using L = FwdLds<H, MFMA>;
+    using T = typename L::T;
+    __shared__ T act[4][16 * L::LD];
+    const MlpView V = mlp_view(H);
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, q = lane >> 4, r = lane & 15;
+    const int tile = blockIdx.x * 4 + wave;
+    const int s0 = tile * 16;  // waves past the end still take part in the barriers
+    T *a = act[wave];
+    // stage the 16 x 32 input tile (rows beyond n are zero)
+    for (int e = lane; e < 16 * MLP_IN; e += 64) {
+        const int m = e / MLP_IN, k = e % MLP_IN;
+        const float x = (s0 + m < n) ? X[size_t(s0 + m) * MLP_IN + k] : 0.0f;
+        a[m * L::LD + k] = T(x);
+    }
+    __syncthreads();
+    for (int l = 0; l < 4; ++l) {
+        const int nin = V.nin[l], nout = V.nout[l];
+        const int ntile = (nout + 15) / 16;
+        float outv[H / 16][4];
+        for (int nt = 0; nt < ntile; ++nt) {
+            const int o = nt * 16 + r;  // output column this lane's B operand and results belong to
+            f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+            if constexpr (MFMA) {
+                for (int k0 = 0; k0 < nin; k0 += 32) {
+                    bf16x8 av, bv;
+#pragma unroll
+                    for (int j = 0; j < 8; ++j) {
+                        av[j] = a[r * L::LD + k0 + 8 * q + j];
+                        bv[j] = (o < nout) ? Pb[V.off_w[l] + long(o) * nin + k0 + 8 * q + j] : __bf16(0.0f);
+                    }
+                    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc, 0, 0, 0);
+                }
+            } else {
+                // same output layout, plain FP32 products
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int m = 4 * q + i;
+                    float s = 0.f;
+                    if (o < nout)
+                        for (int k = 0; k < nin; ++k) s = fmaf(float(a[m * L::LD + k]), P[V.off_w[l] + long(o) * nin + k], s);
+                    acc[i] = s;
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < 4; ++i) outv[nt][i] = acc[i];
+        }
+        __syncthreads();  // every lane has read this layer's input
+        for (int nt = 0; nt < ntile; ++nt) {
+            const int o = nt * 16 + r;
+            if (o >= nout) continue;
+            const float bias = P[V.off_b[l] + o];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int m = 4 * q + i;
+                const float z = outv[nt][i] + bias;
+                if (s0 + m >= n) continue;
+                if (l < 3) {
+                    if (Zsave) Zsave[(size_t(l) * n + s0 + m) * H + o] = z;
+                    a[m * L::LD + o] = T(silu(z));
+                } else {
+                    Y[size_t(s0 + m) * MLP_OUT + o] = z;
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// ------------------------------------------------------------------------------------------------
+// generic product for the backward pass: C[M x N] = A[M x K] B[K x N] (+ C when ACC), element (m, k)
+// of A at A[m * am + k * ak], element (k, n) of B at B[k * bk + n * bn]; rows/cols/k beyond the sizes
+// read as 0. One wave per 16 x 16 tile of C.
+
+template <bool MFMA, bool ACC>
+__global__ void __launch_bounds__(256) k_gemm(int M, int N, int K, const float *__restrict__ A, long am, long ak,
+                                              const float *__restrict__ B, long bk, long bn, float *__restrict__ C,
+                                              long ldc) {
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, q = lane >> 4, r = lane & 15;
+    const int tiles_n = (N + 15) / 16;
+    const int t = blockIdx.x * 4 + wave;
+    const int tm = t / tiles_n, tn = t % tiles_n;
+    if (tm * 16 >= M) return;
+    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+    const int mrow = tm * 16 + r, ncol = tn * 16 + r;
+    if constexpr (MFMA) {
+        for (int k0 = 0; k0 < K; k0 += 32) {
+            bf16x8 av, bv;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const int k = k0 + 8 * q + j;
+                av[j] = __bf16((mrow < M && k < K) ? A[mrow * am + k * ak] : 0.0f);
+                bv[j] = __bf16((ncol < N && k < K) ? B[k * bk + ncol * bn] : 0.0f);
+            }
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc, 0, 0, 0);
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int m = tm * 16 + 4 * q + i;
+            float s = 0.f;
+            if (m < M && ncol < N)
+                for (int k = 0; k < K; ++k) s = fmaf(A[m * am + k * ak], B[k * bk + ncol * bn], s);
+            acc[i] = s;
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int m = tm * 16 + 4 * q + i;
+        if (m < M && ncol < N) {
+            float *c = C + m * ldc + ncol;
+            *c = ACC ? *c + acc[i] : acc[i];
+        }
+    }
+}
+
+// dY = 2 (Y - T) / (8 n); also the per-sample squared error (for the loss)
+__global__ void k_loss_grad(int n, const float *__restrict__ Y, const float *__restrict__ Tt, float *__restrict__ dY,
+                            float *__restrict__ sqerr) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n * MLP_OUT) return;
+    const float d = Y[i] - Tt[i];
+    dY[i] = 2.0f * d / (8.0f * float(n));
+    sqerr[i] = d * d;
+}
+
+// dZ = dA * silu'(Z), elementwise over n x H
+__global__ void k_silu_back(long count, const float *__restrict__ dA, const float *__restrict__ Z, float *__restrict__ dZ) {
+    const long i = long(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < count) dZ[i] = dA[i] * silu_grad(Z[i]);
+}
+
+// A = silu(Z), elementwise
+__global__ void k_silu(long count, const float *__restrict__ Z, float *__restrict__ A) {
+    const long i = long(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < count) A[i] = silu(Z[i]);
+}
+
+// column sums of G[n][cols] into out[cols] (one thread per column, fixed order: deterministic)
+__global__ void k_colsum(int n, int cols, const float *__restrict__ G, float *__restrict__ out) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= cols) return;
+    float s = 0.f;
+    for (int i = 0; i < n; ++i) s += G[size_t(i) * cols + c];
+    out[c] = s;
+}
+
+// Adam on the FP32 master vector; refreshes the BF16 copy
+__global__ void k_adam(long np, float *__restrict__ p, __bf16 *__restrict__ pb, float *__restrict__ m, float *__restrict__ v,
+                       const float *__restrict__ g, float lr, float b1, float b2, float eps, float c1, float c2) {
+    const long i = long(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= np) return;
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.0f - b1) * gi;
+    const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    const float pi = p[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+    p[i] = pi;
+    pb[i] = __bf16(pi);
+}
+
+__global__ void k_to_bf16(long np, const float *__restrict__ p, __bf16 *__restrict__ pb) {
+    const long i = long(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < np) pb[i] = __bf16(p[i]);
+}
+
+}  // namespace bmhd
+
+// ================================================================================================
+// C ABI
+
+using namespace bmhd;
+
+namespace {
+thread_local std::string m_err;
+int32_t mfail(int32_t code, const char *msg) {
+    m_err = msg;
+    return code;
+}
+int32_t mcheck(const char *what) {
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) return BMHD_OK;
+    m_err = std::string(what) + ": " + hipGetErrorString(e);
+    return BMHD_EHIP;
+}
+unsigned blocks_for(long n, int t) { return unsigned((n + t - 1) / t); }
+
+template <bool MFMA>
+void gemm(int M, int N, int K, const float *A, long am, long ak, const float *B, long bk, long bn, float *C, long ldc,
+          bool acc, hipStream_t s) {
+    const long tiles = long((M + 15) / 16) * ((N + 15) / 16);
+    if (acc) k_gemm<MFMA, true><<<blocks_for(tiles, 4), 256, 0, s>>>(M, N, K, A, am, ak, B, bk, bn, C, ldc);
+    else k_gemm<MFMA, false><<<blocks_for(tiles, 4), 256, 0, s>>>(M, N, K, A, am, ak, B, bk, bn, C, ldc);
+}
+
+template <int H>
+int32_t forward_h(const float *P, const uint16_t *Pb, int n, const float *X, float *Y, float *Z, int mode, hipStream_t s) {
+    const unsigned grid = blocks_for((n + 15) / 16, 4);
+    const __bf16 *pb = reinterpret_cast<const __bf16 *>(Pb);
+    if (mode == 0) k_mlp_forward<H, true><<<grid, 256, 0, s>>>(P, pb, n, X, Y, Z);
+    else k_mlp_forward<H, false><<<grid, 256, 0, s>>>(P, pb, n, X, Y, Z);
+    return mcheck("mlp forward");
+}
+}  // namespace
+
+extern "C" {
+
+const char *bmhd_mlp_last_error(void) { return m_err.c_str(); }
+
+int64_t bmhd_mlp_n_params(int32_t hidden) { return mlp_params(hidden); }
+
+size_t bmhd_mlp_work_bytes(int32_t hidden, int32_t n) {
+    // dY, squared errors [n][8]; two [n][H] gradient buffers
+    return sizeof(float) * (size_t(n) * 16 + 2 * size_t(n) * hidden);
+}
+
+int32_t bmhd_mlp_forward(const float *d_params, const uint16_t *d_params_bf16, int32_t hidden, int32_t n,
+                         const float *d_x, float *d_y, float *d_save, int32_t mode, void *stream) {
+    if (!d_params || !d_params_bf16 || !d_x || !d_y || n < 0 || (mode != 0 && mode != 1))
+        return mfail(BMHD_EINVAL, "mlp_forward: bad arguments");
+    if (n == 0) return BMHD_OK;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    switch (hidden) {
+        case 32: return forward_h<32>(d_params, d_params_bf16, n, d_x, d_y, d_save, mode, s);
+        case 64: return forward_h<64>(d_params, d_params_bf16, n, d_x, d_y, d_save, mode, s);
+        case 128: return forward_h<128>(d_params, d_params_bf16, n, d_x, d_y, d_save, mode, s);
+        default: return mfail(BMHD_EUNSUPPORTED, "mlp_forward: hidden must be 32, 64 or 128");
+    }
+}
+
+int32_t bmhd_mlp_backward(const float *d_params, int32_t hidden, int32_t n, const float *d_x, const float *d_t,
+                          const float *d_save, const float *d_y, float *d_grad, float *d_sqerr, float *d_work,
+                          int32_t mode, void *stream) {
+    if (!d_params || !d_x || !d_t || !d_save || !d_y || !d_grad || !d_sqerr || !d_work || n <= 0 ||
+        (mode != 0 && mode != 1))
+        return mfail(BMHD_EINVAL, "mlp_backward: bad arguments");
+    if (hidden != 32 && hidden != 64 && hidden != 128) return mfail(BMHD_EUNSUPPORTED, "hidden must be 32, 64 or 128");
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    const int H = hidden;
+    const MlpView V = mlp_view(H);
+    float *dY = d_work;                                  // [n][8]
+    float *bufA = d_work + size_t(n) * 16;               // [n][H]
+    float *bufB = bufA + size_t(n) * H;                  // [n][H]
+    const bool mf = mode == 0;
+    auto G = [&](int M, int N, int K, const float *A, long am, long ak, const float *B, long bk, long bn, float *C,
+                 long ldc) {
+        if (mf) gemm<true>(M, N, K, A, am, ak, B, bk, bn, C, ldc, false, s);
+        else gemm<false>(M, N, K, A, am, ak, B, bk, bn, C, ldc, false, s);
+    };
+    k_loss_grad<<<blocks_for(long(n) * 8, 256), 256, 0, s>>>(n, d_y, d_t, dY, d_sqerr);
+    // layer 4: dW4[o][i] = sum_n dY[n][o] A3[n][i], db4 = sum_n dY, dA3 = dY W4
+    float *A3 = bufB;
+    k_silu<<<blocks_for(long(n) * H, 256), 256, 0, s>>>(long(n) * H, d_save + size_t(2) * n * H, A3);
+    G(8, H, n, dY, 1, 8, A3, H, 1, d_grad + V.off_w[3], H);
+    k_colsum<<<1, 64, 0, s>>>(n, 8, dY, d_grad + V.off_b[3]);
+    float *dA = bufA, *other = bufB;
+    G(n, H, 8, dY, 8, 1, d_params + V.off_w[3], H, 1, dA, H);
+    // hidden layers 3, 2, 1 (index l = 2, 1, 0)
+    for (int l = 2; l >= 0; --l) {
+        const float *Z = d_save + size_t(l) * n * H;
+        float *dZ = dA;  // in place: dZ overwrites dA
+        k_silu_back<<<blocks_for(long(n) * H, 256), 256, 0, s>>>(long(n) * H, dA, Z, dZ);
+        const int nin = V.nin[l];
+        if (l > 0) {
+            float *Ain = other;
+            k_silu<<<blocks_for(long(n) * H, 256), 256, 0, s>>>(long(n) * H, d_save + size_t(l - 1) * n * H, Ain);
+            G(H, nin, n, dZ, 1, H, Ain, H, 1, d_grad + V.off_w[l], nin);
+        } else {
+            G(H, nin, n, dZ, 1, H, d_x, MLP_IN, 1, d_grad + V.off_w[l], nin);
+        }
+        k_colsum<<<blocks_for(H, 64), 64, 0, s>>>(n, H, dZ, d_grad + V.off_b[l]);
+        if (l > 0) {
+            // dA_{l-1}[n][i] = sum_o dZ[n][o] W_l[o][i], into the buffer the inputs no longer need
+            G(n, nin, H, dZ, H, 1, d_params + V.off_w[l], nin, 1, other, nin);
+            float *t = dA;
+            dA = other;
+            other = t;
+        }
+    }
+    return mcheck("mlp backward");
+}
+
+int32_t bmhd_mlp_adam(float *d_params, uint16_t *d_params_bf16, float *d_m, float *d_v, const float *d_grad,
+                      int64_t n_params, float lr, float b1, float b2, float eps, int32_t t, void *stream) {
+    if (!d_params || !d_params_bf16 || !d_m || !d_v || !d_grad || n_params <= 0 || t < 1)
+        return mfail(BMHD_EINVAL, "mlp_adam: bad arguments");
+    const float c1 = 1.0f - powf(b1, float(t)), c2 = 1.0f - powf(b2, float(t));
+    k_adam<<<blocks_for(n_params, 256), 256, 0, reinterpret_cast<hipStream_t>(stream)>>>(
+        n_params, d_params, reinterpret_cast<__bf16 *>(d_params_bf16), d_m, d_v, d_grad, lr, b1, b2, eps, c1, c2);
+    return mcheck("mlp adam");
+}
+
+int32_t bmhd_mlp_to_bf16(const float *d_params, uint16_t *d_params_bf16, int64_t n_params, void *stream) {
+    if (!d_params || !d_params_bf16 || n_params <= 0) return mfail(BMHD_EINVAL, "mlp_to_bf16: bad arguments");
+    k_to_bf16<<<blocks_for(n_params, 256), 256, 0, reinterpret_cast<hipStream_t>(stream)>>>(
+        n_params, d_params, reinterpret_cast<__bf16 *>(d_params_bf16));
+    return mcheck("mlp to bf16");
+}
+
+}  // extern "C"

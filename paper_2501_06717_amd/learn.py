@@ -1,0 +1,295 @@
+"""Learned flux correction for coarse magnetosphere grids: data, training and evaluation.
+
+The network corrects the plain HLLE flux of a coarse grid (128^3 cells, dx = 2) toward the flux a grid
+twice as fine would put through the same face. Training data come from plain FP64 runs on the fine
+grid (256^3, dx = 1) of solar-wind states drawn at random:
+
+* every `snap_every` fine steps, the fine state is restricted to the coarse grid (mean of the 8 fine
+  cells); the target of a coarse face is the mean of the 4 fine face fluxes covering it minus the plain
+  HLLE flux of the restricted coarse state, both in the face-normal frame;
+* the inputs are the 4-cell stencils of coarse primitives in the face-normal frame;
+* per snapshot and direction, half the sampled faces are uniform and half come from the top decile of
+  the target magnitude; inputs and targets are z-scored with training-set statistics.
+
+Training and inference run in the library's kernels (BF16 matrix cores, FP32 master weights, Adam).
+Data preparation (restriction, face averaging, sampling, statistics) uses torch tensor operations on
+the GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import dataclasses
+import json
+import math
+import sys
+import time
+
+import numpy as np
+
+from . import workloads as wk
+
+GAMMA = 5.0 / 3.0
+
+
+def solar_wind_states(n, seed):
+    """Random solar-wind states: rho ~ U[1, 20], speed ~ U[300, 800] along -x, Bz ~ U[-10, 10]; pressure
+    from sonic Mach 8."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(n):
+        rho = rng.uniform(1.0, 20.0)
+        speed = rng.uniform(300.0, 800.0)
+        bz = rng.uniform(-10.0, 10.0)
+        out.append(dict(rho=rho, ux=-speed, bz=bz))
+    return out
+
+
+def magnetosphere_pair(state, n_fine=256, M=7.9e4):
+    """Fine (n_fine^3, dx = 1) and coarse (n_fine/2)^3 (dx = 2) workloads of one solar-wind state."""
+    fine = wk.magnetosphere(n_fine, M=M, **state)
+    sim_c = wk.magnetosphere_sim(n_fine // 2, **state)
+    lv, ijk, sid = wk.uniform_blocks(sim_c.nroot)
+    coarse = wk.Workload(f"coarse_{n_fine // 2}", lv, ijk, sid, [sim_c], wk.magnetosphere_state(sim_c, lv, ijk, M),
+                         flux="hlle", powell=True, cfl=0.8)
+    return fine, coarse
+
+
+# --------------------------------------------------------------------------------------------------
+# global arrays from per-block data
+
+def to_global(U, nb):
+    """[8, nb^3 blocks (i fastest), 8, 8, 8] -> [8, N, N, N] (z, y, x)."""
+    v = U.shape[0]
+    t = U.reshape(v, nb, nb, nb, 8, 8, 8)           # (bz, by, bx, k, j, i)
+    return t.permute(0, 1, 4, 2, 5, 3, 6).reshape(v, nb * 8, nb * 8, nb * 8)
+
+
+def from_global(G, nb):
+    v = G.shape[0]
+    t = G.reshape(v, nb, 8, nb, 8, nb, 8)           # (bz, k, by, j, bx, i)
+    return t.permute(0, 1, 3, 5, 2, 4, 6).reshape(v, nb ** 3, 8, 8, 8).contiguous()
+
+
+def restrict(Uf, nbf):
+    """Mean of the 8 fine cells of each coarse cell (conserved variables)."""
+    G = to_global(Uf, nbf)
+    n = G.shape[1] // 2
+    Gc = G.reshape(8, n, 2, n, 2, n, 2).mean(dim=(2, 4, 6))
+    return from_global(Gc, nbf // 2)
+
+
+def faces_global(F, nb, d, c):
+    """Per-block face data [nb^3 * 3 * 576, c] -> global faces of direction d: [c, Nz', Ny', Nx'] with
+    N + 1 positions along d."""
+    import torch
+    N = nb * 8
+    t = F.reshape(nb, nb, nb, 3, 576, c)[:, :, :, d]        # (bz, by, bx, f, c)
+    if d == 0:
+        t = t.reshape(nb, nb, nb, 8, 8, 9, c)               # (bz, by, bx, z, y, x)
+        body = t[..., :8, :].permute(6, 0, 3, 1, 4, 2, 5).reshape(c, N, N, N)
+        last = t[:, :, -1, :, :, 8, :].permute(4, 0, 2, 1, 3).reshape(c, N, N, 1)
+        return torch.cat([body, last], dim=3)
+    if d == 1:
+        t = t.reshape(nb, nb, nb, 8, 9, 8, c)
+        body = t[:, :, :, :, :8].permute(6, 0, 3, 1, 4, 2, 5).reshape(c, N, N, N)
+        last = t[:, -1, :, :, 8, :, :].permute(4, 0, 2, 1, 3).reshape(c, N, 1, N)
+        return torch.cat([body, last], dim=2)
+    t = t.reshape(nb, nb, nb, 9, 8, 8, c)
+    body = t[:, :, :, :8].permute(6, 0, 3, 1, 4, 2, 5).reshape(c, N, N, N)
+    last = t[-1, :, :, 8].permute(4, 0, 2, 1, 3).reshape(c, 1, N, N)
+    return torch.cat([body, last], dim=1)
+
+
+def coarse_face_mean(Ff, d):
+    """Mean of the 4 fine faces covering each coarse face: fine global faces [c, ...] of direction d."""
+    c = Ff.shape[0]
+    if d == 0:
+        t = Ff[:, :, :, ::2]
+        nz, ny, nx = t.shape[1] // 2, t.shape[2] // 2, t.shape[3]
+        return t.reshape(c, nz, 2, ny, 2, nx).mean(dim=(2, 4))
+    if d == 1:
+        t = Ff[:, :, ::2, :]
+        nz, ny, nx = t.shape[1] // 2, t.shape[2], t.shape[3] // 2
+        return t.reshape(c, nz, 2, ny, nx, 2).mean(dim=(2, 5))
+    t = Ff[:, ::2, :, :]
+    nz, ny, nx = t.shape[1], t.shape[2] // 2, t.shape[3] // 2
+    return t.reshape(c, nz, ny, 2, nx, 2).mean(dim=(3, 5))
+
+
+# --------------------------------------------------------------------------------------------------
+# data generation
+
+@dataclasses.dataclass
+class Config:
+    n_fine: int = 256
+    train_states: int = 8
+    heldout_states: int = 2
+    fine_steps: int = 200
+    snap_every: int = 20
+    samples_per_dir: int = 16384
+    hidden: int = 128
+    epochs: int = 4
+    batch: int = 4096
+    lr: float = 1e-3
+    seed_train: int = 5
+    seed_heldout: int = 1005
+
+
+def fine_dt(g, U, cfl=0.8):
+    return g.reduce_dt(U, cfl)
+
+
+def snapshot_data(bd, gf, gc, Uf, nbf, gen):
+    """(X, T) samples of one fine snapshot: coarse stencil features and flux corrections."""
+    import torch
+    Uc = restrict(Uf, nbf)
+    Xc, Fc = gc.face_data(Uc, flux="hlle")
+    _, Ff = gf.face_data(Uf, flux="hlle", want_x=False)
+    nbc = nbf // 2
+    xs, ts = [], []
+    for d in range(3):
+        Fg = faces_global(Ff, nbf, d, 8)
+        target = coarse_face_mean(Fg, d) - faces_global(Fc, nbc, d, 8)
+        Xg = faces_global(Xc, nbc, d, 32)
+        T = target.reshape(8, -1).t()
+        X = Xg.reshape(32, -1).t()
+        n = T.shape[0]
+        k = gen["samples"] // 2
+        mag = (T / (T.std(dim=0) + 1e-30)).norm(dim=1)
+        top = torch.topk(mag, max(n // 10, k)).indices
+        pick_top = top[torch.randint(0, top.numel(), (k,), generator=gen["g"], device=top.device)]
+        pick_uni = torch.randint(0, n, (k,), generator=gen["g"], device=top.device)
+        idx = torch.cat([pick_uni, pick_top])
+        xs.append(X[idx])
+        ts.append(T[idx])
+        del Fg, target, Xg
+    return torch.cat(xs), torch.cat(ts)
+
+
+def generate(bd, cfg: Config, states, log=print):
+    """Training samples from fine plain FP64 runs of the given solar-wind states."""
+    import torch
+    gen = {"g": torch.Generator(device="cuda"), "samples": cfg.samples_per_dir}
+    gen["g"].manual_seed(cfg.seed_train)
+    X, T = [], []
+    nbf = cfg.n_fine // 8
+    for si, st in enumerate(states):
+        fine, coarse = magnetosphere_pair(st, cfg.n_fine)
+        gf = bd.Grid.from_workload(fine).upload()
+        gc = bd.Grid.from_workload(coarse).upload()
+        U0 = gf.set_state(torch.from_numpy(fine.W).cuda())
+        U1 = torch.empty_like(U0)
+        dt = torch.zeros(1, dtype=torch.float64, device="cuda")
+        t0 = time.time()
+        for s0 in range(0, cfg.fine_steps, cfg.snap_every):
+            gf.advance(U0, U1, dt, 2 * cfg.snap_every, flux="hlle", powell=True, cfl=0.8)
+            x, t = snapshot_data(bd, gf, gc, U0, nbf, gen)
+            X.append(x)
+            T.append(t)
+        torch.cuda.synchronize()
+        log(f"state {si}: {st}, {cfg.fine_steps} fine steps + snapshots in {time.time() - t0:.1f} s")
+        del gf, gc, U0, U1
+    return torch.cat(X), torch.cat(T)
+
+
+def train(bd, cfg: Config, X, T, log=print):
+    """Adam on z-scored inputs and targets; returns (mlp, stats[80], loss history)."""
+    import torch
+    xm, xs = X.mean(0), X.std(0) + 1e-12
+    tm, ts = T.mean(0), T.std(0) + 1e-30
+    Xn = ((X - xm) / xs).contiguous()
+    Tn = ((T - tm) / ts).contiguous()
+    stats = torch.cat([xm, xs, tm, ts]).float()
+    rng = np.random.default_rng(cfg.seed_train)
+    npar = int(bd.lib().bmhd_mlp_n_params(cfg.hidden))
+    # He-style initialisation of the FP32 master weights
+    p = np.zeros(npar, np.float32)
+    o = 0
+    for (nout, nin) in [(cfg.hidden, 32), (cfg.hidden, cfg.hidden), (cfg.hidden, cfg.hidden), (8, cfg.hidden)]:
+        p[o:o + nout * nin] = rng.normal(scale=math.sqrt(2.0 / nin), size=nout * nin)
+        o += nout * nin + nout
+    mlp = bd.Mlp(cfg.hidden, torch.from_numpy(p))
+    n = Xn.shape[0]
+    hist = []
+    g = torch.Generator(device="cuda")
+    g.manual_seed(cfg.seed_train)
+    for ep in range(cfg.epochs):
+        perm = torch.randperm(n, generator=g, device="cuda")
+        tot, nb = 0.0, 0
+        for b0 in range(0, n - cfg.batch + 1, cfg.batch):
+            idx = perm[b0:b0 + cfg.batch]
+            loss, grad = mlp.loss_grad(Xn[idx].contiguous(), Tn[idx].contiguous())
+            mlp.adam(grad, lr=cfg.lr)
+            tot += float(loss)
+            nb += 1
+        hist.append(tot / max(nb, 1))
+        log(f"epoch {ep}: mean batch loss {hist[-1]:.4f}")
+    return mlp, stats, hist
+
+
+def evaluate(bd, cfg: Config, mlp, stats, states, log=print):
+    """Coarse plain vs coarse learned against the fine run restricted, at the same time."""
+    import torch
+    out = []
+    nbf = cfg.n_fine // 8
+    for st in states:
+        fine, coarse = magnetosphere_pair(st, cfg.n_fine)
+        gf = bd.Grid.from_workload(fine).upload()
+        gc = bd.Grid.from_workload(coarse).upload()
+        Uf = gf.set_state(torch.from_numpy(fine.W).cuda())
+        dtf = gf.reduce_dt(Uf, 0.8)
+        Uc0 = restrict(Uf, nbf)
+        U1 = torch.empty_like(Uf)
+        gf.advance(Uf, U1, dtf, 2 * cfg.fine_steps, flux="hlle", powell=True, recompute_dt=False)
+        ref = restrict(Uf, nbf)
+        del U1
+        dtc = dtf * 2.0
+        res = {}
+        for name, learned in (("plain", None), ("learned", gc.learned(mlp, stats))):
+            U = Uc0.clone()
+            Ub = torch.empty_like(U)
+            dt = dtc.clone()
+            faults = torch.zeros(1, dtype=torch.int32, device="cuda")
+            gc.advance(U, Ub, dt, cfg.fine_steps, flux="hlle", powell=True, recompute_dt=False, learned=learned,
+                       faults=faults)
+            torch.cuda.synchronize()
+            l1 = [float((U[v] - ref[v]).abs().sum() / ref[v].abs().sum()) for v in range(8)]
+            res[name] = {"l1_rel_mean": float(np.mean(l1)), "l1_rel": l1, "faults": int(faults.item())}
+        res["gain"] = res["plain"]["l1_rel_mean"] / max(res["learned"]["l1_rel_mean"], 1e-300)
+        log(f"held-out {st}: plain L1 {res['plain']['l1_rel_mean']:.4e}, learned {res['learned']['l1_rel_mean']:.4e}, "
+            f"gain {res['gain']:.3f}")
+        out.append(res)
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--n-fine", type=int, default=256)
+    ap.add_argument("--train-states", type=int, default=8)
+    ap.add_argument("--heldout-states", type=int, default=2)
+    ap.add_argument("--fine-steps", type=int, default=200)
+    ap.add_argument("--epochs", type=int, default=4)
+    ap.add_argument("--samples", type=int, default=16384)
+    ap.add_argument("--out", default=None)
+    a = ap.parse_args()
+    import torch
+    from . import binding as bd
+    cfg = Config(n_fine=a.n_fine, train_states=a.train_states, heldout_states=a.heldout_states,
+                 fine_steps=a.fine_steps, epochs=a.epochs, samples_per_dir=a.samples)
+    log = lambda *m: print(*m, file=sys.stderr, flush=True)
+    t0 = time.time()
+    X, T = generate(bd, cfg, solar_wind_states(cfg.train_states, cfg.seed_train), log)
+    log(f"{X.shape[0]} samples in {time.time() - t0:.1f} s")
+    t1 = time.time()
+    mlp, stats, hist = train(bd, cfg, X, T, log)
+    log(f"training {time.time() - t1:.1f} s")
+    ev = evaluate(bd, cfg, mlp, stats, solar_wind_states(cfg.heldout_states, cfg.seed_heldout), log)
+    summary = {"samples": int(X.shape[0]), "loss": hist, "heldout": ev,
+               "gain_mean": float(np.mean([e["gain"] for e in ev])), "config": dataclasses.asdict(cfg)}
+    if a.out:
+        torch.save({"params": mlp.p.cpu(), "stats": stats.cpu(), "hidden": cfg.hidden, "summary": summary}, a.out)
+    print(json.dumps(summary))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,113 @@
+"""GPU tests of the learned flux-correction form: per-face data, the zero-correction identity, and the
+fallback to the plain flux."""
+import numpy as np
+import pytest
+
+from paper_2501_06717_amd import workloads as wk
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def bd():
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    from paper_2501_06717_amd import binding
+    binding.lib()
+    return binding
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def face_index(d, i, j, z):
+    return ((z * 8 + j) * 9 + i) if d == 0 else (((z * 9 + j) * 8 + i) if d == 1 else ((z * 8 + j) * 8 + i))
+
+
+def test_face_fluxes_reproduce_the_stage(bd):
+    """One forward-Euler stage equals U + dt * (-sum_d (F_d+ - F_d-) / dx) built from bmhd_face_data's
+    fluxes (rotated back from the face-normal frame)."""
+    wl = wk.with_state(wk.uniform_state((2, 2, 2)), wk.random_positive_state(wk.uniform_state((2, 2, 2)), 3))
+    g = bd.Grid.from_workload(wl).upload()
+    U0 = g.set_state(dev(wl.W))
+    _, F = g.face_data(U0, flux="rusanov", want_x=False)
+    U1 = torch.zeros_like(U0)
+    dt = torch.tensor([0.01], dtype=torch.float64, device="cuda")
+    Ua = U0.clone()
+    g.advance(Ua, U1, dt, 1, flux="rusanov", powell=False, recompute_dt=False, alpha=(0.0, 0.5), beta=(1.0, 0.5))
+    L = ((U1 - U0) / 0.01).cpu().numpy()
+    F = F.cpu().numpy().reshape(wl.n_blocks, 3, 576, 8).astype(np.float64)
+    # back to x, y, z components
+    Fx = np.empty_like(F)
+    for d in range(3):
+        Fx[:, d, :, 0] = F[:, d, :, 0]
+        Fx[:, d, :, 7] = F[:, d, :, 7]
+        for a in range(3):
+            Fx[:, d, :, 1 + (d + a) % 3] = F[:, d, :, 1 + a]
+            Fx[:, d, :, 4 + (d + a) % 3] = F[:, d, :, 4 + a]
+    ref = np.zeros((8, wl.n_blocks, 8, 8, 8))
+    for z in range(8):
+        for j in range(8):
+            for i in range(8):
+                for d in range(3):
+                    lo = face_index(d, i, j, z)
+                    hi = face_index(d, i + (d == 0), j + (d == 1), z + (d == 2))
+                    ref[:, :, z, j, i] -= (Fx[:, d, hi, :] - Fx[:, d, lo, :]).T
+    scale = np.abs(ref).max()
+    assert np.abs(L - ref).max() <= 1e-5 * scale
+
+
+def test_features_are_normal_frame_stencils(bd):
+    wl = wk.with_state(wk.uniform_state((2, 1, 1)), wk.random_positive_state(wk.uniform_state((2, 1, 1)), 5))
+    g = bd.Grid.from_workload(wl).upload()
+    U0 = g.set_state(dev(wl.W))
+    X, _ = g.face_data(U0, want_f=False)
+    X = X.cpu().numpy().reshape(wl.n_blocks, 3, 576, 32)
+    W = wl.W
+    # interior face of block 0 along y at (i=3, j=4, z=5): stencil cells j = 2..5
+    f = face_index(1, 3, 4, 5)
+    for q in range(4):
+        cell = W[:, 0, 5, 2 + q, 3]
+        expect = np.array([cell[0], cell[2], cell[3], cell[1], cell[5], cell[6], cell[4], cell[7]])
+        assert np.allclose(X[0, 1, f, q * 8:(q + 1) * 8], expect, rtol=1e-6, atol=1e-6)
+
+
+def _learned_run(bd, wl, mlp, stats, n_stages, precision, flux, powell, fallback=None):
+    g = bd.Grid.from_workload(wl).upload()
+    U0 = g.set_state(dev(wl.W))
+    U1 = torch.zeros_like(U0)
+    dt = torch.zeros(len(wl.sims), dtype=torch.float64, device="cuda")
+    faults = torch.zeros(1, dtype=torch.int32, device="cuda")
+    L = g.learned(mlp, stats, fallback=fallback) if mlp is not None else None
+    g.advance(U0, U1, dt, n_stages, faults=faults, flux=flux, powell=powell, precision=precision, learned=L)
+    torch.cuda.synchronize()
+    return U0.cpu().numpy(), dt.cpu().numpy(), int(faults.item())
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_flux"])
+def test_zero_correction_equals_plain(bd, precision):
+    wl = wk.magnetosphere_cut(32)
+    mlp = bd.Mlp(32)                                 # all parameters zero: the network outputs 0
+    stats = torch.zeros(80); stats[32:64] = 1.0; stats[72:80] = 1.0
+    a, adt, af = _learned_run(bd, wl, mlp, stats, 4, precision, "hlle", True)
+    b, bdt, bf = _learned_run(bd, wl, None, None, 4, precision, "hlle", True)
+    assert af == 0 and bf == 0
+    assert np.array_equal(adt, bdt)
+    assert np.array_equal(a, b)
+
+
+def test_bad_correction_falls_back_to_plain(bd):
+    wl = wk.magnetosphere_cut(32)
+    rng = np.random.default_rng(0)
+    mlp = bd.Mlp(32, torch.from_numpy(rng.normal(scale=0.3, size=bd.lib().bmhd_mlp_n_params(32)).astype(np.float32)))
+    stats = torch.zeros(80); stats[32:64] = 1.0
+    stats[64:72] = 0.0; stats[72:80] = 1e3                    # huge corrections
+    fb = torch.zeros(1, dtype=torch.int32, device="cuda")
+    a, _, af = _learned_run(bd, wl, mlp, stats, 2, "fp64", "hlle", True, fallback=fb)
+    b, _, _ = _learned_run(bd, wl, None, None, 2, "fp64", "hlle", True)
+    print("flagged cells", int(fb.item()), "of", wl.n_cells * 2, flush=True)
+    assert int(fb.item()) > wl.n_cells // 2
+    err = max(np.abs(a[v] - b[v]).max() / np.abs(b[v]).max() for v in range(8))
+    assert err <= 1e-8, err

@@ -1,0 +1,66 @@
+"""Host tests of the learned-correction data plumbing (index bookkeeping only, CPU tensors)."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from paper_2501_06717_amd import learn
+
+
+def face_index(d, i, j, z):
+    return ((z * 8 + j) * 9 + i) if d == 0 else (((z * 9 + j) * 8 + i) if d == 1 else ((z * 8 + j) * 8 + i))
+
+
+def per_block_faces(nb, fn):
+    """Per-block face arrays [nb^3 * 3 * 576, 1] with value fn(d, X, Y, Z) at global face positions."""
+    out = np.zeros((nb, nb, nb, 3, 576, 1))
+    for bz in range(nb):
+        for by in range(nb):
+            for bx in range(nb):
+                for d in range(3):
+                    ext = [8, 8, 8]
+                    ext[d] = 9
+                    for z in range(ext[2]):
+                        for y in range(ext[1]):
+                            for x in range(ext[0]):
+                                out[bz, by, bx, d, face_index(d, x, y, z), 0] = fn(d, 8 * bx + x, 8 * by + y, 8 * bz + z)
+    return torch.from_numpy(out.reshape(-1, 1))
+
+
+def test_global_roundtrip_and_restriction():
+    nb = 2
+    U = torch.arange(8 * nb ** 3 * 512, dtype=torch.float64).reshape(8, nb ** 3, 8, 8, 8)
+    G = learn.to_global(U, nb)
+    assert torch.equal(learn.from_global(G, nb), U)
+    # block 1 is bx = 1: its cell (k, j, i) is global (z=k, y=j, x=8+i)
+    assert G[3, 2, 5, 8 + 4] == U[3, 1, 2, 5, 4]
+    R = learn.restrict(U, nb)
+    Gr = learn.to_global(R, 1)
+    assert torch.isclose(Gr[0, 1, 2, 3], G[0, 2:4, 4:6, 6:8].mean())
+
+
+@pytest.mark.parametrize("d", [0, 1, 2])
+def test_faces_global_and_coarse_mean(d):
+    nb = 2
+    fn = lambda dd, X, Y, Z: 1000.0 * dd + X + 100.0 * Y + 10000.0 * Z
+    F = per_block_faces(nb, fn)
+    Fg = learn.faces_global(F, nb, d, 1)
+    N = 8 * nb
+    shape = [N, N, N]
+    shape[2 - d] += 1
+    assert tuple(Fg.shape[1:]) == tuple(shape)
+    Z, Y, X = np.meshgrid(np.arange(shape[0]), np.arange(shape[1]), np.arange(shape[2]), indexing="ij")
+    assert np.array_equal(Fg[0].numpy(), fn(d, X, Y, Z))
+    # coarse face (Zc, Yc, Xc) averages fine faces at twice the position along d, 2x2 across
+    M = learn.coarse_face_mean(Fg, d)[0].numpy()
+    c = [5, 3, 6]          # x, y, z of a coarse face
+    f = [2 * v for v in c]
+    acc = 0.0
+    for a in range(2):
+        for b in range(2):
+            g = list(f)
+            t = [ax for ax in range(3) if ax != d]
+            g[t[0]] += a
+            g[t[1]] += b
+            acc += fn(d, g[0], g[1], g[2])
+    assert M[c[2], c[1], c[0]] == acc / 4
