@@ -46,6 +46,7 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-forms", action="store_true")
     p.add_argument("--cpu-steps", type=int, default=1)
+    p.add_argument("--form-steps", type=int, default=20, help="timed steps of the batched and learned forms")
     p.add_argument("--profile", action="store_true", help="short run for a profiler: no CPU leg, no forms")
     p.add_argument("--calib", action="store_true",
                    help="also run a plain 256 MiB device copy (scales the HBM byte counters of a profiler run)")
@@ -78,6 +79,74 @@ def time_form(g, W, steps, warmup, precision, slab, persist=0):
     for s in range(2 * steps):
         st[s % 2].append(events[2 * s].elapsed_time(events[2 * s + 1]) * 1e-3)
     return U0, wall, st, int(faults.item()), float(dt.item())
+
+
+def time_advance(g, U0, U1, dt, steps, **opts):
+    """Wall time of `steps` steps on the current stream, inputs resident."""
+    import torch
+    g.advance(U0, U1, dt, 2, **opts)   # warm-up (and graph capture)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    g.advance(U0, U1, dt, 2 * steps, **opts)
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0
+
+
+def bench_batched(steps):
+    """64 independent periodic simulations (block counts log-uniform in 64..4096, 8 linear waves each),
+    Rusanov, FP32 flux with FP64 state, per-simulation dt: one persistent kernel per stage over all
+    blocks and graph-replayed steps, launch shape from the autotuner."""
+    import torch
+    from paper_2501_06717_amd import binding, workloads as wk
+    wl = wk.batched_waves()
+    g = binding.Grid.from_workload(wl).upload()
+    W = torch.from_numpy(wl.W).cuda()
+    U0 = g.set_state(W)
+    U1 = torch.empty_like(U0)
+    dt = torch.zeros(len(wl.sims), dtype=torch.float64, device="cuda")
+    base = dict(flux="rusanov", powell=False, precision="fp32_flux", cfl=0.8)
+    best, ms = g.autotune(U0.clone(), U1, dt, n_steps=2, **base)
+    shape = dict(slab=int(best.slab), persist_wgs=int(best.persist_wgs))
+    U0 = g.set_state(W)
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        t = time_advance(g, U0, U1, dt, steps, use_graph=True, **shape, **base)
+    cells = wl.n_cells
+    log(f"batched: {len(wl.sims)} simulations, {cells} cells, {t * 1e3:.2f} ms for {steps} steps, shape {shape}")
+    return {"value": cells * steps / t, "unit": "cell-updates/s", "workload": f"{len(wl.sims)} simulations, "
+            f"{wl.n_blocks} blocks, {cells} cells, Rusanov, FP32 flux / FP64 state", "steps": steps,
+            "ms_per_step": t * 1e3 / steps, "shape": shape, "autotune_ms": ms, "graph": True}
+
+
+def bench_learned(steps):
+    """The learned flux correction on the 128^3 magnetosphere grid (dx = 2): MLP 32-128-128-128-8 on
+    BF16 matrix cores, HLLE + Powell, FP64 update, beside the plain FP64 path on the same grid."""
+    import torch
+    from paper_2501_06717_amd import binding, learn
+    state = learn.solar_wind_states(1, 1005)[0]
+    _, coarse = learn.magnetosphere_pair(state, 256)
+    g = binding.Grid.from_workload(coarse).upload()
+    W = torch.from_numpy(coarse.W).cuda()
+    rng = np.random.default_rng(0)
+    npar = int(binding.lib().bmhd_mlp_n_params(128))
+    mlp = binding.Mlp(128, torch.from_numpy((rng.normal(size=npar) * 0.05).astype(np.float32)))
+    stats = torch.zeros(80)
+    stats[32:64] = 1.0
+    stats[72:80] = 1e-3
+    fb = torch.zeros(1, dtype=torch.int32, device="cuda")
+    res = {}
+    for name, L in (("plain", None), ("learned", g.learned(mlp, stats, fallback=fb))):
+        U0 = g.set_state(W)
+        U1 = torch.empty_like(U0)
+        dt = torch.zeros(1, dtype=torch.float64, device="cuda")
+        t = time_advance(g, U0, U1, dt, steps, flux="hlle", powell=True, learned=L)
+        res[name] = coarse.n_cells * steps / t
+    cells = coarse.n_cells
+    log(f"learned: {res['learned']:.3e} vs plain {res['plain']:.3e} cell-updates/s on {cells} cells")
+    return {"value": res["learned"], "unit": "cell-updates/s", "plain_value": res["plain"],
+            "workload": f"magnetosphere 128^3 ({cells} cells), MLP 32-128-128-128-8 BF16, HLLE + Powell",
+            "steps": steps, "flagged_cells_per_stage": int(fb.item()) / (2 * (steps + 1)),
+            "accuracy": "see the learned-correction profile summary (trained network, held-out states)"}
 
 
 def main():
@@ -147,6 +216,11 @@ def main():
         del U32
     del U64
     torch.cuda.synchronize()
+    if not (a.no_forms or a.profile):
+        del g, W
+        out.setdefault("forms", {})
+        out["forms"]["batched"] = bench_batched(a.form_steps)
+        out["forms"]["learned"] = bench_learned(a.form_steps)
     if not (a.no_cpu_baseline or a.profile):
         import oracle
         o = oracle.Grid.from_workload(wl)

@@ -1147,7 +1147,7 @@ int32_t launch_stage_prec(const HostGrid &h, const StageArgs &a, int flux, bool 
 
 Shape pick_shape(const bmhd_opts &o) {
     Shape sh;
-    sh.ks = o.slab == 0 ? (o.precision == BMHD_FP64 ? 4 : 8) : o.slab;
+    sh.ks = o.slab == 0 ? 8 : o.slab;
     sh.persist_wgs = o.persist_wgs;
     return sh;
 }
