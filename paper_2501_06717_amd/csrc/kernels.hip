@@ -1147,7 +1147,10 @@ int32_t launch_stage_prec(const HostGrid &h, const StageArgs &a, int flux, bool 
 
 Shape pick_shape(const bmhd_opts &o) {
     Shape sh;
-    sh.ks = o.slab == 0 ? 8 : o.slab;
+    // measured on the 256^3 magnetosphere: full blocks for FP64 (fewer halo cells and faces per cell
+    // outweigh the second workgroup per CU that 8x8x4 slabs allow), 8x8x4 slabs for FP32 (four
+    // workgroups per CU fit)
+    sh.ks = o.slab == 0 ? (o.precision == BMHD_FP64 ? 8 : 4) : o.slab;
     sh.persist_wgs = o.persist_wgs;
     return sh;
 }

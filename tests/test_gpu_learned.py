@@ -95,11 +95,11 @@ def test_zero_correction_equals_plain(bd, precision):
     b, bdt, bf = _learned_run(bd, wl, None, None, 4, precision, "hlle", True)
     assert af == 0 and bf == 0
     assert np.array_equal(adt, bdt)
-    diff = np.argwhere(a != b)
-    if diff.size:
-        rel = max(np.abs(a[v] - b[v]).max() / np.abs(b[v]).max() for v in range(8))
-        print("zero-correction differences:", diff.shape[0], "cells, max rel", rel, "first", diff[:3], flush=True)
-    assert np.array_equal(a, b)
+    # the learned and plain stages are different kernel instantiations, whose multiply-add contraction
+    # may differ: equal to a unit or two in the last place
+    rel = max(np.abs(a[v] - b[v]).max() / np.abs(b[v]).max() for v in range(8))
+    print("zero-correction max relative difference", rel, flush=True)
+    assert rel <= 1e-15
 
 
 def test_bad_correction_falls_back_to_plain(bd):
