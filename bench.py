@@ -42,6 +42,8 @@ def parse():
     p.add_argument("--warmup", type=int, default=3)
     p.add_argument("--n", type=int, default=256, help="cells per axis of the magnetosphere grid")
     p.add_argument("--slab", type=int, default=0)
+    p.add_argument("--scheme", default="default", choices=["default", "face", "plane"],
+                   help="work split of the stage kernel")
     p.add_argument("--persist", type=int, default=0, help="persistent grid size of the stage kernel (0: off)")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-forms", action="store_true")
@@ -53,14 +55,15 @@ def parse():
     return p.parse_args()
 
 
-def time_form(g, W, steps, warmup, precision, slab, persist=0):
+def time_form(g, W, steps, warmup, precision, slab, persist=0, scheme="default"):
     import torch
     from paper_2501_06717_amd import binding
     U0 = g.set_state(W)
     U1 = torch.empty_like(U0)
     dt = torch.zeros(1, dtype=torch.float64, device="cuda")
     faults = torch.zeros(1, dtype=torch.int32, device="cuda")
-    base = dict(flux="hlle", powell=True, precision=precision, cfl=0.8, slab=slab, persist_wgs=persist)
+    base = dict(flux="hlle", powell=True, precision=precision, cfl=0.8, slab=slab, persist_wgs=persist,
+                scheme=scheme)
     if warmup:
         g.advance(U0, U1, dt, 2 * warmup, faults=faults, **base)
         U0 = g.set_state(W)  # restart from the initial state: the timed run is the first `steps` steps
@@ -106,7 +109,7 @@ def bench_batched(steps):
     dt = torch.zeros(len(wl.sims), dtype=torch.float64, device="cuda")
     base = dict(flux="rusanov", powell=False, precision="fp32_flux", cfl=0.8)
     best, ms = g.autotune(U0.clone(), U1, dt, n_steps=2, **base)
-    shape = dict(slab=int(best.slab), persist_wgs=int(best.persist_wgs))
+    shape = dict(scheme=int(best.scheme), slab=int(best.slab), persist_wgs=int(best.persist_wgs))
     U0 = g.set_state(W)
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
@@ -164,7 +167,7 @@ def main():
     W = torch.from_numpy(wl.W).cuda()
     steps, warm = a.steps, a.warmup
 
-    U64, wall, st, faults, dt_last = time_form(g, W, steps, warm, "fp64", a.slab, a.persist)
+    U64, wall, st, faults, dt_last = time_form(g, W, steps, warm, "fp64", a.slab, a.persist, a.scheme)
     cells = wl.n_cells
     value = cells * steps / wall
     t1, t2 = float(np.mean(st[0])), float(np.mean(st[1]))
@@ -201,7 +204,7 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     if not (a.no_forms or a.profile):
-        U32, wall32, st32, f32, _ = time_form(g, W, steps, warm, "fp32_flux", a.slab, a.persist)
+        U32, wall32, st32, f32, _ = time_form(g, W, steps, warm, "fp32_flux", a.slab, a.persist, a.scheme)
         ref = U64.cpu().numpy()
         got = U32.cpu().numpy()
         l1 = float(np.abs(got - ref).sum() / np.abs(ref).sum())

@@ -48,6 +48,8 @@ extern "C" {
 
 #define BMHD_FP64 0      /* every step in float64 */
 #define BMHD_FP32_FLUX 1 /* reconstruction and fluxes in float32; update, flux correction, dt in float64 */
+#define BMHD_SCHEME_FACE 1
+#define BMHD_SCHEME_PLANE 2
 
 /* Neighbour relations reported by bmhd_grid_neighbors. */
 #define BMHD_REL_SAME 0
@@ -109,6 +111,10 @@ typedef struct {
     double alpha[2];      /* stage table: out = alpha U^n + (1 - alpha) U_in + beta dt L(U_in) */
     double beta[2];       /* Heun: alpha = {0, 0.5}, beta = {1, 0.5} */
     int32_t slab;         /* tile depth of the stage kernel: 0 = default, 4 or 8 cells along z */
+    int32_t scheme;       /* work split of the stage kernel: 0 = default; BMHD_SCHEME_FACE: one face per
+                             thread and direction, fluxes exchanged through LDS; BMHD_SCHEME_PLANE: one
+                             wave per cell layer of the tile plus one wave for the tile's high-side faces,
+                             fluxes exchanged across lanes (less LDS, more workgroups per CU) */
     int32_t persist_wgs;  /* 0: one workgroup per tile; > 0: a persistent grid of this many workgroups
                              (rounded up to a multiple of 8), each looping over tiles */
     int32_t use_graph;    /* 1: steps after the first replay one captured HIP graph of a whole step
@@ -197,11 +203,12 @@ int32_t bmhd_advance(const bmhd_grid *g, double *d_U0, double *d_U1, double *d_d
 int32_t bmhd_face_data(const bmhd_grid *g, const double *d_U, int32_t flux, const float *d_stats, float *d_X,
                        float *d_F, void *stream);
 
-/* Autotuner: time every launch shape of the stage kernel (tile depth 4 or 8 cells, one workgroup per
- * tile or a persistent grid of 2 or 4 workgroups per compute unit) for n_steps steps each with `base`'s
- * other options, on the caller's buffers (they are advanced: pass scratch copies), and write `base` with
- * the fastest shape into *best. h_ms (host, may be NULL) receives the milliseconds of the 6 candidates
- * in the order (4,0) (4,2/CU) (4,4/CU) (8,0) (8,2/CU) (8,4/CU). Blocking: synchronises `stream`. */
+/* Autotuner: time every launch shape of the stage kernel (scheme FACE or PLANE, tile depth 4 or 8
+ * cells, one workgroup per tile or a persistent grid of 2 or 4 workgroups per compute unit) for n_steps
+ * steps each with `base`'s other options, on the caller's buffers (they are advanced: pass scratch
+ * copies), and write `base` with the fastest shape into *best. h_ms (host, may be NULL) receives the
+ * milliseconds of the 12 candidates: scheme FACE then PLANE, each in the order (4,0) (4,2/CU) (4,4/CU)
+ * (8,0) (8,2/CU) (8,4/CU). Blocking: synchronises `stream`. */
 int32_t bmhd_autotune(const bmhd_grid *g, double *d_U0, double *d_U1, double *d_dt, const bmhd_opts *base,
                       int32_t n_steps, bmhd_opts *best, float *h_ms, void *stream);
 

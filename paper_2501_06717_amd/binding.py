@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(HERE, "libbmhd.so")
 BC_PERIODIC, BC_OUTFLOW, BC_INFLOW = 0, 1, 2
 FLUX = {"rusanov": 0, "hlle": 1}
 PRECISION = {"fp64": 0, "fp32_flux": 1}
+SCHEME = {"default": 0, "face": 1, "plane": 2}
 
 EXPORTS = ["bmhd_version", "bmhd_last_error", "bmhd_grid_create", "bmhd_grid_destroy", "bmhd_grid_info_get",
            "bmhd_grid_neighbors", "bmhd_grid_upload", "bmhd_set_state", "bmhd_fill_ghosts", "bmhd_reduce_dt",
@@ -47,7 +48,8 @@ class Learned(ctypes.Structure):
 class Opts(ctypes.Structure):
     _fields_ = [("flux", ctypes.c_int32), ("powell", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("recompute_dt", ctypes.c_int32), ("cfl", ctypes.c_double), ("alpha", ctypes.c_double * 2),
-                ("beta", ctypes.c_double * 2), ("slab", ctypes.c_int32), ("persist_wgs", ctypes.c_int32),
+                ("beta", ctypes.c_double * 2), ("slab", ctypes.c_int32), ("scheme", ctypes.c_int32),
+                ("persist_wgs", ctypes.c_int32),
                 ("use_graph", ctypes.c_int32), ("learned", ctypes.POINTER(Learned)), ("n_events", ctypes.c_int32),
                 ("events", ctypes.POINTER(ctypes.c_void_p))]
 
@@ -123,8 +125,8 @@ def _check(rc):
 
 
 def make_opts(flux="rusanov", powell=False, precision="fp64", recompute_dt=True, cfl=0.8,
-              alpha=(0.0, 0.5), beta=(1.0, 0.5), slab=0, persist_wgs=0, use_graph=False, events=None,
-              learned=None) -> Opts:
+              alpha=(0.0, 0.5), beta=(1.0, 0.5), slab=0, scheme=0, persist_wgs=0, use_graph=False,
+              events=None, learned=None) -> Opts:
     """Options for bmhd_advance. `events`: optional list of torch.cuda.Event (enable_timing=True), two per
     stage, recorded by the library around each stage kernel."""
     o = Opts()
@@ -136,6 +138,7 @@ def make_opts(flux="rusanov", powell=False, precision="fp64", recompute_dt=True,
     o.alpha[:] = [float(a) for a in alpha]
     o.beta[:] = [float(b) for b in beta]
     o.slab = int(slab)
+    o.scheme = SCHEME[scheme] if isinstance(scheme, str) else int(scheme)
     o.persist_wgs = int(persist_wgs)
     o.use_graph = int(bool(use_graph))
     if learned is not None:
@@ -305,11 +308,11 @@ class Grid:
         import torch
         base = make_opts(**kw)
         best = Opts()
-        ms = (ctypes.c_float * 6)()
+        ms = (ctypes.c_float * 12)()
         _check(lib().bmhd_autotune(self.h, _dev_ptr(U0, torch.float64), _dev_ptr(U1, torch.float64),
                                    _dev_ptr(dt, torch.float64), ctypes.byref(base), int(n_steps), ctypes.byref(best),
                                    ms, _stream_ptr(stream)))
-        names = ["slab4", "slab4_persist2", "slab4_persist4", "slab8", "slab8_persist2", "slab8_persist4"]
+        names = [f"{s}_slab{k}{p}" for s in ("face", "plane") for k in (4, 8) for p in ("", "_persist2", "_persist4")]
         return best, dict(zip(names, list(ms)))
 
 

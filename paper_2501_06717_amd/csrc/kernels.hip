@@ -531,17 +531,25 @@ __device__ __forceinline__ int lane_tid() {
     return t;
 }
 
-template <int KS, typename R, int D, int FLUX, bool BODY, bool LEARN>
-__device__ __forceinline__ void sweep(const Tables &T, const StageArgs &A, const DevBlock &B, int b, int slab,
-                                      R (*sW)[Slab<KS>::NC], const unsigned char *sM, R (*sF)[Slab<KS>::NF]) {
+// Body mask of the LDS cells of a slab: one byte per cell, or one bit per cell (32 cells per word).
+struct ByteMask {
+    const unsigned char *m;
+    __device__ __forceinline__ bool operator()(int c) const { return m[c] != 0; }
+};
+struct BitMask {
+    const uint32_t *m;
+    __device__ __forceinline__ bool operator()(int c) const { return (m[c >> 5] >> (c & 31)) & 1u; }
+};
+
+// Flux through one face of direction D of a slab whose primitives are in LDS: the face between cells
+// (i-1, j, k) and (i, j, k) for D = 0 (likewise j for D = 1, k for D = 2), slab-local coordinates, the face
+// coordinate in 0..8 (0..KS along z). Returns the 8 flux components and the face-averaged normal field
+// (for the divergence of the Powell source), and records the flux of block faces that take part in a
+// flux correction.
+template <int KS, typename R, int D, int FLUX, bool BODY, bool LEARN, typename Mask>
+__device__ __forceinline__ void face_flux(const Tables &T, const StageArgs &A, const DevBlock &B, int b, int slab,
+                                          R (*sW)[Slab<KS>::NC], Mask sM, int i, int j, int k, R fl[8], R &bbar) {
     using SL = Slab<KS>;
-    constexpr int NF = D == 2 ? SL::NFZ : SL::NFX;
-    const int f = lane_tid();
-    if (f >= NF) return;
-    int i, j, k;
-    if (D == 0) { i = f % 9; j = (f / 9) & 7; k = f / 72; }
-    else if (D == 1) { i = f & 7; j = (f >> 3) % 9; k = f / 72; }
-    else { i = f & 7; j = (f >> 3) & 7; k = f >> 6; }
     int c[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
@@ -549,10 +557,10 @@ __device__ __forceinline__ void sweep(const Tables &T, const StageArgs &A, const
         c[q] = D == 0 ? SL::idx(i + o, j, k) : (D == 1 ? SL::idx(i, j + o, k) : SL::idx(i, j, k + o));
     }
     // face values: W_L = W_{i-1} + slope/2, W_R = W_i - slope/2 (monotonized central)
-    R wl[8], wr[8], fl[8];
+    R wl[8], wr[8];
     bool m0 = false, m1 = false, m2 = false, m3 = false;
     if constexpr (BODY) {
-        m0 = sM[c[0]]; m1 = sM[c[1]]; m2 = sM[c[2]]; m3 = sM[c[3]];
+        m0 = sM(c[0]); m1 = sM(c[1]); m2 = sM(c[2]); m3 = sM(c[3]);
     }
 #pragma unroll
     for (int v = 0; v < 8; ++v) {
@@ -592,7 +600,7 @@ __device__ __forceinline__ void sweep(const Tables &T, const StageArgs &A, const
             for (int v = 0; v < 8; ++v) fl[v] += dF[v];
         }
     }
-    R bbar = R(0.5) * (wl[4 + D] + wr[4 + D]);
+    bbar = R(0.5) * (wl[4 + D] + wr[4 + D]);
     if constexpr (BODY) {
         if (skip) {
 #pragma unroll
@@ -600,9 +608,6 @@ __device__ __forceinline__ void sweep(const Tables &T, const StageArgs &A, const
             bbar = R(0);
         }
     }
-#pragma unroll
-    for (int v = 0; v < 8; ++v) sF[v][f] = fl[v];
-    sF[8][f] = bbar;
     // fluxes through block faces that take part in a flux correction
     if (B.flags & BF_FC) {
         int bf = -1, t1 = 0, t2 = 0;
@@ -626,6 +631,26 @@ __device__ __forceinline__ void sweep(const Tables &T, const StageArgs &A, const
             }
         }
     }
+}
+
+// One sweep of the face-per-thread scheme: thread f takes face f of direction D and leaves its flux in
+// sF for the two cells on either side.
+template <int KS, typename R, int D, int FLUX, bool BODY, bool LEARN>
+__device__ __forceinline__ void sweep(const Tables &T, const StageArgs &A, const DevBlock &B, int b, int slab,
+                                      R (*sW)[Slab<KS>::NC], const unsigned char *sM, R (*sF)[Slab<KS>::NF]) {
+    using SL = Slab<KS>;
+    constexpr int NF = D == 2 ? SL::NFZ : SL::NFX;
+    const int f = lane_tid();
+    if (f >= NF) return;
+    int i, j, k;
+    if (D == 0) { i = f % 9; j = (f / 9) & 7; k = f / 72; }
+    else if (D == 1) { i = f & 7; j = (f >> 3) % 9; k = f / 72; }
+    else { i = f & 7; j = (f >> 3) & 7; k = f >> 6; }
+    R fl[8], bbar;
+    face_flux<KS, R, D, FLUX, BODY, LEARN>(T, A, B, b, slab, sW, ByteMask{sM}, i, j, k, fl, bbar);
+#pragma unroll
+    for (int v = 0; v < 8; ++v) sF[v][f] = fl[v];
+    sF[8][f] = bbar;
 }
 
 template <int KS, typename R, int D>
@@ -715,40 +740,19 @@ __device__ __forceinline__ void gather_store(const Tables &T, int b, int slab, c
     }
 }
 
-// Sweeps, source, update and end-of-step bookkeeping for one slab whose primitives are in LDS.
-template <int KS, typename R, int FLUX, bool POWELL, bool LEARN>
-__device__ __forceinline__ void slab_compute(const Tables &T, const StageArgs &A, int b, int slab, const double (&uin)[8],
-                                             R (*sW)[Slab<KS>::NC], unsigned char *sM, R (*sF)[Slab<KS>::NF],
-                                             double *red, int *redi) {
+// Powell source, stage update and write of the thread's own cell (threads below 64 KS own cell tid of
+// the slab), then the end-of-step bookkeeping: positivity check and the next time-step bound.
+template <int KS, typename R, bool POWELL, bool LEARN, typename Mask>
+__device__ __forceinline__ void cell_update(const Tables &T, const StageArgs &A, int b, int slab, const double (&uin)[8],
+                                            R (*sW)[Slab<KS>::NC], Mask sM, double (&rhs)[8], double divb,
+                                            double inv_dx, double *red, int *redi) {
     using SL = Slab<KS>;
     const DevBlock &B = T.blocks[b];
-    const DevSim &S = T.sims[B.sim];
     const size_t vs = size_t(T.nb) * 512;
     const bool near_body = (B.flags & BF_NEAR_BODY) != 0;
     const int tid = lane_tid();
     const bool owner = tid < SL::NCELLS;
-
-    // three flux sweeps, one face per thread; fluxes meet their two cells through LDS
-    const double inv_dx = double(1 << B.level) / S.dx0;
-    double rhs[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    double divb = 0.0;
-    if (near_body) sweep<KS, R, 0, FLUX, true, LEARN>(T, A, B, b, slab, sW, sM, sF);
-    else sweep<KS, R, 0, FLUX, false, LEARN>(T, A, B, b, slab, sW, sM, sF);
-    __syncthreads();
-    if (owner) accumulate<KS, R, 0>(sF, rhs, divb, inv_dx);
-    __syncthreads();
-    if (near_body) sweep<KS, R, 1, FLUX, true, LEARN>(T, A, B, b, slab, sW, sM, sF);
-    else sweep<KS, R, 1, FLUX, false, LEARN>(T, A, B, b, slab, sW, sM, sF);
-    __syncthreads();
-    if (owner) accumulate<KS, R, 1>(sF, rhs, divb, inv_dx);
-    __syncthreads();
-    if (near_body) sweep<KS, R, 2, FLUX, true, LEARN>(T, A, B, b, slab, sW, sM, sF);
-    else sweep<KS, R, 2, FLUX, false, LEARN>(T, A, B, b, slab, sW, sM, sF);
-    __syncthreads();
-    if (owner) accumulate<KS, R, 2>(sF, rhs, divb, inv_dx);
-
-    // source and update of the thread's own cell
-    const bool body = owner && near_body && sM[tid];
+    const bool body = owner && near_body && sM(tid);
     const int cell = tid + slab * 64 * KS;
     const size_t off = size_t(b) * 512 + cell;
     double out[8];
@@ -827,6 +831,40 @@ __device__ __forceinline__ void slab_compute(const Tables &T, const StageArgs &A
     }
 }
 
+// Sweeps, source, update and end-of-step bookkeeping for one slab whose primitives are in LDS.
+template <int KS, typename R, int FLUX, bool POWELL, bool LEARN>
+__device__ __forceinline__ void slab_compute(const Tables &T, const StageArgs &A, int b, int slab, const double (&uin)[8],
+                                             R (*sW)[Slab<KS>::NC], unsigned char *sM, R (*sF)[Slab<KS>::NF],
+                                             double *red, int *redi) {
+    using SL = Slab<KS>;
+    const DevBlock &B = T.blocks[b];
+    const DevSim &S = T.sims[B.sim];
+    const size_t vs = size_t(T.nb) * 512;
+    const bool near_body = (B.flags & BF_NEAR_BODY) != 0;
+    const int tid = lane_tid();
+    const bool owner = tid < SL::NCELLS;
+
+    // three flux sweeps, one face per thread; fluxes meet their two cells through LDS
+    const double inv_dx = double(1 << B.level) / S.dx0;
+    double rhs[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    double divb = 0.0;
+    if (near_body) sweep<KS, R, 0, FLUX, true, LEARN>(T, A, B, b, slab, sW, sM, sF);
+    else sweep<KS, R, 0, FLUX, false, LEARN>(T, A, B, b, slab, sW, sM, sF);
+    __syncthreads();
+    if (owner) accumulate<KS, R, 0>(sF, rhs, divb, inv_dx);
+    __syncthreads();
+    if (near_body) sweep<KS, R, 1, FLUX, true, LEARN>(T, A, B, b, slab, sW, sM, sF);
+    else sweep<KS, R, 1, FLUX, false, LEARN>(T, A, B, b, slab, sW, sM, sF);
+    __syncthreads();
+    if (owner) accumulate<KS, R, 1>(sF, rhs, divb, inv_dx);
+    __syncthreads();
+    if (near_body) sweep<KS, R, 2, FLUX, true, LEARN>(T, A, B, b, slab, sW, sM, sF);
+    else sweep<KS, R, 2, FLUX, false, LEARN>(T, A, B, b, slab, sW, sM, sF);
+    __syncthreads();
+    if (owner) accumulate<KS, R, 2>(sF, rhs, divb, inv_dx);
+    cell_update<KS, R, POWELL, LEARN>(T, A, b, slab, uin, sW, ByteMask{sM}, rhs, divb, inv_dx, red, redi);
+}
+
 // Work item -> (block, slab). Items are the slabs of the Morton-ordered block list. XCD x (workgroups
 // w with w % 8 == x) owns the contiguous item range [first(x), first(x) + count(x)).
 __device__ __forceinline__ int xcd_first(int nwork, int x) {
@@ -874,6 +912,191 @@ __global__ void __launch_bounds__(Slab<KS>::NT) k_stage(Tables T, StageArgs A) {
             slab_compute<KS, R, FLUX, POWELL, LEARN>(T, A, b, slab, u[0], sW, sM, sF, red, redi);
             __syncthreads();
             // keep the scheduler from overlapping iterations (that would hold two slabs' values live)
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    }
+}
+
+// ------------------------------------------------------------------------------------------------
+// Wave-per-plane form of the stage kernel. A slab of KS z-layers is worked by KS + 1 waves: wave k < KS
+// owns cell layer k (lane = (i, j)) and computes the face on the low side of each of its cells in every
+// direction; wave KS computes the slab's high-side faces (x = 8, y = 8, z = KS). The flux through the
+// high side of a cell then comes from the neighbouring lane (x: lane + 1, y: lane + 8, by cross-lane
+// permute), from the next wave (z) or from the last wave (the slab's high faces), so no per-face flux
+// array is kept: the z fluxes reuse the LDS space of the x and y halos, which is dead once the x and y
+// faces are done. LDS per slab of four layers: 53.9 KB in FP64, small enough for three workgroups per CU.
+
+// Convert the gathered conserved values to primitives in LDS and set one body-mask bit per cell.
+template <int KS, typename R>
+__device__ __forceinline__ void gather_store_bits(const Tables &T, int b, int slab,
+                                                  const double (&u)[Slab<KS>::NPT][8], R (*sW)[Slab<KS>::NC],
+                                                  uint32_t *sMb) {
+    using SL = Slab<KS>;
+    const DevBlock &B = T.blocks[b];
+    const bool near_body = (B.flags & BF_NEAR_BODY) != 0;
+    const int tid = lane_tid();
+#pragma unroll
+    for (int m = 0; m < SL::NPT; ++m) {
+        // NC and NT are multiples of 64: a wave's cells are all valid or all past the end
+        const int c = tid + m * SL::NT;
+        if (c >= SL::NC) break;
+        double w[8];
+        cons_to_prim(u[m], w);
+#pragma unroll
+        for (int v = 0; v < 8; ++v) sW[v][c] = R(w[v]);
+        if (near_body) {
+            int i, j, k;
+            SL::decode(c, i, j, k);
+            const bool inb = in_body(T.sims[B.sim], B.level, B.ijk, i, j, slab * KS + k);
+            const unsigned long long bits = __ballot(inb);
+            if ((tid & 63) == 0) {
+                sMb[c >> 5] = uint32_t(bits);
+                sMb[(c >> 5) + 1] = uint32_t(bits >> 32);
+            }
+        }
+    }
+}
+
+template <int KS, typename R, int D, int FLUX>
+__device__ __forceinline__ void wp_face(const Tables &T, const StageArgs &A, const DevBlock &B, int b, int slab,
+                                        R (*sW)[Slab<KS>::NC], BitMask sM, bool near_body, int i, int j, int k,
+                                        R fl[8], R &bbar) {
+    if (near_body) face_flux<KS, R, D, FLUX, true, false>(T, A, B, b, slab, sW, sM, i, j, k, fl, bbar);
+    else face_flux<KS, R, D, FLUX, false, false>(T, A, B, b, slab, sW, sM, i, j, k, fl, bbar);
+}
+
+template <typename R>
+__device__ __forceinline__ R lane_down(R x, int delta) { return __shfl_down(x, delta, 64); }
+
+template <int KS, typename R, int FLUX, bool POWELL>
+__device__ __forceinline__ void wp_compute(const Tables &T, const StageArgs &A, int b, int slab, const double (&uin)[8],
+                                           R (*sW)[Slab<KS>::NC], R (*sXR)[8 * KS], R (*sYR)[8 * KS],
+                                           const uint32_t *sMb, double *red, int *redi) {
+    using SL = Slab<KS>;
+    constexpr int NE = 8 * KS;
+    const DevBlock &B = T.blocks[b];
+    const DevSim &S = T.sims[B.sim];
+    const bool near_body = (B.flags & BF_NEAR_BODY) != 0;
+    const BitMask mk{sMb};
+    const int tid = lane_tid();
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int l = tid & 63, ci = l & 7, cj = l >> 3;
+    const bool cellw = w < KS;
+    const double inv_dx = double(1 << B.level) / S.dx0;
+    double rhs[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    double divb = 0.0;
+    R fl[8], fr[8], bb, bbr;
+
+    // x: low-x face of each cell; the last wave takes the faces at x = 8 of the slab's 8 KS rows
+    if (cellw) {
+        wp_face<KS, R, 0, FLUX>(T, A, B, b, slab, sW, mk, near_body, ci, cj, w, fl, bb);
+#pragma unroll
+        for (int v = 0; v < 8; ++v) fr[v] = lane_down(fl[v], 1);
+        bbr = lane_down(bb, 1);
+    } else if (l < NE) {
+        wp_face<KS, R, 0, FLUX>(T, A, B, b, slab, sW, mk, near_body, 8, l & 7, l >> 3, fl, bb);
+#pragma unroll
+        for (int v = 0; v < 8; ++v) sXR[v][l] = fl[v];
+        sXR[8][l] = bb;
+    }
+    __syncthreads();
+    if (cellw) {
+        if (ci == 7) {
+#pragma unroll
+            for (int v = 0; v < 8; ++v) fr[v] = sXR[v][w * 8 + cj];
+            bbr = sXR[8][w * 8 + cj];
+        }
+#pragma unroll
+        for (int v = 0; v < 8; ++v) rhs[v] += (double(fl[v]) - double(fr[v])) * inv_dx;
+        divb += (double(bbr) - double(bb)) * inv_dx;
+    }
+
+    // y: low-y faces; the last wave takes the faces at y = 8
+    if (cellw) {
+        wp_face<KS, R, 1, FLUX>(T, A, B, b, slab, sW, mk, near_body, ci, cj, w, fl, bb);
+#pragma unroll
+        for (int v = 0; v < 8; ++v) fr[v] = lane_down(fl[v], 8);
+        bbr = lane_down(bb, 8);
+    } else if (l < NE) {
+        wp_face<KS, R, 1, FLUX>(T, A, B, b, slab, sW, mk, near_body, l & 7, 8, l >> 3, fl, bb);
+#pragma unroll
+        for (int v = 0; v < 8; ++v) sYR[v][l] = fl[v];
+        sYR[8][l] = bb;
+    }
+    // past this barrier no x or y halo cell is read again, and sXR has been consumed: the z fluxes of
+    // face layer p + 1 go to the x/y halo space of each variable (64 KS values per variable) and their
+    // face-averaged normal field to sXR
+    __syncthreads();
+    if (cellw) {
+        if (cj == 7) {
+#pragma unroll
+            for (int v = 0; v < 8; ++v) fr[v] = sYR[v][w * 8 + ci];
+            bbr = sYR[8][w * 8 + ci];
+        }
+#pragma unroll
+        for (int v = 0; v < 8; ++v) rhs[v] += (double(fl[v]) - double(fr[v])) * inv_dx;
+        divb += (double(bbr) - double(bb)) * inv_dx;
+    }
+
+    // z: wave k < KS takes face layer k (low side of its cells), the last wave face layer KS
+    R *zb = &sXR[0][0];
+    {
+        const int kf = cellw ? w : KS;
+        wp_face<KS, R, 2, FLUX>(T, A, B, b, slab, sW, mk, near_body, ci, cj, kf, fl, bb);
+        if (kf > 0) {
+#pragma unroll
+            for (int v = 0; v < 8; ++v) sW[v][SL::XH + (kf - 1) * 64 + l] = fl[v];
+            zb[(kf - 1) * 64 + l] = bb;
+        }
+    }
+    __syncthreads();
+    if (cellw) {
+#pragma unroll
+        for (int v = 0; v < 8; ++v) fr[v] = sW[v][SL::XH + w * 64 + l];
+        bbr = zb[w * 64 + l];
+#pragma unroll
+        for (int v = 0; v < 8; ++v) rhs[v] += (double(fl[v]) - double(fr[v])) * inv_dx;
+        divb += (double(bbr) - double(bb)) * inv_dx;
+    }
+    cell_update<KS, R, POWELL, false>(T, A, b, slab, uin, sW, mk, rhs, divb, inv_dx, red, redi);
+}
+
+template <int KS, typename R, int FLUX, bool POWELL, bool PERSIST>
+__global__ void __launch_bounds__(64 * (KS + 1), 4) k_stage_wp(Tables T, StageArgs A) {
+    using SL = Slab<KS>;
+    static_assert(SL::NT == 64 * (KS + 1), "one wave per cell layer plus one");
+    static_assert(SL::NC - SL::XH == 64 * KS && 9 * 8 * KS >= 64 * KS, "z-flux exchange space");
+    constexpr int S_PER_BLOCK = 8 / KS;
+    __shared__ R sW[8][SL::NC];
+    __shared__ R sXR[9][8 * KS];
+    __shared__ R sYR[9][8 * KS];
+    __shared__ uint32_t sMb[SL::NC / 32];
+    __shared__ double red[KS + 1];
+    __shared__ int redi[KS + 1];
+
+    const int nwork = T.nb * S_PER_BLOCK;
+    const int wg = blockIdx.x, xcd = wg & 7, slot = wg >> 3;
+    const int first = xcd_first(nwork, xcd), count = xcd_count(nwork, xcd);
+    if constexpr (!PERSIST) {
+        const int item = first + slot;
+        const int b = T.order[item / S_PER_BLOCK], slab = item % S_PER_BLOCK;
+        double u[SL::NPT][8];
+        gather_issue<KS>(T, A, b, slab, u);
+        gather_store_bits<KS, R>(T, b, slab, u, sW, sMb);
+        __syncthreads();
+        wp_compute<KS, R, FLUX, POWELL>(T, A, b, slab, u[0], sW, sXR, sYR, sMb, red, redi);
+    } else {
+        const int step = int(gridDim.x >> 3);
+#pragma nounroll
+        for (int it = slot; it < count; it += step) {
+            const int item = first + it;
+            const int b = T.order[item / S_PER_BLOCK], slab = item % S_PER_BLOCK;
+            double u[SL::NPT][8];
+            gather_issue<KS>(T, A, b, slab, u);
+            gather_store_bits<KS, R>(T, b, slab, u, sW, sMb);
+            __syncthreads();
+            wp_compute<KS, R, FLUX, POWELL>(T, A, b, slab, u[0], sW, sXR, sYR, sMb, red, redi);
+            __syncthreads();
             __builtin_amdgcn_sched_barrier(0);
         }
     }
@@ -1114,35 +1337,43 @@ int32_t launch_check(const char *what) { return hip_check(hipGetLastError(), wha
 
 bool ptr_ok(const void *p) { return p && (reinterpret_cast<uintptr_t>(p) & 7u) == 0; }
 
-// Launch shape of the stage kernel: tile depth (4 or 8 cells) and persistent grid size (0: one
-// workgroup per slab).
+// Launch shape of the stage kernel: work split (face per thread or wave per cell layer), tile depth (4
+// or 8 cells) and persistent grid size (0: one workgroup per slab).
 struct Shape {
+    int scheme;
     int ks;
     int persist_wgs;
 };
 
 template <int KS, typename R, int FLUX, bool POWELL>
-int32_t launch_stage_shape(const HostGrid &h, const StageArgs &a, int persist_wgs, hipStream_t s) {
+int32_t launch_stage_shape(const HostGrid &h, const StageArgs &a, int scheme, int persist_wgs, hipStream_t s) {
     constexpr int nt = Slab<KS>::NT;
     const int items = h.nb * (8 / KS);
+    int grid = items;
     if (persist_wgs > 0) {
-        int grid = persist_wgs < items ? persist_wgs : items;
+        grid = persist_wgs < items ? persist_wgs : items;
         grid = (grid + 7) & ~7;
-        k_stage<KS, R, FLUX, POWELL, true><<<grid, nt, 0, s>>>(h.dev, a);
+    }
+    if (scheme == BMHD_SCHEME_PLANE) {
+        if (persist_wgs > 0) k_stage_wp<KS, R, FLUX, POWELL, true><<<grid, nt, 0, s>>>(h.dev, a);
+        else k_stage_wp<KS, R, FLUX, POWELL, false><<<grid, nt, 0, s>>>(h.dev, a);
     } else {
-        k_stage<KS, R, FLUX, POWELL, false><<<items, nt, 0, s>>>(h.dev, a);
+        if (persist_wgs > 0) k_stage<KS, R, FLUX, POWELL, true><<<grid, nt, 0, s>>>(h.dev, a);
+        else k_stage<KS, R, FLUX, POWELL, false><<<grid, nt, 0, s>>>(h.dev, a);
     }
     return launch_check("stage kernel");
 }
 
 template <int KS, typename R>
-int32_t launch_stage_prec(const HostGrid &h, const StageArgs &a, int flux, bool powell, int pw, hipStream_t s) {
+int32_t launch_stage_prec(const HostGrid &h, const StageArgs &a, int flux, bool powell, const Shape &sh,
+                          hipStream_t s) {
+    const int sc = sh.scheme, pw = sh.persist_wgs;
     if (flux == BMHD_FLUX_RUSANOV) {
-        if (powell) return launch_stage_shape<KS, R, BMHD_FLUX_RUSANOV, true>(h, a, pw, s);
-        return launch_stage_shape<KS, R, BMHD_FLUX_RUSANOV, false>(h, a, pw, s);
+        if (powell) return launch_stage_shape<KS, R, BMHD_FLUX_RUSANOV, true>(h, a, sc, pw, s);
+        return launch_stage_shape<KS, R, BMHD_FLUX_RUSANOV, false>(h, a, sc, pw, s);
     }
-    if (powell) return launch_stage_shape<KS, R, BMHD_FLUX_HLLE, true>(h, a, pw, s);
-    return launch_stage_shape<KS, R, BMHD_FLUX_HLLE, false>(h, a, pw, s);
+    if (powell) return launch_stage_shape<KS, R, BMHD_FLUX_HLLE, true>(h, a, sc, pw, s);
+    return launch_stage_shape<KS, R, BMHD_FLUX_HLLE, false>(h, a, sc, pw, s);
 }
 
 Shape pick_shape(const bmhd_opts &o) {
@@ -1150,6 +1381,7 @@ Shape pick_shape(const bmhd_opts &o) {
     // measured on the 256^3 magnetosphere: full blocks for FP64 (fewer halo cells and faces per cell
     // outweigh the second workgroup per CU that 8x8x4 slabs allow), 8x8x4 slabs for FP32 (four
     // workgroups per CU fit)
+    sh.scheme = o.scheme == 0 ? BMHD_SCHEME_FACE : o.scheme;
     sh.ks = o.slab == 0 ? (o.precision == BMHD_FP64 ? 8 : 4) : o.slab;
     sh.persist_wgs = o.persist_wgs;
     return sh;
@@ -1158,11 +1390,11 @@ Shape pick_shape(const bmhd_opts &o) {
 int32_t launch_stage(const HostGrid &h, const StageArgs &a, const bmhd_opts &o, hipStream_t s) {
     const Shape sh = pick_shape(o);
     if (o.precision == BMHD_FP64) {
-        if (sh.ks == 4) return launch_stage_prec<4, double>(h, a, o.flux, o.powell, sh.persist_wgs, s);
-        return launch_stage_prec<8, double>(h, a, o.flux, o.powell, sh.persist_wgs, s);
+        if (sh.ks == 4) return launch_stage_prec<4, double>(h, a, o.flux, o.powell, sh, s);
+        return launch_stage_prec<8, double>(h, a, o.flux, o.powell, sh, s);
     }
-    if (sh.ks == 4) return launch_stage_prec<4, float>(h, a, o.flux, o.powell, sh.persist_wgs, s);
-    return launch_stage_prec<8, float>(h, a, o.flux, o.powell, sh.persist_wgs, s);
+    if (sh.ks == 4) return launch_stage_prec<4, float>(h, a, o.flux, o.powell, sh, s);
+    return launch_stage_prec<8, float>(h, a, o.flux, o.powell, sh, s);
 }
 
 template <typename R, int FLUX>
@@ -1186,6 +1418,8 @@ int32_t check_opts(const bmhd_opts &o) {
     if (o.flux != BMHD_FLUX_RUSANOV && o.flux != BMHD_FLUX_HLLE) return fail(BMHD_EINVAL, "unknown flux");
     if (o.precision != BMHD_FP64 && o.precision != BMHD_FP32_FLUX) return fail(BMHD_EINVAL, "unknown precision");
     if (o.slab != 0 && o.slab != 4 && o.slab != 8) return fail(BMHD_EINVAL, "slab must be 0, 4 or 8");
+    if (o.scheme != 0 && o.scheme != BMHD_SCHEME_FACE && o.scheme != BMHD_SCHEME_PLANE)
+        return fail(BMHD_EINVAL, "unknown scheme");
     if (o.persist_wgs < 0 || o.persist_wgs > (1 << 20)) return fail(BMHD_EINVAL, "persist_wgs out of range");
     if (o.recompute_dt && !(o.cfl > 0.0)) return fail(BMHD_EINVAL, "cfl must be positive");
     if (o.learned) {
@@ -1491,10 +1725,11 @@ int32_t bmhd_autotune(const bmhd_grid *g, double *d_U0, double *d_U1, double *d_
     float best_ms = 1e30f;
     int32_t rc = BMHD_OK;
     *best = *base;
-    for (int c = 0; c < 6 && rc == BMHD_OK; ++c) {
+    for (int c = 0; c < 12 && rc == BMHD_OK; ++c) {
         bmhd_opts o = *base;
-        o.slab = shapes[c][0];
-        o.persist_wgs = shapes[c][1] * cus;
+        o.scheme = c < 6 ? BMHD_SCHEME_FACE : BMHD_SCHEME_PLANE;
+        o.slab = shapes[c % 6][0];
+        o.persist_wgs = shapes[c % 6][1] * cus;
         o.events = nullptr;
         o.n_events = 0;
         rc = bmhd_advance(g, d_U0, d_U1, d_dt, 2, &o, nullptr, stream);  // warm-up

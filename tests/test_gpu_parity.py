@@ -135,13 +135,14 @@ STAGE_CASES = {
 }
 
 
+@pytest.mark.parametrize("scheme", ["face", "plane"])
 @pytest.mark.parametrize("case", list(STAGE_CASES))
 @pytest.mark.parametrize("n_stages", [1, 2, 6])
-def test_advance_parity(bd, oracle_mod, case, n_stages):
+def test_advance_parity(bd, oracle_mod, case, n_stages, scheme):
     make, kw = STAGE_CASES[case]
     wl = make()
-    say("advance", case, n_stages, wl.n_blocks)
-    U0, U1, dt, f = gpu_run(bd, wl, wl.W, n_stages, **kw)
+    say("advance", case, n_stages, scheme, wl.n_blocks)
+    U0, U1, dt, f = gpu_run(bd, wl, wl.W, n_stages, scheme=scheme, **kw)
     R0, R1, rdt, rf = oracle_run(oracle_mod, wl, wl.W, n_stages, **kw)
     assert f == 0 and rf == 0
     assert np.all(np.abs(dt - rdt) <= 1e-14 * rdt), (dt, rdt)
@@ -159,13 +160,30 @@ def test_slab_choice_is_bitwise_neutral(bd, slab):
     assert np.array_equal(a[0], b[0]) and np.array_equal(a[2], b[2])
 
 
-@pytest.mark.parametrize("slab,persist", [(4, 8), (4, 256), (8, 24), (4, 1024)])
-def test_persistent_form_is_bitwise_identical(bd, slab, persist):
+@pytest.mark.parametrize("slab,persist,scheme", [(4, 8, "face"), (4, 256, "face"), (8, 24, "face"), (4, 1024, "face"),
+                                                 (4, 8, "plane"), (4, 256, "plane"), (8, 24, "plane")])
+def test_persistent_form_is_bitwise_identical(bd, slab, persist, scheme):
     wl = wk.two_level_magnetosphere(48)
-    kw = dict(flux="hlle", powell=True)
+    kw = dict(flux="hlle", powell=True, scheme=scheme)
     a = gpu_run(bd, wl, wl.W, 4, slab=slab, persist_wgs=persist, **kw)
-    b = gpu_run(bd, wl, wl.W, 4, slab=4, **kw)
+    b = gpu_run(bd, wl, wl.W, 4, slab=slab, **kw)
     assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]) and np.array_equal(a[2], b[2])
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_flux"])
+@pytest.mark.parametrize("slab", [4, 8])
+def test_plane_scheme_matches_face_scheme(bd, precision, slab):
+    """The two work splits evaluate the same face fluxes and sum them in the same order; they may differ
+    only where the compiler contracts a multiply-add differently."""
+    wl = wk.two_level_magnetosphere(48)
+    kw = dict(flux="hlle", powell=True, precision=precision, slab=slab)
+    a = gpu_run(bd, wl, wl.W, 4, scheme="plane", **kw)
+    b = gpu_run(bd, wl, wl.W, 4, scheme="face", **kw)
+    err = group_err(a[0], b[0])
+    say("plane vs face", precision, slab, err)
+    assert a[3] == 0 and b[3] == 0
+    assert max(err.values()) <= (1e-13 if precision == "fp64" else 1e-5), err
+    assert np.all(np.abs(a[2] - b[2]) <= 1e-14 * b[2])
 
 
 def test_cp_alfven_ten_steps(bd, oracle_mod):
@@ -259,12 +277,13 @@ def test_batched_member_equals_alone(bd):
         assert np.array_equal(A0, U0[:, sel])
 
 
+@pytest.mark.parametrize("scheme", ["face", "plane"])
 @pytest.mark.parametrize("precision", ["fp64", "fp32_flux"])
-def test_graph_replay_matches_eager(bd, precision):
+def test_graph_replay_matches_eager(bd, precision, scheme):
     """Graph replays interleaved with eager work and synchronisations, each checked bitwise."""
     wl = small_batch()
     g = bd.Grid.from_workload(wl).upload()
-    kw = dict(flux="rusanov", precision=precision, persist_wgs=64)
+    kw = dict(flux="rusanov", precision=precision, persist_wgs=64, scheme=scheme)
     Ue = g.set_state(dev(wl.W)); U1e = torch.zeros_like(Ue); dte = torch.zeros(len(wl.sims), dtype=torch.float64, device="cuda")
     Ug = g.set_state(dev(wl.W)); U1g = torch.zeros_like(Ug); dtg = torch.zeros_like(dte)
     fe = torch.zeros(1, dtype=torch.int32, device="cuda"); fg = torch.zeros_like(fe)
@@ -284,7 +303,8 @@ def test_autotune_picks_a_valid_shape(bd):
     U0 = g.set_state(dev(wl.W)); U1 = torch.zeros_like(U0)
     dt = torch.zeros(len(wl.sims), dtype=torch.float64, device="cuda")
     best, ms = g.autotune(U0, U1, dt, n_steps=2, flux="rusanov", precision="fp32_flux")
-    say("autotune", ms, best.slab, best.persist_wgs)
-    assert best.slab in (4, 8) and best.persist_wgs >= 0
+    say("autotune", ms, best.scheme, best.slab, best.persist_wgs)
+    assert len(ms) == 12 and all(v > 0 for v in ms.values())
+    assert best.scheme in (1, 2) and best.slab in (4, 8) and best.persist_wgs >= 0
     assert all(v > 0 for v in ms.values())
     assert min(ms.values()) == pytest.approx(ms[min(ms, key=ms.get)])
