@@ -143,6 +143,118 @@ __global__ void __launch_bounds__(256) k_mlp_forward(const float *__restrict__ P
 }
 
 // ------------------------------------------------------------------------------------------------
+// inference (BF16 products, no saved pre-activations): a persistent grid of one workgroup per CU keeps
+// every BF16 weight in LDS (rows padded by 8 elements against bank conflicts; the 8-row output layer
+// padded to 16 zero rows) and each wave streams tiles of 16 samples through the four layers, its
+// activations in a private LDS tile. For H = 128: 84.2 KB of weights + 8 x 4.4 KB of activations.
+
+template <int H>
+struct InferLds {
+    static constexpr int L1 = MLP_IN + 8;  // padded row of the first layer (32 inputs)
+    static constexpr int LH = H + 8;       // padded row of the H-input layers
+    static constexpr int W1 = 0;
+    static constexpr int W2 = W1 + H * L1;
+    static constexpr int W3 = W2 + H * LH;
+    static constexpr int W4 = W3 + H * LH;
+    static constexpr int NWE = W4 + 16 * LH;
+    static constexpr int LA = (H > MLP_IN ? H : MLP_IN) + 8;  // activation row
+};
+
+// make this wave's LDS writes visible to its other lanes before they read them
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <int H, int NW>
+__global__ void __launch_bounds__(64 * NW) k_mlp_infer(const float *__restrict__ P, const __bf16 *__restrict__ Pb,
+                                                       int n, const float *__restrict__ X, float *__restrict__ Y) {
+    using Z = InferLds<H>;
+    constexpr int NT = H / 16;
+    __shared__ __attribute__((aligned(16))) __bf16 sw[Z::NWE];
+    __shared__ __attribute__((aligned(16))) __bf16 sa[NW][16 * Z::LA];
+    __shared__ float sb[3 * H + 8];
+    const MlpView V = mlp_view(H);
+    // stage the weights (16-byte moves) and biases
+    const int ldl[4] = {Z::L1, Z::LH, Z::LH, Z::LH}, basel[4] = {Z::W1, Z::W2, Z::W3, Z::W4};
+    for (int l = 0; l < 4; ++l) {
+        const int nin = V.nin[l], nout = V.nout[l], rows = l == 3 ? 16 : nout, per = nin / 8;
+        for (int c = threadIdx.x; c < rows * per; c += blockDim.x) {
+            const int row = c / per, c8 = c % per;
+            bf16x8 v;
+            if (row < nout) v = *reinterpret_cast<const bf16x8 *>(Pb + V.off_w[l] + long(row) * nin + 8 * c8);
+            else
+#pragma unroll
+                for (int j = 0; j < 8; ++j) v[j] = __bf16(0.0f);
+            *reinterpret_cast<bf16x8 *>(sw + basel[l] + row * ldl[l] + 8 * c8) = v;
+        }
+        for (int o = threadIdx.x; o < nout; o += blockDim.x) sb[l * H + o] = P[V.off_b[l] + o];
+    }
+    __syncthreads();
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, q = lane >> 4, r = lane & 15;
+    __bf16 *a = sa[wave];
+    const int ntiles = (n + 15) / 16;
+    for (int t = blockIdx.x * NW + wave; t < ntiles; t += gridDim.x * NW) {
+        const int s0 = t * 16;
+        {
+            // input tile: lane -> sample lane / 4, inputs 8 (lane % 4) .. +7
+            const int m = lane >> 2, k = (lane & 3) * 8;
+            bf16x8 v;
+            if (s0 + m < n) {
+                const float4 x0 = *reinterpret_cast<const float4 *>(X + size_t(s0 + m) * MLP_IN + k);
+                const float4 x1 = *reinterpret_cast<const float4 *>(X + size_t(s0 + m) * MLP_IN + k + 4);
+                v[0] = __bf16(x0.x); v[1] = __bf16(x0.y); v[2] = __bf16(x0.z); v[3] = __bf16(x0.w);
+                v[4] = __bf16(x1.x); v[5] = __bf16(x1.y); v[6] = __bf16(x1.z); v[7] = __bf16(x1.w);
+            } else {
+#pragma unroll
+                for (int j = 0; j < 8; ++j) v[j] = __bf16(0.0f);
+            }
+            *reinterpret_cast<bf16x8 *>(a + m * Z::LA + k) = v;
+        }
+        wave_sync();
+        f32x4 acc[NT];
+#pragma unroll
+        for (int l = 0; l < 3; ++l) {
+            const int nin = l == 0 ? MLP_IN : H, ld = l == 0 ? Z::L1 : Z::LH, wb = l == 0 ? Z::W1 : (l == 1 ? Z::W2 : Z::W3);
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt) acc[nt] = f32x4{0.f, 0.f, 0.f, 0.f};
+            for (int k0 = 0; k0 < nin; k0 += 32) {
+                const bf16x8 av = *reinterpret_cast<const bf16x8 *>(a + r * Z::LA + k0 + 8 * q);
+#pragma unroll
+                for (int nt = 0; nt < NT; ++nt) {
+                    const bf16x8 bv = *reinterpret_cast<const bf16x8 *>(sw + wb + (16 * nt + r) * ld + k0 + 8 * q);
+                    acc[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc[nt], 0, 0, 0);
+                }
+            }
+            wave_sync();  // every lane has read this layer's input
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt) {
+                const float bias = sb[l * H + 16 * nt + r];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) a[(4 * q + i) * Z::LA + 16 * nt + r] = __bf16(silu(acc[nt][i] + bias));
+            }
+            wave_sync();
+        }
+        f32x4 out = {0.f, 0.f, 0.f, 0.f};
+        for (int k0 = 0; k0 < H; k0 += 32) {
+            const bf16x8 av = *reinterpret_cast<const bf16x8 *>(a + r * Z::LA + k0 + 8 * q);
+            const bf16x8 bv = *reinterpret_cast<const bf16x8 *>(sw + Z::W4 + r * Z::LH + k0 + 8 * q);
+            out = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, out, 0, 0, 0);
+        }
+        if (r < MLP_OUT) {
+            const float bias = sb[3 * H + r];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int m = 4 * q + i;
+                if (s0 + m < n) Y[size_t(s0 + m) * MLP_OUT + r] = out[i] + bias;
+            }
+        }
+        wave_sync();  // the next tile overwrites this one's activations
+    }
+}
+
+// ------------------------------------------------------------------------------------------------
 // generic product for the backward pass: C[M x N] = A[M x K] B[K x N] (+ C when ACC), element (m, k)
 // of A at A[m * am + k * ak], element (k, n) of B at B[k * bk + n * bn]; rows/cols/k beyond the sizes
 // read as 0. One wave per 16 x 16 tile of C.
@@ -273,6 +385,19 @@ template <int H>
 int32_t forward_h(const float *P, const uint16_t *Pb, int n, const float *X, float *Y, float *Z, int mode, hipStream_t s) {
     const unsigned grid = blocks_for((n + 15) / 16, 4);
     const __bf16 *pb = reinterpret_cast<const __bf16 *>(Pb);
+    if (mode == 0 && !Z) {
+        // inference: persistent, one workgroup of 8 waves per CU
+        static int cus = 0;
+        if (cus == 0) {
+            int dev = 0;
+            if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+                cus = 256;
+        }
+        const unsigned tiles = unsigned((n + 15) / 16);
+        const unsigned g = tiles < unsigned(8 * cus) ? blocks_for(tiles, 8) : unsigned(cus);
+        k_mlp_infer<H, 8><<<g, 512, 0, s>>>(P, pb, n, X, Y);
+        return mcheck("mlp inference");
+    }
     if (mode == 0) k_mlp_forward<H, true><<<grid, 256, 0, s>>>(P, pb, n, X, Y, Z);
     else k_mlp_forward<H, false><<<grid, 256, 0, s>>>(P, pb, n, X, Y, Z);
     return mcheck("mlp forward");

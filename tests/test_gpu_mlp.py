@@ -43,6 +43,21 @@ def test_forward_matches_oracle(bd, oracle_mod, H, n, mode):
     assert err <= (1e-5 if mode == "fp32" else BF16_BOUND)
 
 
+@pytest.mark.parametrize("H,n", [(128, 70001), (64, 33), (32, 4097)])
+def test_inference_kernel_equals_training_forward(bd, oracle_mod, H, n):
+    """The persistent LDS-resident inference kernel (no saved activations) evaluates the same BF16
+    products in the same order as the training forward: equal bitwise, also over many tiles per wave."""
+    p, x, _ = _setup(oracle_mod, H, n, 3)
+    net = bd.Mlp(H, torch.from_numpy(p.astype(np.float32)))
+    xd = torch.from_numpy(x.astype(np.float32)).cuda()
+    y_inf = net.forward(xd).cpu().numpy()
+    y_tr, _ = net.forward(xd, save=True)
+    assert np.array_equal(y_inf, y_tr.cpu().numpy())
+    sel = np.arange(0, n, max(1, n // 50))
+    ref = oracle_mod.mlp_forward(p.astype(np.float32).astype(np.float64), H, x[sel].astype(np.float32).astype(np.float64))
+    assert _rel(y_inf[sel], ref) <= BF16_BOUND
+
+
 @pytest.mark.parametrize("H,n", [(32, 50), (128, 96)])
 @pytest.mark.parametrize("mode", ["fp32", "bf16"])
 def test_gradients_match_oracle(bd, oracle_mod, H, n, mode):
