@@ -924,7 +924,8 @@ __global__ void __launch_bounds__(Slab<KS>::NT) k_stage(Tables T, StageArgs A) {
 // high side of a cell then comes from the neighbouring lane (x: lane + 1, y: lane + 8, by cross-lane
 // permute), from the next wave (z) or from the last wave (the slab's high faces), so no per-face flux
 // array is kept: the z fluxes reuse the LDS space of the x and y halos, which is dead once the x and y
-// faces are done. LDS per slab of four layers: 53.9 KB in FP64, small enough for three workgroups per CU.
+// faces are done, and one small buffer carries the last wave's high faces (x, then y, then the z faces'
+// normal field). LDS per slab of four layers: 51.6 KB in FP64, small enough for three workgroups per CU.
 
 // Convert the gathered conserved values to primitives in LDS and set one body-mask bit per cell.
 template <int KS, typename R>
@@ -969,9 +970,9 @@ template <typename R>
 __device__ __forceinline__ R lane_down(R x, int delta) { return __shfl_down(x, delta, 64); }
 
 template <int KS, typename R, int FLUX, bool POWELL>
-__device__ __forceinline__ void wp_compute(const Tables &T, const StageArgs &A, int b, int slab, const double (&uin)[8],
-                                           R (*sW)[Slab<KS>::NC], R (*sXR)[8 * KS], R (*sYR)[8 * KS],
-                                           const uint32_t *sMb, double *red, int *redi) {
+__device__ __forceinline__ void wp_compute(const Tables &T, const StageArgs &A, int b, int slab,
+                                           R (*sW)[Slab<KS>::NC], R (*sH)[8 * KS], const uint32_t *sMb, double *red,
+                                           int *redi) {
     using SL = Slab<KS>;
     constexpr int NE = 8 * KS;
     const DevBlock &B = T.blocks[b];
@@ -996,20 +997,21 @@ __device__ __forceinline__ void wp_compute(const Tables &T, const StageArgs &A, 
     } else if (l < NE) {
         wp_face<KS, R, 0, FLUX>(T, A, B, b, slab, sW, mk, near_body, 8, l & 7, l >> 3, fl, bb);
 #pragma unroll
-        for (int v = 0; v < 8; ++v) sXR[v][l] = fl[v];
-        sXR[8][l] = bb;
+        for (int v = 0; v < 8; ++v) sH[v][l] = fl[v];
+        sH[8][l] = bb;
     }
     __syncthreads();
     if (cellw) {
         if (ci == 7) {
 #pragma unroll
-            for (int v = 0; v < 8; ++v) fr[v] = sXR[v][w * 8 + cj];
-            bbr = sXR[8][w * 8 + cj];
+            for (int v = 0; v < 8; ++v) fr[v] = sH[v][w * 8 + cj];
+            bbr = sH[8][w * 8 + cj];
         }
 #pragma unroll
         for (int v = 0; v < 8; ++v) rhs[v] += (double(fl[v]) - double(fr[v])) * inv_dx;
         divb += (double(bbr) - double(bb)) * inv_dx;
     }
+    __syncthreads();  // sH is read: it takes the y faces next
 
     // y: low-y faces; the last wave takes the faces at y = 8
     if (cellw) {
@@ -1020,26 +1022,27 @@ __device__ __forceinline__ void wp_compute(const Tables &T, const StageArgs &A, 
     } else if (l < NE) {
         wp_face<KS, R, 1, FLUX>(T, A, B, b, slab, sW, mk, near_body, l & 7, 8, l >> 3, fl, bb);
 #pragma unroll
-        for (int v = 0; v < 8; ++v) sYR[v][l] = fl[v];
-        sYR[8][l] = bb;
+        for (int v = 0; v < 8; ++v) sH[v][l] = fl[v];
+        sH[8][l] = bb;
     }
-    // past this barrier no x or y halo cell is read again, and sXR has been consumed: the z fluxes of
-    // face layer p + 1 go to the x/y halo space of each variable (64 KS values per variable) and their
-    // face-averaged normal field to sXR
     __syncthreads();
     if (cellw) {
         if (cj == 7) {
 #pragma unroll
-            for (int v = 0; v < 8; ++v) fr[v] = sYR[v][w * 8 + ci];
-            bbr = sYR[8][w * 8 + ci];
+            for (int v = 0; v < 8; ++v) fr[v] = sH[v][w * 8 + ci];
+            bbr = sH[8][w * 8 + ci];
         }
 #pragma unroll
         for (int v = 0; v < 8; ++v) rhs[v] += (double(fl[v]) - double(fr[v])) * inv_dx;
         divb += (double(bbr) - double(bb)) * inv_dx;
     }
+    // past this barrier no x or y halo cell is read again and sH is consumed: the z fluxes of face layer
+    // p + 1 go to the x/y halo space of each variable (64 KS values per variable), their face-averaged
+    // normal field to sH
+    __syncthreads();
 
     // z: wave k < KS takes face layer k (low side of its cells), the last wave face layer KS
-    R *zb = &sXR[0][0];
+    R *zb = &sH[0][0];
     {
         const int kf = cellw ? w : KS;
         wp_face<KS, R, 2, FLUX>(T, A, B, b, slab, sW, mk, near_body, ci, cj, kf, fl, bb);
@@ -1050,6 +1053,7 @@ __device__ __forceinline__ void wp_compute(const Tables &T, const StageArgs &A, 
         }
     }
     __syncthreads();
+    double uin[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     if (cellw) {
 #pragma unroll
         for (int v = 0; v < 8; ++v) fr[v] = sW[v][SL::XH + w * 64 + l];
@@ -1057,6 +1061,10 @@ __device__ __forceinline__ void wp_compute(const Tables &T, const StageArgs &A, 
 #pragma unroll
         for (int v = 0; v < 8; ++v) rhs[v] += (double(fl[v]) - double(fr[v])) * inv_dx;
         divb += (double(bbr) - double(bb)) * inv_dx;
+        // the cell's own stage input, read again here rather than held in registers through the sweeps
+        const size_t vs = size_t(T.nb) * 512, off = size_t(b) * 512 + slab * 64 * KS + tid;
+#pragma unroll
+        for (int v = 0; v < 8; ++v) uin[v] = A.Uin[v * vs + off];
     }
     cell_update<KS, R, POWELL, false>(T, A, b, slab, uin, sW, mk, rhs, divb, inv_dx, red, redi);
 }
@@ -1068,8 +1076,7 @@ __global__ void __launch_bounds__(64 * (KS + 1), 4) k_stage_wp(Tables T, StageAr
     static_assert(SL::NC - SL::XH == 64 * KS && 9 * 8 * KS >= 64 * KS, "z-flux exchange space");
     constexpr int S_PER_BLOCK = 8 / KS;
     __shared__ R sW[8][SL::NC];
-    __shared__ R sXR[9][8 * KS];
-    __shared__ R sYR[9][8 * KS];
+    __shared__ R sH[9][8 * KS];
     __shared__ uint32_t sMb[SL::NC / 32];
     __shared__ double red[KS + 1];
     __shared__ int redi[KS + 1];
@@ -1080,22 +1087,26 @@ __global__ void __launch_bounds__(64 * (KS + 1), 4) k_stage_wp(Tables T, StageAr
     if constexpr (!PERSIST) {
         const int item = first + slot;
         const int b = T.order[item / S_PER_BLOCK], slab = item % S_PER_BLOCK;
-        double u[SL::NPT][8];
-        gather_issue<KS>(T, A, b, slab, u);
-        gather_store_bits<KS, R>(T, b, slab, u, sW, sMb);
+        {
+            double u[SL::NPT][8];
+            gather_issue<KS>(T, A, b, slab, u);
+            gather_store_bits<KS, R>(T, b, slab, u, sW, sMb);
+        }
         __syncthreads();
-        wp_compute<KS, R, FLUX, POWELL>(T, A, b, slab, u[0], sW, sXR, sYR, sMb, red, redi);
+        wp_compute<KS, R, FLUX, POWELL>(T, A, b, slab, sW, sH, sMb, red, redi);
     } else {
         const int step = int(gridDim.x >> 3);
 #pragma nounroll
         for (int it = slot; it < count; it += step) {
             const int item = first + it;
             const int b = T.order[item / S_PER_BLOCK], slab = item % S_PER_BLOCK;
-            double u[SL::NPT][8];
-            gather_issue<KS>(T, A, b, slab, u);
-            gather_store_bits<KS, R>(T, b, slab, u, sW, sMb);
+            {
+                double u[SL::NPT][8];
+                gather_issue<KS>(T, A, b, slab, u);
+                gather_store_bits<KS, R>(T, b, slab, u, sW, sMb);
+            }
             __syncthreads();
-            wp_compute<KS, R, FLUX, POWELL>(T, A, b, slab, u[0], sW, sXR, sYR, sMb, red, redi);
+            wp_compute<KS, R, FLUX, POWELL>(T, A, b, slab, sW, sH, sMb, red, redi);
             __syncthreads();
             __builtin_amdgcn_sched_barrier(0);
         }
@@ -1186,6 +1197,53 @@ __global__ void __launch_bounds__(Slab<8>::NT) k_face_data(Tables T, StageArgs A
                 F[g * 8 + 1 + a] = float(fl[1 + (D + a) % 3]);
                 F[g * 8 + 4 + a] = float(fl[4 + (D + a) % 3]);
             }
+        }
+    }
+}
+
+// Z-scored stencil features of every face of a block for the learned correction's inference: the
+// layout of bmhd_face_data's X, FP32 primitives in LDS (40 KB per block, so several blocks per CU), one
+// face per thread and direction, each face's 32 features written as eight 16-byte stores.
+__global__ void __launch_bounds__(Slab<8>::NT) k_face_features(Tables T, StageArgs A, const float *__restrict__ stats,
+                                                               float *__restrict__ X) {
+    using SL = Slab<8>;
+    __shared__ float sW[8][SL::NC];
+    __shared__ unsigned char sM[SL::NC];
+    __shared__ float sMean[32], sInv[32];
+    const int b = blockIdx.x;
+    if (threadIdx.x < 32) {
+        sMean[threadIdx.x] = stats[threadIdx.x];
+        sInv[threadIdx.x] = 1.0f / stats[32 + threadIdx.x];
+    }
+    double u[SL::NPT][8];
+    gather_issue<8>(T, A, b, 0, u);
+    gather_store<8, float>(T, b, 0, u, sW, sM);
+    __syncthreads();
+    const int f = lane_tid();
+    if (f >= 576) return;
+#pragma unroll
+    for (int D = 0; D < 3; ++D) {
+        int i, j, k;
+        if (D == 0) { i = f % 9; j = (f / 9) & 7; k = f / 72; }
+        else if (D == 1) { i = f & 7; j = (f >> 3) % 9; k = f / 72; }
+        else { i = f & 7; j = (f >> 3) & 7; k = f >> 6; }
+        float4 *out = reinterpret_cast<float4 *>(X + ((size_t(b) * 3 + D) * 576 + f) * 32);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int o = q - 2;
+            const int c = D == 0 ? SL::idx(i + o, j, k) : (D == 1 ? SL::idx(i, j + o, k) : SL::idx(i, j, k + o));
+            float x[8];
+            x[0] = sW[0][c];
+            x[7] = sW[7][c];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                x[1 + a] = sW[1 + (D + a) % 3][c];
+                x[4 + a] = sW[4 + (D + a) % 3][c];
+            }
+#pragma unroll
+            for (int v = 0; v < 8; ++v) x[v] = (x[v] - sMean[q * 8 + v]) * sInv[q * 8 + v];
+            out[2 * q] = make_float4(x[0], x[1], x[2], x[3]);
+            out[2 * q + 1] = make_float4(x[4], x[5], x[6], x[7]);
         }
     }
 }
@@ -1462,7 +1520,7 @@ int32_t enqueue_stage(const HostGrid &h, const bmhd_opts &o, int e, double *d_U0
         a.want_lam = 0;
         const int count = a.count_faults;
         a.count_faults = 0;
-        k_face_data<BMHD_FLUX_HLLE><<<h.nb, Slab<8>::NT, 0, s>>>(h.dev, a, L.stats, L.x_buf, nullptr);
+        k_face_features<<<h.nb, Slab<8>::NT, 0, s>>>(h.dev, a, L.stats, L.x_buf);
         if (int32_t rc = launch_check("face features")) return rc;
         if (int32_t rc = bmhd_mlp_forward(L.params, L.params_bf16, L.hidden, h.nb * 1728, L.x_buf, L.y_buf, nullptr,
                                           L.mode, s))

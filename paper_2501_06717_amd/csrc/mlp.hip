@@ -53,7 +53,8 @@ __host__ __device__ inline long mlp_params(int H) {
     return long(H) * MLP_IN + H + 2L * (long(H) * H + H) + long(MLP_OUT) * H + MLP_OUT;
 }
 
-__device__ __forceinline__ float silu(float z) { return z / (1.0f + __expf(-z)); }
+// z * sigmoid(z) with the hardware exponential and reciprocal (no IEEE division sequence)
+__device__ __forceinline__ float silu(float z) { return z * __builtin_amdgcn_rcpf(1.0f + __expf(-z)); }
 __device__ __forceinline__ float silu_grad(float z) {
     const float s = 1.0f / (1.0f + __expf(-z));
     return s * (1.0f + z * (1.0f - s));
@@ -146,7 +147,9 @@ __global__ void __launch_bounds__(256) k_mlp_forward(const float *__restrict__ P
 // inference (BF16 products, no saved pre-activations): a persistent grid of one workgroup per CU keeps
 // every BF16 weight in LDS (rows padded by 8 elements against bank conflicts; the 8-row output layer
 // padded to 16 zero rows) and each wave streams tiles of 16 samples through the four layers, its
-// activations in a private LDS tile. For H = 128: 84.2 KB of weights + 8 x 4.4 KB of activations.
+// activations in a private LDS tile. For H = 128: 84.2 KB of weights + 12 x 4.4 KB of activations.
+
+constexpr int MLP_INFER_WAVES = 12;  // per workgroup: three wavefronts per SIMD
 
 template <int H>
 struct InferLds {
@@ -174,7 +177,7 @@ __global__ void __launch_bounds__(64 * NW) k_mlp_infer(const float *__restrict__
     constexpr int NT = H / 16;
     __shared__ __attribute__((aligned(16))) __bf16 sw[Z::NWE];
     __shared__ __attribute__((aligned(16))) __bf16 sa[NW][16 * Z::LA];
-    __shared__ float sb[3 * H + 8];
+    __shared__ float sb[3 * H + 16];
     const MlpView V = mlp_view(H);
     // stage the weights (16-byte moves) and biases
     const int ldl[4] = {Z::L1, Z::LH, Z::LH, Z::LH}, basel[4] = {Z::W1, Z::W2, Z::W3, Z::W4};
@@ -189,9 +192,13 @@ __global__ void __launch_bounds__(64 * NW) k_mlp_infer(const float *__restrict__
                 for (int j = 0; j < 8; ++j) v[j] = __bf16(0.0f);
             *reinterpret_cast<bf16x8 *>(sw + basel[l] + row * ldl[l] + 8 * c8) = v;
         }
-        for (int o = threadIdx.x; o < nout; o += blockDim.x) sb[l * H + o] = P[V.off_b[l] + o];
+        for (int o = threadIdx.x; o < rows; o += blockDim.x) sb[l * H + o] = o < nout ? P[V.off_b[l] + o] : 0.0f;
     }
     __syncthreads();
+    // Products are formed transposed, D[out][sample] = W x act^T: the weight tile is the A operand (lane
+    // holds W[o][8q .. 8q+7]), the activation tile the B operand (lane holds act[sample r][8q .. 8q+7]),
+    // so lane (q, r) ends with outputs 4q .. 4q+3 of sample r: four neighbouring activations, written
+    // back with one 8-byte store.
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, q = lane >> 4, r = lane & 15;
     __bf16 *a = sa[wave];
     const int ntiles = (n + 15) / 16;
@@ -220,35 +227,41 @@ __global__ void __launch_bounds__(64 * NW) k_mlp_infer(const float *__restrict__
 #pragma unroll
             for (int nt = 0; nt < NT; ++nt) acc[nt] = f32x4{0.f, 0.f, 0.f, 0.f};
             for (int k0 = 0; k0 < nin; k0 += 32) {
-                const bf16x8 av = *reinterpret_cast<const bf16x8 *>(a + r * Z::LA + k0 + 8 * q);
+                const bf16x8 bv = *reinterpret_cast<const bf16x8 *>(a + r * Z::LA + k0 + 8 * q);
 #pragma unroll
                 for (int nt = 0; nt < NT; ++nt) {
-                    const bf16x8 bv = *reinterpret_cast<const bf16x8 *>(sw + wb + (16 * nt + r) * ld + k0 + 8 * q);
+                    const bf16x8 av = *reinterpret_cast<const bf16x8 *>(sw + wb + (16 * nt + r) * ld + k0 + 8 * q);
                     acc[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc[nt], 0, 0, 0);
                 }
             }
             wave_sync();  // every lane has read this layer's input
 #pragma unroll
             for (int nt = 0; nt < NT; ++nt) {
-                const float bias = sb[l * H + 16 * nt + r];
-#pragma unroll
-                for (int i = 0; i < 4; ++i) a[(4 * q + i) * Z::LA + 16 * nt + r] = __bf16(silu(acc[nt][i] + bias));
+                const float4 bias = *reinterpret_cast<const float4 *>(sb + l * H + 16 * nt + 4 * q);
+                typedef __attribute__((__vector_size__(4 * sizeof(__bf16)))) __bf16 bf16x4;
+                bf16x4 o;
+                o[0] = __bf16(silu(acc[nt][0] + bias.x));
+                o[1] = __bf16(silu(acc[nt][1] + bias.y));
+                o[2] = __bf16(silu(acc[nt][2] + bias.z));
+                o[3] = __bf16(silu(acc[nt][3] + bias.w));
+                *reinterpret_cast<bf16x4 *>(a + r * Z::LA + 16 * nt + 4 * q) = o;
             }
             wave_sync();
         }
         f32x4 out = {0.f, 0.f, 0.f, 0.f};
         for (int k0 = 0; k0 < H; k0 += 32) {
-            const bf16x8 av = *reinterpret_cast<const bf16x8 *>(a + r * Z::LA + k0 + 8 * q);
-            const bf16x8 bv = *reinterpret_cast<const bf16x8 *>(sw + Z::W4 + r * Z::LH + k0 + 8 * q);
+            const bf16x8 bv = *reinterpret_cast<const bf16x8 *>(a + r * Z::LA + k0 + 8 * q);
+            const bf16x8 av = *reinterpret_cast<const bf16x8 *>(sw + Z::W4 + r * Z::LH + k0 + 8 * q);
             out = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, out, 0, 0, 0);
         }
-        if (r < MLP_OUT) {
-            const float bias = sb[3 * H + r];
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int m = 4 * q + i;
-                if (s0 + m < n) Y[size_t(s0 + m) * MLP_OUT + r] = out[i] + bias;
-            }
+        if (q < 2 && s0 + r < n) {
+            const float4 bias = *reinterpret_cast<const float4 *>(sb + 3 * H + 4 * q);
+            float4 y;
+            y.x = out[0] + bias.x;
+            y.y = out[1] + bias.y;
+            y.z = out[2] + bias.z;
+            y.w = out[3] + bias.w;
+            *reinterpret_cast<float4 *>(Y + size_t(s0 + r) * MLP_OUT + 4 * q) = y;
         }
         wave_sync();  // the next tile overwrites this one's activations
     }
@@ -386,7 +399,7 @@ int32_t forward_h(const float *P, const uint16_t *Pb, int n, const float *X, flo
     const unsigned grid = blocks_for((n + 15) / 16, 4);
     const __bf16 *pb = reinterpret_cast<const __bf16 *>(Pb);
     if (mode == 0 && !Z) {
-        // inference: persistent, one workgroup of 8 waves per CU
+        // inference: persistent, one workgroup per CU
         static int cus = 0;
         if (cus == 0) {
             int dev = 0;
@@ -394,8 +407,8 @@ int32_t forward_h(const float *P, const uint16_t *Pb, int n, const float *X, flo
                 cus = 256;
         }
         const unsigned tiles = unsigned((n + 15) / 16);
-        const unsigned g = tiles < unsigned(8 * cus) ? blocks_for(tiles, 8) : unsigned(cus);
-        k_mlp_infer<H, 8><<<g, 512, 0, s>>>(P, pb, n, X, Y);
+        const unsigned g = tiles < unsigned(MLP_INFER_WAVES * cus) ? blocks_for(tiles, MLP_INFER_WAVES) : unsigned(cus);
+        k_mlp_infer<H, MLP_INFER_WAVES><<<g, 64 * MLP_INFER_WAVES, 0, s>>>(P, pb, n, X, Y);
         return mcheck("mlp inference");
     }
     if (mode == 0) k_mlp_forward<H, true><<<grid, 256, 0, s>>>(P, pb, n, X, Y, Z);

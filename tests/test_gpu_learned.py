@@ -115,3 +115,57 @@ def test_bad_correction_falls_back_to_plain(bd):
     assert int(fb.item()) > wl.n_cells // 2
     err = max(np.abs(a[v] - b[v]).max() / np.abs(b[v]).max() for v in range(8))
     assert err <= 1e-8, err
+
+
+def test_learned_stage_adds_the_network_increment(bd):
+    """One learned stage: the features it builds equal bmhd_face_data's z-scored features, and its result
+    differs from the plain stage by the flux differences of the network's de-normalised increments,
+    rotated back to x, y, z (small increments: no cell is flagged)."""
+    wl = wk.with_state(wk.uniform_state((2, 2, 2)), wk.random_positive_state(wk.uniform_state((2, 2, 2)), 7))
+    g = bd.Grid.from_workload(wl).upload()
+    U0 = g.set_state(dev(wl.W))
+    rng = np.random.default_rng(2)
+    mlp = bd.Mlp(32, torch.from_numpy(rng.normal(scale=0.3, size=bd.lib().bmhd_mlp_n_params(32)).astype(np.float32)))
+    stats = torch.zeros(80)
+    stats[0:32] = torch.from_numpy(rng.uniform(-0.5, 0.5, 32).astype(np.float32))
+    stats[32:64] = torch.from_numpy(rng.uniform(0.5, 2.0, 32).astype(np.float32))
+    stats[64:72] = 1e-4
+    stats[72:80] = torch.from_numpy(rng.uniform(1e-4, 1e-3, 8).astype(np.float32))
+    fb = torch.zeros(1, dtype=torch.int32, device="cuda")
+    L = g.learned(mlp, stats, fallback=fb)
+    dt = torch.tensor([0.01], dtype=torch.float64, device="cuda")
+    kw = dict(flux="hlle", powell=True, recompute_dt=False)
+    Ua, U1a = U0.clone(), torch.zeros_like(U0)
+    g.advance(Ua, U1a, dt, 1, learned=L, **kw)
+    torch.cuda.synchronize()
+    X_in = g._lx.clone()
+    Xref, _ = g.face_data(U0, flux="hlle", stats=stats.cuda(), want_f=False)
+    assert int(fb.item()) == 0
+    assert torch.allclose(X_in, Xref, rtol=1e-5, atol=1e-5), float((X_in - Xref).abs().max())
+    Ub, U1b = U0.clone(), torch.zeros_like(U0)
+    g.advance(Ub, U1b, dt, 1, **kw)
+    # the stage de-normalises in FP32 (a multiply-add per component)
+    Y = mlp.forward(X_in).cpu().numpy()
+    s = stats.numpy()
+    dF = (Y * s[72:80] + s[64:72]).astype(np.float64).reshape(wl.n_blocks, 3, 576, 8)
+    dFx = np.empty_like(dF)          # face-normal frame -> x, y, z components
+    for d in range(3):
+        dFx[:, d, :, 0] = dF[:, d, :, 0]
+        dFx[:, d, :, 7] = dF[:, d, :, 7]
+        for a in range(3):
+            dFx[:, d, :, 1 + (d + a) % 3] = dF[:, d, :, 1 + a]
+            dFx[:, d, :, 4 + (d + a) % 3] = dF[:, d, :, 4 + a]
+    expect = np.zeros((8, wl.n_blocks, 8, 8, 8))
+    for z in range(8):
+        for j in range(8):
+            for i in range(8):
+                for d in range(3):
+                    lo = face_index(d, i, j, z)
+                    hi = face_index(d, i + (d == 0), j + (d == 1), z + (d == 2))
+                    expect[:, :, z, j, i] -= 0.01 * (dFx[:, d, hi, :] - dFx[:, d, lo, :]).T
+    got = (U1a - U1b).cpu().numpy()
+    scale = np.abs(expect).max()
+    print("increment scale", scale, "max deviation", np.abs(got - expect).max(), flush=True)
+    assert scale > 1e-7
+    # bound: FP32 rounding of the de-normalised increments, and FP64 rounding of the stage sums
+    assert np.abs(got - expect).max() <= 1e-6 * scale + 1e-14 * np.abs(U1b.cpu().numpy()).max()
