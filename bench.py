@@ -26,6 +26,19 @@ sys.path.insert(0, ROOT)
 
 METRIC = "cell-updates/sec (FP64 plain vs FP32-flux vs learned) at stated L1 err; % HBM roofline"
 HBM_PEAK_GBS = 8000.0
+# HBM bytes per launch of the FP64 stage kernel on this workload (stage 1, stage 2), from rocprofv3
+# FETCH_SIZE and WRITE_SIZE runs scaled by a plain device copy (the summaries under profiles/); valid
+# only for the kernel version they were taken on, keyed by (scheme, tile depth)
+TRAFFIC = {
+    ("face", 8): (1.722e9 + 1.074e9, 2.807e9 + 1.074e9),
+}
+
+
+def resolve_shape(scheme, slab, precision):
+    """The launch shape the library picks for scheme / slab 0 ("default") requests."""
+    sc = "plane" if scheme == "default" else scheme
+    ks = slab if slab else (8 if (precision == "fp64" and sc == "face") else 4)
+    return sc, ks
 # algorithmic HBM bytes per cell and stage: stage 1 reads U^n and writes U^1 (2 x 64 B); stage 2 reads
 # U^1 and U^n and writes U^{n+1} (3 x 64 B): 320 B per cell-update
 BYTES_STAGE = (128.0, 192.0)
@@ -172,6 +185,10 @@ def main():
     value = cells * steps / wall
     t1, t2 = float(np.mean(st[0])), float(np.mean(st[1]))
     achieved = cells * (BYTES_STAGE[0] + BYTES_STAGE[1]) / (t1 + t2) / 1e9
+    scheme, ks = resolve_shape(a.scheme, a.slab, "fp64")
+    kname = ("k_stage_wp" if scheme == "plane" else "k_stage") + f"<{ks}, double, HLLE, Powell>"
+    meas = TRAFFIC.get((scheme, ks)) if (a.n == 256 and not a.persist) else None
+    traffic = 0.5 * (meas[0] + meas[1]) if meas else None
     log(f"fp64: {wall * 1e3:.2f} ms for {steps} steps, stage kernels {t1 * 1e6:.1f} / {t2 * 1e6:.1f} us, "
         f"faults {faults}, dt {dt_last:.4e}")
     out = {
@@ -191,8 +208,11 @@ def main():
                                "inflow, body r=2.5, HLLE + Powell, MC, Heun, CFL 0.8, FP64",
                    "cells": cells, "blocks": wl.n_blocks, "parallelism": "1 GPU"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "k_stage (FP64, both stages)",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "traffic_unit": "HBM bytes per stage-kernel launch, mean of the two stages",
+                     "algorithmic_bytes_per_launch": 0.5 * cells * (BYTES_STAGE[0] + BYTES_STAGE[1]),
+                     "kernel": kname + " (both stages; " + ("wave per cell layer" if scheme == "plane"
+                                                            else "face per thread") + f", tile 8x8x{ks})",
                      "stage_us": [t1 * 1e6, t2 * 1e6], "bytes_per_cell_update": 320},
         "faults": faults,
     }

@@ -1436,11 +1436,11 @@ int32_t launch_stage_prec(const HostGrid &h, const StageArgs &a, int flux, bool 
 
 Shape pick_shape(const bmhd_opts &o) {
     Shape sh;
-    // measured on the 256^3 magnetosphere: full blocks for FP64 (fewer halo cells and faces per cell
-    // outweigh the second workgroup per CU that 8x8x4 slabs allow), 8x8x4 slabs for FP32 (four
-    // workgroups per CU fit)
-    sh.scheme = o.scheme == 0 ? BMHD_SCHEME_FACE : o.scheme;
-    sh.ks = o.slab == 0 ? (o.precision == BMHD_FP64 ? 8 : 4) : o.slab;
+    // measured on the 256^3 magnetosphere: the wave-per-layer scheme on 8x8x4 slabs in both precisions
+    // (FP64: 1.79 / 2.11 ms per stage against 1.91 / 2.16 for the face scheme on full blocks; FP32 flux:
+    // 1.03 / 1.24 against 1.12 / 1.35 on 8x8x4 slabs). With the face scheme, full blocks for FP64.
+    sh.scheme = o.scheme == 0 ? BMHD_SCHEME_PLANE : o.scheme;
+    sh.ks = o.slab == 0 ? ((o.precision == BMHD_FP64 && sh.scheme == BMHD_SCHEME_FACE) ? 8 : 4) : o.slab;
     sh.persist_wgs = o.persist_wgs;
     return sh;
 }

@@ -8,8 +8,8 @@ grid (256^3, dx = 1) of solar-wind states drawn at random:
   cells); the target of a coarse face is the mean of the 4 fine face fluxes covering it minus the plain
   HLLE flux of the restricted coarse state, both in the face-normal frame;
 * the inputs are the 4-cell stencils of coarse primitives in the face-normal frame;
-* per snapshot and direction, half the sampled faces are uniform and half come from the top decile of
-  the target magnitude; inputs and targets are z-scored with training-set statistics.
+* per snapshot and direction, a share `top_frac` of the sampled faces comes from the top decile of the
+  target magnitude and the rest is uniform; inputs and targets are z-scored with training-set statistics.
 
 Training and inference run in the library's kernels (BF16 matrix cores, FP32 master weights, Adam).
 Data preparation (restriction, face averaging, sampling, statistics) uses torch tensor operations on
@@ -122,13 +122,14 @@ def coarse_face_mean(Ff, d):
 @dataclasses.dataclass
 class Config:
     n_fine: int = 256
-    train_states: int = 8
+    train_states: int = 32
     heldout_states: int = 2
     fine_steps: int = 200
     snap_every: int = 20
     samples_per_dir: int = 16384
+    top_frac: float = 0.5          # share of each snapshot's samples drawn from the top decile of |target|
     hidden: int = 128
-    epochs: int = 4
+    epochs: int = 8
     batch: int = 4096
     lr: float = 1e-3
     seed_train: int = 5
@@ -154,11 +155,12 @@ def snapshot_data(bd, gf, gc, Uf, nbf, gen):
         T = target.reshape(8, -1).t()
         X = Xg.reshape(32, -1).t()
         n = T.shape[0]
-        k = gen["samples"] // 2
+        kt = int(round(gen["samples"] * gen["top_frac"]))
+        ku = gen["samples"] - kt
         mag = (T / (T.std(dim=0) + 1e-30)).norm(dim=1)
-        top = torch.topk(mag, max(n // 10, k)).indices
-        pick_top = top[torch.randint(0, top.numel(), (k,), generator=gen["g"], device=top.device)]
-        pick_uni = torch.randint(0, n, (k,), generator=gen["g"], device=top.device)
+        top = torch.topk(mag, max(n // 10, kt)).indices
+        pick_top = top[torch.randint(0, top.numel(), (kt,), generator=gen["g"], device=top.device)]
+        pick_uni = torch.randint(0, n, (ku,), generator=gen["g"], device=top.device)
         idx = torch.cat([pick_uni, pick_top])
         xs.append(X[idx])
         ts.append(T[idx])
@@ -169,7 +171,7 @@ def snapshot_data(bd, gf, gc, Uf, nbf, gen):
 def generate(bd, cfg: Config, states, log=print):
     """Training samples from fine plain FP64 runs of the given solar-wind states."""
     import torch
-    gen = {"g": torch.Generator(device="cuda"), "samples": cfg.samples_per_dir}
+    gen = {"g": torch.Generator(device="cuda"), "samples": cfg.samples_per_dir, "top_frac": cfg.top_frac}
     gen["g"].manual_seed(cfg.seed_train)
     X, T = [], []
     nbf = cfg.n_fine // 8
@@ -213,13 +215,18 @@ def train(bd, cfg: Config, X, T, log=print):
     hist = []
     g = torch.Generator(device="cuda")
     g.manual_seed(cfg.seed_train)
+    steps = cfg.epochs * (n // cfg.batch)
+    it = 0
     for ep in range(cfg.epochs):
         perm = torch.randperm(n, generator=g, device="cuda")
         tot, nb = 0.0, 0
         for b0 in range(0, n - cfg.batch + 1, cfg.batch):
             idx = perm[b0:b0 + cfg.batch]
             loss, grad = mlp.loss_grad(Xn[idx].contiguous(), Tn[idx].contiguous())
-            mlp.adam(grad, lr=cfg.lr)
+            # cosine decay of the learning rate to a tenth over the run
+            lr = cfg.lr * (0.1 + 0.45 * (1.0 + math.cos(math.pi * it / max(steps, 1))))
+            mlp.adam(grad, lr=lr)
+            it += 1
             tot += float(loss)
             nb += 1
         hist.append(tot / max(nb, 1))
@@ -265,17 +272,18 @@ def evaluate(bd, cfg: Config, mlp, stats, states, log=print):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--n-fine", type=int, default=256)
-    ap.add_argument("--train-states", type=int, default=8)
+    ap.add_argument("--train-states", type=int, default=32)
     ap.add_argument("--heldout-states", type=int, default=2)
     ap.add_argument("--fine-steps", type=int, default=200)
-    ap.add_argument("--epochs", type=int, default=4)
+    ap.add_argument("--epochs", type=int, default=8)
     ap.add_argument("--samples", type=int, default=16384)
+    ap.add_argument("--top-frac", type=float, default=0.5)
     ap.add_argument("--out", default=None)
     a = ap.parse_args()
     import torch
     from . import binding as bd
     cfg = Config(n_fine=a.n_fine, train_states=a.train_states, heldout_states=a.heldout_states,
-                 fine_steps=a.fine_steps, epochs=a.epochs, samples_per_dir=a.samples)
+                 fine_steps=a.fine_steps, epochs=a.epochs, samples_per_dir=a.samples, top_frac=a.top_frac)
     log = lambda *m: print(*m, file=sys.stderr, flush=True)
     t0 = time.time()
     X, T = generate(bd, cfg, solar_wind_states(cfg.train_states, cfg.seed_train), log)

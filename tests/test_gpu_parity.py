@@ -152,11 +152,11 @@ def test_advance_parity(bd, oracle_mod, case, n_stages, scheme):
     assert max(err.values()) <= TOL, err
 
 
-@pytest.mark.parametrize("slab", [4, 8])
-def test_slab_choice_is_bitwise_neutral(bd, slab):
+@pytest.mark.parametrize("scheme", ["face", "plane"])
+def test_slab_choice_is_bitwise_neutral(bd, scheme):
     wl = wk.magnetosphere_cut(32)
-    a = gpu_run(bd, wl, wl.W, 4, flux="hlle", powell=True, slab=slab)
-    b = gpu_run(bd, wl, wl.W, 4, flux="hlle", powell=True, slab=4)
+    a = gpu_run(bd, wl, wl.W, 4, flux="hlle", powell=True, slab=8, scheme=scheme)
+    b = gpu_run(bd, wl, wl.W, 4, flux="hlle", powell=True, slab=4, scheme=scheme)
     assert np.array_equal(a[0], b[0]) and np.array_equal(a[2], b[2])
 
 
