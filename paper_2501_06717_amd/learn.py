@@ -234,6 +234,34 @@ def train(bd, cfg: Config, X, T, log=print):
     return mlp, stats, hist
 
 
+def one_step_gain(bd, cfg: Config, mlp, stats, st, warm_steps=100):
+    """Local (one coarse step) error: from the restricted fine state after `warm_steps` fine steps, one
+    coarse step (dt = 2 fine dt) plain and learned against the fine run advanced two steps and restricted.
+    L1 of the change of state, per variable, relative to the fine change."""
+    import torch
+    nbf = cfg.n_fine // 8
+    fine, coarse = magnetosphere_pair(st, cfg.n_fine)
+    gf = bd.Grid.from_workload(fine).upload()
+    gc = bd.Grid.from_workload(coarse).upload()
+    Uf = gf.set_state(torch.from_numpy(fine.W).cuda())
+    U1 = torch.empty_like(Uf)
+    dtf = torch.zeros(1, dtype=torch.float64, device="cuda")
+    gf.advance(Uf, U1, dtf, 2 * warm_steps, flux="hlle", powell=True, cfl=0.8)
+    dtf = gf.reduce_dt(Uf, 0.8)
+    Uc0 = restrict(Uf, nbf)
+    gf.advance(Uf, U1, dtf, 4, flux="hlle", powell=True, recompute_dt=False)
+    dref = restrict(Uf, nbf) - Uc0
+    out = {}
+    for name, learned in (("plain", None), ("learned", gc.learned(mlp, stats))):
+        U = Uc0.clone()
+        Ub = torch.empty_like(U)
+        gc.advance(U, Ub, dtf * 2.0, 2, flux="hlle", powell=True, recompute_dt=False, learned=learned)
+        d = U - Uc0
+        out[name] = [float((d[v] - dref[v]).abs().sum() / dref[v].abs().sum()) for v in range(8)]
+    out["gain"] = float(np.mean(out["plain"]) / max(np.mean(out["learned"]), 1e-300))
+    return out
+
+
 def evaluate(bd, cfg: Config, mlp, stats, states, log=print):
     """Coarse plain vs coarse learned against the fine run restricted, at the same time."""
     import torch
@@ -263,8 +291,9 @@ def evaluate(bd, cfg: Config, mlp, stats, states, log=print):
             l1 = [float((U[v] - ref[v]).abs().sum() / ref[v].abs().sum()) for v in range(8)]
             res[name] = {"l1_rel_mean": float(np.mean(l1)), "l1_rel": l1, "faults": int(faults.item())}
         res["gain"] = res["plain"]["l1_rel_mean"] / max(res["learned"]["l1_rel_mean"], 1e-300)
+        res["one_step"] = one_step_gain(bd, cfg, mlp, stats, st)
         log(f"held-out {st}: plain L1 {res['plain']['l1_rel_mean']:.4e}, learned {res['learned']['l1_rel_mean']:.4e}, "
-            f"gain {res['gain']:.3f}")
+            f"gain {res['gain']:.3f}; one-step gain {res['one_step']['gain']:.3f}")
         out.append(res)
     return out
 
@@ -293,7 +322,9 @@ def main():
     log(f"training {time.time() - t1:.1f} s")
     ev = evaluate(bd, cfg, mlp, stats, solar_wind_states(cfg.heldout_states, cfg.seed_heldout), log)
     summary = {"samples": int(X.shape[0]), "loss": hist, "heldout": ev,
-               "gain_mean": float(np.mean([e["gain"] for e in ev])), "config": dataclasses.asdict(cfg)}
+               "gain_mean": float(np.mean([e["gain"] for e in ev])),
+               "one_step_gain_mean": float(np.mean([e["one_step"]["gain"] for e in ev])),
+               "config": dataclasses.asdict(cfg)}
     if a.out:
         torch.save({"params": mlp.p.cpu(), "stats": stats.cpu(), "hidden": cfg.hidden, "summary": summary}, a.out)
     print(json.dumps(summary))
