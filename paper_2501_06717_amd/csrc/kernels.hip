@@ -1087,6 +1087,21 @@ __device__ __forceinline__ void wp_compute(const Tables &T, const StageArgs &A, 
     cell_update<KS, R, POWELL, false>(T, A, b, slab, uin, sW, mk, rhs, divb, inv_dx, red, redi);
 }
 
+// One work item of the persistent form, kept out of line: inlined into the persistent loop the compiler
+// keeps loop-carried copies live through the flux computation and spills (71 VGPRs at 128).
+template <int KS, typename R, int FLUX, bool POWELL>
+__device__ __noinline__ void wp_item(const Tables &T, const StageArgs &A, int b, int slab, R (*sW)[Slab<KS>::NC],
+                                     R (*sH)[8 * KS], uint32_t *sMb, double *red, int *redi) {
+    using SL = Slab<KS>;
+    {
+        double u[SL::NPT][8];
+        gather_issue<KS>(T, A, b, slab, u);
+        gather_store_bits<KS, R>(T, b, slab, u, sW, sMb);
+    }
+    __syncthreads();
+    wp_compute<KS, R, FLUX, POWELL>(T, A, b, slab, sW, sH, sMb, red, redi);
+}
+
 template <int KS, typename R, int FLUX, bool POWELL, bool PERSIST>
 __global__ void __launch_bounds__(64 * (KS + 1), 4) k_stage_wp(Tables T, StageArgs A) {
     using SL = Slab<KS>;
@@ -1118,13 +1133,7 @@ __global__ void __launch_bounds__(64 * (KS + 1), 4) k_stage_wp(Tables T, StageAr
         for (int it = slot; it < count; it += step) {
             const int item = first + it;
             const int b = T.order[item / S_PER_BLOCK], slab = item % S_PER_BLOCK;
-            {
-                double u[SL::NPT][8];
-                gather_issue<KS>(T, A, b, slab, u);
-                gather_store_bits<KS, R>(T, b, slab, u, sW, sMb);
-            }
-            __syncthreads();
-            wp_compute<KS, R, FLUX, POWELL>(T, A, b, slab, sW, sH, sMb, red, redi);
+            wp_item<KS, R, FLUX, POWELL>(T, A, b, slab, sW, sH, sMb, red, redi);
             __syncthreads();
             __builtin_amdgcn_sched_barrier(0);
         }
