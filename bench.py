@@ -126,6 +126,7 @@ def bench_batched(steps):
     shape = dict(scheme=int(best.scheme), slab=int(best.slab), persist_wgs=int(best.persist_wgs))
     U0 = g.set_state(W)
     stream = torch.cuda.Stream()
+    torch.cuda.synchronize()  # the state is set on the current stream, the timed steps run on `stream`
     with torch.cuda.stream(stream):
         t = time_advance(g, U0, U1, dt, steps, use_graph=True, **shape, **base)
     cells = wl.n_cells

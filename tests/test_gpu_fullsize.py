@@ -1,0 +1,118 @@
+"""GPU parity at the full sizes the benchmark runs, in the launch configuration it times: the 256^3
+magnetosphere (one step, default stage-kernel shape), the two-level magnetosphere of 3.8 M cells, and
+the 64-simulation batch (autotuned shape, graph-replayed steps). The oracle computes every cell of
+these steps on the host's cores (seconds), so the comparison covers the whole state, not a sample.
+FP64 within 1e-12 per variable group; the FP32-flux form within a stated bound."""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2501_06717_amd import workloads as wk
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+GROUPS = {"rho": [0], "mom": [1, 2, 3], "B": [4, 5, 6], "e": [7]}
+TOL = 1e-12
+FP32_TOL = 1e-5
+
+
+@pytest.fixture(scope="module")
+def bd():
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    from paper_2501_06717_amd import binding
+    binding.lib()
+    return binding
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def group_err(got, ref):
+    return {g: float(np.abs(got[vs] - ref[vs]).max() / max(np.abs(ref[vs]).max(), 1e-300)) for g, vs in GROUPS.items()}
+
+
+def gpu_steps(bd, wl, n_stages, stream=None, **kw):
+    g = bd.Grid.from_workload(wl).upload()
+    U0 = g.set_state(torch.from_numpy(wl.W).cuda())
+    U1 = torch.zeros_like(U0)
+    dt = torch.zeros(len(wl.sims), dtype=torch.float64, device="cuda")
+    faults = torch.zeros(1, dtype=torch.int32, device="cuda")
+    torch.cuda.synchronize()  # the state is set on the current stream; the steps may run on another
+    g.advance(U0, U1, dt, n_stages, faults=faults, stream=stream, **kw)
+    torch.cuda.synchronize()
+    out = (U0.cpu().numpy(), dt.cpu().numpy(), int(faults.item()))
+    del U0, U1, g
+    return out
+
+
+def oracle_steps(oracle_mod, wl, n_stages, **kw):
+    o = oracle_mod.Grid.from_workload(wl)
+    U0 = o.set_state(wl.W)
+    U1 = np.zeros_like(U0)
+    dt, faults = o.advance(U0, U1, np.zeros(len(wl.sims)), n_stages, **kw)
+    del U1
+    return U0, np.asarray(dt), faults
+
+
+def test_magnetosphere_256_one_step(bd, oracle_mod):
+    wl = wk.magnetosphere(256)
+    kw = dict(flux="hlle", powell=True, cfl=0.8)
+    say("magnetosphere 256^3:", wl.n_blocks, "blocks")
+    R, rdt, rf = oracle_steps(oracle_mod, wl, 2, **kw)
+    G, dt, f = gpu_steps(bd, wl, 2, **kw)
+    assert f == 0 and rf == 0
+    assert np.all(np.abs(dt - rdt) <= 1e-14 * rdt), (dt, rdt)
+    err = group_err(G, R)
+    say("  fp64 err", err)
+    assert max(err.values()) <= TOL, err
+    del G
+    G32, _, f32 = gpu_steps(bd, wl, 2, precision="fp32_flux", **kw)
+    err32 = group_err(G32, R)
+    say("  fp32_flux err", err32)
+    assert f32 == 0 and max(err32.values()) <= FP32_TOL, err32
+
+
+def test_two_level_magnetosphere_one_step(bd, oracle_mod):
+    wl = wk.two_level_magnetosphere(144)
+    kw = dict(flux="hlle", powell=True, cfl=0.8)
+    say("two-level magnetosphere:", wl.n_blocks, "blocks,", wl.n_cells, "cells")
+    R, rdt, rf = oracle_steps(oracle_mod, wl, 2, **kw)
+    for precision, tol in (("fp64", TOL), ("fp32_flux", FP32_TOL)):
+        G, dt, f = gpu_steps(bd, wl, 2, precision=precision, **kw)
+        err = group_err(G, R)
+        say(" ", precision, "err", err)
+        assert f == 0 and rf == 0
+        assert np.all(np.abs(dt - rdt) <= 1e-14 * rdt)
+        assert max(err.values()) <= tol, err
+
+
+def test_batched_64_simulations_two_steps(bd, oracle_mod):
+    wl = wk.batched_waves()
+    kw = dict(flux="rusanov", powell=False, cfl=0.8)
+    say("batch:", len(wl.sims), "simulations,", wl.n_blocks, "blocks")
+    # the shape the benchmark picks: autotuned on scratch buffers, then graph-replayed steps on a side stream
+    g = bd.Grid.from_workload(wl).upload()
+    U0 = g.set_state(torch.from_numpy(wl.W).cuda())
+    U1 = torch.empty_like(U0)
+    dt = torch.zeros(len(wl.sims), dtype=torch.float64, device="cuda")
+    best, ms = g.autotune(U0, U1, dt, n_steps=1, precision="fp32_flux", **kw)
+    shape = dict(scheme=int(best.scheme), slab=int(best.slab), persist_wgs=int(best.persist_wgs))
+    say("  shape", shape)
+    del U0, U1, g
+    R, rdt, rf = oracle_steps(oracle_mod, wl, 4, **kw)
+    stream = torch.cuda.Stream()
+    G, dt, f = gpu_steps(bd, wl, 4, stream=stream, use_graph=True, **shape, **kw)
+    err = group_err(G, R)
+    say("  fp64 err", err)
+    assert f == 0 and rf == 0
+    assert np.all(np.abs(dt - rdt) <= 1e-14 * rdt)
+    assert max(err.values()) <= TOL, err
+    G32, _, f32 = gpu_steps(bd, wl, 4, stream=stream, use_graph=True, precision="fp32_flux", **shape, **kw)
+    err32 = group_err(G32, R)
+    say("  fp32_flux err", err32)
+    assert f32 == 0 and max(err32.values()) <= FP32_TOL, err32
