@@ -116,3 +116,35 @@ def test_batched_64_simulations_two_steps(bd, oracle_mod):
     err32 = group_err(G32, R)
     say("  fp32_flux err", err32)
     assert f32 == 0 and max(err32.values()) <= FP32_TOL, err32
+
+
+def test_learned_form_zero_network_128(bd, oracle_mod):
+    """The learned form on its configuration (the 128^3 magnetosphere, dx = 2, MLP 32-128-128-128-8 in
+    BF16) with an all-zero network equals the plain path to the last place, and the plain path there
+    matches the oracle; a random network's run stays finite and positive under the fallback."""
+    from paper_2501_06717_amd import learn
+    state = learn.solar_wind_states(1, 1005)[0]
+    _, wl = learn.magnetosphere_pair(state, 256)
+    kw = dict(flux="hlle", powell=True, cfl=0.8)
+    R, rdt, rf = oracle_steps(oracle_mod, wl, 2, **kw)
+    P, dt, f = gpu_steps(bd, wl, 2, scheme="face", slab=4, **kw)
+    assert f == 0 and rf == 0 and max(group_err(P, R).values()) <= TOL
+    mlp0 = bd.Mlp(128)
+    stats = torch.zeros(80)
+    stats[32:64] = 1.0
+    stats[72:80] = 1.0
+    g = bd.Grid.from_workload(wl).upload()
+    Lz = g.learned(mlp0, stats)
+    Z, zdt, zf = gpu_steps(bd, wl, 2, learned=Lz, **kw)
+    rel = max(np.abs(Z[v] - P[v]).max() / np.abs(P[v]).max() for v in range(8))
+    say("  zero network vs plain", rel)
+    assert zf == 0 and rel <= 1e-15 and np.array_equal(zdt, dt)
+    rng = np.random.default_rng(0)
+    npar = int(bd.lib().bmhd_mlp_n_params(128))
+    mlp = bd.Mlp(128, torch.from_numpy((rng.normal(size=npar) * 0.05).astype(np.float32)))
+    stats[72:80] = 1e-3
+    fb = torch.zeros(1, dtype=torch.int32, device="cuda")
+    Lr = g.learned(mlp, stats, fallback=fb)
+    X, _, xf = gpu_steps(bd, wl, 2, learned=Lr, **kw)
+    say("  random network: flagged cells", int(fb.item()), "faults", xf)
+    assert xf == 0 and np.isfinite(X).all()
