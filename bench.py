@@ -31,7 +31,7 @@ HBM_PEAK_GBS = 8000.0
 # only for the kernel version they were taken on, keyed by (scheme, tile depth)
 TRAFFIC = {
     ("face", 8): (1.722e9 + 1.074e9, 2.807e9 + 1.074e9),
-    ("plane", 4): (2.092e9 + 1.074e9, 3.123e9 + 1.074e9),
+    ("plane", 4): (2.019e9 + 1.074e9, 3.007e9 + 1.074e9),
 }
 
 
