@@ -1229,8 +1229,9 @@ __global__ void __launch_bounds__(Slab<8>::NT) k_face_data(Tables T, StageArgs A
 }
 
 // Z-scored stencil features of every face of a block for the learned correction's inference: the
-// layout of bmhd_face_data's X, FP32 primitives in LDS (40 KB per block, so several blocks per CU), one
-// face per thread and direction, each face's 32 features written as eight 16-byte stores.
+// layout of bmhd_face_data's X, FP32 primitives in LDS (40 KB per block, so several blocks per CU); each
+// thread takes one stencil cell of a face at a time (8 features), so a wavefront's stores cover 2 KB of
+// contiguous memory.
 __global__ void __launch_bounds__(Slab<8>::NT) k_face_features(Tables T, StageArgs A, const float *__restrict__ stats,
                                                                float *__restrict__ X) {
     using SL = Slab<8>;
@@ -1246,17 +1247,18 @@ __global__ void __launch_bounds__(Slab<8>::NT) k_face_features(Tables T, StageAr
     gather_issue<8>(T, A, b, 0, u);
     gather_store<8, float>(T, b, 0, u, sW, sM);
     __syncthreads();
-    const int f = lane_tid();
-    if (f >= 576) return;
+    // task t = 4 f + q: stencil cell q of face f, so consecutive lanes write consecutive 32-byte pieces
+    const int tid = lane_tid();
 #pragma unroll
     for (int D = 0; D < 3; ++D) {
-        int i, j, k;
-        if (D == 0) { i = f % 9; j = (f / 9) & 7; k = f / 72; }
-        else if (D == 1) { i = f & 7; j = (f >> 3) % 9; k = f / 72; }
-        else { i = f & 7; j = (f >> 3) & 7; k = f >> 6; }
-        float4 *out = reinterpret_cast<float4 *>(X + ((size_t(b) * 3 + D) * 576 + f) * 32);
+        float *base = X + (size_t(b) * 3 + D) * 576 * 32;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
+        for (int m = 0; m < 4; ++m) {
+            const int t = tid + m * SL::NT, f = t >> 2, q = t & 3;
+            int i, j, k;
+            if (D == 0) { i = f % 9; j = (f / 9) & 7; k = f / 72; }
+            else if (D == 1) { i = f & 7; j = (f >> 3) % 9; k = f / 72; }
+            else { i = f & 7; j = (f >> 3) & 7; k = f >> 6; }
             const int o = q - 2;
             const int c = D == 0 ? SL::idx(i + o, j, k) : (D == 1 ? SL::idx(i, j + o, k) : SL::idx(i, j, k + o));
             float x[8];
@@ -1269,8 +1271,9 @@ __global__ void __launch_bounds__(Slab<8>::NT) k_face_features(Tables T, StageAr
             }
 #pragma unroll
             for (int v = 0; v < 8; ++v) x[v] = (x[v] - sMean[q * 8 + v]) * sInv[q * 8 + v];
-            out[2 * q] = make_float4(x[0], x[1], x[2], x[3]);
-            out[2 * q + 1] = make_float4(x[4], x[5], x[6], x[7]);
+            float4 *out = reinterpret_cast<float4 *>(base + size_t(t) * 8);
+            out[0] = make_float4(x[0], x[1], x[2], x[3]);
+            out[1] = make_float4(x[4], x[5], x[6], x[7]);
         }
     }
 }

@@ -149,7 +149,10 @@ __global__ void __launch_bounds__(256) k_mlp_forward(const float *__restrict__ P
 // padded to 16 zero rows) and each wave streams tiles of 16 samples through the four layers, its
 // activations in a private LDS tile. For H = 128: 84.2 KB of weights + 12 x 4.4 KB of activations.
 
-constexpr int MLP_INFER_WAVES = 12;  // per workgroup: three wavefronts per SIMD
+// per workgroup: three wavefronts per SIMD, one 16-sample tile each per iteration (measured on the 128^3
+// learned stage: 1.15 ms; two tiles per wavefront with eight wavefronts, 1.18 ms)
+constexpr int MLP_INFER_WAVES = 12;
+constexpr int MLP_INFER_TILES = 1;
 
 template <int H>
 struct InferLds {
@@ -170,13 +173,14 @@ __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-template <int H, int NW>
+template <int H, int NW, int TP>
 __global__ void __launch_bounds__(64 * NW) k_mlp_infer(const float *__restrict__ P, const __bf16 *__restrict__ Pb,
                                                        int n, const float *__restrict__ X, float *__restrict__ Y) {
     using Z = InferLds<H>;
     constexpr int NT = H / 16;
+    typedef __attribute__((__vector_size__(4 * sizeof(__bf16)))) __bf16 bf16x4;
     __shared__ __attribute__((aligned(16))) __bf16 sw[Z::NWE];
-    __shared__ __attribute__((aligned(16))) __bf16 sa[NW][16 * Z::LA];
+    __shared__ __attribute__((aligned(16))) __bf16 sa[NW][TP][16 * Z::LA];
     __shared__ float sb[3 * H + 16];
     const MlpView V = mlp_view(H);
     // stage the weights (16-byte moves) and biases
@@ -198,15 +202,15 @@ __global__ void __launch_bounds__(64 * NW) k_mlp_infer(const float *__restrict__
     // Products are formed transposed, D[out][sample] = W x act^T: the weight tile is the A operand (lane
     // holds W[o][8q .. 8q+7]), the activation tile the B operand (lane holds act[sample r][8q .. 8q+7]),
     // so lane (q, r) ends with outputs 4q .. 4q+3 of sample r: four neighbouring activations, written
-    // back with one 8-byte store.
+    // back with one 8-byte store. A wavefront carries TP tiles of 16 samples at once, so each weight
+    // fragment read from LDS feeds TP products.
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, q = lane >> 4, r = lane & 15;
-    __bf16 *a = sa[wave];
     const int ntiles = (n + 15) / 16;
-    for (int t = blockIdx.x * NW + wave; t < ntiles; t += gridDim.x * NW) {
-        const int s0 = t * 16;
-        {
+    for (int t0 = (blockIdx.x * NW + wave) * TP; t0 < ntiles; t0 += gridDim.x * NW * TP) {
+#pragma unroll
+        for (int p = 0; p < TP; ++p) {
             // input tile: lane -> sample lane / 4, inputs 8 (lane % 4) .. +7
-            const int m = lane >> 2, k = (lane & 3) * 8;
+            const int s0 = (t0 + p) * 16, m = lane >> 2, k = (lane & 3) * 8;
             bf16x8 v;
             if (s0 + m < n) {
                 const float4 x0 = *reinterpret_cast<const float4 *>(X + size_t(s0 + m) * MLP_IN + k);
@@ -217,53 +221,69 @@ __global__ void __launch_bounds__(64 * NW) k_mlp_infer(const float *__restrict__
 #pragma unroll
                 for (int j = 0; j < 8; ++j) v[j] = __bf16(0.0f);
             }
-            *reinterpret_cast<bf16x8 *>(a + m * Z::LA + k) = v;
+            *reinterpret_cast<bf16x8 *>(sa[wave][p] + m * Z::LA + k) = v;
         }
         wave_sync();
-        f32x4 acc[NT];
+        f32x4 acc[TP][NT];
 #pragma unroll
         for (int l = 0; l < 3; ++l) {
             const int nin = l == 0 ? MLP_IN : H, ld = l == 0 ? Z::L1 : Z::LH, wb = l == 0 ? Z::W1 : (l == 1 ? Z::W2 : Z::W3);
 #pragma unroll
-            for (int nt = 0; nt < NT; ++nt) acc[nt] = f32x4{0.f, 0.f, 0.f, 0.f};
+            for (int p = 0; p < TP; ++p)
+#pragma unroll
+                for (int nt = 0; nt < NT; ++nt) acc[p][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
             for (int k0 = 0; k0 < nin; k0 += 32) {
-                const bf16x8 bv = *reinterpret_cast<const bf16x8 *>(a + r * Z::LA + k0 + 8 * q);
+                bf16x8 bv[TP];
+#pragma unroll
+                for (int p = 0; p < TP; ++p) bv[p] = *reinterpret_cast<const bf16x8 *>(sa[wave][p] + r * Z::LA + k0 + 8 * q);
 #pragma unroll
                 for (int nt = 0; nt < NT; ++nt) {
                     const bf16x8 av = *reinterpret_cast<const bf16x8 *>(sw + wb + (16 * nt + r) * ld + k0 + 8 * q);
-                    acc[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc[nt], 0, 0, 0);
+#pragma unroll
+                    for (int p = 0; p < TP; ++p)
+                        acc[p][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv[p], acc[p][nt], 0, 0, 0);
                 }
             }
             wave_sync();  // every lane has read this layer's input
 #pragma unroll
-            for (int nt = 0; nt < NT; ++nt) {
-                const float4 bias = *reinterpret_cast<const float4 *>(sb + l * H + 16 * nt + 4 * q);
-                typedef __attribute__((__vector_size__(4 * sizeof(__bf16)))) __bf16 bf16x4;
-                bf16x4 o;
-                o[0] = __bf16(silu(acc[nt][0] + bias.x));
-                o[1] = __bf16(silu(acc[nt][1] + bias.y));
-                o[2] = __bf16(silu(acc[nt][2] + bias.z));
-                o[3] = __bf16(silu(acc[nt][3] + bias.w));
-                *reinterpret_cast<bf16x4 *>(a + r * Z::LA + 16 * nt + 4 * q) = o;
-            }
+            for (int p = 0; p < TP; ++p)
+#pragma unroll
+                for (int nt = 0; nt < NT; ++nt) {
+                    const float4 bias = *reinterpret_cast<const float4 *>(sb + l * H + 16 * nt + 4 * q);
+                    bf16x4 o;
+                    o[0] = __bf16(silu(acc[p][nt][0] + bias.x));
+                    o[1] = __bf16(silu(acc[p][nt][1] + bias.y));
+                    o[2] = __bf16(silu(acc[p][nt][2] + bias.z));
+                    o[3] = __bf16(silu(acc[p][nt][3] + bias.w));
+                    *reinterpret_cast<bf16x4 *>(sa[wave][p] + r * Z::LA + 16 * nt + 4 * q) = o;
+                }
             wave_sync();
         }
-        f32x4 out = {0.f, 0.f, 0.f, 0.f};
+        f32x4 out[TP];
+#pragma unroll
+        for (int p = 0; p < TP; ++p) out[p] = f32x4{0.f, 0.f, 0.f, 0.f};
         for (int k0 = 0; k0 < H; k0 += 32) {
-            const bf16x8 bv = *reinterpret_cast<const bf16x8 *>(a + r * Z::LA + k0 + 8 * q);
             const bf16x8 av = *reinterpret_cast<const bf16x8 *>(sw + Z::W4 + r * Z::LH + k0 + 8 * q);
-            out = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, out, 0, 0, 0);
+#pragma unroll
+            for (int p = 0; p < TP; ++p) {
+                const bf16x8 bv = *reinterpret_cast<const bf16x8 *>(sa[wave][p] + r * Z::LA + k0 + 8 * q);
+                out[p] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, out[p], 0, 0, 0);
+            }
         }
-        if (q < 2 && s0 + r < n) {
-            const float4 bias = *reinterpret_cast<const float4 *>(sb + 3 * H + 4 * q);
-            float4 y;
-            y.x = out[0] + bias.x;
-            y.y = out[1] + bias.y;
-            y.z = out[2] + bias.z;
-            y.w = out[3] + bias.w;
-            *reinterpret_cast<float4 *>(Y + size_t(s0 + r) * MLP_OUT + 4 * q) = y;
+#pragma unroll
+        for (int p = 0; p < TP; ++p) {
+            const int s0 = (t0 + p) * 16;
+            if (q < 2 && s0 + r < n) {
+                const float4 bias = *reinterpret_cast<const float4 *>(sb + 3 * H + 4 * q);
+                float4 y;
+                y.x = out[p][0] + bias.x;
+                y.y = out[p][1] + bias.y;
+                y.z = out[p][2] + bias.z;
+                y.w = out[p][3] + bias.w;
+                *reinterpret_cast<float4 *>(Y + size_t(s0 + r) * MLP_OUT + 4 * q) = y;
+            }
         }
-        wave_sync();  // the next tile overwrites this one's activations
+        wave_sync();  // the next tiles overwrite these activations
     }
 }
 
@@ -407,8 +427,9 @@ int32_t forward_h(const float *P, const uint16_t *Pb, int n, const float *X, flo
                 cus = 256;
         }
         const unsigned tiles = unsigned((n + 15) / 16);
-        const unsigned g = tiles < unsigned(MLP_INFER_WAVES * cus) ? blocks_for(tiles, MLP_INFER_WAVES) : unsigned(cus);
-        k_mlp_infer<H, MLP_INFER_WAVES><<<g, 64 * MLP_INFER_WAVES, 0, s>>>(P, pb, n, X, Y);
+        const unsigned per = MLP_INFER_WAVES * MLP_INFER_TILES;
+        const unsigned g = tiles < per * unsigned(cus) ? blocks_for(tiles, int(per)) : unsigned(cus);
+        k_mlp_infer<H, MLP_INFER_WAVES, MLP_INFER_TILES><<<g, 64 * MLP_INFER_WAVES, 0, s>>>(P, pb, n, X, Y);
         return mcheck("mlp inference");
     }
     if (mode == 0) k_mlp_forward<H, true><<<grid, 256, 0, s>>>(P, pb, n, X, Y, Z);
