@@ -758,12 +758,31 @@ __device__ __forceinline__ void gather_store(const Tables &T, int b, int slab, c
     }
 }
 
+// Range of density and pressure over the old 7-point neighbourhood of slab cell tid (learned
+// correction's acceptance test): rng = {rho min, rho max, p min, p max}.
+template <int KS, typename R>
+__device__ __forceinline__ void neighbour_range(R (*sW)[Slab<KS>::NC], int tid, double rng[4]) {
+    using SL = Slab<KS>;
+    const int i = tid & 7, j = (tid >> 3) & 7, kk = tid >> 6;
+    const int nb7[7] = {SL::idx(i, j, kk), SL::idx(i - 1, j, kk), SL::idx(i + 1, j, kk), SL::idx(i, j - 1, kk),
+                        SL::idx(i, j + 1, kk), SL::idx(i, j, kk - 1), SL::idx(i, j, kk + 1)};
+    double rlo = 1e300, rhi = -1e300, plo = 1e300, phi = -1e300;
+#pragma unroll
+    for (int q = 0; q < 7; ++q) {
+        const double r0 = double(sW[0][nb7[q]]), p0 = double(sW[7][nb7[q]]);
+        rlo = fmin(rlo, r0); rhi = fmax(rhi, r0);
+        plo = fmin(plo, p0); phi = fmax(phi, p0);
+    }
+    rng[0] = rlo; rng[1] = rhi; rng[2] = plo; rng[3] = phi;
+}
+
 // Powell source, stage update and write of the thread's own cell (threads below 64 KS own cell tid of
-// the slab), then the end-of-step bookkeeping: positivity check and the next time-step bound.
+// the slab), then the end-of-step bookkeeping: positivity check and the next time-step bound. With the
+// learned correction, `rng` (or the LDS primitives when it is null) gives the old neighbourhood range.
 template <int KS, typename R, bool POWELL, bool LEARN, typename Mask>
 __device__ __forceinline__ void cell_update(const Tables &T, const StageArgs &A, int b, int slab, const double (&uin)[8],
                                             R (*sW)[Slab<KS>::NC], Mask sM, double (&rhs)[8], double divb,
-                                            double inv_dx, double *red, int *redi) {
+                                            double inv_dx, double *red, int *redi, const double *rng = nullptr) {
     using SL = Slab<KS>;
     const DevBlock &B = T.blocks[b];
     const size_t vs = size_t(T.nb) * 512;
@@ -810,16 +829,14 @@ __device__ __forceinline__ void cell_update(const Tables &T, const StageArgs &A,
             if (!body) {
                 double w[8];
                 cons_to_prim(out, w);
-                const int i = tid & 7, j = (tid >> 3) & 7, kk = tid >> 6;
-                const int nb7[7] = {SL::idx(i, j, kk), SL::idx(i - 1, j, kk), SL::idx(i + 1, j, kk), SL::idx(i, j - 1, kk),
-                                    SL::idx(i, j + 1, kk), SL::idx(i, j, kk - 1), SL::idx(i, j, kk + 1)};
-                double rlo = 1e300, rhi = -1e300, plo = 1e300, phi = -1e300;
+                double nr[4];
+                if (rng) {
 #pragma unroll
-                for (int q = 0; q < 7; ++q) {
-                    const double r0 = double(sW[0][nb7[q]]), p0 = double(sW[7][nb7[q]]);
-                    rlo = fmin(rlo, r0); rhi = fmax(rhi, r0);
-                    plo = fmin(plo, p0); phi = fmax(phi, p0);
+                    for (int q = 0; q < 4; ++q) nr[q] = rng[q];
+                } else {
+                    neighbour_range<KS, R>(sW, tid, nr);
                 }
+                const double rlo = nr[0], rhi = nr[1], plo = nr[2], phi = nr[3];
                 const double rr = A.tau * (rhi - rlo), pr = A.tau * (phi - plo);
                 bad = !(w[0] > 0.0) || !(w[7] > 0.0) || w[0] < rlo - rr || w[0] > rhi + rr || w[7] < plo - pr ||
                       w[7] > phi + pr;
@@ -976,18 +993,18 @@ __device__ __forceinline__ void gather_store_bits(const Tables &T, int b, int sl
     }
 }
 
-template <int KS, typename R, int D, int FLUX>
+template <int KS, typename R, int D, int FLUX, bool LEARN>
 __device__ __forceinline__ void wp_face(const Tables &T, const StageArgs &A, const DevBlock &B, int b, int slab,
                                         R (*sW)[Slab<KS>::NC], BitMask sM, bool near_body, int i, int j, int k,
                                         R fl[8], R &bbar) {
-    if (near_body) face_flux<KS, R, D, FLUX, true, false>(T, A, B, b, slab, sW, sM, i, j, k, fl, bbar);
-    else face_flux<KS, R, D, FLUX, false, false>(T, A, B, b, slab, sW, sM, i, j, k, fl, bbar);
+    if (near_body) face_flux<KS, R, D, FLUX, true, LEARN>(T, A, B, b, slab, sW, sM, i, j, k, fl, bbar);
+    else face_flux<KS, R, D, FLUX, false, LEARN>(T, A, B, b, slab, sW, sM, i, j, k, fl, bbar);
 }
 
 template <typename R>
 __device__ __forceinline__ R lane_down(R x, int delta) { return __shfl_down(x, delta, 64); }
 
-template <int KS, typename R, int FLUX, bool POWELL>
+template <int KS, typename R, int FLUX, bool POWELL, bool LEARN>
 __device__ __forceinline__ void wp_compute(const Tables &T, const StageArgs &A, int b, int slab,
                                            R (*sW)[Slab<KS>::NC], R (*sH)[8 * KS], const uint32_t *sMb, double *red,
                                            int *redi) {
@@ -1005,15 +1022,19 @@ __device__ __forceinline__ void wp_compute(const Tables &T, const StageArgs &A, 
     double rhs[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     double divb = 0.0;
     R fl[8], fr[8], bb, bbr;
+    // learned correction: the old neighbourhood range, taken before the x/y halos are overwritten
+    double rng[4] = {0, 0, 0, 0};
+    if constexpr (LEARN)
+        if (cellw) neighbour_range<KS, R>(sW, tid, rng);
 
     // x: low-x face of each cell; the last wave takes the faces at x = 8 of the slab's 8 KS rows
     if (cellw) {
-        wp_face<KS, R, 0, FLUX>(T, A, B, b, slab, sW, mk, near_body, ci, cj, w, fl, bb);
+        wp_face<KS, R, 0, FLUX, LEARN>(T, A, B, b, slab, sW, mk, near_body, ci, cj, w, fl, bb);
 #pragma unroll
         for (int v = 0; v < 8; ++v) fr[v] = lane_down(fl[v], 1);
         bbr = lane_down(bb, 1);
     } else if (l < NE) {
-        wp_face<KS, R, 0, FLUX>(T, A, B, b, slab, sW, mk, near_body, 8, l & 7, l >> 3, fl, bb);
+        wp_face<KS, R, 0, FLUX, LEARN>(T, A, B, b, slab, sW, mk, near_body, 8, l & 7, l >> 3, fl, bb);
 #pragma unroll
         for (int v = 0; v < 8; ++v) sH[v][l] = fl[v];
         sH[8][l] = bb;
@@ -1033,12 +1054,12 @@ __device__ __forceinline__ void wp_compute(const Tables &T, const StageArgs &A, 
 
     // y: low-y faces; the last wave takes the faces at y = 8
     if (cellw) {
-        wp_face<KS, R, 1, FLUX>(T, A, B, b, slab, sW, mk, near_body, ci, cj, w, fl, bb);
+        wp_face<KS, R, 1, FLUX, LEARN>(T, A, B, b, slab, sW, mk, near_body, ci, cj, w, fl, bb);
 #pragma unroll
         for (int v = 0; v < 8; ++v) fr[v] = lane_down(fl[v], 8);
         bbr = lane_down(bb, 8);
     } else if (l < NE) {
-        wp_face<KS, R, 1, FLUX>(T, A, B, b, slab, sW, mk, near_body, l & 7, 8, l >> 3, fl, bb);
+        wp_face<KS, R, 1, FLUX, LEARN>(T, A, B, b, slab, sW, mk, near_body, l & 7, 8, l >> 3, fl, bb);
 #pragma unroll
         for (int v = 0; v < 8; ++v) sH[v][l] = fl[v];
         sH[8][l] = bb;
@@ -1063,7 +1084,7 @@ __device__ __forceinline__ void wp_compute(const Tables &T, const StageArgs &A, 
     R *zb = &sH[0][0];
     {
         const int kf = cellw ? w : KS;
-        wp_face<KS, R, 2, FLUX>(T, A, B, b, slab, sW, mk, near_body, ci, cj, kf, fl, bb);
+        wp_face<KS, R, 2, FLUX, LEARN>(T, A, B, b, slab, sW, mk, near_body, ci, cj, kf, fl, bb);
         if (kf > 0) {
 #pragma unroll
             for (int v = 0; v < 8; ++v) sW[v][SL::XH + (kf - 1) * 64 + l] = fl[v];
@@ -1084,12 +1105,12 @@ __device__ __forceinline__ void wp_compute(const Tables &T, const StageArgs &A, 
 #pragma unroll
         for (int v = 0; v < 8; ++v) uin[v] = A.Uin[v * vs + off];
     }
-    cell_update<KS, R, POWELL, false>(T, A, b, slab, uin, sW, mk, rhs, divb, inv_dx, red, redi);
+    cell_update<KS, R, POWELL, LEARN>(T, A, b, slab, uin, sW, mk, rhs, divb, inv_dx, red, redi, rng);
 }
 
 // One work item of the persistent form, kept out of line: inlined into the persistent loop the compiler
 // keeps loop-carried copies live through the flux computation and spills (71 VGPRs at 128).
-template <int KS, typename R, int FLUX, bool POWELL>
+template <int KS, typename R, int FLUX, bool POWELL, bool LEARN>
 __device__ __noinline__ void wp_item(const Tables &T, const StageArgs &A, int b, int slab, R (*sW)[Slab<KS>::NC],
                                      R (*sH)[8 * KS], uint32_t *sMb, double *red, int *redi) {
     using SL = Slab<KS>;
@@ -1099,10 +1120,10 @@ __device__ __noinline__ void wp_item(const Tables &T, const StageArgs &A, int b,
         gather_store_bits<KS, R>(T, b, slab, u, sW, sMb);
     }
     __syncthreads();
-    wp_compute<KS, R, FLUX, POWELL>(T, A, b, slab, sW, sH, sMb, red, redi);
+    wp_compute<KS, R, FLUX, POWELL, LEARN>(T, A, b, slab, sW, sH, sMb, red, redi);
 }
 
-template <int KS, typename R, int FLUX, bool POWELL, bool PERSIST>
+template <int KS, typename R, int FLUX, bool POWELL, bool PERSIST, bool LEARN = false>
 __global__ void __launch_bounds__(64 * (KS + 1), 4) k_stage_wp(Tables T, StageArgs A) {
     using SL = Slab<KS>;
     static_assert(SL::NT == 64 * (KS + 1), "one wave per cell layer plus one");
@@ -1126,14 +1147,14 @@ __global__ void __launch_bounds__(64 * (KS + 1), 4) k_stage_wp(Tables T, StageAr
             gather_store_bits<KS, R>(T, b, slab, u, sW, sMb);
         }
         __syncthreads();
-        wp_compute<KS, R, FLUX, POWELL>(T, A, b, slab, sW, sH, sMb, red, redi);
+        wp_compute<KS, R, FLUX, POWELL, LEARN>(T, A, b, slab, sW, sH, sMb, red, redi);
     } else {
         const int step = int(gridDim.x >> 3);
 #pragma nounroll
         for (int it = slot; it < count; it += step) {
             const int item = first + it;
             const int b = T.order[item / S_PER_BLOCK], slab = item % S_PER_BLOCK;
-            wp_item<KS, R, FLUX, POWELL>(T, A, b, slab, sW, sH, sMb, red, redi);
+            wp_item<KS, R, FLUX, POWELL, LEARN>(T, A, b, slab, sW, sH, sMb, red, redi);
             __syncthreads();
             __builtin_amdgcn_sched_barrier(0);
         }
@@ -1488,8 +1509,8 @@ int32_t launch_stage(const HostGrid &h, const StageArgs &a, const bmhd_opts &o, 
 template <typename R, int FLUX>
 int32_t launch_learn_flux(const HostGrid &h, const StageArgs &a, bool powell, hipStream_t s) {
     constexpr int nt = Slab<4>::NT;
-    if (powell) k_stage<4, R, FLUX, true, false, true><<<h.nb * 2, nt, 0, s>>>(h.dev, a);
-    else k_stage<4, R, FLUX, false, false, true><<<h.nb * 2, nt, 0, s>>>(h.dev, a);
+    if (powell) k_stage_wp<4, R, FLUX, true, false, true><<<h.nb * 2, nt, 0, s>>>(h.dev, a);
+    else k_stage_wp<4, R, FLUX, false, false, true><<<h.nb * 2, nt, 0, s>>>(h.dev, a);
     return launch_check("learned stage kernel");
 }
 

@@ -127,7 +127,7 @@ def test_learned_form_zero_network_128(bd, oracle_mod):
     _, wl = learn.magnetosphere_pair(state, 256)
     kw = dict(flux="hlle", powell=True, cfl=0.8)
     R, rdt, rf = oracle_steps(oracle_mod, wl, 2, **kw)
-    P, dt, f = gpu_steps(bd, wl, 2, scheme="face", slab=4, **kw)
+    P, dt, f = gpu_steps(bd, wl, 2, scheme="plane", slab=4, **kw)
     assert f == 0 and rf == 0 and max(group_err(P, R).values()) <= TOL
     mlp0 = bd.Mlp(128)
     stats = torch.zeros(80)

@@ -81,9 +81,9 @@ def _learned_run(bd, wl, mlp, stats, n_stages, precision, flux, powell, fallback
     dt = torch.zeros(len(wl.sims), dtype=torch.float64, device="cuda")
     faults = torch.zeros(1, dtype=torch.int32, device="cuda")
     L = g.learned(mlp, stats, fallback=fallback) if mlp is not None else None
-    # the learned stage runs the face-per-thread kernel on 8x8x4 slabs: compare with the same plain kernel
+    # the learned stage runs the wave-per-layer kernel on 8x8x4 slabs: compare with the same plain kernel
     g.advance(U0, U1, dt, n_stages, faults=faults, flux=flux, powell=powell, precision=precision, learned=L,
-              scheme="face", slab=4)
+              scheme="plane", slab=4)
     torch.cuda.synchronize()
     return U0.cpu().numpy(), dt.cpu().numpy(), int(faults.item())
 
@@ -145,7 +145,7 @@ def test_learned_stage_adds_the_network_increment(bd):
     assert int(fb.item()) == 0
     assert torch.allclose(X_in, Xref, rtol=1e-5, atol=1e-5), float((X_in - Xref).abs().max())
     Ub, U1b = U0.clone(), torch.zeros_like(U0)
-    g.advance(Ub, U1b, dt, 1, scheme="face", slab=4, **kw)
+    g.advance(Ub, U1b, dt, 1, scheme="plane", slab=4, **kw)
     # the stage de-normalises in FP32 (a multiply-add per component)
     Y = mlp.forward(X_in).cpu().numpy()
     s = stats.numpy()
