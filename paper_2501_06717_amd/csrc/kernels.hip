@@ -3,13 +3,14 @@
 // Hot path per stage (the GPU solver's block sweep, Algorithm 2, redesigned for MI355X):
 //   k_halo_fill   ghost layers of faces that border another level (restriction / prolongation,
 //                 Sec. 4.2), only on grids with two levels;
-//   k_stage       one workgroup per slab of a block (8 x 8 x KS cells). It gathers the slab and its
+//   k_stage_wp    (default) one workgroup per slab of a block (8 x 8 x KS cells), one wavefront per
+//   / k_stage     cell layer plus one (or, k_stage, one thread per face). It gathers the slab and its
 //                 2-deep face halos from HBM straight into LDS as primitive variables (same-level
 //                 neighbours are read in place: no separate ghost-fill pass), computes every face flux
-//                 once (MC-limited reconstruction, Rusanov or HLLE), exchanges fluxes through LDS,
-//                 adds the Powell source (Eqs. 2-4) and writes the stage result. The second stage also
-//                 folds in the next time-step bound (wave-level max, one filtered 64-bit atomic per
-//                 workgroup) and the positivity check;
+//                 once (MC-limited reconstruction, Rusanov or HLLE), hands each flux to the cells on
+//                 both sides (cross-lane permutes and LDS), adds the Powell source (Eqs. 2-4) and
+//                 writes the stage result. The second stage also folds in the next time-step bound
+//                 (wave-level max, one filtered 64-bit atomic per workgroup) and the positivity check;
 //   k_flux_correct coarse cells next to a coarse-fine face swap their coarse flux for the mean of the
 //                 four fine fluxes (FP64 in every precision form);
 //   k_dt_finalize dt = CFL / max bound per simulation.
@@ -653,7 +654,7 @@ __device__ __forceinline__ void face_flux(const Tables &T, const StageArgs &A, c
 
 // One sweep of the face-per-thread scheme: thread f takes face f of direction D and leaves its flux in
 // sF for the two cells on either side.
-template <int KS, typename R, int D, int FLUX, bool BODY, bool LEARN>
+template <int KS, typename R, int D, int FLUX, bool BODY>
 __device__ __forceinline__ void sweep(const Tables &T, const StageArgs &A, const DevBlock &B, int b, int slab,
                                       R (*sW)[Slab<KS>::NC], const unsigned char *sM, R (*sF)[Slab<KS>::NF]) {
     using SL = Slab<KS>;
@@ -665,7 +666,7 @@ __device__ __forceinline__ void sweep(const Tables &T, const StageArgs &A, const
     else if (D == 1) { i = f & 7; j = (f >> 3) % 9; k = f / 72; }
     else { i = f & 7; j = (f >> 3) & 7; k = f >> 6; }
     R fl[8], bbar;
-    face_flux<KS, R, D, FLUX, BODY, LEARN>(T, A, B, b, slab, sW, ByteMask{sM}, i, j, k, fl, bbar);
+    face_flux<KS, R, D, FLUX, BODY, false>(T, A, B, b, slab, sW, ByteMask{sM}, i, j, k, fl, bbar);
 #pragma unroll
     for (int v = 0; v < 8; ++v) sF[v][f] = fl[v];
     sF[8][f] = bbar;
@@ -867,7 +868,7 @@ __device__ __forceinline__ void cell_update(const Tables &T, const StageArgs &A,
 }
 
 // Sweeps, source, update and end-of-step bookkeeping for one slab whose primitives are in LDS.
-template <int KS, typename R, int FLUX, bool POWELL, bool LEARN>
+template <int KS, typename R, int FLUX, bool POWELL>
 __device__ __forceinline__ void slab_compute(const Tables &T, const StageArgs &A, int b, int slab, const double (&uin)[8],
                                              R (*sW)[Slab<KS>::NC], unsigned char *sM, R (*sF)[Slab<KS>::NF],
                                              double *red, int *redi) {
@@ -883,21 +884,21 @@ __device__ __forceinline__ void slab_compute(const Tables &T, const StageArgs &A
     const double inv_dx = double(1 << B.level) / S.dx0;
     double rhs[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     double divb = 0.0;
-    if (near_body) sweep<KS, R, 0, FLUX, true, LEARN>(T, A, B, b, slab, sW, sM, sF);
-    else sweep<KS, R, 0, FLUX, false, LEARN>(T, A, B, b, slab, sW, sM, sF);
+    if (near_body) sweep<KS, R, 0, FLUX, true>(T, A, B, b, slab, sW, sM, sF);
+    else sweep<KS, R, 0, FLUX, false>(T, A, B, b, slab, sW, sM, sF);
     __syncthreads();
     if (owner) accumulate<KS, R, 0>(sF, rhs, divb, inv_dx);
     __syncthreads();
-    if (near_body) sweep<KS, R, 1, FLUX, true, LEARN>(T, A, B, b, slab, sW, sM, sF);
-    else sweep<KS, R, 1, FLUX, false, LEARN>(T, A, B, b, slab, sW, sM, sF);
+    if (near_body) sweep<KS, R, 1, FLUX, true>(T, A, B, b, slab, sW, sM, sF);
+    else sweep<KS, R, 1, FLUX, false>(T, A, B, b, slab, sW, sM, sF);
     __syncthreads();
     if (owner) accumulate<KS, R, 1>(sF, rhs, divb, inv_dx);
     __syncthreads();
-    if (near_body) sweep<KS, R, 2, FLUX, true, LEARN>(T, A, B, b, slab, sW, sM, sF);
-    else sweep<KS, R, 2, FLUX, false, LEARN>(T, A, B, b, slab, sW, sM, sF);
+    if (near_body) sweep<KS, R, 2, FLUX, true>(T, A, B, b, slab, sW, sM, sF);
+    else sweep<KS, R, 2, FLUX, false>(T, A, B, b, slab, sW, sM, sF);
     __syncthreads();
     if (owner) accumulate<KS, R, 2>(sF, rhs, divb, inv_dx);
-    cell_update<KS, R, POWELL, LEARN>(T, A, b, slab, uin, sW, ByteMask{sM}, rhs, divb, inv_dx, red, redi);
+    cell_update<KS, R, POWELL, false>(T, A, b, slab, uin, sW, ByteMask{sM}, rhs, divb, inv_dx, red, redi);
 }
 
 // Work item -> (block, slab). Items are the slabs of the Morton-ordered block list. XCD x (workgroups
@@ -913,7 +914,7 @@ __device__ __forceinline__ int xcd_count(int nwork, int x) { return (nwork >> 3)
 // gather of a slab is issued at the top of its iteration: holding the next slab's 24 values per thread
 // in registers across the flux sweeps would double the register footprint and halve occupancy, while
 // two co-resident workgroups per CU already overlap one's gather with the other's sweeps.
-template <int KS, typename R, int FLUX, bool POWELL, bool PERSIST, bool LEARN = false>
+template <int KS, typename R, int FLUX, bool POWELL, bool PERSIST>
 __global__ void __launch_bounds__(Slab<KS>::NT) k_stage(Tables T, StageArgs A) {
     using SL = Slab<KS>;
     constexpr int S_PER_BLOCK = 8 / KS;
@@ -933,7 +934,7 @@ __global__ void __launch_bounds__(Slab<KS>::NT) k_stage(Tables T, StageArgs A) {
         gather_issue<KS>(T, A, b, slab, u);
         gather_store<KS, R>(T, b, slab, u, sW, sM);
         __syncthreads();
-        slab_compute<KS, R, FLUX, POWELL, LEARN>(T, A, b, slab, u[0], sW, sM, sF, red, redi);
+        slab_compute<KS, R, FLUX, POWELL>(T, A, b, slab, u[0], sW, sM, sF, red, redi);
     } else {
         const int step = int(gridDim.x >> 3);
 #pragma nounroll
@@ -944,7 +945,7 @@ __global__ void __launch_bounds__(Slab<KS>::NT) k_stage(Tables T, StageArgs A) {
             gather_issue<KS>(T, A, b, slab, u);
             gather_store<KS, R>(T, b, slab, u, sW, sM);
             __syncthreads();
-            slab_compute<KS, R, FLUX, POWELL, LEARN>(T, A, b, slab, u[0], sW, sM, sF, red, redi);
+            slab_compute<KS, R, FLUX, POWELL>(T, A, b, slab, u[0], sW, sM, sF, red, redi);
             __syncthreads();
             // keep the scheduler from overlapping iterations (that would hold two slabs' values live)
             __builtin_amdgcn_sched_barrier(0);
