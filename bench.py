@@ -7,9 +7,10 @@ step of the whole hot path: dt reduction, two fused stage kernels (ghost gather,
 source, update, next-dt bound). Inputs are resident in HBM before the timed region starts.
 
 Prints one JSON line (rank 0). Extra fields: "roofline" for the dominant kernel (the stage kernel, timed
-live with HIP events that the library records on its stream), "cpu_baseline" (the CPU oracle on the
-host's cores over a bounded sample), and "forms" (the FP32-flux form on the same workload, with its
-error against the FP64 path).
+live with HIP events that the library records on its stream; its "valu" object puts the same timing
+against the VALU issue peak, the bound this FP64 kernel actually meets), "cpu_baseline" (the CPU oracle
+on the host's cores over a bounded sample), and "forms" (the FP32-flux form on the same workload with
+its error against the FP64 path, the 64-simulation batch, the learned correction).
 """
 from __future__ import annotations
 
@@ -33,6 +34,14 @@ TRAFFIC = {
     ("face", 8): (1.722e9 + 1.074e9, 2.807e9 + 1.074e9),
     ("plane", 4): (2.019e9 + 1.074e9, 3.007e9 + 1.074e9),
 }
+
+
+# VALU lane instructions per cell and stage of the FP64 stage kernel on this workload (mean of the two
+# stages, SQ_INSTS_VALU x 64 / cells from a rocprofv3 counter run; the summary under profiles/), keyed
+# like TRAFFIC; the VALU issue peak is one wave64 instruction per CU per clock (4 SIMDs x 16 lanes):
+# 256 CUs x 2.4 GHz x 64 lanes
+VALU_PER_CELL_STAGE = {("plane", 4): 1933.0}
+VALU_PEAK_LANE_OPS = 256 * 2.4e9 * 64
 
 
 def resolve_shape(scheme, slab, precision):
@@ -194,6 +203,14 @@ def main():
     kname = ("k_stage_wp" if scheme == "plane" else "k_stage") + f"<{ks}, double, HLLE, Powell>"
     meas = TRAFFIC.get((scheme, ks)) if (a.n == 256 and not a.persist) else None
     traffic = 0.5 * (meas[0] + meas[1]) if meas else None
+    vpc = VALU_PER_CELL_STAGE.get((scheme, ks)) if (a.n == 256 and not a.persist) else None
+    valu = None
+    if vpc:
+        rate = vpc * cells * 2 / (t1 + t2)
+        valu = {"bound": "alu", "achieved": rate / 1e12, "peak": VALU_PEAK_LANE_OPS / 1e12,
+                "unit": "T VALU lane-instructions/s", "frac": rate / VALU_PEAK_LANE_OPS,
+                "instructions_per_cell_stage": vpc,
+                "hbm_frac_at_full_valu_issue": VALU_PEAK_LANE_OPS / (2 * vpc) * 320 / (HBM_PEAK_GBS * 1e9)}
     log(f"fp64: {wall * 1e3:.2f} ms for {steps} steps, stage kernels {t1 * 1e6:.1f} / {t2 * 1e6:.1f} us, "
         f"faults {faults}, dt {dt_last:.4e}")
     out = {
@@ -218,7 +235,8 @@ def main():
                      "algorithmic_bytes_per_launch": 0.5 * cells * (BYTES_STAGE[0] + BYTES_STAGE[1]),
                      "kernel": kname + " (both stages; " + ("wave per cell layer" if scheme == "plane"
                                                             else "face per thread") + f", tile 8x8x{ks})",
-                     "stage_us": [t1 * 1e6, t2 * 1e6], "bytes_per_cell_update": 320},
+                     "stage_us": [t1 * 1e6, t2 * 1e6], "bytes_per_cell_update": 320,
+                     "valu": valu},
         "faults": faults,
     }
     if a.calib:
