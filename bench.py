@@ -9,8 +9,9 @@ source, update, next-dt bound). Inputs are resident in HBM before the timed regi
 Prints one JSON line (rank 0). Extra fields: "roofline" for the dominant kernel (the stage kernel, timed
 live with HIP events that the library records on its stream; its "valu" object puts the same timing
 against the VALU issue peak, the bound this FP64 kernel actually meets), "cpu_baseline" (the CPU oracle
-on the host's cores over a bounded sample), and "forms" (the FP32-flux form on the same workload with
-its error against the FP64 path, the 64-simulation batch, the learned correction).
+on the host's cores over a bounded sample), "forms" (the FP32-flux form on the same workload with its
+error against the FP64 path, the 64-simulation batch, the learned correction) and "paper_context" (the
+paper's one-GPU fast-wave run on the same grid geometry, beside its published one-A100 time).
 """
 from __future__ import annotations
 
@@ -179,6 +180,32 @@ def bench_learned(steps):
                         "(gain 0.49-0.70) or diverged (profiles/learned_correction_magnetosphere128.md)"}
 
 
+def bench_paper_fast_wave():
+    """The paper's one-GPU fast-wave run (Sec. 5.1, Eq. 6, Table 2 at m = 6) in 8^3 blocks: the periodic
+    domain [-32, 32]^3 as 10^3 root blocks (dx = 0.8) with the octant [-32, 0]^3 refined once, 1,875
+    blocks = 960,000 cells as in the paper's 960 blocks of 10^3; FP64, HLLE + Powell (the paper uses the
+    Linde flux), MC, Heun, CFL 0.8, 500 steps. Context beside Table 3's one-A100 total, not a target."""
+    import torch
+    from paper_2501_06717_amd import binding, workloads as wk
+    wl = wk.fast_wave((10, 10, 10), refine_octant=True)
+    g = binding.Grid.from_workload(wl).upload()
+    U0 = g.set_state(torch.from_numpy(wl.W).cuda())
+    U1 = torch.empty_like(U0)
+    dt = torch.zeros(1, dtype=torch.float64, device="cuda")
+    faults = torch.zeros(1, dtype=torch.int32, device="cuda")
+    steps = 500
+    t = time_advance(g, U0, U1, dt, steps, flux="hlle", powell=True, cfl=0.8, faults=faults)
+    cells = wl.n_cells
+    log(f"paper fast wave: {cells} cells, {steps} steps in {t:.3f} s")
+    return {"value": cells * steps / t, "unit": "cell-updates/s", "wall_s": t, "steps": steps,
+            "workload": f"fast wave (Eq. 6), [-32,32]^3 periodic, 10^3 root blocks of 8^3 + refined octant: "
+                        f"{wl.n_blocks} blocks, {cells} cells, FP64, HLLE + Powell, MC, Heun, CFL 0.8",
+            "faults": int(faults.item()),
+            "paper_one_a100": {"wall_s": 5.76, "value": 960000 * 500 / 5.76, "unit": "cell-updates/s",
+                               "workload": "960 blocks of 10^3 cells, Linde flux, 500 steps (Table 3, m = 6)"},
+            "ratio_to_paper": cells * steps / t / (960000 * 500 / 5.76)}
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -267,6 +294,7 @@ def main():
         out.setdefault("forms", {})
         out["forms"]["batched"] = bench_batched(a.form_steps)
         out["forms"]["learned"] = bench_learned(a.form_steps)
+        out["paper_context"] = {"fast_wave": bench_paper_fast_wave()}
     if not (a.no_cpu_baseline or a.profile):
         import oracle
         o = oracle.Grid.from_workload(wl)

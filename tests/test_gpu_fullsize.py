@@ -1,7 +1,8 @@
 """GPU parity at the full sizes the benchmark runs, in the launch configuration it times: the 256^3
-magnetosphere (one step, default stage-kernel shape), the two-level magnetosphere of 3.8 M cells, and
-the 64-simulation batch (autotuned shape, graph-replayed steps). The oracle computes every cell of
-these steps on the host's cores (seconds), so the comparison covers the whole state, not a sample.
+magnetosphere (one step, default stage-kernel shape), the paper's one-GPU fast-wave grid, the two-level
+magnetosphere of 3.8 M cells, and the 64-simulation batch (autotuned shape, graph-replayed steps). The
+oracle computes every cell of these steps on the host's cores (seconds), so the comparison covers the
+whole state, not a sample.
 FP64 within 1e-12 per variable group; the FP32-flux form within a stated bound."""
 import sys
 
@@ -75,6 +76,21 @@ def test_magnetosphere_256_one_step(bd, oracle_mod):
     err32 = group_err(G32, R)
     say("  fp32_flux err", err32)
     assert f32 == 0 and max(err32.values()) <= FP32_TOL, err32
+
+
+def test_paper_fast_wave_grid_two_steps(bd, oracle_mod):
+    """The paper's one-GPU fast-wave grid (Table 2 at m = 6, in 8^3 blocks: 1,875 blocks, 960,000 cells,
+    one refined octant, periodic) with the Eq. (6) state: two steps, every cell against the oracle."""
+    wl = wk.fast_wave((10, 10, 10), refine_octant=True)
+    kw = dict(flux="hlle", powell=True, cfl=0.8)
+    say("paper fast wave:", wl.n_blocks, "blocks")
+    R, rdt, rf = oracle_steps(oracle_mod, wl, 4, **kw)
+    G, dt, f = gpu_steps(bd, wl, 4, **kw)
+    assert f == 0 and rf == 0
+    assert np.all(np.abs(dt - rdt) <= 1e-14 * rdt), (dt, rdt)
+    err = group_err(G, R)
+    say("  fp64 err", err)
+    assert max(err.values()) <= TOL, err
 
 
 def test_two_level_magnetosphere_one_step(bd, oracle_mod):
