@@ -38,7 +38,7 @@ class _Sim(ctypes.Structure):
 class _Opts(ctypes.Structure):
     _fields_ = [("flux", ctypes.c_int32), ("powell", ctypes.c_int32), ("n_table", ctypes.c_int32),
                 ("recompute_dt", ctypes.c_int32), ("alpha", ctypes.c_double * 2),
-                ("beta", ctypes.c_double * 2), ("cfl", ctypes.c_double)]
+                ("beta", ctypes.c_double * 2), ("cfl", ctypes.c_double), ("local_dt", ctypes.c_int32)]
 
 
 _lib = None
@@ -198,12 +198,14 @@ class Grid:
         return out
 
     def advance(self, U0, U1, dt, n_stages, flux="rusanov", powell=False, cfl=0.8, recompute_dt=True,
-                alpha=(0.0, 0.5), beta=(1.0, 0.5)):
-        """Advance in place (U0, U1 updated; returns (dt, faults)). Heun by default."""
+                alpha=(0.0, 0.5), beta=(1.0, 0.5), local_dt=False):
+        """Advance in place (U0, U1 updated; returns (dt, faults)). Heun by default. With local_dt (local
+        time stepping) dt is one value per cell, shape (nB, 8, 8, 8), instead of one per simulation."""
         assert U0.flags.c_contiguous and U1.flags.c_contiguous
-        dt = np.ascontiguousarray(np.broadcast_to(np.asarray(dt, np.float64), (self.ns,))).copy()
+        shape = (self.nb, 8, 8, 8) if local_dt else (self.ns,)
+        dt = np.ascontiguousarray(np.broadcast_to(np.asarray(dt, np.float64), shape)).copy()
         o = _Opts(FLUX[flux], int(bool(powell)), 2, int(bool(recompute_dt)),
-                  (ctypes.c_double * 2)(*alpha), (ctypes.c_double * 2)(*beta), float(cfl))
+                  (ctypes.c_double * 2)(*alpha), (ctypes.c_double * 2)(*beta), float(cfl), int(bool(local_dt)))
         faults = ctypes.c_long(0)
         rc = lib().or_advance(self.h, _dp(U0), _dp(U1), _dp(dt), int(n_stages), ctypes.byref(o),
                               ctypes.byref(faults))

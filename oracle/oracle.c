@@ -59,6 +59,7 @@ typedef struct {
     double alpha[2];
     double beta[2];
     double cfl;
+    int32_t local_dt;  /* 1: local time stepping, dt[] holds one dt per cell ([nB][8][8][8]) */
 } or_opts;
 
 typedef struct {
@@ -562,6 +563,30 @@ static void compute_dt(const or_grid *g, double *st, double cfl, double *dt)
     }
 }
 
+/* Local time stepping (the paper's steady-state sessions, Sec. 5.2): every fluid cell advances with its
+ * own step, the same CFL bound as compute_dt taken per cell, dt_i = CFL * 1 / sum_d ((|u_d| + c_f,d) / dx).
+ * Body cells get 0 (they are not updated). dt[] has the layout of one variable, [nB][8][8][8]. */
+static void compute_local_dt(const or_grid *g, double *st, double cfl, double *dt)
+{
+    for (int b = 0; b < g->nb; b++) {
+        double dx = cell_dx(g, b);
+        for (int k = 0; k < NC; k++)
+            for (int j = 0; j < NC; j++)
+                for (int i = 0; i < NC; i++) {
+                    double *t = dt + (size_t)b * NC * NC * NC + (k * NC + j) * NC + i;
+                    if (is_body(g, b, i, j, k)) {
+                        *t = 0.0;
+                        continue;
+                    }
+                    double w[NV];
+                    or_cons_to_prim(pcell(st, b, i, j, k), w);
+                    double lam = 0.0;
+                    for (int d = 0; d < 3; d++) lam = lam + (fabs(w[1 + d]) + or_fast_speed(w, d)) / dx;
+                    *t = cfl * (1.0 / lam);
+                }
+    }
+}
+
 /* ------------------------------------------------------------------------------------------------ */
 /* one stage on one block (Algorithm 1, body of the block loop)                                     */
 
@@ -622,9 +647,11 @@ static void calc_face_values_and_fluxes(const or_grid *g, int b, double *st, con
 }
 
 /* Source (Powell terms, right-hand sides of Eqs. 2-4) and update of the physical cells.
- * out = alpha * u0 + (1 - alpha) * in + beta * dt * (-sum_d dF_d / dx + S). Body cells are copied. */
+ * out = alpha * u0 + (1 - alpha) * in + beta * dt * (-sum_d dF_d / dx + S). Body cells are copied.
+ * dloc (may be NULL): the block's per-cell dt under local time stepping, in place of dt. */
 static void calc_source_and_update(const or_grid *g, int b, double *in, double *u0, double *out, double dt,
-                                   double alpha, double beta, const or_opts *o, const or_faces *F)
+                                   const double *dloc, double alpha, double beta, const or_opts *o,
+                                   const or_faces *F)
 {
     double dx = cell_dx(g, b);
     for (int k = 0; k < NC; k++)
@@ -655,8 +682,9 @@ static void calc_source_and_update(const or_grid *g, int b, double *in, double *
                     }
                     rhs[7] = rhs[7] - divb * ub;
                 }
+                double dtc = dloc ? dloc[(k * NC + j) * NC + i] : dt;
                 for (int v = 0; v < NV; v++)
-                    co[v] = alpha * c0[v] + (1.0 - alpha) * ci[v] + beta * dt * rhs[v];
+                    co[v] = alpha * c0[v] + (1.0 - alpha) * ci[v] + beta * dtc * rhs[v];
             }
 }
 
@@ -691,7 +719,9 @@ static int find_fine_faces(const or_grid *g, int s, int bc, int d, int side, int
     return 1;
 }
 
-static void flux_correction(const or_grid *g, or_faces **faces, double *out, const double *dt, double beta)
+/* dt: per simulation, or per cell when local (local time stepping) */
+static void flux_correction(const or_grid *g, or_faces **faces, double *out, const double *dt, int local,
+                            double beta)
 {
     for (int b = 0; b < g->nb; b++) {
         if (g->level[b] != 0 || !faces[b]) continue;
@@ -714,12 +744,13 @@ static void flux_correction(const or_grid *g, or_faces **faces, double *out, con
                         face_cell(d, side ? NC - 1 : 0, t1, t2, ci);
                         double *co = pcell(out, b, ci[0], ci[1], ci[2]);
                         if (is_body(g, b, ci[0], ci[1], ci[2])) continue;
+                        double dtc = local ? dt[(size_t)b * NC * NC * NC + (ci[2] * NC + ci[1]) * NC + ci[0]] : dt[s];
                         for (int v = 0; v < NV; v++) {
                             double a = Ff->f[d][ff][f2][f1][v], bq = Ff->f[d][ff][f2][f1 + 1][v];
                             double c = Ff->f[d][ff][f2 + 1][f1][v], e = Ff->f[d][ff][f2 + 1][f1 + 1][v];
                             double fmean = ((a + bq) + (c + e)) * 0.25;
                             double fcv = faces[b]->f[d][fc][t2][t1][v];
-                            co[v] = co[v] + beta * dt[s] * sgn * (fcv - fmean) / dxc;
+                            co[v] = co[v] + beta * dtc * sgn * (fcv - fmean) / dxc;
                         }
                     }
             }
@@ -800,7 +831,8 @@ static long count_faults(const or_grid *g, double *st)
 /* Advance n_stages stages. Stage s uses table entry s % n_table; even stages read U0 and write U1,
  * odd stages read U1 (and U0 as the step's starting state) and overwrite U0. With recompute_dt, dt is
  * recomputed from U0 at the start of every step; otherwise dt[] is used as given. On return dt[] holds
- * the last step's dt and *faults the number of non-positive cells after the last stage. */
+ * the last step's dt and *faults the number of non-positive cells after the last stage. With local_dt,
+ * dt[] holds one dt per cell ([nB][8][8][8], local time stepping) instead of one per simulation. */
 int or_advance(const or_grid *g, double *U0, double *U1, double *dt, int n_stages, const or_opts *o, long *faults)
 {
     if (o->n_table != 2) return -1;
@@ -818,7 +850,10 @@ int or_advance(const or_grid *g, double *U0, double *U1, double *dt, int n_stage
         int e = st % 2;
         double alpha = o->alpha[e], beta = o->beta[e];
         double *in = e ? s1 : s0, *out = e ? s0 : s1;
-        if (e == 0 && o->recompute_dt) compute_dt(g, s0, o->cfl, dt);
+        if (e == 0 && o->recompute_dt) {
+            if (o->local_dt) compute_local_dt(g, s0, o->cfl, dt);
+            else compute_dt(g, s0, o->cfl, dt);
+        }
         exchange_messages(g, in);
 #pragma omp parallel
         {
@@ -827,11 +862,13 @@ int or_advance(const or_grid *g, double *U0, double *U1, double *dt, int n_stage
             for (int b = 0; b < g->nb; b++) {
                 or_faces *F = faces[b] ? faces[b] : tmp;
                 calc_face_values_and_fluxes(g, b, in, o, F);
-                calc_source_and_update(g, b, in, s0, out, dt[g->sim[b]], alpha, beta, o, F);
+                const double *dloc = o->local_dt ? dt + (size_t)b * NC * NC * NC : NULL;
+                calc_source_and_update(g, b, in, s0, out, o->local_dt ? 0.0 : dt[g->sim[b]], dloc, alpha, beta,
+                                       o, F);
             }
             free(tmp);
         }
-        if (any_change) flux_correction(g, faces, out, dt, beta);
+        if (any_change) flux_correction(g, faces, out, dt, o->local_dt, beta);
     }
     if (faults) *faults = count_faults(g, (n_stages % 2) ? s1 : s0);
     pad_to_ext(g, s0, U0);

@@ -328,6 +328,19 @@ def two_level_box(nroot=(4, 3, 2), refine=((1, 1, 0), (2, 1, 0), (1, 0, 1)), bc=
     return with_state(wl, random_positive_state(wl, seed))
 
 
+def uniform_bound_state(wl: Workload, seed=0, rho=1.0, p=0.6, u0=0.3, b0=0.8):
+    """A state whose CFL bound is the same in every cell although the state is not uniform: density and
+    pressure uniform, velocity (0, +-u0, 0) and field (0, 0, +-b0) with independent random signs per cell.
+    Every cell then has the same |u_d| and the same fast speed along each axis."""
+    rng = np.random.default_rng(seed)
+    W = _empty_W(wl.n_blocks)
+    W[0] = rho
+    W[7] = p
+    W[2] = u0 * rng.choice([-1.0, 1.0], size=W[2].shape)
+    W[6] = b0 * rng.choice([-1.0, 1.0], size=W[6].shape)
+    return W
+
+
 # --------------------------------------------------------------------------------------------------
 # batched simulations of superposed linear MHD waves
 

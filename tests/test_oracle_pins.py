@@ -492,3 +492,59 @@ def test_paper_fast_wave_phase_speed(oracle_mod):
     shift = (ph0 - ph1) % (2 * math.pi)
     speed = shift / k / t_end
     assert abs(speed - g_["c_F"]) < 0.02 * g_["c_F"], speed
+
+
+# ------------------------------------------------------------------------------------------------
+# local time stepping: each cell advances with its own CFL step
+
+def test_local_dt_minimum_is_the_global_dt(oracle_mod):
+    """Per-cell steps are the CFL bound taken cell by cell: their minimum over fluid cells is the global
+    step of the same state, and body cells get 0."""
+    for wl in (wk.magnetosphere_cut(32), wk.two_level_box()):
+        o = oracle_mod.Grid.from_workload(wl)
+        U0 = o.set_state(wl.W)
+        dt_global = o.dt(U0, 0.8)
+        U1 = np.zeros_like(U0)
+        dloc, _ = o.advance(U0.copy(), U1, 0.0, 2, flux="hlle", powell=True, cfl=0.8, local_dt=True)
+        body = dloc == 0.0
+        assert body.any() == wl.name.startswith("magnetosphere")
+        assert np.all(dloc[~body] > 0.0)
+        assert dloc[~body].min() == dt_global[0]
+        # a cell with a smaller bound takes a larger step: dt_i * bound_i is the same CFL number everywhere
+        assert dloc[~body].max() > dt_global[0]
+
+
+def test_local_dt_with_a_uniform_bound_is_the_global_step(oracle_mod):
+    """When every cell has the same CFL bound (one level, a state with the same |u_d| and fast speeds
+    everywhere), one step of local time stepping is one step of the global scheme bit for bit."""
+    wl = wk.odd_box()
+    wl = wk.with_state(wl, wk.uniform_bound_state(wl, seed=1))
+    o = oracle_mod.Grid.from_workload(wl)
+    for flux, powell in (("hlle", True), ("rusanov", False)):
+        Ug, Ul = o.set_state(wl.W), o.set_state(wl.W)
+        dtg, fg = o.advance(Ug, np.zeros_like(Ug), 0.0, 2, flux=flux, powell=powell, cfl=0.8)
+        dtl, fl = o.advance(Ul, np.zeros_like(Ul), 0.0, 2, flux=flux, powell=powell, cfl=0.8, local_dt=True)
+        assert fg == 0 and fl == 0
+        assert np.all(dtl == dtg[0])
+        assert np.array_equal(Ug, Ul)
+        # the state did change: the pin is not the trivial uniform case
+        assert np.abs(Ug - o.set_state(wl.W)).max() > 1e-3
+
+
+@pytest.mark.parametrize("case", ["body", "two_level"])
+def test_local_dt_stage_uses_each_cells_step(oracle_mod, case):
+    """One stage of local time stepping is U + dt_i L_i(U), with L the residual of the global scheme
+    (a stage with dt = 1 given), cell by cell; on the two-level grid L includes the flux correction of the
+    coarse cells at the resolution change, which is linear in dt as well."""
+    wl = wk.magnetosphere_cut(32) if case == "body" else wk.two_level_box()
+    o = oracle_mod.Grid.from_workload(wl)
+    U = o.set_state(wl.W)
+    Ug = U.copy(); Ug1 = np.zeros_like(U)
+    o.advance(Ug, Ug1, 1.0, 1, flux="hlle", powell=True, recompute_dt=False)
+    L = Ug1 - U
+    Ul = U.copy(); Ul1 = np.zeros_like(U)
+    dloc, _ = o.advance(Ul, Ul1, 0.0, 1, flux="hlle", powell=True, cfl=0.8, local_dt=True)
+    expect = U + dloc[None] * L
+    scale = np.abs(U).max(axis=(1, 2, 3, 4), keepdims=True)
+    assert np.all(np.abs(Ul1 - expect) <= 8 * np.finfo(float).eps * scale)
+    assert np.abs(Ul1 - U).max() > 0.0
