@@ -124,6 +124,11 @@ typedef struct {
     void **events;        /* optional caller-created hipEvent_t handles: when n_events >= 2 * n_stages,
                              events[2s] and events[2s+1] are recorded on `stream` right before and after
                              the stage kernel of stage s (for timing the dominant kernel) */
+    int32_t local_dt;     /* 1: local time stepping (the steady-state sessions of Sec. 5.2): every fluid
+                             cell advances with its own CFL step, dt_i = cfl * 1 / sum_d ((|u_d| + c_f,d) /
+                             dx), in both stages and in the flux correction; d_dt is then one value per cell,
+                             [n_blocks][8][8][8] like one variable of d_U (0 for body cells). Not combined
+                             with `learned` (BMHD_EUNSUPPORTED). */
 } bmhd_opts;
 
 typedef struct {
@@ -184,9 +189,10 @@ int32_t bmhd_reduce_dt(const bmhd_grid *g, const double *d_U, double cfl, double
 /* Advance n_stages stages of the two-stage scheme (Algorithm 2's block sweep, repeated). Stage s uses
  * table entry s % 2: even stages read d_U0 (with ghost cells from neighbours) and write d_U1; odd
  * stages read d_U1 and d_U0 and overwrite d_U0, so a whole step leaves U^{n+1} in d_U0. A call starts
- * at a step boundary; after an odd n_stages the intermediate state is in d_U1. d_dt[n_sims]: with
- * recompute_dt, dt is recomputed at the start of every step and d_dt returns the last step's dt;
- * otherwise d_dt is read as given. d_faults (int32[1], may be NULL) is incremented by the number of
+ * at a step boundary; after an odd n_stages the intermediate state is in d_U1. d_dt[n_sims] (with
+ * local_dt: d_dt[n_blocks * 512], one step per cell): with recompute_dt, dt is recomputed at the start of
+ * every step (under local_dt by the first stage, from its input state) and d_dt returns the last step's
+ * dt; otherwise d_dt is read as given. d_faults (int32[1], may be NULL) is incremented by the number of
  * fluid cells with rho <= 0, p <= 0 or a non-finite value at the end of each step. Requires a prior
  * bmhd_grid_upload. */
 int32_t bmhd_advance(const bmhd_grid *g, double *d_U0, double *d_U1, double *d_dt, int32_t n_stages,

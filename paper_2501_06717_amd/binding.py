@@ -51,7 +51,7 @@ class Opts(ctypes.Structure):
                 ("beta", ctypes.c_double * 2), ("slab", ctypes.c_int32), ("scheme", ctypes.c_int32),
                 ("persist_wgs", ctypes.c_int32),
                 ("use_graph", ctypes.c_int32), ("learned", ctypes.POINTER(Learned)), ("n_events", ctypes.c_int32),
-                ("events", ctypes.POINTER(ctypes.c_void_p))]
+                ("events", ctypes.POINTER(ctypes.c_void_p)), ("local_dt", ctypes.c_int32)]
 
 
 class GridInfo(ctypes.Structure):
@@ -126,9 +126,10 @@ def _check(rc):
 
 def make_opts(flux="rusanov", powell=False, precision="fp64", recompute_dt=True, cfl=0.8,
               alpha=(0.0, 0.5), beta=(1.0, 0.5), slab=0, scheme=0, persist_wgs=0, use_graph=False,
-              events=None, learned=None) -> Opts:
+              events=None, learned=None, local_dt=False) -> Opts:
     """Options for bmhd_advance. `events`: optional list of torch.cuda.Event (enable_timing=True), two per
-    stage, recorded by the library around each stage kernel."""
+    stage, recorded by the library around each stage kernel. `local_dt`: local time stepping (dt is then
+    one float64 per cell, shape (n_blocks, 8, 8, 8))."""
     o = Opts()
     o.flux = FLUX[flux]
     o.powell = int(bool(powell))
@@ -141,6 +142,7 @@ def make_opts(flux="rusanov", powell=False, precision="fp64", recompute_dt=True,
     o.scheme = SCHEME[scheme] if isinstance(scheme, str) else int(scheme)
     o.persist_wgs = int(persist_wgs)
     o.use_graph = int(bool(use_graph))
+    o.local_dt = int(bool(local_dt))
     if learned is not None:
         o._learned_keepalive = learned
         o.learned = ctypes.pointer(learned)
@@ -264,6 +266,9 @@ class Grid:
     def advance(self, U0, U1, dt, n_stages, opts: Optional[Opts] = None, faults=None, stream=None, **kw):
         import torch
         o = opts if opts is not None else make_opts(**kw)
+        need = self.nb * 512 if o.local_dt else self.ns
+        if dt.numel() < need:
+            raise BmhdError(f"dt holds {dt.numel()} values; this grid and local_dt={o.local_dt} need {need}")
         fp = _dev_ptr(faults, torch.int32) if faults is not None else ctypes.c_void_p(0)
         _check(lib().bmhd_advance(self.h, _dev_ptr(U0, torch.float64), _dev_ptr(U1, torch.float64),
                                   _dev_ptr(dt, torch.float64), int(n_stages), ctypes.byref(o), fp,

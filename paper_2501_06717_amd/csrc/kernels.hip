@@ -507,12 +507,15 @@ struct StageArgs {
     const double *Uin;
     const double *U0;
     double *Uout;
-    const double *dt;
+    double *dt;      // one step per simulation, or per cell with local_dt (written by the first stage)
     int32_t *faults;
     double alpha, beta;
     int use_u0;      // add alpha * U0 (second stage)
     int want_lam;    // accumulate the next dt bound
     int count_faults;
+    int local_dt;    // local time stepping: dt holds one step per cell ([nB][512]) instead of one per simulation
+    int write_dt;    // with local_dt: this stage forms each cell's step from its own input state and stores it
+    double cfl;
     // learned correction (only read by the LEARN variants)
     const float *lrn_y;      // MLP outputs per face, normalised, face-normal frame
     const float *lrn_stats;  // in_mean[32], in_std[32], out_mean[8], out_std[8]
@@ -798,6 +801,7 @@ __device__ __forceinline__ void cell_update(const Tables &T, const StageArgs &A,
         if (body) {
 #pragma unroll
             for (int v = 0; v < 8; ++v) out[v] = uin[v];
+            if (A.local_dt && A.write_dt) A.dt[off] = 0.0;
         } else {
             if (POWELL) {
                 const double ux = double(sW[1][tid]), uy = double(sW[2][tid]), uz = double(sW[3][tid]);
@@ -811,7 +815,20 @@ __device__ __forceinline__ void cell_update(const Tables &T, const StageArgs &A,
                 rhs[6] -= divb * uz;
                 rhs[7] -= divb * ub;
             }
-            const double bdt = A.beta * A.dt[B.sim];
+            double dtc;
+            if (!A.local_dt) {
+                dtc = A.dt[B.sim];
+            } else if (A.write_dt) {
+                // local time stepping: the cell's own CFL step from its stage input (the step's starting
+                // state), the same expression as the global step of one cell
+                double w[8];
+                cons_to_prim(uin, w);
+                dtc = A.cfl * (1.0 / cell_bound(w, inv_dx));
+                A.dt[off] = dtc;
+            } else {
+                dtc = A.dt[off];
+            }
+            const double bdt = A.beta * dtc;
             if (A.use_u0) {
                 const double a0 = A.alpha, a1 = 1.0 - A.alpha;
 #pragma unroll
@@ -1385,7 +1402,7 @@ __global__ void __launch_bounds__(256) k_flux_correct(Tables T, StageArgs A) {
         sim = B.sim;
         const size_t vs = size_t(T.nb) * 512, off = size_t(C.block) * 512 + C.cell;
         const double inv_dx = 1.0 / S.dx0;
-        const double bdt = A.beta * A.dt[B.sim];
+        const double bdt = A.beta * (A.local_dt ? A.dt[off] : A.dt[B.sim]);
         double u[8];
 #pragma unroll
         for (int v = 0; v < 8; ++v) u[v] = A.Uout[v * vs + off];
@@ -1540,7 +1557,9 @@ int32_t check_opts(const bmhd_opts &o) {
             return fail(BMHD_EINVAL, "learned: null buffer");
         if (!(L.tau >= 0.0)) return fail(BMHD_EINVAL, "learned: tau must be >= 0");
         if (o.use_graph) return fail(BMHD_EUNSUPPORTED, "learned correction is not captured in graphs");
+        if (o.local_dt) return fail(BMHD_EUNSUPPORTED, "learned correction with local time stepping");
     }
+    if (o.local_dt != 0 && o.local_dt != 1) return fail(BMHD_EINVAL, "local_dt must be 0 or 1");
     return BMHD_OK;
 }
 
@@ -1563,6 +1582,12 @@ int32_t enqueue_stage(const HostGrid &h, const bmhd_opts &o, int e, double *d_U0
     a.use_u0 = o.alpha[e] != 0.0 ? 1 : 0;
     a.want_lam = want_lam ? 1 : 0;
     a.count_faults = (e == 1 && d_faults) ? 1 : 0;
+    if (o.local_dt) {
+        a.local_dt = 1;
+        a.write_dt = (e == 0 && o.recompute_dt) ? 1 : 0;
+        a.cfl = o.cfl;
+        a.want_lam = 0;
+    }
     if (o.learned) {
         const bmhd_learned &L = *o.learned;
         a.lrn_y = L.y_buf;
@@ -1621,9 +1646,10 @@ int32_t ensure_step_graph(HostGrid &h, const bmhd_opts &o, double *d_U0, double 
     hipStream_t cs = reinterpret_cast<hipStream_t>(h.capture_stream);
     if (int32_t rc = hip_check(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal), "begin capture")) return rc;
     int32_t rc = BMHD_OK;
-    if (o.recompute_dt) k_dt_finalize<<<(h.ns + 63) / 64, 64, 0, cs>>>(h.dev, o.cfl, d_dt);
+    if (o.recompute_dt && !o.local_dt) k_dt_finalize<<<(h.ns + 63) / 64, 64, 0, cs>>>(h.dev, o.cfl, d_dt);
     for (int e = 0; e < 2 && rc == BMHD_OK; ++e)
-        rc = enqueue_stage(h, ko, e, d_U0, d_U1, d_dt, d_faults, e == 1 && o.recompute_dt, nullptr, nullptr, cs);
+        rc = enqueue_stage(h, ko, e, d_U0, d_U1, d_dt, d_faults, e == 1 && o.recompute_dt && !o.local_dt, nullptr,
+                           nullptr, cs);
     hipGraph_t graph = nullptr;
     const int32_t rc2 = hip_check(hipStreamEndCapture(cs, &graph), "end capture");
     if (rc) return rc;
@@ -1780,7 +1806,7 @@ int32_t bmhd_advance(const bmhd_grid *g, double *d_U0, double *d_U1, double *d_d
         for (int e = 0; e < 2; ++e) {
             const int st = 2 * step + e;
             if (st >= n_stages) break;
-            if (e == 0 && o.recompute_dt) {
+            if (e == 0 && o.recompute_dt && !o.local_dt) {
                 const int sb = (h.ns + 63) / 64;
                 if (st == 0 || !fused_dt) {
                     k_lam_reset<<<sb, 64, 0, s>>>(h.dev);
@@ -1789,7 +1815,7 @@ int32_t bmhd_advance(const bmhd_grid *g, double *d_U0, double *d_U1, double *d_d
                 k_dt_finalize<<<sb, 64, 0, s>>>(h.dev, o.cfl, d_dt);
             }
             void *ev0 = timed ? o.events[2 * st] : nullptr, *ev1 = timed ? o.events[2 * st + 1] : nullptr;
-            const bool want_lam = fused_dt && e == 1 && o.recompute_dt && st + 1 < n_stages;
+            const bool want_lam = fused_dt && e == 1 && o.recompute_dt && !o.local_dt && st + 1 < n_stages;
             if (int32_t rc = enqueue_stage(h, o, e, d_U0, d_U1, d_dt, d_faults, want_lam, ev0, ev1, s)) return rc;
         }
     }
