@@ -10,8 +10,9 @@ Prints one JSON line (rank 0). Extra fields: "roofline" for the dominant kernel 
 live with HIP events that the library records on its stream; its "valu" object puts the same timing
 against the VALU issue peak, the bound this FP64 kernel actually meets), "cpu_baseline" (the CPU oracle
 on the host's cores over a bounded sample), "forms" (the FP32-flux form on the same workload with its
-error against the FP64 path, the 64-simulation batch, the learned correction) and "paper_context" (the
-paper's one-GPU fast-wave run on the same grid geometry, beside its published one-A100 time).
+error against the FP64 path, local time stepping, the 64-simulation batch, the learned correction) and
+"paper_context" (the paper's one-GPU fast-wave run on the same grid geometry, beside its published
+one-A100 time).
 """
 from __future__ import annotations
 
@@ -180,6 +181,23 @@ def bench_learned(steps):
                         "(gain 0.49-0.70) or diverged (profiles/learned_correction_magnetosphere128.md)"}
 
 
+def bench_local_dt(g, W, cells, steps):
+    """Local time stepping (the steady-state mode: every cell advances with its own CFL step) on the same
+    workload, FP64, default launch shape: the per-cell step is formed in the first stage from its input."""
+    import torch
+    U0 = g.set_state(W)
+    U1 = torch.empty_like(U0)
+    dt = torch.zeros((g.nb, 8, 8, 8), dtype=torch.float64, device="cuda")
+    faults = torch.zeros(1, dtype=torch.int32, device="cuda")
+    t = time_advance(g, U0, U1, dt, steps, flux="hlle", powell=True, cfl=0.8, local_dt=True, faults=faults)
+    d = dt.cpu().numpy()
+    fluid = d > 0.0
+    log(f"local_dt: {cells * steps / t:.3e} cell-updates/s")
+    return {"value": cells * steps / t, "unit": "cell-updates/s", "steps": steps, "faults": int(faults.item()),
+            "dt_ratio_max_min": float(d[fluid].max() / d[fluid].min()),
+            "workload": "the same grid, FP64, HLLE + Powell, each fluid cell its own CFL 0.8 step"}
+
+
 def bench_paper_fast_wave():
     """The paper's one-GPU fast-wave run (Sec. 5.1, Eq. 6, Table 2 at m = 6) in 8^3 blocks: the periodic
     domain [-32, 32]^3 as 10^3 root blocks (dx = 0.8) with the octant [-32, 0]^3 refined once, 1,875
@@ -287,6 +305,7 @@ def main():
                                                          "1e-12 of the CPU oracle)"}}
         log(f"fp32_flux: {wall32 * 1e3:.2f} ms, L1 {l1:.3e}")
         del U32
+        out["forms"]["local_dt"] = bench_local_dt(g, W, cells, a.form_steps)
     del U64
     torch.cuda.synchronize()
     if not (a.no_forms or a.profile):
