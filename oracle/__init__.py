@@ -59,6 +59,8 @@ def lib():
         L.or_set_state.argtypes = [ctypes.c_void_p, dp, dp]
         L.or_fill_ghosts.argtypes = [ctypes.c_void_p, dp, dp]
         L.or_dt.argtypes = [ctypes.c_void_p, dp, ctypes.c_double, dp]
+        L.or_remap.argtypes = [ctypes.c_void_p, dp, ctypes.c_void_p, dp]
+        L.or_remap.restype = ctypes.c_int
         L.or_advance.argtypes = [ctypes.c_void_p, dp, dp, dp, ctypes.c_int, P(_Opts), P(ctypes.c_long)]
         L.or_advance.restype = ctypes.c_int
         L.or_prim_to_cons.argtypes = [dp, dp]
@@ -195,6 +197,15 @@ class Grid:
         U = np.ascontiguousarray(U, np.float64)
         out = np.empty(self.ns)
         lib().or_dt(self.h, _dp(U), float(cfl), _dp(out))
+        return out
+
+    def remap(self, U, to):
+        """The state U of this grid moved onto grid `to` (same simulations, blocks refined or coarsened):
+        copy, prolongation or restriction per cell (or_remap)."""
+        U = np.ascontiguousarray(U, np.float64)
+        out = np.empty((8, to.nb, 8, 8, 8))
+        if lib().or_remap(self.h, _dp(U), to.h, _dp(out)) != 0:
+            raise ValueError("remap: the grids differ in their simulations or a block of `to` cannot be supplied")
         return out
 
     def advance(self, U0, U1, dt, n_stages, flux="rusanov", powell=False, cfl=0.8, recompute_dt=True,

@@ -812,6 +812,65 @@ void or_dt(const or_grid *g, const double *U, double cfl, double *dt)
     free(st);
 }
 
+/* Move a state to another grid of the same simulations after a refinement change (Sec. 2: a block is
+ * refined into its 8 children, or 8 children are coarsened into their parent; Sec. 3 does this on the CPU
+ * between steps, then rebuilds the message maps). Every cell of `to` takes the value the ghost rules of
+ * `from` give at its level and global index: the leaf's own value where the block is unchanged, the
+ * prolongation of a fine ghost cell (parent value plus limited slopes) where a level-0 block was refined,
+ * the restriction (pairwise-tree mean) where 8 level-1 blocks were coarsened. Returns -1 when the
+ * simulations differ or `to` holds a block that `from` cannot supply this way. */
+static int same_sim(const or_sim *a, const or_sim *b)
+{
+    for (int q = 0; q < 3; q++)
+        if (a->nroot[q] != b->nroot[q] || a->origin[q] != b->origin[q] || a->body_c[q] != b->body_c[q]) return 0;
+    for (int q = 0; q < 6; q++)
+        if (a->bc[q] != b->bc[q]) return 0;
+    for (int q = 0; q < NV; q++)
+        if (a->inflow_w[q] != b->inflow_w[q]) return 0;
+    return a->dx0 == b->dx0 && a->body_r == b->body_r;
+}
+
+int or_remap(const or_grid *from, const double *U_from, const or_grid *to, double *U_to)
+{
+    if (from->ns != to->ns) return -1;
+    for (int s = 0; s < from->ns; s++)
+        if (!same_sim(&from->sims[s], &to->sims[s])) return -1;
+    for (int b = 0; b < to->nb; b++) {
+        int s = to->sim[b], l = to->level[b];
+        long bb[3] = {to->ijk[3 * b], to->ijk[3 * b + 1], to->ijk[3 * b + 2]};
+        int ok = lut_get(from, s, l, bb) >= 0;
+        if (!ok && l == 1) {
+            long pb[3] = {bb[0] / 2, bb[1] / 2, bb[2] / 2};
+            ok = lut_get(from, s, 0, pb) >= 0;
+        }
+        if (!ok && l == 0) {
+            ok = 1;
+            for (int q = 0; q < 8; q++) {
+                long cb[3] = {2 * bb[0] + (q & 1), 2 * bb[1] + ((q >> 1) & 1), 2 * bb[2] + ((q >> 2) & 1)};
+                if (lut_get(from, s, 1, cb) < 0) ok = 0;
+            }
+        }
+        if (!ok) return -1;
+    }
+    double *st = pad_alloc(from->nb);
+    pad_from_ext(from, U_from, st);
+    const size_t nbp = (size_t)to->nb * NC * NC * NC;
+    for (int b = 0; b < to->nb; b++) {
+        int s = to->sim[b], l = to->level[b];
+        for (int k = 0; k < NC; k++)
+            for (int j = 0; j < NC; j++)
+                for (int i = 0; i < NC; i++) {
+                    long G[3] = {(long)to->ijk[3 * b] * NC + i, (long)to->ijk[3 * b + 1] * NC + j,
+                                 (long)to->ijk[3 * b + 2] * NC + k};
+                    double u[NV];
+                    ghost_value(from, st, s, l, G, u);
+                    for (int v = 0; v < NV; v++) U_to[v * nbp + (size_t)b * NC * NC * NC + (k * NC + j) * NC + i] = u[v];
+                }
+    }
+    free(st);
+    return 0;
+}
+
 /* Count of fluid cells whose density or pressure is not positive (or not finite). */
 static long count_faults(const or_grid *g, double *st)
 {

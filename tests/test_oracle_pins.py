@@ -548,3 +548,67 @@ def test_local_dt_stage_uses_each_cells_step(oracle_mod, case):
     scale = np.abs(U).max(axis=(1, 2, 3, 4), keepdims=True)
     assert np.all(np.abs(Ul1 - expect) <= 8 * np.finfo(float).eps * scale)
     assert np.abs(Ul1 - U).max() > 0.0
+
+
+# ------------------------------------------------------------------------------------------------
+# state remap after a refinement change (refine a level-0 block into 8, coarsen 8 into their parent)
+
+REFINED = ((1, 1, 1), (2, 2, 1), (2, 1, 2))
+
+
+def _box(refine, seed=5, nroot=(4, 4, 4), bc=(1,) * 6):
+    return wk.two_level_box(nroot=nroot, refine=refine, bc=bc, seed=seed)
+
+
+def test_remap_onto_the_same_grid_is_a_copy(oracle_mod):
+    wl = _box(REFINED)
+    o = oracle_mod.Grid.from_workload(wl)
+    U = o.set_state(wl.W)
+    assert np.array_equal(o.remap(U, o), U)
+
+
+def test_remap_refine_then_coarsen_returns_the_state_and_conserves(oracle_mod):
+    base, fine = _box(()), _box(REFINED)
+    ob, of = oracle_mod.Grid.from_workload(base), oracle_mod.Grid.from_workload(fine)
+    U = ob.set_state(base.W)
+    Uf = ob.remap(U, of)
+    assert np.all(np.abs(total(fine, Uf) - total(base, U)) <= 1e-14 * np.abs(total(base, U)).max())
+    back = of.remap(Uf, ob)
+    scale = np.abs(U).max(axis=(1, 2, 3, 4), keepdims=True)
+    assert np.all(np.abs(back - U) <= 8 * np.finfo(float).eps * scale)
+    assert not np.array_equal(Uf[:, :base.n_blocks], U)  # the grids really differ
+
+
+def _linear(wl, grad):
+    """U_v = 1 + v + grad . x at cell centres (x from the block's level and position)"""
+    sim = wl.sims[0]
+    U = np.zeros((8, wl.n_blocks, 8, 8, 8))
+    idx = np.arange(8) + 0.5
+    for b in range(wl.n_blocks):
+        dx = sim.dx0 / (1 << int(wl.level[b]))
+        x = sim.origin[0] + (wl.ijk[b][0] * 8 + idx) * dx
+        y = sim.origin[1] + (wl.ijk[b][1] * 8 + idx) * dx
+        z = sim.origin[2] + (wl.ijk[b][2] * 8 + idx) * dx
+        f = grad[0] * x[None, None, :] + grad[1] * y[None, :, None] + grad[2] * z[:, None, None]
+        for v in range(8):
+            U[v, b] = 1.0 + v + f
+    return U
+
+
+def test_remap_of_a_linear_field_is_exact_both_ways(oracle_mod):
+    """Refining an interior block holds a linear field exactly (the limited slopes equal the gradient);
+    coarsening gives the field at the coarse centres (the mean of the 8 fine centres)."""
+    grad = (0.3, -0.2, 0.1)
+    base, fine = _box(()), _box(REFINED)
+    ob, of = oracle_mod.Grid.from_workload(base), oracle_mod.Grid.from_workload(fine)
+    Ub, Uf = _linear(base, grad), _linear(fine, grad)
+    tol = 64 * np.finfo(float).eps * np.abs(Uf).max()
+    assert np.abs(ob.remap(Ub, of) - Uf).max() <= tol
+    assert np.abs(of.remap(Uf, ob) - Ub).max() <= tol
+
+
+def test_remap_rejects_another_domain(oracle_mod):
+    a, b = _box(()), _box((), nroot=(4, 4, 2))
+    oa, ob = oracle_mod.Grid.from_workload(a), oracle_mod.Grid.from_workload(b)
+    with pytest.raises(ValueError):
+        oa.remap(oa.set_state(a.W), ob)
