@@ -183,6 +183,18 @@ int32_t bmhd_set_state(const bmhd_grid *g, const double *d_W, double *d_U, void 
  * (no contraction). */
 int32_t bmhd_fill_ghosts(const bmhd_grid *g, const double *d_U, double *d_view, void *stream);
 
+/* State of one grid moved onto another grid of the same simulations after a refinement change (Sec. 2:
+ * a block is refined into its 8 children or 8 children are coarsened into their parent; Sec. 3 adapts the
+ * grid on the CPU between steps and then rebuilds its message maps, which here is bmhd_grid_create and
+ * bmhd_grid_upload of the new block list). Every cell of `to` takes the value the ghost rules of `from`
+ * (as in bmhd_fill_ghosts) give at its level and global index: a copy where the block exists in both
+ * grids, prolongation from the level-0 parent where a block was refined, restriction of the 8 children
+ * where blocks were coarsened. d_U_from [8][from.n_blocks][512], d_U_to [8][to.n_blocks][512], both
+ * caller-owned device memory, distinct. Bit-exact (no contraction). Both grids must be uploaded. Errors:
+ * BMHD_EINVAL when the simulation descriptors differ or a block of `to` cannot be supplied that way. */
+int32_t bmhd_remap(const bmhd_grid *from, const double *d_U_from, const bmhd_grid *to, double *d_U_to,
+                   void *stream);
+
 /* d_dt[n_sims] = cfl * min over fluid cells of 1 / sum_d ((|u_d| + c_f,d) / dx) from d_U. */
 int32_t bmhd_reduce_dt(const bmhd_grid *g, const double *d_U, double cfl, double *d_dt, void *stream);
 

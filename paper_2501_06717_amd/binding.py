@@ -21,8 +21,8 @@ PRECISION = {"fp64": 0, "fp32_flux": 1}
 SCHEME = {"default": 0, "face": 1, "plane": 2}
 
 EXPORTS = ["bmhd_version", "bmhd_last_error", "bmhd_grid_create", "bmhd_grid_destroy", "bmhd_grid_info_get",
-           "bmhd_grid_neighbors", "bmhd_grid_upload", "bmhd_set_state", "bmhd_fill_ghosts", "bmhd_reduce_dt",
-           "bmhd_advance", "bmhd_autotune", "bmhd_mlp_last_error", "bmhd_mlp_n_params", "bmhd_mlp_work_bytes",
+           "bmhd_grid_neighbors", "bmhd_grid_upload", "bmhd_set_state", "bmhd_fill_ghosts", "bmhd_remap",
+           "bmhd_reduce_dt", "bmhd_advance", "bmhd_autotune", "bmhd_mlp_last_error", "bmhd_mlp_n_params", "bmhd_mlp_work_bytes",
            "bmhd_mlp_forward", "bmhd_mlp_backward", "bmhd_mlp_adam", "bmhd_mlp_to_bf16", "bmhd_face_data"]
 
 
@@ -92,6 +92,8 @@ def lib():
     L.bmhd_set_state.restype = i32
     L.bmhd_fill_ghosts.argtypes = [vp, vp, vp, vp]
     L.bmhd_fill_ghosts.restype = i32
+    L.bmhd_remap.argtypes = [vp, vp, vp, vp, vp]
+    L.bmhd_remap.restype = i32
     L.bmhd_reduce_dt.argtypes = [vp, vp, ctypes.c_double, vp, vp]
     L.bmhd_reduce_dt.restype = i32
     L.bmhd_advance.argtypes = [vp, vp, vp, vp, i32, P(Opts), vp, vp]
@@ -254,6 +256,16 @@ class Grid:
         _check(lib().bmhd_fill_ghosts(self.h, _dev_ptr(U, torch.float64), _dev_ptr(view, torch.float64),
                                       _stream_ptr(stream)))
         return view
+
+    def remap(self, U, to, out=None, stream=None):
+        """The state U of this grid moved onto grid `to` (same simulations; blocks refined or coarsened):
+        copy, prolongation or restriction per cell, on the device."""
+        import torch
+        if out is None:
+            out = torch.empty((8, to.nb, 8, 8, 8), dtype=torch.float64, device=U.device)
+        _check(lib().bmhd_remap(self.h, _dev_ptr(U, torch.float64), to.h, _dev_ptr(out, torch.float64),
+                                _stream_ptr(stream)))
+        return out
 
     def reduce_dt(self, U, cfl, dt=None, stream=None):
         import torch

@@ -352,6 +352,26 @@ __global__ void __launch_bounds__(256) k_fill_view(Tables T, const double *__res
 }
 
 // ghost layers of one level-change face: item = (block << 3) | face; 128 threads = 2 layers x 64
+// State remap after a refinement change: every cell of the new grid N takes the value that the ghost rules
+// of the old grid F give at its level and global index -- the leaf's own value (block unchanged), the
+// prolongation of a fine ghost cell (block refined from a level-0 parent) or the restriction of the 8
+// children (block coarsened). One workgroup per new block, one thread per cell; no contraction (inside
+// ghost_cell), so the result is exact to the oracle's.
+__global__ void __launch_bounds__(512) k_remap(Tables F, const double *__restrict__ Uf, Tables N,
+                                               double *__restrict__ Un) {
+    const int b = blockIdx.x, c = threadIdx.x;
+    const DevBlock &B = N.blocks[b];
+    const DevSim &S = F.sims[B.sim];
+    const Cursor cur{&F, Uf, size_t(F.nb) * 512};
+    const long long G[3] = {(long long)B.ijk[0] * 8 + (c & 7), (long long)B.ijk[1] * 8 + ((c >> 3) & 7),
+                            (long long)B.ijk[2] * 8 + (c >> 6)};
+    double u[8];
+    ghost_cell(cur, S, B.level, G, u);
+    const size_t vs = size_t(N.nb) * 512, off = size_t(b) * 512 + c;
+#pragma unroll
+    for (int v = 0; v < 8; ++v) Un[v * vs + off] = u[v];
+}
+
 __global__ void __launch_bounds__(128) k_halo_fill(Tables T, const double *__restrict__ U) {
     const int32_t item = T.halo_items[blockIdx.x];
     const int b = item >> 3, f = item & 7;
@@ -1665,6 +1685,40 @@ int32_t ensure_step_graph(HostGrid &h, const bmhd_opts &o, double *d_U0, double 
     return BMHD_OK;
 }
 
+// block id of level-l block (bx, by, bz) of simulation s in the host lookup table, or -1
+int32_t host_lut(const HostGrid &g, int s, int l, long long bx, long long by, long long bz) {
+    const DevSim &S = g.sims[s];
+    const long long nx = (long long)S.nroot[0] << l, ny = (long long)S.nroot[1] << l, nz = (long long)S.nroot[2] << l;
+    if (bx < 0 || by < 0 || bz < 0 || bx >= nx || by >= ny || bz >= nz) return -1;
+    return g.lut[S.lut_off[l] + (bz * ny + by) * nx + bx];
+}
+
+bool remap_compatible(const HostGrid &f, const HostGrid &t) {
+    if (f.ns != t.ns) return false;
+    for (int s = 0; s < f.ns; ++s) {
+        const bmhd_sim_desc &a = f.sdesc[s], &b = t.sdesc[s];
+        for (int q = 0; q < 3; ++q)
+            if (a.nroot[q] != b.nroot[q] || a.origin[q] != b.origin[q] || a.body_c[q] != b.body_c[q]) return false;
+        for (int q = 0; q < 6; ++q)
+            if (a.bc[q] != b.bc[q]) return false;
+        for (int q = 0; q < 8; ++q)
+            if (a.inflow_W[q] != b.inflow_W[q]) return false;
+        if (a.dx0 != b.dx0 || a.body_r != b.body_r) return false;
+    }
+    return true;
+}
+
+// a new block can be filled from the old grid: same block, child of an old level-0 block, or parent of 8
+// old level-1 blocks
+bool remap_source(const HostGrid &f, int s, int l, const int32_t *ijk) {
+    if (host_lut(f, s, l, ijk[0], ijk[1], ijk[2]) >= 0) return true;
+    if (l == 1) return host_lut(f, s, 0, ijk[0] >> 1, ijk[1] >> 1, ijk[2] >> 1) >= 0;
+    for (int q = 0; q < 8; ++q)
+        if (host_lut(f, s, 1, 2 * ijk[0] + (q & 1), 2 * ijk[1] + ((q >> 1) & 1), 2 * ijk[2] + (q >> 2)) < 0)
+            return false;
+    return true;
+}
+
 int32_t need_upload(const bmhd_grid *g) {
     if (!g) return fail(BMHD_EINVAL, "null grid");
     if (!g->h.d_work) return fail(BMHD_EINVAL, "grid not uploaded (call bmhd_grid_upload first)");
@@ -1765,6 +1819,23 @@ int32_t bmhd_fill_ghosts(const bmhd_grid *g, const double *d_U, double *d_view, 
     if (g->h.nb == 0) return BMHD_OK;
     k_fill_view<<<g->h.nb, 256, 0, reinterpret_cast<hipStream_t>(stream)>>>(g->h.dev, d_U, d_view);
     return launch_check("fill_ghosts");
+}
+
+int32_t bmhd_remap(const bmhd_grid *from, const double *d_U_from, const bmhd_grid *to, double *d_U_to,
+                   void *stream) {
+    if (int32_t rc = need_upload(from)) return rc;
+    if (int32_t rc = need_upload(to)) return rc;
+    if (!ptr_ok(d_U_from) || !ptr_ok(d_U_to) || d_U_from == d_U_to)
+        return fail(BMHD_EINVAL, "remap: null, misaligned or aliased state pointers");
+    const HostGrid &f = from->h, &t = to->h;
+    if (!remap_compatible(f, t)) return fail(BMHD_EINVAL, "remap: the grids differ in their simulations");
+    for (int b = 0; b < t.nb; ++b)
+        if (!remap_source(f, t.sim[b], t.level[b], &t.ijk[3 * b]))
+            return fail(BMHD_EINVAL, "remap: a block of the new grid is neither a block of the old one, a child of "
+                                     "an old level-0 block nor the parent of 8 old level-1 blocks");
+    if (t.nb == 0) return BMHD_OK;
+    k_remap<<<t.nb, 512, 0, reinterpret_cast<hipStream_t>(stream)>>>(f.dev, d_U_from, t.dev, d_U_to);
+    return launch_check("remap");
 }
 
 int32_t bmhd_reduce_dt(const bmhd_grid *g, const double *d_U, double cfl, double *d_dt, void *stream) {
