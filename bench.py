@@ -148,20 +148,18 @@ def bench_batched(steps):
 
 
 def bench_learned(steps):
-    """The learned flux correction on the 128^3 magnetosphere grid (dx = 2): MLP 32-128-128-128-8 on
-    BF16 matrix cores, HLLE + Powell, FP64 update, beside the plain FP64 path on the same grid."""
+    """The learned flux correction on the 128^3 magnetosphere grid (dx = 2) with the network shipped in
+    paper_2501_06717_amd/trained (MLP 32-128-128-128-8 on BF16 matrix cores), HLLE + Powell, FP64 update,
+    beside the plain FP64 path on the same grid; and what it gains over the plain path on one held-out
+    solar-wind state against the restricted 256^3 run (100 coarse steps, and one step)."""
     import torch
     from paper_2501_06717_amd import binding, learn
+    net = os.path.join(ROOT, "paper_2501_06717_amd", "trained", "flux_mlp_h128.npz")
+    mlp, stats, meta = learn.load(net)
     state = learn.solar_wind_states(1, 1005)[0]
     _, coarse = learn.magnetosphere_pair(state, 256)
     g = binding.Grid.from_workload(coarse).upload()
     W = torch.from_numpy(coarse.W).cuda()
-    rng = np.random.default_rng(0)
-    npar = int(binding.lib().bmhd_mlp_n_params(128))
-    mlp = binding.Mlp(128, torch.from_numpy((rng.normal(size=npar) * 0.05).astype(np.float32)))
-    stats = torch.zeros(80)
-    stats[32:64] = 1.0
-    stats[72:80] = 1e-3
     fb = torch.zeros(1, dtype=torch.int32, device="cuda")
     res = {}
     for name, L in (("plain", None), ("learned", g.learned(mlp, stats, fallback=fb))):
@@ -171,14 +169,18 @@ def bench_learned(steps):
         t = time_advance(g, U0, U1, dt, steps, flux="hlle", powell=True, learned=L)
         res[name] = coarse.n_cells * steps / t
     cells = coarse.n_cells
+    flagged = int(fb.item()) / (2 * (steps + 1))
+    del g, W
+    ev = learn.evaluate(binding, learn.Config(hidden=meta["hidden"]), mlp, stats, [state], log=log)[0]
     log(f"learned: {res['learned']:.3e} vs plain {res['plain']:.3e} cell-updates/s on {cells} cells")
     return {"value": res["learned"], "unit": "cell-updates/s", "plain_value": res["plain"],
             "workload": f"magnetosphere 128^3 ({cells} cells), MLP 32-128-128-128-8 BF16, HLLE + Powell",
-            "steps": steps, "flagged_cells_per_stage": int(fb.item()) / (2 * (steps + 1)),
-            "weights": "random (timing only: the cost per stage does not depend on the weights)",
-            "accuracy": "trained network on 4 held-out solar-wind states, 100 coarse steps against the restricted "
-                        "256^3 FP64 run: mean relative L1 of the plain coarse path 0.156-0.158, learned 0.22-0.32 "
-                        "(gain 0.49-0.70) or diverged (profiles/learned_correction_magnetosphere128.md)"}
+            "steps": steps, "flagged_cells_per_stage": flagged,
+            "weights": "trained (paper_2501_06717_amd/trained/flux_mlp_h128.npz, strength %.2f)" % meta["strength"],
+            "accuracy": {"state": state, "reference": "256^3 FP64 run restricted to 128^3, same time",
+                         "l1_rel_plain": ev["plain"]["l1_rel_mean"], "l1_rel_learned": ev["learned"]["l1_rel_mean"],
+                         "gain_100_steps": ev["gain"], "gain_one_step": ev["one_step"]["gain"],
+                         "gain_one_step_exact_target": ev["one_step_exact_target"]["gain"]}}
 
 
 def bench_local_dt(g, W, cells, steps):

@@ -90,7 +90,9 @@ typedef struct {
  * flagged cell falls back to the plain flux on both sides and the affected cells are recomputed once. */
 typedef struct {
     int32_t hidden;              /* 32, 64 or 128 */
-    int32_t mode;                /* 0: BF16 matrix cores, 1: FP32 reference */
+    int32_t mode;                /* 0: BF16 matrix cores, 1: FP32 reference, 2: no network: y_buf holds
+                                    the normalised corrections as given (corrections from another source;
+                                    params and x_buf may be NULL) */
     const float *params;         /* device [n_params] float32 */
     const uint16_t *params_bf16; /* device [n_params] bfloat16 copy */
     const float *stats;          /* device: in_mean[32], in_std[32], out_mean[8], out_std[8] */

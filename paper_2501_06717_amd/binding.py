@@ -320,6 +320,25 @@ class Grid:
         L.tau = float(tau)
         return L
 
+    def given_corrections(self, y, stats, tau=0.1, fallback=None):
+        """Options of the learned form with the normalised flux corrections y [n_blocks * 1728, 8] float32
+        (face-normal frame, the face order of bmhd_face_data) given instead of a network's outputs."""
+        import torch
+        if tuple(y.shape) != (self.nb * 1728, 8) or y.dtype != torch.float32 or not y.is_contiguous():
+            raise BmhdError("given corrections must be a contiguous float32 tensor [n_blocks * 1728, 8]")
+        self._ly = y
+        self._lf = torch.zeros(self.nb * 512, dtype=torch.uint8, device=y.device)
+        self._lstats = stats.to(y.device, torch.float32).contiguous()
+        L = Learned()
+        L.hidden = 32
+        L.mode = 2
+        L.stats = self._lstats.data_ptr()
+        L.y_buf = y.data_ptr()
+        L.flags = self._lf.data_ptr()
+        L.fallback_cells = fallback.data_ptr() if fallback is not None else None
+        L.tau = float(tau)
+        return L
+
     def autotune(self, U0, U1, dt, n_steps=3, stream=None, **kw):
         """Time the stage kernel's launch shapes on (scratch) buffers; returns (best Opts, {shape: ms})."""
         import torch

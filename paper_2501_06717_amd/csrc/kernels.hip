@@ -1572,8 +1572,8 @@ int32_t check_opts(const bmhd_opts &o) {
     if (o.learned) {
         const bmhd_learned &L = *o.learned;
         if (L.hidden != 32 && L.hidden != 64 && L.hidden != 128) return fail(BMHD_EINVAL, "learned: hidden must be 32, 64 or 128");
-        if (L.mode != 0 && L.mode != 1) return fail(BMHD_EINVAL, "learned: mode must be 0 or 1");
-        if (!L.params || !L.params_bf16 || !L.stats || !L.x_buf || !L.y_buf || !L.flags)
+        if (L.mode != 0 && L.mode != 1 && L.mode != 2) return fail(BMHD_EINVAL, "learned: mode must be 0, 1 or 2");
+        if (!L.stats || !L.y_buf || !L.flags || (L.mode != 2 && (!L.params || !L.params_bf16 || !L.x_buf)))
             return fail(BMHD_EINVAL, "learned: null buffer");
         if (!(L.tau >= 0.0)) return fail(BMHD_EINVAL, "learned: tau must be >= 0");
         if (o.use_graph) return fail(BMHD_EUNSUPPORTED, "learned correction is not captured in graphs");
@@ -1617,11 +1617,13 @@ int32_t enqueue_stage(const HostGrid &h, const bmhd_opts &o, int e, double *d_U0
         a.want_lam = 0;
         const int count = a.count_faults;
         a.count_faults = 0;
-        k_face_features<<<h.nb, Slab<8>::NT, 0, s>>>(h.dev, a, L.stats, L.x_buf);
-        if (int32_t rc = launch_check("face features")) return rc;
-        if (int32_t rc = bmhd_mlp_forward(L.params, L.params_bf16, L.hidden, h.nb * 1728, L.x_buf, L.y_buf, nullptr,
-                                          L.mode, s))
-            return fail(rc, bmhd_mlp_last_error());
+        if (L.mode != 2) {  // mode 2: y_buf is given
+            k_face_features<<<h.nb, Slab<8>::NT, 0, s>>>(h.dev, a, L.stats, L.x_buf);
+            if (int32_t rc = launch_check("face features")) return rc;
+            if (int32_t rc = bmhd_mlp_forward(L.params, L.params_bf16, L.hidden, h.nb * 1728, L.x_buf, L.y_buf,
+                                              nullptr, L.mode, s))
+                return fail(rc, bmhd_mlp_last_error());
+        }
         if (ev0)
             if (int32_t rc = hip_check(hipEventRecord(reinterpret_cast<hipEvent_t>(ev0), s), "event")) return rc;
         if (int32_t rc = launch_learn(h, a, o, s)) return rc;

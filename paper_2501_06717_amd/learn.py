@@ -9,7 +9,14 @@ grid (256^3, dx = 1) of solar-wind states drawn at random:
   HLLE flux of the restricted coarse state, both in the face-normal frame;
 * the inputs are the 4-cell stencils of coarse primitives in the face-normal frame;
 * per snapshot and direction, a share `top_frac` of the sampled faces comes from the top decile of the
-  target magnitude and the rest is uniform; inputs and targets are z-scored with training-set statistics.
+  target magnitude and the rest is uniform; inputs and targets are z-scored with training-set statistics;
+* optionally (`pair`) the samples are the two faces of a coarse cell along each direction and the loss
+  weighs the error of their difference, which is what the cell update sees;
+* the stage applies `strength` times the network's correction (folded into the output statistics).
+
+Evaluation on held-out states: coarse plain and coarse learned runs against the fine run restricted, over
+many steps and over one step; the one-step test also runs with the exact target of that state given as
+the correction (no network), the bound for any correction of this form.
 
 Training and inference run in the library's kernels (BF16 matrix cores, FP32 master weights, Adam).
 Data preparation (restriction, face averaging, sampling, statistics) uses torch tensor operations on
@@ -127,9 +134,13 @@ class Config:
     fine_steps: int = 200
     snap_every: int = 20
     samples_per_dir: int = 16384
-    top_frac: float = 0.5          # share of each snapshot's samples drawn from the top decile of |target|
+    top_frac: float = 0.0          # share of each snapshot's samples drawn from the top decile of |target|
+    pair: float = 0.0              # > 0: samples are the two faces of a coarse cell along each direction, and
+                                   # this weight goes to the error of their difference (what the cell update
+                                   # sees); the rest to the error of each face
     hidden: int = 128
-    epochs: int = 8
+    epochs: int = 24
+    strength: float = 0.25         # the correction applied is this fraction of the network's output
     batch: int = 4096
     lr: float = 1e-3
     seed_train: int = 5
@@ -168,6 +179,42 @@ def snapshot_data(bd, gf, gc, Uf, nbf, gen):
     return torch.cat(xs), torch.cat(ts)
 
 
+def snapshot_pairs(bd, gf, gc, Uf, nbf, gen):
+    """Samples of one fine snapshot as face pairs: the low and high face of a coarse cell along each
+    direction, X [n, 2, 32] (coarse stencil features) and T [n, 2, 8] (flux corrections). Half of them are
+    uniform, `top_frac` from the top decile of the difference of the two corrections."""
+    import torch
+    Uc = restrict(Uf, nbf)
+    Xc, Fc = gc.face_data(Uc, flux="hlle")
+    _, Ff = gf.face_data(Uf, flux="hlle", want_x=False)
+    nbc = nbf // 2
+    xs, ts = [], []
+    for d in range(3):
+        Fg = faces_global(Ff, nbf, d, 8)
+        target = coarse_face_mean(Fg, d) - faces_global(Fc, nbc, d, 8)
+        Xg = faces_global(Xc, nbc, d, 32)
+        ax = 3 - d                                   # global face arrays are [c, z, y, x]
+        lo = [slice(None)] * 4
+        hi = [slice(None)] * 4
+        lo[ax] = slice(0, -1)
+        hi[ax] = slice(1, None)
+        Ta, Tb = target[tuple(lo)].reshape(8, -1).t(), target[tuple(hi)].reshape(8, -1).t()
+        Xa, Xb = Xg[tuple(lo)].reshape(32, -1).t(), Xg[tuple(hi)].reshape(32, -1).t()
+        n = Ta.shape[0]
+        kt = int(round(gen["samples"] * gen["top_frac"]))
+        ku = gen["samples"] - kt
+        dT = Tb - Ta
+        mag = (dT / (dT.std(dim=0) + 1e-30)).norm(dim=1)
+        top = torch.topk(mag, max(n // 10, kt)).indices
+        pick_top = top[torch.randint(0, top.numel(), (kt,), generator=gen["g"], device=top.device)]
+        pick_uni = torch.randint(0, n, (ku,), generator=gen["g"], device=top.device)
+        idx = torch.cat([pick_uni, pick_top])
+        xs.append(torch.stack([Xa[idx], Xb[idx]], dim=1))
+        ts.append(torch.stack([Ta[idx], Tb[idx]], dim=1))
+        del Fg, target, Xg
+    return torch.cat(xs), torch.cat(ts)
+
+
 def generate(bd, cfg: Config, states, log=print):
     """Training samples from fine plain FP64 runs of the given solar-wind states."""
     import torch
@@ -185,7 +232,7 @@ def generate(bd, cfg: Config, states, log=print):
         t0 = time.time()
         for s0 in range(0, cfg.fine_steps, cfg.snap_every):
             gf.advance(U0, U1, dt, 2 * cfg.snap_every, flux="hlle", powell=True, cfl=0.8)
-            x, t = snapshot_data(bd, gf, gc, U0, nbf, gen)
+            x, t = (snapshot_pairs if cfg.pair > 0 else snapshot_data)(bd, gf, gc, U0, nbf, gen)
             X.append(x)
             T.append(t)
         torch.cuda.synchronize()
@@ -197,10 +244,13 @@ def generate(bd, cfg: Config, states, log=print):
 def train(bd, cfg: Config, X, T, log=print):
     """Adam on z-scored inputs and targets; returns (mlp, stats[80], loss history)."""
     import torch
-    xm, xs = X.mean(0), X.std(0) + 1e-12
-    tm, ts = T.mean(0), T.std(0) + 1e-30
+    pairs = X.dim() == 3
+    Xf, Tf = (X.reshape(-1, 32), T.reshape(-1, 8)) if pairs else (X, T)
+    xm, xs = Xf.mean(0), Xf.std(0) + 1e-12
+    tm, ts = Tf.mean(0), Tf.std(0) + 1e-30
     Xn = ((X - xm) / xs).contiguous()
     Tn = ((T - tm) / ts).contiguous()
+    wd = cfg.pair if pairs else 0.0
     stats = torch.cat([xm, xs, tm, ts]).float()
     rng = np.random.default_rng(cfg.seed_train)
     npar = int(bd.lib().bmhd_mlp_n_params(cfg.hidden))
@@ -222,7 +272,20 @@ def train(bd, cfg: Config, X, T, log=print):
         tot, nb = 0.0, 0
         for b0 in range(0, n - cfg.batch + 1, cfg.batch):
             idx = perm[b0:b0 + cfg.batch]
-            loss, grad = mlp.loss_grad(Xn[idx].contiguous(), Tn[idx].contiguous())
+            if pairs:
+                # difference loss through the face loss's gradient: the pseudo-target of each face is
+                # (1 - wd) * its target + wd * (the other face's prediction + the target difference), so the
+                # gradient is (1 - wd) * face error + wd * error of the difference
+                xa, xb = Xn[idx, 0].contiguous(), Xn[idx, 1].contiguous()
+                ta, tb = Tn[idx, 0], Tn[idx, 1]
+                ya, yb = mlp.forward(xa), mlp.forward(xb)
+                dT = ta - tb
+                pa = (1.0 - wd) * ta + wd * (yb + dT)
+                pb = (1.0 - wd) * tb + wd * (ya - dT)
+                loss, grad = mlp.loss_grad(torch.cat([xa, xb]), torch.cat([pa, pb]).contiguous())
+                loss = ((ya - yb) - dT).pow(2).mean()
+            else:
+                loss, grad = mlp.loss_grad(Xn[idx].contiguous(), Tn[idx].contiguous())
             # cosine decay of the learning rate to a tenth over the run
             lr = cfg.lr * (0.1 + 0.45 * (1.0 + math.cos(math.pi * it / max(steps, 1))))
             mlp.adam(grad, lr=lr)
@@ -262,6 +325,59 @@ def one_step_gain(bd, cfg: Config, mlp, stats, st, warm_steps=100):
     return out
 
 
+def faces_to_blocks(G, nb, d):
+    """Inverse of faces_global: global faces of direction d [c, ...] -> per-block faces [nb^3, 576, c] in
+    the face order of bmhd_face_data."""
+    import torch
+    ar = lambda n: torch.arange(n, device=G.device)
+    bz, by, bx = torch.meshgrid(ar(nb), ar(nb), ar(nb), indexing="ij")
+    dims = {0: (8, 8, 9), 1: (8, 9, 8), 2: (9, 8, 8)}[d]
+    z, y, x = torch.meshgrid(ar(dims[0]), ar(dims[1]), ar(dims[2]), indexing="ij")
+    Z = bz.reshape(-1, 1) * 8 + z.reshape(1, -1)
+    Y = by.reshape(-1, 1) * 8 + y.reshape(1, -1)
+    X = bx.reshape(-1, 1) * 8 + x.reshape(1, -1)
+    return G[:, Z, Y, X].permute(1, 2, 0)
+
+
+def exact_target_one_step(bd, cfg: Config, st, warm_steps=100):
+    """The one_step_gain test with the exact a-priori target (from the fine state, not a network) given to
+    the learned stage as its correction: the best a correction of this form can do from this state."""
+    import torch
+    nbf, nbc = cfg.n_fine // 8, cfg.n_fine // 16
+    fine, coarse = magnetosphere_pair(st, cfg.n_fine)
+    gf = bd.Grid.from_workload(fine).upload()
+    gc = bd.Grid.from_workload(coarse).upload()
+    Uf = gf.set_state(torch.from_numpy(fine.W).cuda())
+    U1 = torch.empty_like(Uf)
+    dtf = torch.zeros(1, dtype=torch.float64, device="cuda")
+    gf.advance(Uf, U1, dtf, 2 * warm_steps, flux="hlle", powell=True, cfl=0.8)
+    dtf = gf.reduce_dt(Uf, 0.8)
+    Uc0 = restrict(Uf, nbf)
+    _, Fc = gc.face_data(Uc0, flux="hlle", want_x=False)
+    _, Ff = gf.face_data(Uf, flux="hlle", want_x=False)
+    ys = []
+    for d in range(3):
+        T = coarse_face_mean(faces_global(Ff, nbf, d, 8), d) - faces_global(Fc, nbc, d, 8)
+        ys.append(faces_to_blocks(T, nbc, d))
+    y = torch.stack(ys, dim=1).reshape(-1, 8).float().contiguous()
+    del Ff, Fc, ys
+    gf.advance(Uf, U1, dtf, 4, flux="hlle", powell=True, recompute_dt=False)
+    dref = restrict(Uf, nbf) - Uc0
+    stats = torch.zeros(80)
+    stats[32:64] = 1.0
+    stats[72:80] = 1.0
+    out = {}
+    for name in ("plain", "exact"):
+        L = gc.given_corrections(y, stats, tau=1e30) if name == "exact" else None
+        U = Uc0.clone()
+        Ub = torch.empty_like(U)
+        gc.advance(U, Ub, dtf * 2.0, 2, flux="hlle", powell=True, recompute_dt=False, learned=L)
+        d = U - Uc0
+        out[name] = [float((d[v] - dref[v]).abs().sum() / dref[v].abs().sum()) for v in range(8)]
+    out["gain"] = float(np.mean(out["plain"]) / max(np.mean(out["exact"]), 1e-300))
+    return out
+
+
 def evaluate(bd, cfg: Config, mlp, stats, states, log=print):
     """Coarse plain vs coarse learned against the fine run restricted, at the same time."""
     import torch
@@ -292,10 +408,37 @@ def evaluate(bd, cfg: Config, mlp, stats, states, log=print):
             res[name] = {"l1_rel_mean": float(np.mean(l1)), "l1_rel": l1, "faults": int(faults.item())}
         res["gain"] = res["plain"]["l1_rel_mean"] / max(res["learned"]["l1_rel_mean"], 1e-300)
         res["one_step"] = one_step_gain(bd, cfg, mlp, stats, st)
+        res["one_step_exact_target"] = exact_target_one_step(bd, cfg, st)
         log(f"held-out {st}: plain L1 {res['plain']['l1_rel_mean']:.4e}, learned {res['learned']['l1_rel_mean']:.4e}, "
-            f"gain {res['gain']:.3f}; one-step gain {res['one_step']['gain']:.3f}")
+            f"gain {res['gain']:.3f}; one-step gain {res['one_step']['gain']:.3f} (exact target: "
+            f"{res['one_step_exact_target']['gain']:.3f})")
         out.append(res)
     return out
+
+
+def with_strength(stats, k):
+    """Output statistics scaled so that the stage applies k times the network's correction."""
+    out = stats.clone()
+    out[64:80] *= k
+    return out
+
+
+def save(path, mlp, stats, cfg: Config, summary=None):
+    """A trained network as a plain .npz (no pickled objects): FP32 parameters, the 80 normalisation
+    values as the stage uses them (strength folded in), the hidden width and the training summary."""
+    np.savez(path, params=mlp.p.detach().cpu().numpy().astype(np.float32),
+             stats=stats.detach().cpu().numpy().astype(np.float32), hidden=np.int32(cfg.hidden),
+             strength=np.float64(cfg.strength), summary=np.str_(json.dumps(summary or {})))
+
+
+def load(path, device="cuda"):
+    """(Mlp, stats tensor, metadata) of a network written by save()."""
+    import torch
+    from . import binding as bd
+    d = np.load(path, allow_pickle=False)
+    mlp = bd.Mlp(int(d["hidden"]), torch.from_numpy(d["params"]), device=device)
+    meta = {"hidden": int(d["hidden"]), "strength": float(d["strength"]), "summary": json.loads(str(d["summary"]))}
+    return mlp, torch.from_numpy(d["stats"]), meta
 
 
 def main():
@@ -304,15 +447,20 @@ def main():
     ap.add_argument("--train-states", type=int, default=32)
     ap.add_argument("--heldout-states", type=int, default=2)
     ap.add_argument("--fine-steps", type=int, default=200)
-    ap.add_argument("--epochs", type=int, default=8)
+    ap.add_argument("--epochs", type=int, default=24)
+    ap.add_argument("--strength", type=float, default=0.25,
+                    help="fraction of the network's correction applied (folded into the output statistics)")
     ap.add_argument("--samples", type=int, default=16384)
-    ap.add_argument("--top-frac", type=float, default=0.5)
+    ap.add_argument("--top-frac", type=float, default=0.0)
+    ap.add_argument("--pair", type=float, default=0.0,
+                    help="train on face pairs with this weight on the error of the pair's difference")
     ap.add_argument("--out", default=None)
     a = ap.parse_args()
     import torch
     from . import binding as bd
     cfg = Config(n_fine=a.n_fine, train_states=a.train_states, heldout_states=a.heldout_states,
-                 fine_steps=a.fine_steps, epochs=a.epochs, samples_per_dir=a.samples, top_frac=a.top_frac)
+                 fine_steps=a.fine_steps, epochs=a.epochs, samples_per_dir=a.samples, top_frac=a.top_frac,
+                 pair=a.pair, strength=a.strength)
     log = lambda *m: print(*m, file=sys.stderr, flush=True)
     t0 = time.time()
     X, T = generate(bd, cfg, solar_wind_states(cfg.train_states, cfg.seed_train), log)
@@ -320,13 +468,15 @@ def main():
     t1 = time.time()
     mlp, stats, hist = train(bd, cfg, X, T, log)
     log(f"training {time.time() - t1:.1f} s")
+    stats = with_strength(stats, cfg.strength)
     ev = evaluate(bd, cfg, mlp, stats, solar_wind_states(cfg.heldout_states, cfg.seed_heldout), log)
     summary = {"samples": int(X.shape[0]), "loss": hist, "heldout": ev,
                "gain_mean": float(np.mean([e["gain"] for e in ev])),
                "one_step_gain_mean": float(np.mean([e["one_step"]["gain"] for e in ev])),
+               "one_step_exact_target_gain_mean": float(np.mean([e["one_step_exact_target"]["gain"] for e in ev])),
                "config": dataclasses.asdict(cfg)}
     if a.out:
-        torch.save({"params": mlp.p.cpu(), "stats": stats.cpu(), "hidden": cfg.hidden, "summary": summary}, a.out)
+        save(a.out, mlp, stats, cfg, summary)
     print(json.dumps(summary))
 
 

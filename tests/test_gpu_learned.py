@@ -171,3 +171,27 @@ def test_learned_stage_adds_the_network_increment(bd):
     assert scale > 1e-7
     # bound: FP32 rounding of the de-normalised increments, and FP64 rounding of the stage sums
     assert np.abs(got - expect).max() <= 1e-6 * scale + 1e-14 * np.abs(U1b.cpu().numpy()).max()
+
+
+def test_given_corrections_equal_the_network_path(bd):
+    """Mode 2 of the learned form takes the normalised corrections as given: handing it the network's own
+    outputs for the step's input reproduces the network path bit for bit (one stage)."""
+    wl = wk.magnetosphere_cut(32)
+    g = bd.Grid.from_workload(wl).upload()
+    U0 = g.set_state(dev(wl.W))
+    rng = np.random.default_rng(4)
+    mlp = bd.Mlp(32, torch.from_numpy(rng.normal(scale=0.3, size=bd.lib().bmhd_mlp_n_params(32)).astype(np.float32)))
+    stats = torch.zeros(80)
+    stats[32:64] = 1.0
+    stats[64:72] = 1e-4
+    stats[72:80] = 1e-3
+    dt = torch.tensor([0.005], dtype=torch.float64, device="cuda")
+    kw = dict(flux="hlle", powell=True, recompute_dt=False, scheme="plane", slab=4)
+    Ua, U1a = U0.clone(), torch.zeros_like(U0)
+    g.advance(Ua, U1a, dt, 1, learned=g.learned(mlp, stats), **kw)
+    torch.cuda.synchronize()
+    y = g._ly.clone()
+    Ub, U1b = U0.clone(), torch.zeros_like(U0)
+    g.advance(Ub, U1b, dt, 1, learned=g.given_corrections(y, stats), **kw)
+    torch.cuda.synchronize()
+    assert torch.equal(U1a, U1b)
