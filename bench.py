@@ -42,7 +42,7 @@ TRAFFIC = {
 # stages, SQ_INSTS_VALU x 64 / cells from a rocprofv3 counter run; the summary under profiles/), keyed
 # like TRAFFIC; the VALU issue peak is one wave64 instruction per CU per clock (4 SIMDs x 16 lanes):
 # 256 CUs x 2.4 GHz x 64 lanes
-VALU_PER_CELL_STAGE = {("plane", 4): 1933.0}
+VALU_PER_CELL_STAGE = {("plane", 4): 1917.0}
 VALU_PEAK_LANE_OPS = 256 * 2.4e9 * 64
 
 
