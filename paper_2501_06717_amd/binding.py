@@ -218,9 +218,11 @@ class Grid:
         return cls(wl.level, wl.ijk, wl.sim, wl.sims)
 
     def __del__(self):
+        # at interpreter exit the module's globals may already be gone: the process frees the grid then
         h = getattr(self, "h", None)
-        if h is not None and h.value:
-            lib().bmhd_grid_destroy(h)
+        L = globals().get("_lib")
+        if h is not None and h.value and L is not None:
+            L.bmhd_grid_destroy(h)
             self.h = None
 
     @property
