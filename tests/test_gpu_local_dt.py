@@ -39,6 +39,7 @@ CASES = {
     "body": lambda: wk.magnetosphere_cut(32),
     "two_level": lambda: wk.two_level_box(),
     "odd_box": lambda: wk.odd_box(),
+    "batch": lambda: wk.batched_waves(n_sims=3, n_lo=8, n_hi=27),
 }
 
 
