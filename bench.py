@@ -302,7 +302,7 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    if not (a.no_forms or a.profile):
+    if not (a.no_forms or a.profile) and fp64:
         U32, wall32, st32, f32, _ = time_form(g, W, steps, warm, "fp32_flux", a.slab, a.persist, a.scheme)
         ref = U64.cpu().numpy()
         got = U32.cpu().numpy()
@@ -319,7 +319,7 @@ def main():
         out["forms"]["local_dt"] = bench_local_dt(g, W, cells, a.form_steps)
     del U64
     torch.cuda.synchronize()
-    if not (a.no_forms or a.profile):
+    if not (a.no_forms or a.profile) and fp64:
         del g, W
         out.setdefault("forms", {})
         out["forms"]["batched"] = bench_batched(a.form_steps)
