@@ -14,6 +14,9 @@
 //   k_flux_correct coarse cells next to a coarse-fine face swap their coarse flux for the mean of the
 //                 four fine fluxes (FP64 in every precision form);
 //   k_dt_finalize dt = CFL / max bound per simulation.
+// Under local time stepping (steady-state sessions, Sec. 5.2) the first stage forms each cell's own CFL
+// step from its FP64 stage input and stores it; the second stage and k_flux_correct read it.
+// Between steps: k_remap moves a state onto an adapted grid (copy, prolongation, restriction).
 // Workgroups are mapped XCD-aware: consecutive workgroup ids go to different XCDs, so each XCD is
 // handed a contiguous run of the Morton-ordered block schedule and neighbouring blocks share an L2.
 #include <hip/hip_runtime.h>
