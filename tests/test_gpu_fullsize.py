@@ -107,6 +107,25 @@ def test_two_level_magnetosphere_one_step(bd, oracle_mod):
         assert max(err.values()) <= tol, err
 
 
+@pytest.mark.parametrize("name,make,steps", [
+    ("two-level magnetosphere", lambda: wk.two_level_magnetosphere(144), 10),
+    ("magnetosphere 256^3", lambda: wk.magnetosphere(256), 5),
+])
+def test_full_size_several_steps(bd, oracle_mod, name, make, steps):
+    """Several steps at full size with the global dt recomputed every step: the rounding differences
+    between the two paths stay at the 1e-15 level (no limiter or fallback decision amplifies them)."""
+    wl = make()
+    kw = dict(flux="hlle", powell=True, cfl=0.8)
+    say(name, "steps", steps)
+    R, rdt, rf = oracle_steps(oracle_mod, wl, 2 * steps, **kw)
+    G, dt, f = gpu_steps(bd, wl, 2 * steps, **kw)
+    err = group_err(G, R)
+    say("  fp64 err", err)
+    assert f == 0 and rf == 0
+    assert np.all(np.abs(dt - rdt) <= 1e-14 * rdt), (dt, rdt)
+    assert max(err.values()) <= TOL, err
+
+
 def test_batched_64_simulations_two_steps(bd, oracle_mod):
     wl = wk.batched_waves()
     kw = dict(flux="rusanov", powell=False, cfl=0.8)
