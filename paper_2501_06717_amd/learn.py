@@ -241,8 +241,9 @@ def generate(bd, cfg: Config, states, log=print):
     return torch.cat(X), torch.cat(T)
 
 
-def train(bd, cfg: Config, X, T, log=print):
-    """Adam on z-scored inputs and targets; returns (mlp, stats[80], loss history)."""
+def train(bd, cfg: Config, X, T, log=print, init=None):
+    """Adam on z-scored inputs and targets; returns (mlp, stats[80], loss history). `init`: parameters to
+    start from (a network written by save(), trained on the same data statistics), else He-style random."""
     import torch
     pairs = X.dim() == 3
     Xf, Tf = (X.reshape(-1, 32), T.reshape(-1, 8)) if pairs else (X, T)
@@ -260,6 +261,8 @@ def train(bd, cfg: Config, X, T, log=print):
     for (nout, nin) in [(cfg.hidden, 32), (cfg.hidden, cfg.hidden), (cfg.hidden, cfg.hidden), (8, cfg.hidden)]:
         p[o:o + nout * nin] = rng.normal(scale=math.sqrt(2.0 / nin), size=nout * nin)
         o += nout * nin + nout
+    if init is not None:
+        p = np.load(init, allow_pickle=False)["params"].astype(np.float32)
     mlp = bd.Mlp(cfg.hidden, torch.from_numpy(p))
     n = Xn.shape[0]
     hist = []
@@ -455,18 +458,20 @@ def main():
     ap.add_argument("--pair", type=float, default=0.0,
                     help="train on face pairs with this weight on the error of the pair's difference")
     ap.add_argument("--out", default=None)
+    ap.add_argument("--init", default=None, help="start from the parameters of a saved network")
+    ap.add_argument("--lr", type=float, default=1e-3)
     a = ap.parse_args()
     import torch
     from . import binding as bd
     cfg = Config(n_fine=a.n_fine, train_states=a.train_states, heldout_states=a.heldout_states,
                  fine_steps=a.fine_steps, epochs=a.epochs, samples_per_dir=a.samples, top_frac=a.top_frac,
-                 pair=a.pair, strength=a.strength)
+                 pair=a.pair, strength=a.strength, lr=a.lr)
     log = lambda *m: print(*m, file=sys.stderr, flush=True)
     t0 = time.time()
     X, T = generate(bd, cfg, solar_wind_states(cfg.train_states, cfg.seed_train), log)
     log(f"{X.shape[0]} samples in {time.time() - t0:.1f} s")
     t1 = time.time()
-    mlp, stats, hist = train(bd, cfg, X, T, log)
+    mlp, stats, hist = train(bd, cfg, X, T, log, init=a.init)
     log(f"training {time.time() - t1:.1f} s")
     stats = with_strength(stats, cfg.strength)
     ev = evaluate(bd, cfg, mlp, stats, solar_wind_states(cfg.heldout_states, cfg.seed_heldout), log)
