@@ -64,3 +64,42 @@ def test_faces_global_and_coarse_mean(d):
             g[t[1]] += b
             acc += fn(d, g[0], g[1], g[2])
     assert M[c[2], c[1], c[0]] == acc / 4
+
+
+@pytest.mark.parametrize("d", [0, 1, 2])
+def test_faces_to_blocks_inverts_faces_global(d):
+    """Per-block faces -> global faces -> per-block faces is the identity (faces shared by two blocks
+    carry the same value in both)."""
+    nb = 2
+    F = per_block_faces(nb, lambda dd, X, Y, Z: 1000.0 * dd + X + 20.0 * Y + 400.0 * Z)
+    G = learn.faces_global(F, nb, d, 1)
+    back = learn.faces_to_blocks(G, nb, d)
+    assert torch.equal(back, F.reshape(nb ** 3, 3, 576, 1)[:, d])
+
+
+def test_strength_scales_only_the_output_statistics():
+    stats = torch.arange(80, dtype=torch.float32) + 1.0
+    s = learn.with_strength(stats, 0.25)
+    assert torch.equal(s[:64], stats[:64])
+    assert torch.equal(s[64:], 0.25 * stats[64:])
+    assert torch.equal(stats, torch.arange(80, dtype=torch.float32) + 1.0)  # the input is not modified
+
+
+def test_saved_network_is_plain_arrays(tmp_path):
+    class Net:
+        p = torch.linspace(-1.0, 1.0, 11)
+    cfg = learn.Config(hidden=32, strength=0.5)
+    path = str(tmp_path / "net.npz")
+    learn.save(path, Net(), torch.ones(80), cfg, {"gain_mean": 1.03})
+    d = np.load(path, allow_pickle=False)
+    assert np.array_equal(d["params"], Net.p.numpy()) and d["params"].dtype == np.float32
+    assert int(d["hidden"]) == 32 and float(d["strength"]) == 0.5
+    assert '"gain_mean": 1.03' in str(d["summary"])
+
+
+def test_shipped_network_file():
+    import os
+    path = os.path.join(os.path.dirname(learn.__file__), "trained", "flux_mlp_h128.npz")
+    d = np.load(path, allow_pickle=False)
+    assert int(d["hidden"]) == 128 and d["params"].shape == (38280,) and d["stats"].shape == (80,)
+    assert np.all(np.isfinite(d["params"])) and np.all(d["stats"][32:64] > 0) and np.all(d["stats"][72:80] > 0)
