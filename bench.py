@@ -79,8 +79,9 @@ def parse():
                    help="also run a plain 256 MiB device copy (scales the HBM byte counters of a profiler run)")
     p.add_argument("--precision", default="fp64", choices=["fp64", "fp32_flux"],
                    help="precision of the timed magnetosphere run (the metric is quoted for fp64)")
-    p.add_argument("--form", default="plain", choices=["plain", "batched"],
-                   help="with --profile: run only this form (batched: the 64-simulation batch, graph-replayed)")
+    p.add_argument("--form", default="plain", choices=["plain", "batched", "learned"],
+                   help="with --profile: run only this form (batched: the 64-simulation batch, graph-replayed; "
+                        "learned: the learned correction on the 128^3 grid)")
     return p.parse_args()
 
 
@@ -239,8 +240,8 @@ def main():
     from paper_2501_06717_amd import binding, workloads as wk
 
     torch.cuda.set_device(0)
-    if a.profile and a.form == "batched":
-        log(json.dumps(bench_batched(a.steps)))
+    if a.profile and a.form != "plain":
+        log(json.dumps(bench_batched(a.steps) if a.form == "batched" else bench_learned(a.steps)))
         return
     wl = wk.magnetosphere(a.n, n_steps=a.steps)
     log(f"workload {wl.name}: {wl.n_blocks} blocks, {wl.n_cells} cells")
