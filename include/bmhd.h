@@ -228,7 +228,11 @@ int32_t bmhd_face_data(const bmhd_grid *g, const double *d_U, int32_t flux, cons
  * steps each with `base`'s other options, on the caller's buffers (they are advanced: pass scratch
  * copies), and write `base` with the fastest shape into *best. h_ms (host, may be NULL) receives the
  * milliseconds of the 12 candidates: scheme FACE then PLANE, each in the order (4,0) (4,2/CU) (4,4/CU)
- * (8,0) (8,2/CU) (8,4/CU). Blocking: synchronises `stream`. */
+ * (8,0) (8,2/CU) (8,4/CU). Blocking: synchronises `stream`. With the environment variable
+ * BMHD_AUTOTUNE_CACHE naming a file, the choice is kept there, one text line per configuration keyed by
+ * the device (architecture, CU count), the grid (sizes and a hash of its block list) and the options
+ * that change the work; a later call with the same key returns the stored shape without timing (h_ms
+ * entries then -1) and leaves the buffers untouched. */
 int32_t bmhd_autotune(const bmhd_grid *g, double *d_U0, double *d_U1, double *d_dt, const bmhd_opts *base,
                       int32_t n_steps, bmhd_opts *best, float *h_ms, void *stream);
 

@@ -22,6 +22,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 
@@ -1724,6 +1725,49 @@ bool remap_source(const HostGrid &f, int s, int l, const int32_t *ijk) {
     return true;
 }
 
+// Autotuner cache key: device (architecture, CU count), grid (sizes and an FNV-1a hash of its block list)
+// and the options that change the work (flux, Powell, precision, learned, local dt, graphs, step count).
+int32_t autotune_key(const HostGrid &h, const bmhd_opts &o, int n_steps, int dev, int cus, std::string &key) {
+    hipDeviceProp_t prop;
+    if (int32_t rc = hip_check(hipGetDeviceProperties(&prop, dev), "device properties")) return rc;
+    uint64_t hsh = 1469598103934665603ull;
+    auto mix = [&](const void *p, size_t n) {
+        const unsigned char *c = static_cast<const unsigned char *>(p);
+        for (size_t q = 0; q < n; ++q) hsh = (hsh ^ c[q]) * 1099511628211ull;
+    };
+    mix(h.level.data(), h.level.size() * sizeof(int32_t));
+    mix(h.ijk.data(), h.ijk.size() * sizeof(int32_t));
+    mix(h.sim.data(), h.sim.size() * sizeof(int32_t));
+    char buf[512];
+    snprintf(buf, sizeof buf, "%s/%d/nb%d/ns%d/h%016llx/f%d/p%d/q%d/l%d/t%d/g%d/s%d", prop.gcnArchName, cus, h.nb, h.ns,
+             (unsigned long long)hsh, o.flux, o.powell, o.precision, o.learned ? 1 : 0, o.local_dt, o.use_graph,
+             n_steps);
+    key = buf;
+    for (char &c : key)
+        if (c == ' ') c = '_';
+    return BMHD_OK;
+}
+
+bool autotune_lookup(const char *path, const std::string &key, int &scheme, int &slab, int &persist) {
+    FILE *f = fopen(path, "r");
+    if (!f) return false;
+    char line[1024];
+    bool hit = false;
+    while (fgets(line, sizeof line, f)) {
+        char k[600];
+        int a = 0, b = 0, c = 0;
+        if (sscanf(line, "%599s %d %d %d", k, &a, &b, &c) == 4 && key == k &&
+            (a == BMHD_SCHEME_FACE || a == BMHD_SCHEME_PLANE) && (b == 4 || b == 8) && (c == 0 || c == 2 || c == 4)) {
+            scheme = a;
+            slab = b;
+            persist = c;
+            hit = true;
+        }
+    }
+    fclose(f);
+    return hit;
+}
+
 int32_t need_upload(const bmhd_grid *g) {
     if (!g) return fail(BMHD_EINVAL, "null grid");
     if (!g->h.d_work) return fail(BMHD_EINVAL, "grid not uploaded (call bmhd_grid_upload first)");
@@ -1930,6 +1974,22 @@ int32_t bmhd_autotune(const bmhd_grid *g, double *d_U0, double *d_U1, double *d_
     int dev = 0, cus = 0;
     if (int32_t rc = hip_check(hipGetDevice(&dev), "device")) return rc;
     if (int32_t rc = hip_check(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev), "attr")) return rc;
+    // on-disk cache (opt-in): one line per tuned configuration, the last matching line wins
+    const char *cache = getenv("BMHD_AUTOTUNE_CACHE");
+    std::string key;
+    if (cache && *cache) {
+        if (int32_t rc = autotune_key(g->h, *base, n_steps, dev, cus, key)) return rc;
+        int sc = 0, sl = 0, pp = 0;
+        if (autotune_lookup(cache, key, sc, sl, pp)) {
+            *best = *base;
+            best->scheme = sc;
+            best->slab = sl;
+            best->persist_wgs = pp * cus;
+            if (h_ms)
+                for (int c = 0; c < 12; ++c) h_ms[c] = -1.0f;
+            return BMHD_OK;
+        }
+    }
     hipEvent_t e0, e1;
     if (int32_t rc = hip_check(hipEventCreate(&e0), "event")) return rc;
     if (int32_t rc = hip_check(hipEventCreate(&e1), "event")) return rc;
@@ -1963,6 +2023,12 @@ int32_t bmhd_autotune(const bmhd_grid *g, double *d_U0, double *d_U1, double *d_
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
+    if (rc == BMHD_OK && !key.empty()) {
+        if (FILE *f = fopen(cache, "a")) {
+            fprintf(f, "%s %d %d %d\n", key.c_str(), best->scheme, best->slab, cus ? best->persist_wgs / cus : 0);
+            fclose(f);
+        }
+    }
     return rc;
 }
 

@@ -308,3 +308,25 @@ def test_autotune_picks_a_valid_shape(bd):
     assert best.scheme in (1, 2) and best.slab in (4, 8) and best.persist_wgs >= 0
     assert all(v > 0 for v in ms.values())
     assert min(ms.values()) == pytest.approx(ms[min(ms, key=ms.get)])
+
+
+def test_autotune_cache(bd, tmp_path, monkeypatch):
+    """With BMHD_AUTOTUNE_CACHE set the autotuner stores its choice and a second call with the same
+    device, grid and options returns it without timing; other options miss."""
+    path = tmp_path / "tune.txt"
+    monkeypatch.setenv("BMHD_AUTOTUNE_CACHE", str(path))
+    wl = wk.two_level_box()
+    g = bd.Grid.from_workload(wl).upload()
+    U0 = g.set_state(dev(wl.W))
+    U1 = torch.zeros_like(U0)
+    dt = torch.zeros(1, dtype=torch.float64, device="cuda")
+    kw = dict(flux="hlle", powell=True)
+    b1, ms1 = g.autotune(U0.clone(), U1, dt, n_steps=1, **kw)
+    assert all(v > 0 for v in ms1.values())
+    assert len(path.read_text().splitlines()) == 1
+    b2, ms2 = g.autotune(U0.clone(), U1, dt, n_steps=1, **kw)
+    assert all(v == -1.0 for v in ms2.values())
+    assert (b2.scheme, b2.slab, b2.persist_wgs) == (b1.scheme, b1.slab, b1.persist_wgs)
+    _, ms3 = g.autotune(U0.clone(), U1, dt, n_steps=1, precision="fp32_flux", **kw)
+    assert all(v > 0 for v in ms3.values())
+    assert len(path.read_text().splitlines()) == 2
