@@ -188,6 +188,25 @@ def bench_learned(steps):
                          "gain_one_step_exact_target": ev["one_step_exact_target"]["gain"]}}
 
 
+def copy_bandwidth():
+    """Achievable HBM bandwidth: a 2 GiB device-to-device copy (read + write), best of 5, HIP events."""
+    import torch
+    n = 256 * 1024 * 1024
+    src = torch.ones(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    best = 1e30
+    for _ in range(5):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        dst.copy_(src)
+        e1.record()
+        torch.cuda.synchronize()
+        best = min(best, e0.elapsed_time(e1) * 1e-3)
+    del src, dst
+    return 2 * n * 8 / best / 1e9
+
+
 def bench_local_dt(g, W, cells, steps):
     """Local time stepping (the steady-state mode: every cell advances with its own CFL step) on the same
     workload, FP64, default launch shape: the per-cell step is formed in the first stage from its input."""
@@ -296,6 +315,11 @@ def main():
                      "valu": valu},
         "faults": faults,
     }
+    if not a.profile:
+        bw = copy_bandwidth()
+        out["roofline"]["measured_copy_GBs"] = bw
+        out["roofline"]["frac_of_measured_copy"] = achieved / bw
+        log(f"device copy: {bw:.0f} GB/s")
     if a.calib:
         src = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device="cuda")
         dst = torch.empty_like(src)
@@ -341,6 +365,25 @@ def main():
                                "sample": f"{a.cpu_steps} full step(s) of the same {a.n}^3 workload "
                                          f"({tc:.1f} s, OpenMP over blocks)"}
         log(f"cpu oracle: {tc:.1f} s for {a.cpu_steps} step(s)")
+        # one thread on a 64^3 cut of the same workload (the per-cell work is the same), for the GPU's
+        # equivalent in host cores
+        import ctypes
+        gomp = ctypes.CDLL("libgomp.so.1")
+        cut = wk.magnetosphere_cut(64)
+        oc = oracle.Grid.from_workload(cut)
+        V0 = oc.set_state(cut.W)
+        V1 = np.zeros_like(V0)
+        gomp.omp_set_num_threads(1)
+        t0 = time.perf_counter()
+        oc.advance(V0, V1, [0.0], 2, flux="hlle", powell=True, cfl=0.8)
+        t1c = time.perf_counter() - t0
+        gomp.omp_set_num_threads(min(cores, threads))
+        one = cut.n_cells / t1c
+        out["cpu_baseline"]["one_thread"] = {"value": one, "unit": "cell-updates/s",
+                                             "sample": f"1 step of the {cut.n_cells}-cell cut of the same workload "
+                                                       f"({t1c:.1f} s, one thread)"}
+        out["cpu_baseline"]["gpu_equivalent_cores"] = value / one
+        log(f"cpu oracle, one thread: {one:.3e} cell-updates/s; GPU = {value / one:.0f} cores")
     print(json.dumps(out), flush=True)
 
 
