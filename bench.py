@@ -253,7 +253,7 @@ def bench_paper_fast_wave():
 def main():
     a = parse()
     if a.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "this benchmark runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
     import torch
     from paper_2501_06717_amd import binding, workloads as wk

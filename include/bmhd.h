@@ -238,8 +238,8 @@ int32_t bmhd_autotune(const bmhd_grid *g, double *d_U0, double *d_U1, double *d_
 
 /* ---------------------------------------------------------------------------------------------
  * Learned flux correction: a multilayer perceptron 32 -> H -> H -> H -> 8 with SiLU activations
- * (hidden width H in {32, 64, 128}). This component is not in the paper; it is the task's learned
- * form. Parameters are one flat float32 vector W1[H][32], b1[H], W2[H][H], b2[H], W3[H][H], b3[H],
+ * (hidden width H in {32, 64, 128}). This component is not in the paper: it corrects the plain flux
+ * of a coarse grid toward that of a grid twice as fine. Parameters are one flat float32 vector W1[H][32], b1[H], W2[H][H], b2[H], W3[H][H], b3[H],
  * W4[8][H], b4[8] (row-major, output index first) plus a bfloat16 copy of it (uint16 storage) that the
  * matrix-core products read. Loss: mean over samples and the 8 outputs of the squared error.
  * mode 0: products on BF16 matrix cores with FP32 accumulation; mode 1: FP32 FMAs (reference mode).

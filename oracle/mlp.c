@@ -3,7 +3,7 @@
  *
  * TEST INFRASTRUCTURE ONLY (see oracle.c). Plain loops, float64, no blocking.
  *
- * Network (a reading of the task's learned-correction form; the paper has no learned component):
+ * Network of the learned flux correction (a component the paper does not have):
  *   h1 = silu(W1 x + b1), h2 = silu(W2 h1 + b2), h3 = silu(W3 h2 + b3), y = W4 h3 + b4,
  * with x in R^32, hidden width H, y in R^8 and silu(z) = z / (1 + exp(-z)). Parameters are one flat
  * vector in the order W1[H][32], b1[H], W2[H][H], b2[H], W3[H][H], b3[H], W4[8][H], b4[8] (weights
