@@ -69,6 +69,7 @@ def test_descriptor_validation():
     s = wk.Sim((2, 1, 1), (0, 0, 0), 1.0)
     _expect_einval([0, 0], [[0, 0, 0], [0, 0, 0]], [0, 0], [s])          # overlap
     _expect_einval([0], [[0, 0, 0]], [0], [s])                            # uncovered root
+    _expect_einval(np.zeros(0), np.zeros((0, 3)), np.zeros(0), [s])       # no blocks at all
     _expect_einval([0, 1], [[0, 0, 0], [2, 0, 0]], [0, 0], [s])           # partial refinement
     _expect_einval([0, 0], [[0, 0, 0], [1, 0, 0]], [0, 1], [s])           # bad simulation id
     _expect_einval([0, 2], [[0, 0, 0], [1, 0, 0]], [0, 0], [s])           # bad level

@@ -128,6 +128,10 @@ STAGE_CASES = {
     "cp_alfven_32": (lambda: wk.cp_alfven(32), dict(flux="rusanov", powell=False)),
     "cp_alfven_32_hlle": (lambda: wk.cp_alfven(32), dict(flux="hlle", powell=True)),
     "odd_box": (lambda: wk.odd_box(), dict(flux="hlle", powell=True)),
+    # one periodic block: every neighbour, across faces, edges and corners, is the block itself
+    "periodic_1": (lambda: wk.with_state(wk.uniform_state((1, 1, 1)),
+                                         wk.random_positive_state(wk.uniform_state((1, 1, 1)), seed=7)),
+                   dict(flux="hlle", powell=True)),
     "magnetosphere_32": (lambda: wk.magnetosphere_cut(32), dict(flux="hlle", powell=True)),
     "two_level_box": (lambda: wk.two_level_box(), dict(flux="rusanov", powell=False)),
     "two_level_box_hlle": (lambda: wk.two_level_box(bc=(1, 2, 0, 0, 2, 1)), dict(flux="hlle", powell=True)),
