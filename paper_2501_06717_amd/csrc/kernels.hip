@@ -916,7 +916,6 @@ __device__ __forceinline__ void slab_compute(const Tables &T, const StageArgs &A
     using SL = Slab<KS>;
     const DevBlock &B = T.blocks[b];
     const DevSim &S = T.sims[B.sim];
-    const size_t vs = size_t(T.nb) * 512;
     const bool near_body = (B.flags & BF_NEAR_BODY) != 0;
     const int tid = lane_tid();
     const bool owner = tid < SL::NCELLS;
@@ -1165,8 +1164,13 @@ __device__ __noinline__ void wp_item(const Tables &T, const StageArgs &A, int b,
     wp_compute<KS, R, FLUX, POWELL, LEARN>(T, A, b, slab, sW, sH, sMb, red, redi);
 }
 
+// Waves per SIMD the register allocator aims for: four (at most 128 VGPRs), except for the FP64 tile of
+// eight cell layers, whose LDS footprint already allows only one workgroup (three waves per SIMD) per CU.
+template <int KS, typename R>
+constexpr int wp_waves_per_simd() { return (KS == 8 && sizeof(R) == 8) ? 3 : 4; }
+
 template <int KS, typename R, int FLUX, bool POWELL, bool PERSIST, bool LEARN = false>
-__global__ void __launch_bounds__(64 * (KS + 1), 4) k_stage_wp(Tables T, StageArgs A) {
+__global__ void __launch_bounds__(64 * (KS + 1), (wp_waves_per_simd<KS, R>())) k_stage_wp(Tables T, StageArgs A) {
     using SL = Slab<KS>;
     static_assert(SL::NT == 64 * (KS + 1), "one wave per cell layer plus one");
     static_assert(SL::NC - SL::XH == 64 * KS && 9 * 8 * KS >= 64 * KS, "z-flux exchange space");
