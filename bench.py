@@ -250,6 +250,33 @@ def bench_paper_fast_wave():
             "ratio_to_paper": cells * steps / t / (960000 * 500 / 5.76)}
 
 
+def accuracy_vs_oracle(binding, wl, R, steps):
+    """L1 and per-group L-infinity error of the FP64 path and of the FP32-flux form against the oracle's
+    result R after the same steps from the same state (the workload the benchmark times, full size)."""
+    import torch
+    g = binding.Grid.from_workload(wl).upload()
+    W = torch.from_numpy(wl.W).cuda()
+    out = {"steps": steps, "reference": "the CPU oracle (FP64) on the same steps of the same workload"}
+    for precision in ("fp64", "fp32_flux"):
+        U0 = g.set_state(W)
+        U1 = torch.empty_like(U0)
+        dt = torch.zeros(1, dtype=torch.float64, device="cuda")
+        faults = torch.zeros(1, dtype=torch.int32, device="cuda")
+        torch.cuda.synchronize()
+        g.advance(U0, U1, dt, 2 * steps, faults=faults, flux="hlle", powell=True, cfl=0.8, precision=precision)
+        torch.cuda.synchronize()
+        got = U0.cpu().numpy()
+        del U0, U1
+        out[precision] = {"l1_rel": float(np.abs(got - R).sum() / np.abs(R).sum()),
+                          "linf_rel": {k: float(np.abs(got[v] - R[v]).max() / np.abs(R[v]).max())
+                                       for k, v in (("rho", [0]), ("mom", [1, 2, 3]), ("B", [4, 5, 6]), ("e", [7]))},
+                          "faults": int(faults.item())}
+        del got
+    del g, W
+    torch.cuda.synchronize()
+    return out
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -365,6 +392,8 @@ def main():
                                "sample": f"{a.cpu_steps} full step(s) of the same {a.n}^3 workload "
                                          f"({tc:.1f} s, OpenMP over blocks)"}
         log(f"cpu oracle: {tc:.1f} s for {a.cpu_steps} step(s)")
+        out["accuracy_vs_oracle"] = accuracy_vs_oracle(binding, wl, U0, a.cpu_steps)
+        log(f"accuracy vs oracle: {json.dumps(out['accuracy_vs_oracle'])}")
         # one thread on a 64^3 cut of the same workload (the per-cell work is the same), for the GPU's
         # equivalent in host cores
         import ctypes
