@@ -96,7 +96,8 @@ typedef struct {
     const float *params;         /* device [n_params] float32 */
     const uint16_t *params_bf16; /* device [n_params] bfloat16 copy */
     const float *stats;          /* device: in_mean[32], in_std[32], out_mean[8], out_std[8] */
-    float *x_buf;                /* device scratch [n_blocks * 1728][32] */
+    float *x_buf;                /* device scratch [n_blocks * 1728][32] float32; mode 0 stores the
+                                    features as bfloat16 in its first half and needs 16-byte alignment */
     float *y_buf;                /* device scratch [n_blocks * 1728][8] */
     uint8_t *flags;              /* device scratch [n_blocks * 512] */
     int32_t *fallback_cells;     /* device counter of flagged cells, incremented per stage (may be NULL) */

@@ -112,6 +112,11 @@ struct HostGrid {
 };
 
 int32_t build_grid(const bmhd_grid_desc *d, HostGrid &g, std::string &err);
+
+// BF16 inference of the flux-correction MLP on inputs already rounded to BF16 ([n][32], 16-byte
+// aligned), the same products as bmhd_mlp_forward in mode 0 on their FP32 originals; enqueued on stream.
+int32_t mlp_infer_bf16_inputs(const float *d_params, const uint16_t *d_params_bf16, int32_t hidden, int32_t n,
+                              const uint16_t *d_x, float *d_y, void *stream, std::string &err);
 void prim_to_cons_host(const double *w, double *u);
 
 }  // namespace bmhd

@@ -25,6 +25,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <string>
+#include <type_traits>
 
 #include "bmhd_internal.h"
 
@@ -1297,10 +1298,12 @@ __global__ void __launch_bounds__(Slab<8>::NT) k_face_data(Tables T, StageArgs A
 
 // Z-scored stencil features of every face of a block for the learned correction's inference: the
 // layout of bmhd_face_data's X, FP32 primitives in LDS (40 KB per block, so several blocks per CU); each
-// thread takes one stencil cell of a face at a time (8 features), so a wavefront's stores cover 2 KB of
-// contiguous memory.
+// thread takes one stencil cell of a face at a time (8 features), so a wavefront's stores cover
+// contiguous memory. TX = __bf16 stores the features rounded as the BF16 network consumes them (half
+// the bytes); TX = float keeps them for the FP32 network.
+template <typename TX>
 __global__ void __launch_bounds__(Slab<8>::NT) k_face_features(Tables T, StageArgs A, const float *__restrict__ stats,
-                                                               float *__restrict__ X) {
+                                                               TX *__restrict__ X) {
     using SL = Slab<8>;
     __shared__ float sW[8][SL::NC];
     __shared__ unsigned char sM[SL::NC];
@@ -1318,7 +1321,7 @@ __global__ void __launch_bounds__(Slab<8>::NT) k_face_features(Tables T, StageAr
     const int tid = lane_tid();
 #pragma unroll
     for (int D = 0; D < 3; ++D) {
-        float *base = X + (size_t(b) * 3 + D) * 576 * 32;
+        TX *base = X + (size_t(b) * 3 + D) * 576 * 32;
 #pragma unroll
         for (int m = 0; m < 4; ++m) {
             const int t = tid + m * SL::NT, f = t >> 2, q = t & 3;
@@ -1338,9 +1341,17 @@ __global__ void __launch_bounds__(Slab<8>::NT) k_face_features(Tables T, StageAr
             }
 #pragma unroll
             for (int v = 0; v < 8; ++v) x[v] = (x[v] - sMean[q * 8 + v]) * sInv[q * 8 + v];
-            float4 *out = reinterpret_cast<float4 *>(base + size_t(t) * 8);
-            out[0] = make_float4(x[0], x[1], x[2], x[3]);
-            out[1] = make_float4(x[4], x[5], x[6], x[7]);
+            if constexpr (std::is_same<TX, __bf16>::value) {
+                typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8_t;
+                bf16x8_t h;
+#pragma unroll
+                for (int v = 0; v < 8; ++v) h[v] = __bf16(x[v]);
+                *reinterpret_cast<bf16x8_t *>(base + size_t(t) * 8) = h;
+            } else {
+                float4 *out = reinterpret_cast<float4 *>(base + size_t(t) * 8);
+                out[0] = make_float4(x[0], x[1], x[2], x[3]);
+                out[1] = make_float4(x[4], x[5], x[6], x[7]);
+            }
         }
     }
 }
@@ -1583,6 +1594,8 @@ int32_t check_opts(const bmhd_opts &o) {
         if (L.mode != 0 && L.mode != 1 && L.mode != 2) return fail(BMHD_EINVAL, "learned: mode must be 0, 1 or 2");
         if (!L.stats || !L.y_buf || !L.flags || (L.mode != 2 && (!L.params || !L.params_bf16 || !L.x_buf)))
             return fail(BMHD_EINVAL, "learned: null buffer");
+        if (L.mode == 0 && (reinterpret_cast<uintptr_t>(L.x_buf) & 15u))
+            return fail(BMHD_EINVAL, "learned: x_buf must be 16-byte aligned");
         if (!(L.tau >= 0.0)) return fail(BMHD_EINVAL, "learned: tau must be >= 0");
         if (o.use_graph) return fail(BMHD_EUNSUPPORTED, "learned correction is not captured in graphs");
         if (o.local_dt) return fail(BMHD_EUNSUPPORTED, "learned correction with local time stepping");
@@ -1625,8 +1638,15 @@ int32_t enqueue_stage(const HostGrid &h, const bmhd_opts &o, int e, double *d_U0
         a.want_lam = 0;
         const int count = a.count_faults;
         a.count_faults = 0;
-        if (L.mode != 2) {  // mode 2: y_buf is given
-            k_face_features<<<h.nb, Slab<8>::NT, 0, s>>>(h.dev, a, L.stats, L.x_buf);
+        if (L.mode == 0) {  // BF16 network: features stored in BF16 in the first half of x_buf
+            uint16_t *xb = reinterpret_cast<uint16_t *>(L.x_buf);
+            k_face_features<__bf16><<<h.nb, Slab<8>::NT, 0, s>>>(h.dev, a, L.stats, reinterpret_cast<__bf16 *>(xb));
+            if (int32_t rc = launch_check("face features")) return rc;
+            std::string err;
+            if (int32_t rc = mlp_infer_bf16_inputs(L.params, L.params_bf16, L.hidden, h.nb * 1728, xb, L.y_buf, s, err))
+                return fail(rc, err);
+        } else if (L.mode == 1) {  // FP32 network; mode 2: y_buf is given
+            k_face_features<float><<<h.nb, Slab<8>::NT, 0, s>>>(h.dev, a, L.stats, L.x_buf);
             if (int32_t rc = launch_check("face features")) return rc;
             if (int32_t rc = bmhd_mlp_forward(L.params, L.params_bf16, L.hidden, h.nb * 1728, L.x_buf, L.y_buf,
                                               nullptr, L.mode, s))

@@ -173,9 +173,10 @@ __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-template <int H, int NW, int TP>
+// X holds FP32 inputs (rounded to BF16 here) or inputs already rounded to BF16 by their producer.
+template <int H, int NW, int TP, typename TX>
 __global__ void __launch_bounds__(64 * NW) k_mlp_infer(const float *__restrict__ P, const __bf16 *__restrict__ Pb,
-                                                       int n, const float *__restrict__ X, float *__restrict__ Y) {
+                                                       int n, const TX *__restrict__ X, float *__restrict__ Y) {
     using Z = InferLds<H>;
     constexpr int NT = H / 16;
     typedef __attribute__((__vector_size__(4 * sizeof(__bf16)))) __bf16 bf16x4;
@@ -213,10 +214,14 @@ __global__ void __launch_bounds__(64 * NW) k_mlp_infer(const float *__restrict__
             const int s0 = (t0 + p) * 16, m = lane >> 2, k = (lane & 3) * 8;
             bf16x8 v;
             if (s0 + m < n) {
-                const float4 x0 = *reinterpret_cast<const float4 *>(X + size_t(s0 + m) * MLP_IN + k);
-                const float4 x1 = *reinterpret_cast<const float4 *>(X + size_t(s0 + m) * MLP_IN + k + 4);
-                v[0] = __bf16(x0.x); v[1] = __bf16(x0.y); v[2] = __bf16(x0.z); v[3] = __bf16(x0.w);
-                v[4] = __bf16(x1.x); v[5] = __bf16(x1.y); v[6] = __bf16(x1.z); v[7] = __bf16(x1.w);
+                if constexpr (std::is_same<TX, __bf16>::value) {
+                    v = *reinterpret_cast<const bf16x8 *>(X + size_t(s0 + m) * MLP_IN + k);
+                } else {
+                    const float4 x0 = *reinterpret_cast<const float4 *>(X + size_t(s0 + m) * MLP_IN + k);
+                    const float4 x1 = *reinterpret_cast<const float4 *>(X + size_t(s0 + m) * MLP_IN + k + 4);
+                    v[0] = __bf16(x0.x); v[1] = __bf16(x0.y); v[2] = __bf16(x0.z); v[3] = __bf16(x0.w);
+                    v[4] = __bf16(x1.x); v[5] = __bf16(x1.y); v[6] = __bf16(x1.z); v[7] = __bf16(x1.w);
+                }
             } else {
 #pragma unroll
                 for (int j = 0; j < 8; ++j) v[j] = __bf16(0.0f);
@@ -414,29 +419,55 @@ void gemm(int M, int N, int K, const float *A, long am, long ak, const float *B,
     else k_gemm<MFMA, false><<<blocks_for(tiles, 4), 256, 0, s>>>(M, N, K, A, am, ak, B, bk, bn, C, ldc);
 }
 
+// BF16 inference: persistent, one workgroup per CU
+template <int H, typename TX>
+int32_t infer_h(const float *P, const uint16_t *Pb, int n, const TX *X, float *Y, hipStream_t s) {
+    static int cus = 0;
+    if (cus == 0) {
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+            cus = 256;
+    }
+    const unsigned tiles = unsigned((n + 15) / 16);
+    const unsigned per = MLP_INFER_WAVES * MLP_INFER_TILES;
+    const unsigned g = tiles < per * unsigned(cus) ? blocks_for(tiles, int(per)) : unsigned(cus);
+    k_mlp_infer<H, MLP_INFER_WAVES, MLP_INFER_TILES, TX><<<g, 64 * MLP_INFER_WAVES, 0, s>>>(
+        P, reinterpret_cast<const __bf16 *>(Pb), n, X, Y);
+    return mcheck("mlp inference");
+}
+
 template <int H>
 int32_t forward_h(const float *P, const uint16_t *Pb, int n, const float *X, float *Y, float *Z, int mode, hipStream_t s) {
     const unsigned grid = blocks_for((n + 15) / 16, 4);
     const __bf16 *pb = reinterpret_cast<const __bf16 *>(Pb);
-    if (mode == 0 && !Z) {
-        // inference: persistent, one workgroup per CU
-        static int cus = 0;
-        if (cus == 0) {
-            int dev = 0;
-            if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
-                cus = 256;
-        }
-        const unsigned tiles = unsigned((n + 15) / 16);
-        const unsigned per = MLP_INFER_WAVES * MLP_INFER_TILES;
-        const unsigned g = tiles < per * unsigned(cus) ? blocks_for(tiles, int(per)) : unsigned(cus);
-        k_mlp_infer<H, MLP_INFER_WAVES, MLP_INFER_TILES><<<g, 64 * MLP_INFER_WAVES, 0, s>>>(P, pb, n, X, Y);
-        return mcheck("mlp inference");
-    }
+    if (mode == 0 && !Z) return infer_h<H, float>(P, Pb, n, X, Y, s);
     if (mode == 0) k_mlp_forward<H, true><<<grid, 256, 0, s>>>(P, pb, n, X, Y, Z);
     else k_mlp_forward<H, false><<<grid, 256, 0, s>>>(P, pb, n, X, Y, Z);
     return mcheck("mlp forward");
 }
 }  // namespace
+
+namespace bmhd {
+int32_t mlp_infer_bf16_inputs(const float *d_params, const uint16_t *d_params_bf16, int32_t hidden, int32_t n,
+                              const uint16_t *d_x, float *d_y, void *stream, std::string &err) {
+    if (!d_params || !d_params_bf16 || !d_x || !d_y || n < 0 || (reinterpret_cast<uintptr_t>(d_x) & 15u)) {
+        err = "mlp inference: null or misaligned buffers";
+        return BMHD_EINVAL;
+    }
+    if (n == 0) return BMHD_OK;
+    const __bf16 *x = reinterpret_cast<const __bf16 *>(d_x);
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    int32_t rc;
+    switch (hidden) {
+        case 32: rc = infer_h<32, __bf16>(d_params, d_params_bf16, n, x, d_y, s); break;
+        case 64: rc = infer_h<64, __bf16>(d_params, d_params_bf16, n, x, d_y, s); break;
+        case 128: rc = infer_h<128, __bf16>(d_params, d_params_bf16, n, x, d_y, s); break;
+        default: err = "mlp inference: hidden must be 32, 64 or 128"; return BMHD_EUNSUPPORTED;
+    }
+    if (rc) err = m_err;
+    return rc;
+}
+}  // namespace bmhd
 
 extern "C" {
 

@@ -140,10 +140,15 @@ def test_learned_stage_adds_the_network_increment(bd):
     Ua, U1a = U0.clone(), torch.zeros_like(U0)
     g.advance(Ua, U1a, dt, 1, learned=L, **kw)
     torch.cuda.synchronize()
-    X_in = g._lx.clone()
+    # the BF16 network's stage keeps its features in BF16, in the first half of the scratch buffer
+    nf = wl.n_blocks * 1728
+    X_in = g._lx.view(-1)[: nf * 16].view(torch.bfloat16).view(nf, 32).float()
     Xref, _ = g.face_data(U0, flux="hlle", stats=stats.cuda(), want_f=False)
     assert int(fb.item()) == 0
-    assert torch.allclose(X_in, Xref, rtol=1e-5, atol=1e-5), float((X_in - Xref).abs().max())
+    # equal up to the rounding to BF16 (one BF16 unit where the FP32 values differ in the last places)
+    bound = 2.0 ** -8 * Xref.abs() + 1e-5
+    assert bool(((X_in - Xref).abs() <= bound).all()), float(((X_in - Xref).abs() - bound).max())
+    assert float((X_in == Xref.to(torch.bfloat16).float()).float().mean()) > 0.99
     Ub, U1b = U0.clone(), torch.zeros_like(U0)
     g.advance(Ub, U1b, dt, 1, scheme="plane", slab=4, **kw)
     # the stage de-normalises in FP32 (a multiply-add per component)
