@@ -147,11 +147,12 @@ __global__ void __launch_bounds__(256) k_mlp_forward(const float *__restrict__ P
 // inference (BF16 products, no saved pre-activations): a persistent grid of one workgroup per CU keeps
 // every BF16 weight in LDS (rows padded by 8 elements against bank conflicts; the 8-row output layer
 // padded to 16 zero rows) and each wave streams tiles of 16 samples through the four layers, its
-// activations in a private LDS tile. For H = 128: 84.2 KB of weights + 12 x 4.4 KB of activations.
+// activations in a private LDS tile. For H = 128: 84.2 KB of weights + 16 x 4.4 KB of activations.
 
-// per workgroup: three wavefronts per SIMD, one 16-sample tile each per iteration (measured on the 128^3
-// learned stage: 1.15 ms; two tiles per wavefront with eight wavefronts, 1.18 ms)
-constexpr int MLP_INFER_WAVES = 12;
+// per workgroup: four wavefronts per SIMD (104 VGPRs allow four), one 16-sample tile each per iteration
+// (measured on the 128^3 learned stage: 0.98 ms; twelve wavefronts 1.04 ms; two tiles per wavefront
+// with eight wavefronts 1.18 ms against 1.15 ms for twelve, with FP32 inputs)
+constexpr int MLP_INFER_WAVES = 16;
 constexpr int MLP_INFER_TILES = 1;
 
 template <int H>
