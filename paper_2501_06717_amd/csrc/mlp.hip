@@ -98,6 +98,9 @@ __global__ void __launch_bounds__(256) k_mlp_forward(const float *__restrict__ P
             const int o = nt * 16 + r;  // output column this lane's B operand and results belong to
             f32x4 acc = {0.f, 0.f, 0.f, 0.f};
             if constexpr (MFMA) {
+                // accumulate onto the bias, as the inference kernel does (equal results bit for bit)
+                const float b0 = (o < nout) ? P[V.off_b[l] + o] : 0.0f;
+                acc = f32x4{b0, b0, b0, b0};
                 for (int k0 = 0; k0 < nin; k0 += 32) {
                     bf16x8 av, bv;
 #pragma unroll
@@ -125,11 +128,11 @@ __global__ void __launch_bounds__(256) k_mlp_forward(const float *__restrict__ P
         for (int nt = 0; nt < ntile; ++nt) {
             const int o = nt * 16 + r;
             if (o >= nout) continue;
-            const float bias = P[V.off_b[l] + o];
+            const float bias = MFMA ? 0.0f : P[V.off_b[l] + o];  // MFMA: already in the products
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 const int m = 4 * q + i;
-                const float z = outv[nt][i] + bias;
+                const float z = MFMA ? outv[nt][i] : outv[nt][i] + bias;
                 if (s0 + m >= n) continue;
                 if (l < 3) {
                     if (Zsave) Zsave[(size_t(l) * n + s0 + m) * H + o] = z;
@@ -149,7 +152,7 @@ __global__ void __launch_bounds__(256) k_mlp_forward(const float *__restrict__ P
 // padded to 16 zero rows) and each wave streams tiles of 16 samples through the four layers, its
 // activations in a private LDS tile. For H = 128: 84.2 KB of weights + 16 x 4.4 KB of activations.
 
-// per workgroup: four wavefronts per SIMD (104 VGPRs allow four), one 16-sample tile each per iteration
+// per workgroup: four wavefronts per SIMD (122 VGPRs allow four), one 16-sample tile each per iteration
 // (measured on the 128^3 learned stage: 0.98 ms; twelve wavefronts 1.04 ms; two tiles per wavefront
 // with eight wavefronts 1.18 ms against 1.15 ms for twelve, with FP32 inputs)
 constexpr int MLP_INFER_WAVES = 16;
@@ -234,10 +237,13 @@ __global__ void __launch_bounds__(64 * NW) k_mlp_infer(const float *__restrict__
 #pragma unroll
         for (int l = 0; l < 3; ++l) {
             const int nin = l == 0 ? MLP_IN : H, ld = l == 0 ? Z::L1 : Z::LH, wb = l == 0 ? Z::W1 : (l == 1 ? Z::W2 : Z::W3);
+            // the products accumulate onto the bias (no separate add in the epilogue)
 #pragma unroll
-            for (int p = 0; p < TP; ++p)
+            for (int nt = 0; nt < NT; ++nt) {
+                const float4 bias = *reinterpret_cast<const float4 *>(sb + l * H + 16 * nt + 4 * q);
 #pragma unroll
-                for (int nt = 0; nt < NT; ++nt) acc[p][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
+                for (int p = 0; p < TP; ++p) acc[p][nt] = f32x4{bias.x, bias.y, bias.z, bias.w};
+            }
             for (int k0 = 0; k0 < nin; k0 += 32) {
                 bf16x8 bv[TP];
 #pragma unroll
@@ -255,19 +261,22 @@ __global__ void __launch_bounds__(64 * NW) k_mlp_infer(const float *__restrict__
             for (int p = 0; p < TP; ++p)
 #pragma unroll
                 for (int nt = 0; nt < NT; ++nt) {
-                    const float4 bias = *reinterpret_cast<const float4 *>(sb + l * H + 16 * nt + 4 * q);
                     bf16x4 o;
-                    o[0] = __bf16(silu(acc[p][nt][0] + bias.x));
-                    o[1] = __bf16(silu(acc[p][nt][1] + bias.y));
-                    o[2] = __bf16(silu(acc[p][nt][2] + bias.z));
-                    o[3] = __bf16(silu(acc[p][nt][3] + bias.w));
+                    o[0] = __bf16(silu(acc[p][nt][0]));
+                    o[1] = __bf16(silu(acc[p][nt][1]));
+                    o[2] = __bf16(silu(acc[p][nt][2]));
+                    o[3] = __bf16(silu(acc[p][nt][3]));
                     *reinterpret_cast<bf16x4 *>(sa[wave][p] + r * Z::LA + 16 * nt + 4 * q) = o;
                 }
             wave_sync();
         }
         f32x4 out[TP];
+        {
+            // output rows 8..15 of the product are padding with zero bias
+            const float4 bias = *reinterpret_cast<const float4 *>(sb + 3 * H + 4 * q);
 #pragma unroll
-        for (int p = 0; p < TP; ++p) out[p] = f32x4{0.f, 0.f, 0.f, 0.f};
+            for (int p = 0; p < TP; ++p) out[p] = f32x4{bias.x, bias.y, bias.z, bias.w};
+        }
         for (int k0 = 0; k0 < H; k0 += 32) {
             const bf16x8 av = *reinterpret_cast<const bf16x8 *>(sw + Z::W4 + r * Z::LH + k0 + 8 * q);
 #pragma unroll
@@ -280,12 +289,7 @@ __global__ void __launch_bounds__(64 * NW) k_mlp_infer(const float *__restrict__
         for (int p = 0; p < TP; ++p) {
             const int s0 = (t0 + p) * 16;
             if (q < 2 && s0 + r < n) {
-                const float4 bias = *reinterpret_cast<const float4 *>(sb + 3 * H + 4 * q);
-                float4 y;
-                y.x = out[p][0] + bias.x;
-                y.y = out[p][1] + bias.y;
-                y.z = out[p][2] + bias.z;
-                y.w = out[p][3] + bias.w;
+                const float4 y = make_float4(out[p][0], out[p][1], out[p][2], out[p][3]);
                 *reinterpret_cast<float4 *>(Y + size_t(s0 + r) * MLP_OUT + 4 * q) = y;
             }
         }
