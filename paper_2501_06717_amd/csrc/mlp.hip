@@ -152,9 +152,10 @@ __global__ void __launch_bounds__(256) k_mlp_forward(const float *__restrict__ P
 // padded to 16 zero rows) and each wave streams tiles of 16 samples through the four layers, its
 // activations in a private LDS tile. For H = 128: 84.2 KB of weights + 16 x 4.4 KB of activations.
 
-// per workgroup: four wavefronts per SIMD (122 VGPRs allow four), one 16-sample tile each per iteration
-// (measured on the 128^3 learned stage: 0.98 ms; twelve wavefronts 1.04 ms; two tiles per wavefront
-// with eight wavefronts 1.18 ms against 1.15 ms for twelve, with FP32 inputs)
+// per workgroup: four wavefronts per SIMD (122 VGPRs allow four), one 16-sample tile each per iteration.
+// Measured per launch on the 128^3 learned stage, before the bias moved into the accumulators (now
+// 0.91 ms): sixteen wavefronts 0.98 ms, twelve 1.04 ms; with FP32 inputs, two tiles per wavefront with
+// eight wavefronts 1.18 ms against 1.15 ms for one tile with twelve.
 constexpr int MLP_INFER_WAVES = 16;
 constexpr int MLP_INFER_TILES = 1;
 
