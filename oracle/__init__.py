@@ -75,6 +75,10 @@ def lib():
         L.or_restrict8.restype = ctypes.c_double
         L.or_prolong1.argtypes = [ctypes.c_double, dp, dp, ip]
         L.or_prolong1.restype = ctypes.c_double
+        L.or_face_features.argtypes = [ctypes.c_void_p, dp, dp, dp]
+        L.or_advance_learned.argtypes = [ctypes.c_void_p, dp, dp, dp, ctypes.c_int, P(_Opts), dp, dp,
+                                         ctypes.c_double, ctypes.c_double, P(ctypes.c_long), P(ctypes.c_long)]
+        L.or_advance_learned.restype = ctypes.c_int
         L.mlp_n_params.argtypes = [ctypes.c_int]
         L.mlp_n_params.restype = ctypes.c_long
         L.mlp_forward.argtypes = [dp, ctypes.c_int, ctypes.c_int, dp, dp]
@@ -223,6 +227,35 @@ class Grid:
         if rc != 0:
             raise RuntimeError(f"oracle advance failed ({rc})")
         return dt, int(faults.value)
+
+    def face_features(self, U, stats=None):
+        """Stencil features of every face, [n_blocks * 1728, 32] (or_face_features); z-scored with
+        stats[0:64] = (mean[32], std[32]) when given."""
+        U = np.ascontiguousarray(U, np.float64)
+        X = np.empty((self.nb * 1728, 32))
+        st = None if stats is None else np.ascontiguousarray(np.asarray(stats, np.float64)[:64])
+        lib().or_face_features(self.h, _dp(U), _dp(st) if st is not None else None, _dp(X))
+        return X
+
+    def advance_learned(self, U0, U1, dt, n_stages, y, ystats, tau=0.1, floor_rel=0.0, flux="hlle",
+                        powell=True, cfl=0.8, recompute_dt=True, alpha=(0.0, 0.5), beta=(1.0, 0.5)):
+        """Advance in place with the learned correction given as normalised per-face corrections
+        y [n_blocks * 1728, 8] (face-normal frame) and ystats = (out_mean[8], out_std[8]); returns
+        (dt, faults, flagged cells summed over the stages)."""
+        assert U0.flags.c_contiguous and U1.flags.c_contiguous
+        dt = np.ascontiguousarray(np.broadcast_to(np.asarray(dt, np.float64), (self.ns,))).copy()
+        y = np.ascontiguousarray(y, np.float64)
+        assert y.shape == (self.nb * 1728, 8)
+        ys = np.ascontiguousarray(np.asarray(ystats, np.float64).reshape(16))
+        o = _Opts(FLUX[flux], int(bool(powell)), 2, int(bool(recompute_dt)),
+                  (ctypes.c_double * 2)(*alpha), (ctypes.c_double * 2)(*beta), float(cfl), 0)
+        faults, flagged = ctypes.c_long(0), ctypes.c_long(0)
+        rc = lib().or_advance_learned(self.h, _dp(U0), _dp(U1), _dp(dt), int(n_stages), ctypes.byref(o), _dp(y),
+                                      _dp(ys), float(tau), float(floor_rel), ctypes.byref(faults),
+                                      ctypes.byref(flagged))
+        if rc != 0:
+            raise RuntimeError("oracle learned advance failed: it needs a single-level grid")
+        return dt, int(faults.value), int(flagged.value)
 
     def run(self, W, n_steps, **kw):
         """Convenience: conserved state after n_steps full steps from primitive W."""

@@ -15,6 +15,11 @@
  *     terms, total energy as in Eq. (5), mu0 = 1 (Eqs. 1-5);
  *   - a two-stage time update with a CFL-limited global time step (Sec. 5.1 uses CFL 0.8; Sec. 5.2
  *     contrasts one- and two-stage schemes).
+ * Beside the paper's method it holds the learned flux correction of this library (not in the paper):
+ * per-face stencil features and a stage that adds given per-face corrections to the plain fluxes, flags
+ * cells whose provisional state is not positive or leaves the widened range of its old neighbourhood,
+ * and falls back to the plain flux on every face of a flagged cell (or_face_features,
+ * or_advance_learned); its network lives in mlp.c.
  * The paper leaves the limiter, reconstruction variables, flux formulas, wave-speed estimate, time-step
  * formula, restriction/prolongation formulas and boundary details unstated; the readings implemented
  * here are listed next to each function.
@@ -885,6 +890,211 @@ static long count_faults(const or_grid *g, double *st)
                     if (!(w[0] > 0.0) || !(w[7] > 0.0)) n++;
                 }
     return n;
+}
+
+/* ------------------------------------------------------------------------------------------------ */
+/* learned flux correction (the learned form; not in the paper)                                      */
+/*                                                                                                  */
+/* Face order of one block: face f of axis d lies between cells f-1 and f along d; its index is     */
+/* (t2 * 8 + t1) * 9 + f for d = 0 (t1 = y, t2 = z), (t2 * 9 + f) * 8 + t1 for d = 1 (t1 = x, t2 = z)   */
+/* and (f * 8 + t2) * 8 + t1 for d = 2 (t1 = x, t2 = y); globally (b * 3 + d) * 576 + index. Faces on a */
+/* block face appear once per block that owns them.                                                 */
+/* Face-normal frame of axis d: (rho, u_n, u_t1, u_t2, B_n, B_t1, B_t2, p) with (n, t1, t2) = (d,     */
+/* d + 1, d + 2) taken cyclically (x -> y -> z -> x); fluxes likewise with the momentum and field      */
+/* components.                                                                                      */
+
+static int face_slot(int d, int f, int t1, int t2)
+{
+    if (d == 0) return (t2 * 8 + t1) * 9 + f;
+    if (d == 1) return (t2 * 9 + f) * 8 + t1;
+    return (f * 8 + t2) * 8 + t1;
+}
+
+/* Stencil features of every face: the primitives of the 4 cells f-2 .. f+1 along d, each in the
+ * face-normal frame, z-scored with stats (mean[32], std[32]) when stats is not NULL:
+ * X[(b * 3 + d) * 576 + slot][q * 8 + v] = (w_q,v - mean[q * 8 + v]) / std[q * 8 + v]. */
+void or_face_features(const or_grid *g, const double *U, const double *stats, double *X)
+{
+    double *st = pad_alloc(g->nb);
+    pad_from_ext(g, U, st);
+    exchange_messages(g, st);
+    for (int b = 0; b < g->nb; b++)
+        for (int d = 0; d < 3; d++)
+            for (int t2 = 0; t2 < NC; t2++)
+                for (int t1 = 0; t1 < NC; t1++)
+                    for (int f = 0; f <= NC; f++) {
+                        double *x = X + ((size_t)(b * 3 + d) * 576 + (size_t)face_slot(d, f, t1, t2)) * 32;
+                        for (int q = 0; q < 4; q++) {
+                            int c[3];
+                            face_cell(d, f - 2 + q, t1, t2, c);
+                            double w[NV], r[NV];
+                            or_cons_to_prim(pcell(st, b, c[0], c[1], c[2]), w);
+                            r[0] = w[0];
+                            r[7] = w[7];
+                            for (int a = 0; a < 3; a++) {
+                                r[1 + a] = w[1 + (d + a) % 3];
+                                r[4 + a] = w[4 + (d + a) % 3];
+                            }
+                            for (int v = 0; v < NV; v++) {
+                                int e = q * 8 + v;
+                                x[e] = stats ? (r[v] - stats[e]) / stats[32 + e] : r[v];
+                            }
+                        }
+                    }
+    free(st);
+}
+
+/* The flag of the cell on the other side of face (d, side) of cell (i, j, k) of block b on a
+ * single-level grid: 0 when that side is outside the domain through a non-periodic face. */
+static int other_side_flag(const or_grid *g, const unsigned char *flags, int b, const int ii[3], int d, int side)
+{
+    int s = g->sim[b];
+    const or_sim *sm = &g->sims[s];
+    long G[3];
+    for (int a = 0; a < 3; a++) G[a] = (long)g->ijk[3 * b + a] * NC + ii[a];
+    G[d] += side ? 1 : -1;
+    long N = ncell_axis(sm, 0, d);
+    if (G[d] < 0 || G[d] >= N) {
+        if (sm->bc[2 * d + (G[d] < 0 ? 0 : 1)] != BC_PERIODIC) return 0;
+        G[d] = (G[d] + N) % N;
+    }
+    long bb[3] = {G[0] / NC, G[1] / NC, G[2] / NC};
+    int nb = lut_get(g, s, 0, bb);
+    return flags[(size_t)nb * 512 + ((G[2] % NC) * NC + G[1] % NC) * NC + G[0] % NC];
+}
+
+/* Advance n_stages stages with the learned correction. y[(b * 3 + d) * 576 + slot][8]: the normalised
+ * flux correction of every face in the face-normal frame, the same for every stage; ystats: out_mean[8],
+ * out_std[8]. Per stage:
+ *   1. ghost exchange and the plain fluxes F (as or_advance);
+ *   2. dF = y * out_std + out_mean, rotated from the face-normal frame to x, y, z; F' = F + dF, except on
+ *      faces next to a body cell (those keep F);
+ *   3. a provisional update with F';
+ *   4. a fluid cell is flagged when its provisional rho <= 0 or p <= 0, or its provisional rho (p) leaves
+ *      [lo - tau h, hi + tau h], where lo and hi are the minimum and maximum of rho (p) over the cell and
+ *      its six face neighbours in the stage input and h = max(hi - lo, floor_rel * max(|lo|, |hi|))
+ *      (floor_rel = 0: h is the range);
+ *   5. every face with a flagged cell on either side takes F again, for both cells, and the stage is
+ *      recomputed once from these fluxes (no second test).
+ * Single-level grids only (returns -1 otherwise). *flagged accumulates the flagged cells of all stages;
+ * *faults counts non-positive cells after the last stage. */
+int or_advance_learned(const or_grid *g, double *U0, double *U1, double *dt, int n_stages, const or_opts *o,
+                       const double *y, const double *ystats, double tau, double floor_rel, long *faults,
+                       long *flagged)
+{
+    if (o->n_table != 2 || o->local_dt) return -1;
+    for (int b = 0; b < g->nb; b++)
+        if (g->level[b] != 0 || has_level_change(g, b)) return -1;
+    double *s0 = pad_alloc(g->nb), *s1 = pad_alloc(g->nb);
+    pad_from_ext(g, U0, s0);
+    pad_from_ext(g, U1, s1);
+    or_faces *plain = malloc(sizeof(or_faces) * (size_t)g->nb);
+    or_faces *used = malloc(sizeof(or_faces) * (size_t)g->nb);
+    unsigned char *flags = calloc((size_t)g->nb * 512, 1);
+    long nflag = 0;
+    for (int st = 0; st < n_stages; st++) {
+        int e = st % 2;
+        double alpha = o->alpha[e], beta = o->beta[e];
+        double *in = e ? s1 : s0, *out = e ? s0 : s1;
+        if (e == 0 && o->recompute_dt) compute_dt(g, s0, o->cfl, dt);
+        exchange_messages(g, in);
+        /* the second stage writes over U^n, which the recompute of step 5 reads again: keep a copy */
+        double *u0 = s0;
+        if (e == 1) {
+            u0 = pad_alloc(g->nb);
+            memcpy(u0, s0, sizeof(double) * (size_t)g->nb * NPAD * NV);
+        }
+        /* steps 1-3 */
+        for (int b = 0; b < g->nb; b++) {
+            calc_face_values_and_fluxes(g, b, in, o, &plain[b]);
+            memcpy(&used[b], &plain[b], sizeof(or_faces));
+            for (int d = 0; d < 3; d++)
+                for (int t2 = 0; t2 < NC; t2++)
+                    for (int t1 = 0; t1 < NC; t1++)
+                        for (int f = 0; f <= NC; f++) {
+                            int cl[3], cr[3];
+                            face_cell(d, f - 1, t1, t2, cl);
+                            face_cell(d, f, t1, t2, cr);
+                            if (is_body(g, b, cl[0], cl[1], cl[2]) || is_body(g, b, cr[0], cr[1], cr[2])) continue;
+                            const double *yf = y + ((size_t)(b * 3 + d) * 576 + (size_t)face_slot(d, f, t1, t2)) * 8;
+                            double dn[NV], dF[NV];
+                            for (int v = 0; v < NV; v++) dn[v] = yf[v] * ystats[8 + v] + ystats[v];
+                            dF[0] = dn[0];
+                            dF[7] = dn[7];
+                            for (int a = 0; a < 3; a++) {
+                                dF[1 + (d + a) % 3] = dn[1 + a];
+                                dF[4 + (d + a) % 3] = dn[4 + a];
+                            }
+                            double *fv = used[b].f[d][f][t2][t1];
+                            for (int v = 0; v < NV; v++) fv[v] = fv[v] + dF[v];
+                        }
+            calc_source_and_update(g, b, in, u0, out, dt[g->sim[b]], NULL, alpha, beta, o, &used[b]);
+        }
+        /* step 4 */
+        for (int b = 0; b < g->nb; b++)
+            for (int k = 0; k < NC; k++)
+                for (int j = 0; j < NC; j++)
+                    for (int i = 0; i < NC; i++) {
+                        unsigned char *fl = &flags[(size_t)b * 512 + (k * NC + j) * NC + i];
+                        *fl = 0;
+                        if (is_body(g, b, i, j, k)) continue;
+                        double w[NV];
+                        or_cons_to_prim(pcell(out, b, i, j, k), w);
+                        const int nb7[7][3] = {{i, j, k}, {i - 1, j, k}, {i + 1, j, k}, {i, j - 1, k},
+                                               {i, j + 1, k}, {i, j, k - 1}, {i, j, k + 1}};
+                        double lo[2] = {INFINITY, INFINITY}, hi[2] = {-INFINITY, -INFINITY};
+                        for (int q = 0; q < 7; q++) {
+                            double wo[NV];
+                            or_cons_to_prim(pcell(in, b, nb7[q][0], nb7[q][1], nb7[q][2]), wo);
+                            const double val[2] = {wo[0], wo[7]};
+                            for (int m = 0; m < 2; m++) {
+                                if (val[m] < lo[m]) lo[m] = val[m];
+                                if (val[m] > hi[m]) hi[m] = val[m];
+                            }
+                        }
+                        const double now[2] = {w[0], w[7]};
+                        int bad = !(w[0] > 0.0) || !(w[7] > 0.0);
+                        for (int m = 0; m < 2; m++) {
+                            double h = hi[m] - lo[m];
+                            double fh = floor_rel * fmax(fabs(lo[m]), fabs(hi[m]));
+                            if (fh > h) h = fh;
+                            if (now[m] < lo[m] - tau * h || now[m] > hi[m] + tau * h) bad = 1;
+                        }
+                        *fl = (unsigned char)bad;
+                        nflag += bad;
+                    }
+        /* step 5 */
+        for (int b = 0; b < g->nb; b++) {
+            int any = 0;
+            for (int d = 0; d < 3; d++)
+                for (int t2 = 0; t2 < NC; t2++)
+                    for (int t1 = 0; t1 < NC; t1++)
+                        for (int f = 0; f <= NC; f++) {
+                            int cl[3], cr[3];
+                            face_cell(d, f - 1, t1, t2, cl);
+                            face_cell(d, f, t1, t2, cr);
+                            int fl_l = f > 0 ? flags[(size_t)b * 512 + (cl[2] * NC + cl[1]) * NC + cl[0]]
+                                             : other_side_flag(g, flags, b, cr, d, 0);
+                            int fl_r = f < NC ? flags[(size_t)b * 512 + (cr[2] * NC + cr[1]) * NC + cr[0]]
+                                              : other_side_flag(g, flags, b, cl, d, 1);
+                            if (!(fl_l || fl_r)) continue;
+                            memcpy(used[b].f[d][f][t2][t1], plain[b].f[d][f][t2][t1], sizeof(double) * NV);
+                            any = 1;
+                        }
+            if (any) calc_source_and_update(g, b, in, u0, out, dt[g->sim[b]], NULL, alpha, beta, o, &used[b]);
+        }
+        if (u0 != s0) free(u0);
+    }
+    if (faults) *faults = count_faults(g, (n_stages % 2) ? s1 : s0);
+    if (flagged) *flagged = nflag;
+    pad_to_ext(g, s0, U0);
+    pad_to_ext(g, s1, U1);
+    free(flags);
+    free(used);
+    free(plain);
+    free(s0);
+    free(s1);
+    return 0;
 }
 
 /* Advance n_stages stages. Stage s uses table entry s % n_table; even stages read U0 and write U1,

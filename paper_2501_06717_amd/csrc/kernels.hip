@@ -1426,7 +1426,8 @@ __global__ void __launch_bounds__(512) k_learn_fixup(Tables T, StageArgs A, int3
     }
 }
 
-// coarse cells at coarse-fine faces: swap the coarse flux for the mean of the four fine fluxes
+// coarse cells at coarse-fine faces: swap the coarse flux for the mean of the four fine fluxes. A body
+// cell on such a face is never updated and never enters dt or the fault count.
 __global__ void __launch_bounds__(256) k_flux_correct(Tables T, StageArgs A) {
     __shared__ double red[4];
     __shared__ int redi[4];
@@ -1434,11 +1435,18 @@ __global__ void __launch_bounds__(256) k_flux_correct(Tables T, StageArgs A) {
     double lam = 0.0;
     int nf = 0;
     int sim = 0;
+    bool body = false;
     if (e < T.n_fc_cells) {
         const DevFcCell C = T.fc_cells[e];
         const DevBlock &B = T.blocks[C.block];
         const DevSim &S = T.sims[B.sim];
         sim = B.sim;
+        body = (B.flags & BF_NEAR_BODY) && in_body(S, B.level, B.ijk, C.cell & 7, (C.cell >> 3) & 7, C.cell >> 6);
+    }
+    if (e < T.n_fc_cells && !body) {
+        const DevFcCell C = T.fc_cells[e];
+        const DevBlock &B = T.blocks[C.block];
+        const DevSim &S = T.sims[B.sim];
         const size_t vs = size_t(T.nb) * 512, off = size_t(C.block) * 512 + C.cell;
         const double inv_dx = 1.0 / S.dx0;
         const double bdt = A.beta * (A.local_dt ? A.dt[off] : A.dt[B.sim]);
@@ -1468,7 +1476,7 @@ __global__ void __launch_bounds__(256) k_flux_correct(Tables T, StageArgs A) {
     }
     if (A.want_lam) {
         // a grid may mix simulations inside one workgroup here: publish per thread (few cells)
-        if (e < T.n_fc_cells) publish_max(T.lam + sim, lam);
+        if (e < T.n_fc_cells && !body) publish_max(T.lam + sim, lam);
     }
     if (A.count_faults) block_publish<256>(0.0, nf, red, redi, nullptr, A.faults);
 }

@@ -318,11 +318,23 @@ def odd_box(nroot=(3, 2, 5), bc=(1, 1, 0, 0, 2, 1), seed=3):
 
 def two_level_box(nroot=(4, 3, 2), refine=((1, 1, 0), (2, 1, 0), (1, 0, 1)), bc=(0,) * 6, seed=5,
                   body=False):
-    """A small two-level grid with a few refined roots and a random positive state."""
-    sim = Sim(tuple(nroot), (0.0, 0.0, 0.0), 1.0, tuple(bc), (1.1, -0.2, 0.1, 0.05, 0.3, 0.6, -0.2, 0.9))
+    """A small two-level grid with a few refined roots and a random positive state. With ``body`` a small
+    body sits on the coarse side of a level face: centred on the level-0 cell two cells below the x-lo face
+    of the first refined root whose x-lo neighbour is a level-0 block, radius 1.2 cells, so the coarse cell
+    next to that face is a body cell while every fine cell stays fluid."""
     mask = np.zeros(nroot[::-1], bool)
     for (i, j, k) in refine:
         mask[k, j, i] = True
+    body_c, body_r = (0.0, 0.0, 0.0), 0.0
+    if body:
+        for (i, j, k) in refine:
+            if i > 0 and not mask[k, j, i - 1]:
+                body_c, body_r = (8.0 * i - 1.5, 8.0 * j + 3.5, 8.0 * k + 3.5), 1.2
+                break
+        else:
+            raise ValueError("two_level_box(body=True) needs a refined root with a level-0 x-lo neighbour")
+    sim = Sim(tuple(nroot), (0.0, 0.0, 0.0), 1.0, tuple(bc), (1.1, -0.2, 0.1, 0.05, 0.3, 0.6, -0.2, 0.9),
+              body_c, body_r)
     lv, ijk, sid = two_level_blocks(nroot, mask)
     wl = Workload("two_level_box", lv, ijk, sid, [sim], _empty_W(len(lv)), flux="hlle", powell=True)
     return with_state(wl, random_positive_state(wl, seed))
@@ -422,3 +434,47 @@ def batched_waves(n_sims=64, seed=4, n_waves=8, amp_max=0.05, n_lo=64, n_hi=4096
         W[:, sel] = Ws
     return Workload(f"batched_{n_sims}", level, ijk, sim, sims, W, flux="rusanov", powell=False, cfl=0.8,
                     n_steps=n_steps)
+
+
+# --------------------------------------------------------------------------------------------------
+# per-face inputs of the learned flux correction
+
+def face_slots():
+    """(d, f, t1, t2) of the 576 faces of each axis of a block, in the face order of the learned form:
+    face f of axis d lies between cells f-1 and f along d, slot (t2*8 + t1)*9 + f for d = 0 (t1 = y,
+    t2 = z), (t2*9 + f)*8 + t1 for d = 1 (t1 = x, t2 = z), (f*8 + t2)*8 + t1 for d = 2 (t1 = x, t2 = y).
+    Returns int arrays f, t1, t2 of shape [3, 576] indexed by (d, slot)."""
+    f = np.empty((3, 576), np.int64)
+    t1 = np.empty((3, 576), np.int64)
+    t2 = np.empty((3, 576), np.int64)
+    for d in range(3):
+        a, b_, c = np.meshgrid(np.arange(9), np.arange(8), np.arange(8), indexing="ij")  # f, t1, t2
+        a, b_, c = a.ravel(), b_.ravel(), c.ravel()
+        slot = (c * 8 + b_) * 9 + a if d == 0 else ((c * 9 + a) * 8 + b_ if d == 1 else (a * 8 + c) * 8 + b_)
+        f[d, slot], t1[d, slot], t2[d, slot] = a, b_, c
+    return f, t1, t2
+
+
+def face_corrections(wl: Workload, seed=0, scale=1.0):
+    """Seeded normalised flux corrections y [n_blocks * 1728, 8] for a single-level grid, drawn per global
+    face (standard normal times ``scale``), so that the two blocks that own a face hold the same value
+    (across periodic boundaries too). Pure indexing: no arithmetic of the method."""
+    assert np.all(wl.level == 0) and wl.sims and len(wl.sims) == 1
+    sim = wl.sims[0]
+    n = [int(v) * NX for v in sim.nroot]
+    rng = np.random.default_rng(seed)
+    tables = [rng.standard_normal((n[2] + (d == 2), n[1] + (d == 1), n[0] + (d == 0), 8)) * scale
+              for d in range(3)]
+    f, t1, t2 = face_slots()
+    y = np.empty((wl.n_blocks, 3, 576, 8))
+    for d in range(3):
+        a1, a2 = (1, 2) if d == 0 else ((0, 2) if d == 1 else (0, 1))
+        periodic = sim.bc[2 * d] == BC_PERIODIC and sim.bc[2 * d + 1] == BC_PERIODIC
+        g = np.empty((wl.n_blocks, 3, 576), np.int64)
+        g[:, d] = wl.ijk[:, d, None] * NX + f[d][None]
+        g[:, a1] = wl.ijk[:, a1, None] * NX + t1[d][None]
+        g[:, a2] = wl.ijk[:, a2, None] * NX + t2[d][None]
+        if periodic:
+            g[:, d] %= n[d]
+        y[:, d] = tables[d][g[:, 2], g[:, 1], g[:, 0]]
+    return np.ascontiguousarray(y.reshape(wl.n_blocks * 1728, 8))

@@ -136,6 +136,8 @@ STAGE_CASES = {
     "two_level_box": (lambda: wk.two_level_box(), dict(flux="rusanov", powell=False)),
     "two_level_box_hlle": (lambda: wk.two_level_box(bc=(1, 2, 0, 0, 2, 1)), dict(flux="hlle", powell=True)),
     "two_level_48": (lambda: wk.two_level_magnetosphere(48), dict(flux="hlle", powell=True)),
+    # a body cell on the coarse side of a level face: flux correction must leave it alone
+    "two_level_box_body": (lambda: wk.two_level_box(body=True), dict(flux="hlle", powell=True)),
 }
 
 

@@ -393,6 +393,104 @@ def test_powell_breaks_conservation_only_through_divB(oracle_mod):
     assert np.any(np.abs(t1[1:] - t0[1:]) > 1e-12 * np.abs(t0[1:]).max())
 
 
+def _powell_advection_errors(oracle_mod, n, t_end=0.25, u0=1.0, b0=1.0, amp=0.1):
+    """Errors after t_end of a divergent field carried by a uniform flow on [0,1] (n cells along x)."""
+    import dataclasses
+    wl = wk.uniform_state((n // 8, 1, 1))
+    sim = dataclasses.replace(wl.sims[0], dx0=1.0 / n, origin=(0.0, 0.0, 0.0))
+    wl = dataclasses.replace(wl, sims=[sim])
+    x, _, _ = wk.cell_centres(sim, wl.level, wl.ijk)
+    k = 2.0 * math.pi
+    W = np.zeros((8,) + x.shape)
+    W[0], W[1], W[7] = 1.0, u0, 1.0
+    W[4] = b0 + amp * np.sin(k * x)
+    g = oracle_mod.Grid.from_workload(wl)
+    U0 = g.set_state(W)
+    n_steps = int(math.ceil(t_end / g.dt(U0, 0.8)[0]))
+    U1 = np.zeros_like(U0)
+    g.advance(U0, U1, [t_end / n_steps], 2 * n_steps, flux="hlle", powell=True, recompute_dt=False)
+    rho = U0[0]
+    ux = U0[1] / rho
+    p = (GAMMA - 1.0) * (U0[7] - 0.5 * (U0[1] ** 2 + U0[2] ** 2 + U0[3] ** 2) / rho
+                         - 0.5 * (U0[4] ** 2 + U0[5] ** 2 + U0[6] ** 2))
+    bx_exact = b0 + amp * np.sin(k * (x - u0 * t_end))
+    transverse = max(np.abs(U0[v]).max() for v in (2, 3, 5, 6))
+    return {"Bx": float(np.abs(U0[4] - bx_exact).mean()), "ux": float(np.abs(ux - u0).mean()),
+            "p": float(np.abs(p - 1.0).mean()), "rho": float(np.abs(rho - 1.0).mean())}, transverse
+
+
+def test_powell_source_carries_a_divergent_field_rigidly(oracle_mod):
+    """Eqs. (2)-(4) with their right-hand sides, for uniform rho, p and u = (u0, 0, 0) and a field
+    B = (B0 + a sin kx, 0, 0) whose divergence a k cos kx is not zero. The magnetic-tension part of the
+    momentum flux, d/dx(-Bx^2/2) = -Bx div B, is cancelled exactly by the source -B div B; the induction
+    flux vanishes and the source -u div B moves Bx with the flow; the energy source -(u.B) div B is
+    exactly the change of Bx^2/2 at fixed p. So the exact solution carries the Bx profile rigidly at u0
+    with rho, u and p constant. The discrete solution must approach it at second order: a wrong sign in
+    any of the three source parts leaves an O(a k t) error that does not shrink with the cell size."""
+    e32, tr32 = _powell_advection_errors(oracle_mod, 32)
+    e64, tr64 = _powell_advection_errors(oracle_mod, 64)
+    assert tr32 == 0.0 and tr64 == 0.0
+    for q in e64:
+        assert e64[q] <= 5e-4, (q, e32, e64)
+        assert math.log2(e32[q] / e64[q]) >= 1.5, (q, e32, e64)
+
+
+def test_reflecting_body_conserves_fluid_mass(oracle_mod):
+    """Around a body in a periodic box (Powell off, a random flow), the only place mass could leave the
+    fluid is a body face. There the body side is the mirror of the fluid state with the normal velocity
+    negated, so the mass flux through the wall is exactly zero (both fluxes), and the total mass is
+    constant to round-off while momentum changes (the wall pushes back). Without the negation the wall
+    would pass mass through."""
+    wl = wk.uniform_state((2, 2, 2), body_r=3.0)
+    W = wk.random_positive_state(wl, seed=17, amp=0.4)
+    g = oracle_mod.Grid.from_workload(wl)
+    U0 = g.set_state(W)
+    t0 = total(wl, U0)
+    for flux in ("rusanov", "hlle"):
+        U, _, faults = _run(oracle_mod, wl, W, 3, flux=flux, powell=False)
+        assert faults == 0
+        t1 = total(wl, U)
+        assert abs(t1[0] - t0[0]) <= 1e-14 * abs(t0[0]), (flux, t1[0] - t0[0])
+        assert np.any(np.abs(t1[1:4] - t0[1:4]) > 1e-9 * np.abs(t0[0])), flux
+
+
+@pytest.mark.parametrize("case", ["uniform", "two_level", "fast_cell", "fast_cell_in_body"])
+def test_dt_closed_form_from_the_paper_speeds(oracle_mod, case):
+    """dt = CFL / sum_d ((|u_d| + c_f,d) / dx) for the paper's fast-wave background V0 (Sec. 5.1, Eq. 6),
+    from the speeds printed with it: along x and z (perpendicular to B0) c_f = c_F = 0.05, along y
+    (parallel to B0) c_f = max(c_s, c_A) = c_A = 0.04, and |u_z| = 0.005, so dt = 0.8 dx / 0.145. A
+    maximum in place of the sum over axes, a missing |u_d|, or the wrong axis' speed changes it. On two
+    levels the finer cells set dt (dx / 2). One cell with u and B doubled and p quadrupled has every
+    speed doubled, so dt halves; inside the body the same cell is ignored."""
+    import dataclasses
+    gd = json.load(open(os.path.join(GOLDEN, "fast_wave_speeds.json")))
+    V0 = np.array(gd["V0"])
+    if case == "uniform":
+        V0[3] = -V0[3]  # the sign of u_z must not matter
+    levels = np.zeros((2, 2, 2), bool) if case != "two_level" else np.array(
+        [[[1, 0], [0, 0]], [[0, 0], [0, 0]]], bool)
+    wl = wk.uniform_state((2, 2, 2), W0=tuple(V0), body_r=2.0 if case == "fast_cell_in_body" else 0.0,
+                          levels=levels if case == "two_level" else None)
+    dx0 = 0.8
+    sim = dataclasses.replace(wl.sims[0], dx0=dx0, origin=(-6.4, -6.4, -6.4), body_c=(0.0, 0.0, 0.0))
+    wl = dataclasses.replace(wl, sims=[sim])
+    W = wl.W.copy()
+    factor = 1.0
+    if case.startswith("fast_cell"):
+        # block 7 holds the domain's upper octant; its cell (0, 0, 0) has its centre at (0.4, 0.4, 0.4),
+        # inside the body of radius 2 centred at the origin
+        for v in (1, 2, 3, 4, 5, 6):
+            W[v, 7, 0, 0, 0] *= 2.0
+        W[7, 7, 0, 0, 0] *= 4.0
+        factor = 1.0 if case == "fast_cell_in_body" else 0.5
+    g = oracle_mod.Grid.from_workload(wl)
+    U = g.set_state(W)
+    dx = dx0 / 2 if case == "two_level" else dx0
+    expect = factor * 0.8 * dx / ((gd["c_F"]) + (gd["c_A"]) + (abs(gd["V0"][3]) + gd["c_F"]))
+    got = g.dt(U, 0.8)[0]
+    assert math.isclose(got, expect, rel_tol=1e-14), (got, expect)
+
+
 def _permute(wl, U):
     """Cyclic axis permutation x->y->z->x of a global single-level field and of vector components."""
     G = to_global(wl, U)
