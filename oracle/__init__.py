@@ -79,6 +79,10 @@ def lib():
         L.or_advance_learned.argtypes = [ctypes.c_void_p, dp, dp, dp, ctypes.c_int, P(_Opts), dp, dp,
                                          ctypes.c_double, ctypes.c_double, P(ctypes.c_long), P(ctypes.c_long)]
         L.or_advance_learned.restype = ctypes.c_int
+        L.or_xchg_messages.argtypes = [ctypes.c_void_p, ip, ctypes.c_int, P(ctypes.c_int64), ctypes.c_long]
+        L.or_xchg_messages.restype = ctypes.c_long
+        L.or_xchg_run.argtypes = [ctypes.c_void_p, ip, ctypes.c_int, dp, dp]
+        L.or_xchg_run.restype = ctypes.c_int
         L.mlp_n_params.argtypes = [ctypes.c_int]
         L.mlp_n_params.restype = ctypes.c_long
         L.mlp_forward.argtypes = [dp, ctypes.c_int, ctypes.c_int, dp, dp]
@@ -256,6 +260,26 @@ class Grid:
         if rc != 0:
             raise RuntimeError("oracle learned advance failed: it needs a single-level grid")
         return dt, int(faults.value), int(flagged.value)
+
+    def xchg_messages(self, rank, n_ranks):
+        """Every message of the exchange between processes for the block-to-process map `rank`, one row of
+        16 int64 per message (see or_xchg_messages)."""
+        rank = np.ascontiguousarray(rank, np.int32)
+        cap = self.nb * 26 * 4 + 1
+        out = np.empty((cap, 16), np.int64)
+        n = lib().or_xchg_messages(self.h, _ip(rank), int(n_ranks), out.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                   cap)
+        if n < 0:
+            raise RuntimeError("xchg_messages: too many messages")
+        return out[:n].copy()
+
+    def xchg_run(self, U, rank, n_ranks):
+        """The padded views [8, nB, 12, 12, 12] after the exchange between simulated processes."""
+        U = np.ascontiguousarray(U, np.float64)
+        rank = np.ascontiguousarray(rank, np.int32)
+        view = np.empty((8, self.nb, 12, 12, 12))
+        lib().or_xchg_run(self.h, _ip(rank), int(n_ranks), _dp(U), _dp(view))
+        return view
 
     def run(self, W, n_steps, **kw):
         """Convenience: conserved state after n_steps full steps from primitive W."""

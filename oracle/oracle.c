@@ -876,6 +876,375 @@ int or_remap(const or_grid *from, const double *U_from, const or_grid *to, doubl
     return 0;
 }
 
+/* ------------------------------------------------------------------------------------------------ */
+/* message passing between processes (Sec. 4.2-4.4, Algorithms 3 and 4), with the processes simulated */
+/* in one address space                                                                             */
+/*                                                                                                  */
+/* Blocks are assigned to processes (rank[b]); a process holds its blocks in its own padded array,   */
+/* in ascending order of global block id (the local index). Ghost cells come from messages: a copy   */
+/* from an equal-level neighbour, a restriction computed by a finer sender, or a prolongation         */
+/* computed by a coarser sender. Messages between blocks of one process are copied directly ("local  */
+/* message passing"); others go through one buffer per (sender, receiver) pair. Copies and            */
+/* restrictions travel first (pass 1); prolongations (pass 2) are computed from the sender's ghost    */
+/* cells as they stand after pass 1. Ghost cells outside the domain are filled by the receiver from  */
+/* its own array (outflow, inflow) after the passes that feed them.                                  */
+/*                                                                                                  */
+/* A message from sender block b: its direction slot is dir * 4 + sub, dir the direction index of    */
+/* the neighbour table (dx fastest) and sub the finer neighbour's position (0 otherwise); its          */
+/* receive box is the part of the receiver's padded box [-2, 10)^3 covered by b's cells at the        */
+/* receiver's level. The counting loop runs over the process's blocks in local order and the slots in */
+/* ascending order; message i_M to a peer starts at start(i_M) = start(i_M - 1) + n_C + n_V *         */
+/* cells(i_M - 1), n_C = 1 + 2 n_D = 7 header values (receiving block's local index on the peer, the   */
+/* box's low corner, its high corner, inclusive) followed by the values in the order (v, i, j, k),    */
+/* v fastest. A slot that would repeat a receiver placement already sent from b is skipped.           */
+
+enum { MSG_COPY = 0, MSG_RESTRICT = 1, MSG_PROLONG = 2 };
+#define XCHG_NC 7
+
+typedef struct {
+    int sender, receiver; /* global block ids */
+    int type, pass, slot;
+    int lo[3], hi[3];     /* receive box in the receiver's padded coordinates, inclusive */
+    long ru[3];           /* the receiver's block position at its level, unwrapped as seen from the sender */
+} or_msg;
+
+static long floordiv(long a, long b) { return a >= 0 ? a / b : -((-a + b - 1) / b); }
+
+/* All messages sent by block b, in slot order; returns their count (at most 26 * 4). */
+static int block_messages(const or_grid *g, int b, or_msg *out)
+{
+    int s = g->sim[b], l = g->level[b];
+    const or_sim *sm = &g->sims[s];
+    int n = 0, dn = 0;
+    for (int dz = -1; dz <= 1; dz++)
+        for (int dy = -1; dy <= 1; dy++)
+            for (int dx = -1; dx <= 1; dx++) {
+                if (dx == 0 && dy == 0 && dz == 0) continue;
+                int dir = dn++;
+                int dd[3] = {dx, dy, dz};
+                long p[3], pw[3];
+                int inside = 1;
+                for (int a = 0; a < 3; a++) {
+                    long N = nblk_axis(sm, l, a);
+                    p[a] = (long)g->ijk[3 * b + a] + dd[a];
+                    pw[a] = p[a];
+                    if (p[a] < 0 || p[a] >= N) {
+                        if (sm->bc[2 * a + (p[a] < 0 ? 0 : 1)] != BC_PERIODIC) inside = 0;
+                        pw[a] = (p[a] + N) % N;
+                    }
+                }
+                if (!inside) continue;
+                or_msg cand[4];
+                int nc = 0;
+                int id = lut_get(g, s, l, pw);
+                if (id >= 0) { /* equal level */
+                    cand[0].receiver = id;
+                    cand[0].type = MSG_COPY;
+                    for (int a = 0; a < 3; a++) cand[0].ru[a] = p[a];
+                    nc = 1;
+                } else if (l == 1) { /* the region is coarser: restriction to the level-0 block there */
+                    long cu[3], cw[3];
+                    for (int a = 0; a < 3; a++) {
+                        cu[a] = floordiv(p[a], 2);
+                        long N = nblk_axis(sm, 0, a);
+                        cw[a] = ((cu[a] % N) + N) % N;
+                    }
+                    cand[0].receiver = lut_get(g, s, 0, cw);
+                    cand[0].type = MSG_RESTRICT;
+                    for (int a = 0; a < 3; a++) cand[0].ru[a] = cu[a];
+                    nc = 1;
+                } else { /* the region is finer: prolongation to each finer block touching b */
+                    int m = 0;
+                    for (int sz = 0; sz < 2; sz++)
+                        for (int sy = 0; sy < 2; sy++)
+                            for (int sx = 0; sx < 2; sx++) {
+                                int sub[3] = {sx, sy, sz}, ok = 1;
+                                for (int a = 0; a < 3; a++) {
+                                    if (dd[a] == 1 && sub[a] != 0) ok = 0;
+                                    if (dd[a] == -1 && sub[a] != 1) ok = 0;
+                                }
+                                if (!ok) continue;
+                                long fw[3];
+                                for (int a = 0; a < 3; a++) fw[a] = 2 * pw[a] + sub[a];
+                                cand[nc].receiver = lut_get(g, s, 1, fw);
+                                cand[nc].type = MSG_PROLONG;
+                                for (int a = 0; a < 3; a++) cand[nc].ru[a] = 2 * p[a] + sub[a];
+                                cand[nc].slot = m++;
+                                nc++;
+                            }
+                }
+                for (int c = 0; c < nc; c++) {
+                    or_msg *mm = &cand[c];
+                    int sub = mm->type == MSG_PROLONG ? mm->slot : 0;
+                    int rl = g->level[mm->receiver];
+                    /* b's cells at the receiver's level, relative to the receiver's origin */
+                    long scale_num = rl > l ? 2 : 1, scale_den = rl < l ? 2 : 1;
+                    int empty = 0;
+                    for (int a = 0; a < 3; a++) {
+                        long lo = (long)g->ijk[3 * b + a] * 8 * scale_num / scale_den - 8 * mm->ru[a];
+                        long hi = lo + 8 * scale_num / scale_den;
+                        if (lo < -2) lo = -2;
+                        if (hi > 10) hi = 10;
+                        if (lo >= hi) empty = 1;
+                        mm->lo[a] = (int)lo;
+                        mm->hi[a] = (int)hi - 1;
+                    }
+                    if (empty) continue;
+                    int dup = 0;
+                    for (int q = 0; q < n; q++)
+                        if (out[q].receiver == mm->receiver && out[q].ru[0] == mm->ru[0] && out[q].ru[1] == mm->ru[1] &&
+                            out[q].ru[2] == mm->ru[2])
+                            dup = 1;
+                    if (dup) continue;
+                    mm->sender = b;
+                    mm->pass = mm->type == MSG_PROLONG ? 2 : 1;
+                    mm->slot = dir * 4 + sub;
+                    out[n++] = *mm;
+                }
+            }
+    return n;
+}
+
+static long box_cells(const or_msg *m)
+{
+    return (long)(m->hi[0] - m->lo[0] + 1) * (m->hi[1] - m->lo[1] + 1) * (m->hi[2] - m->lo[2] + 1);
+}
+
+/* The value of receive cell (i, j, k) of message m, from the sender's padded array sb (block m->sender's
+ * cells at their process-local slot). */
+static void message_value(const or_grid *g, const or_msg *m, const double *sst, int sb, int i, int j, int k,
+                          double *u)
+{
+    int b = m->sender, sl = g->level[b];
+    long gr[3] = {8 * m->ru[0] + i, 8 * m->ru[1] + j, 8 * m->ru[2] + k}; /* receiver level, unwrapped */
+    if (m->type == MSG_COPY) {
+        memcpy(u, pcell((double *)sst, sb, (int)(gr[0] - 8L * g->ijk[3 * b]), (int)(gr[1] - 8L * g->ijk[3 * b + 1]),
+                        (int)(gr[2] - 8L * g->ijk[3 * b + 2])),
+               sizeof(double) * NV);
+    } else if (m->type == MSG_RESTRICT) {
+        double c[8][NV];
+        for (int q = 0; q < 8; q++) {
+            long f[3] = {2 * gr[0] + (q & 1), 2 * gr[1] + ((q >> 1) & 1), 2 * gr[2] + ((q >> 2) & 1)};
+            memcpy(c[q], pcell((double *)sst, sb, (int)(f[0] - 8L * g->ijk[3 * b]), (int)(f[1] - 8L * g->ijk[3 * b + 1]),
+                               (int)(f[2] - 8L * g->ijk[3 * b + 2])),
+                   sizeof(double) * NV);
+        }
+        for (int v = 0; v < NV; v++) {
+            double cv[8];
+            for (int q = 0; q < 8; q++) cv[q] = c[q][v];
+            u[v] = or_restrict8(cv);
+        }
+    } else {
+        long C[3];
+        int sg[3];
+        for (int a = 0; a < 3; a++) {
+            C[a] = floordiv(gr[a], 2) - 8L * g->ijk[3 * b + a];
+            sg[a] = (gr[a] & 1) ? 1 : -1;
+        }
+        (void)sl;
+        const double *uc = pcell((double *)sst, sb, (int)C[0], (int)C[1], (int)C[2]);
+        const double *um[3], *up[3];
+        for (int d = 0; d < 3; d++) {
+            long cm[3] = {C[0], C[1], C[2]}, cp[3] = {C[0], C[1], C[2]};
+            cm[d] -= 1;
+            cp[d] += 1;
+            um[d] = pcell((double *)sst, sb, (int)cm[0], (int)cm[1], (int)cm[2]);
+            up[d] = pcell((double *)sst, sb, (int)cp[0], (int)cp[1], (int)cp[2]);
+        }
+        for (int v = 0; v < NV; v++) {
+            double cm[3] = {um[0][v], um[1][v], um[2][v]}, cp[3] = {up[0][v], up[1][v], up[2][v]};
+            u[v] = or_prolong1(uc[v], cm, cp, sg);
+        }
+    }
+}
+
+/* Ghost cells of block b outside the domain, from its own padded array: inflow when an out-of-domain
+ * axis is an inflow face, otherwise the cell at the out-of-domain outflow axes clamped to the block's
+ * boundary row (periodic axes keep their ghost index: those ghost cells came by message). */
+static void fill_boundary_ghosts(const or_grid *g, int b, double *st, int lb)
+{
+    int s = g->sim[b], l = g->level[b];
+    const or_sim *sm = &g->sims[s];
+    for (int k = -NGH; k < NC + NGH; k++)
+        for (int j = -NGH; j < NC + NGH; j++)
+            for (int i = -NGH; i < NC + NGH; i++) {
+                int ii[3] = {i, j, k}, src[3] = {i, j, k};
+                int out = 0, inflow = 0;
+                for (int a = 0; a < 3; a++) {
+                    long G = (long)g->ijk[3 * b + a] * NC + ii[a];
+                    long N = ncell_axis(sm, l, a);
+                    if (G >= 0 && G < N) continue;
+                    int t = sm->bc[2 * a + (G < 0 ? 0 : 1)];
+                    if (t == BC_PERIODIC) continue;
+                    out = 1;
+                    if (t == BC_INFLOW) inflow = 1;
+                    src[a] = G < 0 ? 0 : NC - 1;
+                }
+                if (!out) continue;
+                double *c = pcell(st, lb, i, j, k);
+                if (inflow) inflow_cons(g, s, c);
+                else memcpy(c, pcell(st, lb, src[0], src[1], src[2]), sizeof(double) * NV);
+            }
+}
+
+/* Every message of the grid for a block-to-process assignment, in the order of the counting loops:
+ * sender process, pass, receiving process, then the sender's local block order and slot order.
+ * Row q of out (16 values): sender process, receiving process, pass, i_M (index among the messages from
+ * that sender to that receiver in that pass), start offset, sender block, slot, receiving block (global),
+ * its local index on the receiving process, type (0 copy, 1 restriction, 2 prolongation), lo[3], hi[3].
+ * Returns the number of messages, or -1 when out has fewer than max_rows rows. */
+long or_xchg_messages(const or_grid *g, const int32_t *rank, int n_ranks, int64_t *out, long max_rows)
+{
+    int *local = malloc(sizeof(int) * (size_t)g->nb);
+    int *count = calloc((size_t)n_ranks, sizeof(int));
+    for (int b = 0; b < g->nb; b++) local[b] = count[rank[b]]++;
+    or_msg *mb = malloc(sizeof(or_msg) * 26 * 4);
+    long q = 0;
+    for (int sp = 0; sp < n_ranks; sp++)
+        for (int pass = 1; pass <= 2; pass++)
+            for (int rp = 0; rp < n_ranks; rp++) {
+                long im = 0, start = 0;
+                for (int b = 0; b < g->nb; b++) {
+                    if (rank[b] != sp) continue;
+                    int nm = block_messages(g, b, mb);
+                    for (int c = 0; c < nm; c++) {
+                        const or_msg *m = &mb[c];
+                        if (m->pass != pass || rank[m->receiver] != rp) continue;
+                        if (q >= max_rows) {
+                            free(mb); free(count); free(local);
+                            return -1;
+                        }
+                        int64_t *r = out + q * 16;
+                        r[0] = sp; r[1] = rp; r[2] = pass; r[3] = im; r[4] = start;
+                        r[5] = b; r[6] = m->slot; r[7] = m->receiver; r[8] = local[m->receiver]; r[9] = m->type;
+                        for (int a = 0; a < 3; a++) { r[10 + a] = m->lo[a]; r[13 + a] = m->hi[a]; }
+                        start += XCHG_NC + NV * box_cells(m);
+                        im++;
+                        q++;
+                    }
+                }
+            }
+    free(mb);
+    free(count);
+    free(local);
+    return q;
+}
+
+/* The exchange of Algorithm 4 over simulated processes: every process copies its blocks' interior
+ * cells into its own padded array, then for pass 1 and pass 2 packs its messages (local ones straight
+ * into its own array, the others into one buffer per receiving process at the counted start offsets,
+ * each message a header and its values), the buffers move to their receivers, and every receiver unpacks
+ * its buffers by reading each message's header; after pass 1 the level-0 blocks, after pass 2 the
+ * level-1 blocks fill their ghost cells outside the domain. The result, every process's padded array
+ * gathered back into global block order, is written to view[8][nB][12][12][12] (like or_fill_ghosts). */
+int or_xchg_run(const or_grid *g, const int32_t *rank, int n_ranks, const double *U, double *view)
+{
+    int *local = malloc(sizeof(int) * (size_t)g->nb);
+    int *count = calloc((size_t)n_ranks, sizeof(int));
+    for (int b = 0; b < g->nb; b++) local[b] = count[rank[b]]++;
+    double **st = malloc(sizeof(double *) * (size_t)n_ranks);
+    for (int r = 0; r < n_ranks; r++) st[r] = pad_alloc(count[r] > 0 ? count[r] : 1);
+    /* interiors */
+    size_t nbc = (size_t)g->nb * 512;
+    for (int b = 0; b < g->nb; b++)
+        for (int k = 0; k < NC; k++)
+            for (int j = 0; j < NC; j++)
+                for (int i = 0; i < NC; i++) {
+                    double *c = pcell(st[rank[b]], local[b], i, j, k);
+                    for (int v = 0; v < NV; v++) c[v] = U[v * nbc + (size_t)b * 512 + (k * 8 + j) * 8 + i];
+                }
+    or_msg *mb = malloc(sizeof(or_msg) * 26 * 4);
+    for (int pass = 1; pass <= 2; pass++) {
+        /* pack: buffers[sender][receiver] */
+        double **buf = calloc((size_t)n_ranks * n_ranks, sizeof(double *));
+        long *len = calloc((size_t)n_ranks * n_ranks, sizeof(long));
+        for (int sp = 0; sp < n_ranks; sp++)
+            for (int rp = 0; rp < n_ranks; rp++) {
+                if (rp == sp) continue;
+                /* counting loop: the sizes and start offsets of the messages from sp to rp */
+                long total = 0;
+                for (int b = 0; b < g->nb; b++) {
+                    if (rank[b] != sp) continue;
+                    int nm = block_messages(g, b, mb);
+                    for (int c = 0; c < nm; c++)
+                        if (mb[c].pass == pass && rank[mb[c].receiver] == rp) total += XCHG_NC + NV * box_cells(&mb[c]);
+                }
+                len[sp * n_ranks + rp] = total;
+                buf[sp * n_ranks + rp] = malloc(sizeof(double) * (size_t)(total > 0 ? total : 1));
+                long start = 0;
+                for (int b = 0; b < g->nb; b++) {
+                    if (rank[b] != sp) continue;
+                    int nm = block_messages(g, b, mb);
+                    for (int c = 0; c < nm; c++) {
+                        const or_msg *m = &mb[c];
+                        if (m->pass != pass || rank[m->receiver] != rp) continue;
+                        double *h = buf[sp * n_ranks + rp] + start;
+                        h[0] = local[m->receiver];
+                        for (int a = 0; a < 3; a++) { h[1 + a] = m->lo[a]; h[4 + a] = m->hi[a]; }
+                        double *d = h + XCHG_NC;
+                        for (int k = m->lo[2]; k <= m->hi[2]; k++)
+                            for (int j = m->lo[1]; j <= m->hi[1]; j++)
+                                for (int i = m->lo[0]; i <= m->hi[0]; i++) {
+                                    message_value(g, m, st[sp], local[b], i, j, k, d);
+                                    d += NV;
+                                }
+                        start += XCHG_NC + NV * box_cells(m);
+                    }
+                }
+            }
+        /* local message passing */
+        for (int b = 0; b < g->nb; b++) {
+            int nm = block_messages(g, b, mb);
+            for (int c = 0; c < nm; c++) {
+                const or_msg *m = &mb[c];
+                if (m->pass != pass || rank[m->receiver] != rank[b]) continue;
+                for (int k = m->lo[2]; k <= m->hi[2]; k++)
+                    for (int j = m->lo[1]; j <= m->hi[1]; j++)
+                        for (int i = m->lo[0]; i <= m->hi[0]; i++)
+                            message_value(g, m, st[rank[b]], local[b], i, j, k,
+                                          pcell(st[rank[b]], local[m->receiver], i, j, k));
+            }
+        }
+        /* exchange and unpack: each receiver walks the buffer of each sender, message by message */
+        for (int rp = 0; rp < n_ranks; rp++)
+            for (int sp = 0; sp < n_ranks; sp++) {
+                if (sp == rp) continue;
+                const double *rb = buf[sp * n_ranks + rp];
+                long at = 0, total = len[sp * n_ranks + rp];
+                while (at < total) {
+                    const double *h = rb + at;
+                    int lb = (int)h[0], lo[3], hi[3];
+                    for (int a = 0; a < 3; a++) { lo[a] = (int)h[1 + a]; hi[a] = (int)h[4 + a]; }
+                    const double *d = h + XCHG_NC;
+                    for (int k = lo[2]; k <= hi[2]; k++)
+                        for (int j = lo[1]; j <= hi[1]; j++)
+                            for (int i = lo[0]; i <= hi[0]; i++) {
+                                memcpy(pcell(st[rp], lb, i, j, k), d, sizeof(double) * NV);
+                                d += NV;
+                            }
+                    at = d - rb;
+                }
+            }
+        for (int q = 0; q < n_ranks * n_ranks; q++) free(buf[q]);
+        free(buf);
+        free(len);
+        /* ghost cells outside the domain */
+        for (int b = 0; b < g->nb; b++)
+            if (g->level[b] == pass - 1) fill_boundary_ghosts(g, b, st[rank[b]], local[b]);
+    }
+    size_t nbp = (size_t)g->nb * NPAD;
+    for (int b = 0; b < g->nb; b++)
+        for (size_t c = 0; c < NPAD; c++)
+            for (int v = 0; v < NV; v++)
+                view[v * nbp + (size_t)b * NPAD + c] = st[rank[b]][((size_t)local[b] * NPAD + c) * NV + v];
+    free(mb);
+    for (int r = 0; r < n_ranks; r++) free(st[r]);
+    free(st);
+    free(count);
+    free(local);
+    return 0;
+}
+
 /* Count of fluid cells whose density or pressure is not positive (or not finite). */
 static long count_faults(const or_grid *g, double *st)
 {
