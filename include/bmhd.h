@@ -258,6 +258,16 @@ int32_t bmhd_mlp_forward(const float *d_params, const uint16_t *d_params_bf16, i
 int32_t bmhd_mlp_backward(const float *d_params, int32_t hidden, int32_t n, const float *d_x, const float *d_t,
                           const float *d_save, const float *d_y, float *d_grad, float *d_sqerr, float *d_work,
                           int32_t mode, void *stream);
+/* bmhd_mlp_backward without the d_work argument, for callers that cannot allocate device memory (code
+ * under HIP graph capture, serving loops, harnesses that forbid allocation): the work area is a static
+ * device array of the library, 32 MiB per device, held until the process ends and looked up on each
+ * device's first call. It calls no allocating routine. n is limited to 8,388,608 / (16 + 2 * hidden)
+ * samples (104,857 at hidden 32; 58,254 at 64; 30,840 at 128); a larger n returns BMHD_EINVAL with a
+ * message and launches nothing. Results equal bmhd_mlp_backward's. Every call on one device shares that
+ * device's array: calls that overlap on one device (different streams or host threads) race. */
+int32_t bmhd_mlp_backward_noalloc(const float *d_params, int32_t hidden, int32_t n, const float *d_x,
+                                  const float *d_t, const float *d_save, const float *d_y, float *d_grad,
+                                  float *d_sqerr, int32_t mode, void *stream);
 /* One Adam step (step count t >= 1) on the float32 parameters; refreshes the bfloat16 copy. */
 int32_t bmhd_mlp_adam(float *d_params, uint16_t *d_params_bf16, float *d_m, float *d_v, const float *d_grad,
                       int64_t n_params, float lr, float b1, float b2, float eps, int32_t t, void *stream);

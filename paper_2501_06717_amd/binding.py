@@ -23,7 +23,7 @@ SCHEME = {"default": 0, "face": 1, "plane": 2}
 EXPORTS = ["bmhd_version", "bmhd_last_error", "bmhd_grid_create", "bmhd_grid_destroy", "bmhd_grid_info_get",
            "bmhd_grid_neighbors", "bmhd_grid_upload", "bmhd_set_state", "bmhd_fill_ghosts", "bmhd_remap",
            "bmhd_reduce_dt", "bmhd_advance", "bmhd_autotune", "bmhd_mlp_last_error", "bmhd_mlp_n_params", "bmhd_mlp_work_bytes",
-           "bmhd_mlp_forward", "bmhd_mlp_backward", "bmhd_mlp_adam", "bmhd_mlp_to_bf16", "bmhd_face_data"]
+           "bmhd_mlp_forward", "bmhd_mlp_backward", "bmhd_mlp_backward_noalloc", "bmhd_mlp_adam", "bmhd_mlp_to_bf16", "bmhd_face_data"]
 
 
 class SimDesc(ctypes.Structure):
@@ -111,6 +111,8 @@ def lib():
     L.bmhd_mlp_forward.restype = i32
     L.bmhd_mlp_backward.argtypes = [vp, i32, i32, vp, vp, vp, vp, vp, vp, vp, i32, vp]
     L.bmhd_mlp_backward.restype = i32
+    L.bmhd_mlp_backward_noalloc.argtypes = [vp, i32, i32, vp, vp, vp, vp, vp, vp, i32, vp]
+    L.bmhd_mlp_backward_noalloc.restype = i32
     L.bmhd_mlp_adam.argtypes = [vp, vp, vp, vp, vp, ctypes.c_int64, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                                 ctypes.c_float, i32, vp]
     L.bmhd_mlp_adam.restype = i32
@@ -396,13 +398,19 @@ class Mlp:
                                        _stream_ptr(stream)))
         return (y, z) if save else y
 
-    def loss_grad(self, x, t, mode="bf16", stream=None):
-        """Returns (loss tensor, gradient tensor) for targets t[n][8]."""
+    def loss_grad(self, x, t, mode="bf16", stream=None, noalloc=False):
+        """Returns (loss tensor, gradient tensor) for targets t[n][8]. With noalloc the backward pass
+        runs on the library's static work area (bmhd_mlp_backward_noalloc) instead of a work tensor."""
         import torch
         n = x.shape[0]
         y, z = self.forward(x, save=True, mode=mode, stream=stream)
         g = torch.empty_like(self.p)
         sq = torch.empty((n, 8), dtype=torch.float32, device=x.device)
+        if noalloc:
+            _mcheck(lib().bmhd_mlp_backward_noalloc(_dev_ptr(self.p), self.H, n, _dev_ptr(x),
+                                                    _dev_ptr(t, torch.float32), _dev_ptr(z), _dev_ptr(y), _dev_ptr(g),
+                                                    _dev_ptr(sq), MLP_MODE[mode], _stream_ptr(stream)))
+            return sq.mean(), g
         work = torch.empty(int(lib().bmhd_mlp_work_bytes(self.H, n)) // 4, dtype=torch.float32, device=x.device)
         _mcheck(lib().bmhd_mlp_backward(_dev_ptr(self.p), self.H, n, _dev_ptr(x), _dev_ptr(t, torch.float32),
                                         _dev_ptr(z), _dev_ptr(y), _dev_ptr(g), _dev_ptr(sq), _dev_ptr(work),

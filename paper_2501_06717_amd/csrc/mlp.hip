@@ -14,6 +14,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <mutex>
 #include <string>
 #include <type_traits>
 
@@ -396,6 +397,13 @@ __global__ void k_to_bf16(long np, const float *__restrict__ p, __bf16 *__restri
     if (i < np) pb[i] = __bf16(p[i]);
 }
 
+// Scratch of bmhd_mlp_backward_noalloc, laid out like bmhd_mlp_backward's d_work (dY in the first n x 16
+// floats, then two [n][H] gradient buffers); every element the backward pass reads it has written first. Every device the library runs on holds its own
+// copy until the process ends. Host code never passes `scratch` itself to a kernel: it passes the
+// device address hipGetSymbolAddress returns for the current device.
+constexpr size_t MLP_SCRATCH_FLOATS = size_t(8) << 20;  // 32 MiB
+static __device__ __align__(256) float scratch[MLP_SCRATCH_FLOATS];
+
 }  // namespace bmhd
 
 // ================================================================================================
@@ -451,10 +459,83 @@ int32_t forward_h(const float *P, const uint16_t *Pb, int n, const float *X, flo
     else k_mlp_forward<H, false><<<grid, 256, 0, s>>>(P, pb, n, X, Y, Z);
     return mcheck("mlp forward");
 }
+
+// Device address of `scratch` on the current device, looked up once per device (with that device
+// current) and kept: the symbol's host-side name is not a device address.
+constexpr int MAX_DEVICES = 64;
+std::mutex scratch_mu;
+float *scratch_dev[MAX_DEVICES] = {};
+
+int32_t scratch_address(float **out) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return mfail(BMHD_EHIP, "mlp_backward_noalloc: hipGetDevice failed");
+    if (dev < 0 || dev >= MAX_DEVICES) return mfail(BMHD_EUNSUPPORTED, "mlp_backward_noalloc: device index out of range");
+    std::lock_guard<std::mutex> lock(scratch_mu);
+    if (!scratch_dev[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return mfail(BMHD_EHIP, (std::string("mlp_backward_noalloc: hipGetSymbolAddress: ") + hipGetErrorString(e)).c_str());
+        scratch_dev[dev] = static_cast<float *>(p);
+    }
+    *out = scratch_dev[dev];
+    return BMHD_OK;
+}
+
+// Backward pass on a caller-supplied work area (bmhd_mlp_work_bytes(hidden, n) bytes); arguments checked
+// by the caller.
+int32_t backward_impl(const float *d_params, int32_t hidden, int32_t n, const float *d_x, const float *d_t,
+                      const float *d_save, const float *d_y, float *d_grad, float *d_sqerr, float *d_work,
+                      int32_t mode, void *stream) {
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    const int H = hidden;
+    const MlpView V = mlp_view(H);
+    float *dY = d_work;                                  // [n][8]
+    float *bufA = d_work + size_t(n) * 16;               // [n][H]
+    float *bufB = bufA + size_t(n) * H;                  // [n][H]
+    const bool mf = mode == 0;
+    auto G = [&](int M, int N, int K, const float *A, long am, long ak, const float *B, long bk, long bn, float *C,
+                 long ldc) {
+        if (mf) gemm<true>(M, N, K, A, am, ak, B, bk, bn, C, ldc, false, s);
+        else gemm<false>(M, N, K, A, am, ak, B, bk, bn, C, ldc, false, s);
+    };
+    k_loss_grad<<<blocks_for(long(n) * 8, 256), 256, 0, s>>>(n, d_y, d_t, dY, d_sqerr);
+    // layer 4: dW4[o][i] = sum_n dY[n][o] A3[n][i], db4 = sum_n dY, dA3 = dY W4
+    float *A3 = bufB;
+    k_silu<<<blocks_for(long(n) * H, 256), 256, 0, s>>>(long(n) * H, d_save + size_t(2) * n * H, A3);
+    G(8, H, n, dY, 1, 8, A3, H, 1, d_grad + V.off_w[3], H);
+    k_colsum<<<1, 64, 0, s>>>(n, 8, dY, d_grad + V.off_b[3]);
+    float *dA = bufA, *other = bufB;
+    G(n, H, 8, dY, 8, 1, d_params + V.off_w[3], H, 1, dA, H);
+    // hidden layers 3, 2, 1 (index l = 2, 1, 0)
+    for (int l = 2; l >= 0; --l) {
+        const float *Z = d_save + size_t(l) * n * H;
+        float *dZ = dA;  // in place: dZ overwrites dA
+        k_silu_back<<<blocks_for(long(n) * H, 256), 256, 0, s>>>(long(n) * H, dA, Z, dZ);
+        const int nin = V.nin[l];
+        if (l > 0) {
+            float *Ain = other;
+            k_silu<<<blocks_for(long(n) * H, 256), 256, 0, s>>>(long(n) * H, d_save + size_t(l - 1) * n * H, Ain);
+            G(H, nin, n, dZ, 1, H, Ain, H, 1, d_grad + V.off_w[l], nin);
+        } else {
+            G(H, nin, n, dZ, 1, H, d_x, MLP_IN, 1, d_grad + V.off_w[l], nin);
+        }
+        k_colsum<<<blocks_for(H, 64), 64, 0, s>>>(n, H, dZ, d_grad + V.off_b[l]);
+        if (l > 0) {
+            // dA_{l-1}[n][i] = sum_o dZ[n][o] W_l[o][i], into the buffer the inputs no longer need
+            G(n, nin, H, dZ, H, 1, d_params + V.off_w[l], nin, 1, other, nin);
+            float *t = dA;
+            dA = other;
+            other = t;
+        }
+    }
+    return mcheck("mlp backward");
+}
 }  // namespace
 
 namespace bmhd {
-int32_t mlp_infer_bf16_inputs(const float *d_params, const uint16_t *d_params_bf16, int32_t hidden, int32_t n,
+int32_t mlp_infer_bf16_inputs(
+const float *d_params, const uint16_t *d_params_bf16, int32_t hidden, int32_t n,
                               const uint16_t *d_x, float *d_y, void *stream, std::string &err) {
     if (!d_params || !d_params_bf16 || !d_x || !d_y || n < 0 || (reinterpret_cast<uintptr_t>(d_x) & 15u)) {
         err = "mlp inference: null or misaligned buffers";
@@ -507,49 +588,24 @@ int32_t bmhd_mlp_backward(const float *d_params, int32_t hidden, int32_t n, cons
         (mode != 0 && mode != 1))
         return mfail(BMHD_EINVAL, "mlp_backward: bad arguments");
     if (hidden != 32 && hidden != 64 && hidden != 128) return mfail(BMHD_EUNSUPPORTED, "hidden must be 32, 64 or 128");
-    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    const int H = hidden;
-    const MlpView V = mlp_view(H);
-    float *dY = d_work;                                  // [n][8]
-    float *bufA = d_work + size_t(n) * 16;               // [n][H]
-    float *bufB = bufA + size_t(n) * H;                  // [n][H]
-    const bool mf = mode == 0;
-    auto G = [&](int M, int N, int K, const float *A, long am, long ak, const float *B, long bk, long bn, float *C,
-                 long ldc) {
-        if (mf) gemm<true>(M, N, K, A, am, ak, B, bk, bn, C, ldc, false, s);
-        else gemm<false>(M, N, K, A, am, ak, B, bk, bn, C, ldc, false, s);
-    };
-    k_loss_grad<<<blocks_for(long(n) * 8, 256), 256, 0, s>>>(n, d_y, d_t, dY, d_sqerr);
-    // layer 4: dW4[o][i] = sum_n dY[n][o] A3[n][i], db4 = sum_n dY, dA3 = dY W4
-    float *A3 = bufB;
-    k_silu<<<blocks_for(long(n) * H, 256), 256, 0, s>>>(long(n) * H, d_save + size_t(2) * n * H, A3);
-    G(8, H, n, dY, 1, 8, A3, H, 1, d_grad + V.off_w[3], H);
-    k_colsum<<<1, 64, 0, s>>>(n, 8, dY, d_grad + V.off_b[3]);
-    float *dA = bufA, *other = bufB;
-    G(n, H, 8, dY, 8, 1, d_params + V.off_w[3], H, 1, dA, H);
-    // hidden layers 3, 2, 1 (index l = 2, 1, 0)
-    for (int l = 2; l >= 0; --l) {
-        const float *Z = d_save + size_t(l) * n * H;
-        float *dZ = dA;  // in place: dZ overwrites dA
-        k_silu_back<<<blocks_for(long(n) * H, 256), 256, 0, s>>>(long(n) * H, dA, Z, dZ);
-        const int nin = V.nin[l];
-        if (l > 0) {
-            float *Ain = other;
-            k_silu<<<blocks_for(long(n) * H, 256), 256, 0, s>>>(long(n) * H, d_save + size_t(l - 1) * n * H, Ain);
-            G(H, nin, n, dZ, 1, H, Ain, H, 1, d_grad + V.off_w[l], nin);
-        } else {
-            G(H, nin, n, dZ, 1, H, d_x, MLP_IN, 1, d_grad + V.off_w[l], nin);
-        }
-        k_colsum<<<blocks_for(H, 64), 64, 0, s>>>(n, H, dZ, d_grad + V.off_b[l]);
-        if (l > 0) {
-            // dA_{l-1}[n][i] = sum_o dZ[n][o] W_l[o][i], into the buffer the inputs no longer need
-            G(n, nin, H, dZ, H, 1, d_params + V.off_w[l], nin, 1, other, nin);
-            float *t = dA;
-            dA = other;
-            other = t;
-        }
+    return backward_impl(d_params, hidden, n, d_x, d_t, d_save, d_y, d_grad, d_sqerr, d_work, mode, stream);
+}
+
+int32_t bmhd_mlp_backward_noalloc(const float *d_params, int32_t hidden, int32_t n, const float *d_x,
+                                  const float *d_t, const float *d_save, const float *d_y, float *d_grad,
+                                  float *d_sqerr, int32_t mode, void *stream) {
+    if (!d_params || !d_x || !d_t || !d_save || !d_y || !d_grad || !d_sqerr || n <= 0 || (mode != 0 && mode != 1))
+        return mfail(BMHD_EINVAL, "mlp_backward_noalloc: bad arguments");
+    if (hidden != 32 && hidden != 64 && hidden != 128) return mfail(BMHD_EUNSUPPORTED, "hidden must be 32, 64 or 128");
+    const size_t need = bmhd_mlp_work_bytes(hidden, n) / sizeof(float);
+    if (need > MLP_SCRATCH_FLOATS) {
+        const size_t max_n = MLP_SCRATCH_FLOATS / (16 + 2 * size_t(hidden));
+        return mfail(BMHD_EINVAL, ("mlp_backward_noalloc: n = " + std::to_string(n) + " exceeds the static scratch (" +
+                                   std::to_string(max_n) + " samples at hidden " + std::to_string(hidden) + ")").c_str());
     }
-    return mcheck("mlp backward");
+    float *work = nullptr;
+    if (int32_t rc = scratch_address(&work)) return rc;
+    return backward_impl(d_params, hidden, n, d_x, d_t, d_save, d_y, d_grad, d_sqerr, work, mode, stream);
 }
 
 int32_t bmhd_mlp_adam(float *d_params, uint16_t *d_params_bf16, float *d_m, float *d_v, const float *d_grad,
