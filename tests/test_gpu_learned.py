@@ -200,3 +200,81 @@ def test_given_corrections_equal_the_network_path(bd):
     g.advance(Ub, U1b, dt, 1, learned=g.given_corrections(y, stats), **kw)
     torch.cuda.synchronize()
     assert torch.equal(U1a, U1b)
+
+
+def _group_err(a, b):
+    return {k: float(np.abs(a[v] - b[v]).max() / np.abs(b[v]).max())
+            for k, v in (("rho", [0]), ("mom", [1, 2, 3]), ("B", [4, 5, 6]), ("e", [7]))}
+
+
+def test_features_match_the_oracle(bd, oracle_mod):
+    """bmhd_face_data's z-scored stencil features against the oracle's (or_face_features, FP64) on the
+    same conserved state, every face of every block of a box with a body, an inflow and outflow faces.
+    The GPU rounds each primitive to FP32 and z-scores in FP32, (x - mean) / std: three roundings of at
+    most half an FP32 unit each, so |X - ref| <= 2^-24 (|w| / std + 2 |ref|) with |w| <= |ref| std +
+    |mean|; the test allows twice that."""
+    base = wk.uniform_state((4, 4, 4), bc=(1, 2, 0, 0, 1, 1), body_r=5.0)
+    wl = wk.with_state(base, wk.random_positive_state(base, seed=21))
+    o = oracle_mod.Grid.from_workload(wl)
+    R = o.set_state(wl.W)
+    rng = np.random.default_rng(22)
+    stats = np.zeros(80)
+    stats[0:32] = rng.uniform(-0.5, 0.5, 32)
+    stats[32:64] = rng.uniform(0.5, 2.0, 32)
+    st32 = stats.astype(np.float32)
+    g = bd.Grid.from_workload(wl).upload()
+    X, _ = g.face_data(dev(R), stats=torch.from_numpy(st32).cuda(), want_f=False)
+    X = X.cpu().numpy().astype(np.float64)
+    mean, std = st32[0:32].astype(np.float64), st32[32:64].astype(np.float64)
+    ref = o.face_features(R, stats=st32.astype(np.float64))
+    assert X.shape == ref.shape
+    bound = 2.0 ** -23 * ((np.abs(ref) * std + np.abs(mean)) / std + 2.0 * np.abs(ref))
+    excess = (np.abs(X - ref) / bound).max()
+    print("features: max error / FP32 bound", float(excess), flush=True)
+    assert excess <= 1.0
+    # the unnormalised features are the primitives rounded once to FP32 (the nearest FP32 value, or its
+    # neighbour where the GPU's FP64 primitive and the oracle's straddle a rounding boundary)
+    X0, _ = g.face_data(dev(R), want_f=False)
+    X0 = X0.cpu().numpy().astype(np.float64)
+    ref0 = o.face_features(R)
+    assert np.all(np.abs(X0 - ref0) <= 2.0 ** -23 * np.abs(ref0))
+
+
+@pytest.mark.parametrize("flux", ["hlle", "rusanov"])
+def test_learned_stage_matches_the_oracle(bd, oracle_mod, flux):
+    """One step of the learned form with corrections given per face (mode 2) against the oracle's learned
+    stage (or_advance_learned): same provisional update, same flag rule on the old 7-point range, the
+    fallback on both sides of every face of a flagged cell. Corrections are multiples of 1/64 scaled by a
+    power of two, exact in FP32, so both sides add the same increments; they are sized so that about a
+    tenth of the cells is flagged per stage. The grid has a body, an inflow face and outflow faces."""
+    base = wk.uniform_state((4, 4, 4), bc=(1, 2, 0, 0, 1, 1), body_r=5.0)
+    wl = wk.with_state(base, wk.random_positive_state(base, seed=31))
+    o = oracle_mod.Grid.from_workload(wl)
+    R0 = o.set_state(wl.W)
+    R1 = np.zeros_like(R0)
+    rng = np.random.default_rng(32)
+    y = (np.round(rng.normal(size=(wl.n_blocks * 1728, 8)) * 64.0) / 64.0).astype(np.float32)
+    ystats = np.zeros(16)
+    ystats[8:16] = 2.0 ** -3
+    rdt, rf, rflag = o.advance_learned(R0, R1, [0.0], 2, y.astype(np.float64), ystats, tau=0.1, flux=flux,
+                                       powell=True)
+    g = bd.Grid.from_workload(wl).upload()
+    U0 = dev(o.set_state(wl.W))
+    U1 = torch.zeros_like(U0)
+    dt = torch.zeros(1, dtype=torch.float64, device="cuda")
+    faults = torch.zeros(1, dtype=torch.int32, device="cuda")
+    fb = torch.zeros(1, dtype=torch.int32, device="cuda")
+    stats = torch.zeros(80)
+    stats[64:72] = torch.from_numpy(ystats[:8].astype(np.float32))
+    stats[72:80] = torch.from_numpy(ystats[8:].astype(np.float32))
+    L = g.given_corrections(dev(y), stats, tau=0.1, fallback=fb)
+    g.advance(U0, U1, dt, 2, faults=faults, flux=flux, powell=True, learned=L, scheme="plane", slab=4)
+    torch.cuda.synchronize()
+    err = _group_err(U0.cpu().numpy(), R0)
+    nflag = int(fb.item())
+    print("learned vs oracle", flux, err, "flagged", nflag, "oracle", rflag, "of", 2 * wl.n_cells, flush=True)
+    assert int(faults.item()) == 0 and rf == 0
+    assert abs(float(dt.item()) - rdt[0]) <= 1e-14 * rdt[0]
+    assert 0.05 * 2 * wl.n_cells <= rflag <= 0.3 * 2 * wl.n_cells
+    assert nflag == rflag
+    assert max(err.values()) <= 1e-12, err
