@@ -46,10 +46,10 @@ VALU_PER_CELL_STAGE = {("plane", 4): 1917.0}
 VALU_PEAK_LANE_OPS = 256 * 2.4e9 * 64
 
 
-def resolve_shape(scheme, slab, precision):
+def resolve_shape(scheme, slab, precision, persist=0):
     """The launch shape the library picks for scheme / slab 0 ("default") requests."""
-    sc = "plane" if scheme == "default" else scheme
-    ks = slab if slab else (8 if (precision == "fp64" and sc == "face") else 4)
+    sc = ("plane" if (slab == 4 or persist) else "block") if scheme == "default" else scheme
+    ks = slab if slab else (8 if ((precision == "fp64" and sc == "face") or sc == "block") else 4)
     return sc, ks
 # algorithmic HBM bytes per cell and stage: stage 1 reads U^n and writes U^1 (2 x 64 B); stage 2 reads
 # U^1 and U^n and writes U^{n+1} (3 x 64 B): 320 B per cell-update
@@ -67,7 +67,7 @@ def parse():
     p.add_argument("--warmup", type=int, default=3)
     p.add_argument("--n", type=int, default=256, help="cells per axis of the magnetosphere grid")
     p.add_argument("--slab", type=int, default=0)
-    p.add_argument("--scheme", default="default", choices=["default", "face", "plane"],
+    p.add_argument("--scheme", default="default", choices=["default", "face", "plane", "block"],
                    help="work split of the stage kernel")
     p.add_argument("--persist", type=int, default=0, help="persistent grid size of the stage kernel (0: off)")
     p.add_argument("--no-cpu-baseline", action="store_true")
@@ -300,9 +300,11 @@ def main():
     value = cells * steps / wall
     t1, t2 = float(np.mean(st[0])), float(np.mean(st[1]))
     achieved = cells * (BYTES_STAGE[0] + BYTES_STAGE[1]) / (t1 + t2) / 1e9
-    scheme, ks = resolve_shape(a.scheme, a.slab, a.precision)
+    scheme, ks = resolve_shape(a.scheme, a.slab, a.precision, a.persist)
     fp64 = a.precision == "fp64"
-    kname = ("k_stage_wp" if scheme == "plane" else "k_stage") + f"<{ks}, {'double' if fp64 else 'float'}, HLLE, Powell>"
+    prec = 'double' if fp64 else 'float'
+    kname = {"plane": f"k_stage_wp<{ks}, {prec}, HLLE, Powell>", "face": f"k_stage<{ks}, {prec}, HLLE, Powell>",
+             "block": f"k_stage_blk<{prec}, HLLE, Powell>"}[scheme]
     meas = TRAFFIC.get((scheme, ks)) if (a.n == 256 and not a.persist and fp64) else None
     traffic = 0.5 * (meas[0] + meas[1]) if meas else None
     vpc = VALU_PER_CELL_STAGE.get((scheme, ks)) if (a.n == 256 and not a.persist and fp64) else None
@@ -336,8 +338,10 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "traffic_unit": "HBM bytes per stage-kernel launch, mean of the two stages",
                      "algorithmic_bytes_per_launch": 0.5 * cells * (BYTES_STAGE[0] + BYTES_STAGE[1]),
-                     "kernel": kname + " (both stages; " + ("wave per cell layer" if scheme == "plane"
-                                                            else "face per thread") + f", tile 8x8x{ks})",
+                     "kernel": kname + " (both stages; " + {"plane": "wave per cell layer",
+                                                            "face": "face per thread",
+                                                            "block": "wave per cell layer, one workgroup per block"}[scheme]
+                               + f", tile 8x8x{ks})",
                      "stage_us": [t1 * 1e6, t2 * 1e6], "bytes_per_cell_update": 320,
                      "valu": valu},
         "faults": faults,

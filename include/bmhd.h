@@ -50,6 +50,8 @@ extern "C" {
 #define BMHD_FP32_FLUX 1 /* reconstruction and fluxes in float32; update, flux correction, dt in float64 */
 #define BMHD_SCHEME_FACE 1
 #define BMHD_SCHEME_PLANE 2
+#define BMHD_SCHEME_BLOCK 3
+#define BMHD_AUTOTUNE_SHAPES 13 /* launch shapes bmhd_autotune times */
 
 /* Neighbour relations reported by bmhd_grid_neighbors. */
 #define BMHD_REL_SAME 0
@@ -114,10 +116,14 @@ typedef struct {
     double alpha[2];      /* stage table: out = alpha U^n + (1 - alpha) U_in + beta dt L(U_in) */
     double beta[2];       /* Heun: alpha = {0, 0.5}, beta = {1, 0.5} */
     int32_t slab;         /* tile depth of the stage kernel: 0 = default, 4 or 8 cells along z */
-    int32_t scheme;       /* work split of the stage kernel: 0 = default; BMHD_SCHEME_FACE: one face per
+    int32_t scheme;       /* work split of the stage kernel: 0 = default (BMHD_SCHEME_BLOCK, or
+                             BMHD_SCHEME_PLANE when slab is 4 or persist_wgs > 0); BMHD_SCHEME_FACE: one face per
                              thread and direction, fluxes exchanged through LDS; BMHD_SCHEME_PLANE: one
                              wave per cell layer of the tile plus one wave for the tile's high-side faces,
-                             fluxes exchanged across lanes (less LDS, more workgroups per CU) */
+                             fluxes exchanged across lanes (less LDS, more workgroups per CU);
+                             BMHD_SCHEME_BLOCK: one workgroup of eight wavefronts per block, one wave per
+                             cell layer, the block's high-side faces shared out over the eight waves (slab
+                             0 or 8, persist_wgs 0) */
     int32_t persist_wgs;  /* 0: one workgroup per tile; > 0: a persistent grid of this many workgroups
                              (rounded up to a multiple of 8), each looping over tiles */
     int32_t use_graph;    /* 1: steps after the first replay one captured HIP graph of a whole step
@@ -126,7 +132,9 @@ typedef struct {
     int32_t n_events;     /* length of `events`, or 0 */
     void **events;        /* optional caller-created hipEvent_t handles: when n_events >= 2 * n_stages,
                              events[2s] and events[2s+1] are recorded on `stream` right before and after
-                             the stage kernel of stage s (for timing the dominant kernel) */
+                             the stage kernel of stage s (for timing the dominant kernel; with the block
+                             scheme they bracket the block-form launch, after the plane-form launch for
+                             the blocks near a body) */
     int32_t local_dt;     /* 1: local time stepping (the steady-state sessions of Sec. 5.2): every fluid
                              cell advances with its own CFL step, dt_i = cfl * 1 / sum_d ((|u_d| + c_f,d) /
                              dx), in both stages and in the flux correction; d_dt is then one value per cell,
@@ -225,11 +233,11 @@ int32_t bmhd_face_data(const bmhd_grid *g, const double *d_U, int32_t flux, cons
                        float *d_F, void *stream);
 
 /* Autotuner: time every launch shape of the stage kernel (scheme FACE or PLANE, tile depth 4 or 8
- * cells, one workgroup per tile or a persistent grid of 2 or 4 workgroups per compute unit) for n_steps
- * steps each with `base`'s other options, on the caller's buffers (they are advanced: pass scratch
- * copies), and write `base` with the fastest shape into *best. h_ms (host, may be NULL) receives the
- * milliseconds of the 12 candidates: scheme FACE then PLANE, each in the order (4,0) (4,2/CU) (4,4/CU)
- * (8,0) (8,2/CU) (8,4/CU). Blocking: synchronises `stream`. With the environment variable
+ * cells, one workgroup per tile or a persistent grid of 2 or 4 workgroups per compute unit; scheme
+ * BLOCK) for n_steps steps each with `base`'s other options, on the caller's buffers (they are advanced:
+ * pass scratch copies), and write `base` with the fastest shape into *best. h_ms (host, may be NULL)
+ * receives the milliseconds of the BMHD_AUTOTUNE_SHAPES (13) candidates: scheme FACE then PLANE, each in
+ * the order (4,0) (4,2/CU) (4,4/CU) (8,0) (8,2/CU) (8,4/CU), then BLOCK. Blocking: synchronises `stream`. With the environment variable
  * BMHD_AUTOTUNE_CACHE naming a file, the choice is kept there, one text line per configuration keyed by
  * the device (architecture, CU count), the grid (sizes and a hash of its block list) and the options
  * that change the work; a later call with the same key returns the stored shape without timing (h_ms

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(HERE, "libbmhd.so")
 BC_PERIODIC, BC_OUTFLOW, BC_INFLOW = 0, 1, 2
 FLUX = {"rusanov": 0, "hlle": 1}
 PRECISION = {"fp64": 0, "fp32_flux": 1}
-SCHEME = {"default": 0, "face": 1, "plane": 2}
+SCHEME = {"default": 0, "face": 1, "plane": 2, "block": 3}
 
 EXPORTS = ["bmhd_version", "bmhd_last_error", "bmhd_grid_create", "bmhd_grid_destroy", "bmhd_grid_info_get",
            "bmhd_grid_neighbors", "bmhd_grid_upload", "bmhd_set_state", "bmhd_fill_ghosts", "bmhd_remap",
@@ -348,11 +348,12 @@ class Grid:
         import torch
         base = make_opts(**kw)
         best = Opts()
-        ms = (ctypes.c_float * 12)()
+        ms = (ctypes.c_float * 13)()
         _check(lib().bmhd_autotune(self.h, _dev_ptr(U0, torch.float64), _dev_ptr(U1, torch.float64),
                                    _dev_ptr(dt, torch.float64), ctypes.byref(base), int(n_steps), ctypes.byref(best),
                                    ms, _stream_ptr(stream)))
         names = [f"{s}_slab{k}{p}" for s in ("face", "plane") for k in (4, 8) for p in ("", "_persist2", "_persist4")]
+        names.append("block")
         return best, dict(zip(names, list(ms)))
 
 

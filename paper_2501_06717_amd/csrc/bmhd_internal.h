@@ -79,12 +79,14 @@ struct Tables {
     const DevSim *sims;
     const int32_t *lut;
     const int32_t *order;       // Morton schedule of blocks
+    const int32_t *order_split; // the same schedule, blocks clear of any body first (n_clear of them), then
+                                // the blocks near a body
     const int32_t *halo_items;  // (block << 3) | face for every level face
     const DevFcCell *fc_cells;
     double *halo;               // [n_halo_slots][HALO_SLOT]
     double *fcbuf;              // [n_fc_rec][FC_REC]
     unsigned long long *lam;    // [n_sims] max of the dt bound (bit patterns of positive doubles)
-    int32_t nb, ns, n_halo_items, n_fc_cells;
+    int32_t nb, ns, n_halo_items, n_fc_cells, n_clear;
 };
 
 // Host-side grid.
@@ -96,12 +98,15 @@ struct HostGrid {
     std::vector<DevSim> sims;
     std::vector<int32_t> lut;
     std::vector<int32_t> order;
+    std::vector<int32_t> order_split;
+    int32_t n_clear = 0;
     std::vector<int32_t> halo_items;
     std::vector<DevFcCell> fc_cells;
     int32_t n_halo_slots = 0, n_fc_rec = 0;
     std::vector<int32_t> nbr;   // [nb][26][5]
     // workspace layout (byte offsets)
-    size_t off_blocks = 0, off_sims = 0, off_lut = 0, off_order = 0, off_halo_items = 0, off_fc_cells = 0;
+    size_t off_blocks = 0, off_sims = 0, off_lut = 0, off_order = 0, off_order_split = 0, off_halo_items = 0,
+           off_fc_cells = 0;
     size_t off_halo = 0, off_fcbuf = 0, off_lam = 0, work_bytes = 0, table_bytes = 0;
     std::vector<unsigned char> blob;  // packed tables (first table_bytes of the workspace)
     void *d_work = nullptr;

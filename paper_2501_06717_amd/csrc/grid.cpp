@@ -337,12 +337,22 @@ int32_t build_grid(const bmhd_grid_desc *d, HostGrid &g, std::string &err) {
         return key[x] < key[y];
     });
 
+    // the same schedule with the blocks clear of any body first (the block form of the stage kernel takes
+    // those; blocks near a body go to the plane form)
+    g.order_split.clear();
+    for (int32_t b : g.order)
+        if (!(g.blocks[b].flags & BF_NEAR_BODY)) g.order_split.push_back(b);
+    g.n_clear = int32_t(g.order_split.size());
+    for (int32_t b : g.order)
+        if (g.blocks[b].flags & BF_NEAR_BODY) g.order_split.push_back(b);
+
     // workspace layout
     size_t off = 0;
     g.off_blocks = off; off = align256(off + sizeof(DevBlock) * g.blocks.size());
     g.off_sims = off; off = align256(off + sizeof(DevSim) * g.sims.size());
     g.off_lut = off; off = align256(off + sizeof(int32_t) * g.lut.size());
     g.off_order = off; off = align256(off + sizeof(int32_t) * g.order.size());
+    g.off_order_split = off; off = align256(off + sizeof(int32_t) * g.order_split.size());
     g.off_halo_items = off; off = align256(off + sizeof(int32_t) * std::max<size_t>(1, g.halo_items.size()));
     g.off_fc_cells = off; off = align256(off + sizeof(DevFcCell) * std::max<size_t>(1, g.fc_cells.size()));
     g.off_lam = off; off = align256(off + sizeof(unsigned long long) * size_t(g.ns));
@@ -356,6 +366,7 @@ int32_t build_grid(const bmhd_grid_desc *d, HostGrid &g, std::string &err) {
     put(g.off_sims, g.sims.data(), sizeof(DevSim) * g.sims.size());
     put(g.off_lut, g.lut.data(), sizeof(int32_t) * g.lut.size());
     put(g.off_order, g.order.data(), sizeof(int32_t) * g.order.size());
+    put(g.off_order_split, g.order_split.data(), sizeof(int32_t) * g.order_split.size());
     put(g.off_halo_items, g.halo_items.data(), sizeof(int32_t) * g.halo_items.size());
     put(g.off_fc_cells, g.fc_cells.data(), sizeof(DevFcCell) * g.fc_cells.size());
     return BMHD_OK;

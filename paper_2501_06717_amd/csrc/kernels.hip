@@ -546,7 +546,15 @@ struct StageArgs {
     const float *lrn_stats;  // in_mean[32], in_std[32], out_mean[8], out_std[8]
     uint8_t *lrn_flags;      // per cell: provisional state rejected
     double tau;
+    // work list of the launch: a part of the Morton schedule (block ids), or null for all of T.order
+    const int32_t *sched;
+    int32_t n_sched;
 };
+
+__device__ __forceinline__ int sched_count(const Tables &T, const StageArgs &A) { return A.sched ? A.n_sched : T.nb; }
+__device__ __forceinline__ int sched_block(const Tables &T, const StageArgs &A, int i) {
+    return A.sched ? A.sched[i] : T.order[i];
+}
 
 // block-local index of face (i, j, z) of direction D (see bmhd_face_data)
 template <int D>
@@ -587,6 +595,28 @@ struct BitMask {
     const uint32_t *m;
     __device__ __forceinline__ bool operator()(int c) const { return (m[c >> 5] >> (c & 31)) & 1u; }
 };
+
+// Record the flux of a face of direction D, (i, j, z) block-local (the face between cells (i-1, j, z) and
+// (i, j, z) for D = 0, likewise j and z), if it lies on a block face that takes part in a flux correction.
+template <int D, typename R>
+__device__ __forceinline__ void record_fc(const Tables &T, const DevBlock &B, int i, int j, int z, const R fl[8]) {
+    int bf = -1, t1 = 0, t2 = 0;
+    if (D == 0) { if (i == 0) bf = 0; else if (i == 8) bf = 1; t1 = j; t2 = z; }
+    if (D == 1) { if (j == 0) bf = 2; else if (j == 8) bf = 3; t1 = i; t2 = z; }
+    if (D == 2) { if (z == 0) bf = 4; else if (z == 8) bf = 5; t1 = i; t2 = j; }
+    if (bf >= 0 && B.fc_rec[bf] >= 0) {
+        double *rec = T.fcbuf + size_t(B.fc_rec[bf]) * FC_REC;
+        if ((B.fc_role >> bf) & 1) {
+#pragma unroll
+            for (int v = 0; v < 8; ++v) rec[v * 64 + t2 * 8 + t1] = double(fl[v]);
+        } else {
+            const int q = B.fc_quad[bf];
+            const int g1 = 8 * (q & 1) + t1, g2 = 8 * (q >> 1) + t2;
+#pragma unroll
+            for (int v = 0; v < 8; ++v) rec[FC_COARSE + v * 256 + g2 * 16 + g1] = double(fl[v]);
+        }
+    }
+}
 
 // Flux through one face of direction D of a slab whose primitives are in LDS: the face between cells
 // (i-1, j, k) and (i, j, k) for D = 0 (likewise j for D = 1, k for D = 2), slab-local coordinates, the face
@@ -655,29 +685,7 @@ __device__ __forceinline__ void face_flux(const Tables &T, const StageArgs &A, c
             bbar = R(0);
         }
     }
-    // fluxes through block faces that take part in a flux correction
-    if (B.flags & BF_FC) {
-        int bf = -1, t1 = 0, t2 = 0;
-        if (D == 0) { if (i == 0) bf = 0; else if (i == 8) bf = 1; t1 = j; t2 = slab * KS + k; }
-        if (D == 1) { if (j == 0) bf = 2; else if (j == 8) bf = 3; t1 = i; t2 = slab * KS + k; }
-        if (D == 2) {
-            const int z = slab * KS + k;
-            if (z == 0) bf = 4; else if (z == 8) bf = 5;
-            t1 = i; t2 = j;
-        }
-        if (bf >= 0 && B.fc_rec[bf] >= 0) {
-            double *rec = T.fcbuf + size_t(B.fc_rec[bf]) * FC_REC;
-            if ((B.fc_role >> bf) & 1) {
-#pragma unroll
-                for (int v = 0; v < 8; ++v) rec[v * 64 + t2 * 8 + t1] = double(fl[v]);
-            } else {
-                const int q = B.fc_quad[bf];
-                const int g1 = 8 * (q & 1) + t1, g2 = 8 * (q >> 1) + t2;
-#pragma unroll
-                for (int v = 0; v < 8; ++v) rec[FC_COARSE + v * 256 + g2 * 16 + g1] = double(fl[v]);
-            }
-        }
-    }
+    if (B.flags & BF_FC) record_fc<D>(T, B, i, j, slab * KS + k, fl);
 }
 
 // One sweep of the face-per-thread scheme: thread f takes face f of direction D and leaves its flux in
@@ -712,18 +720,23 @@ __device__ __forceinline__ void accumulate(R (*sF)[Slab<KS>::NF], double rhs[8],
     divb += (double(sF[8][fr]) - double(sF[8][fl])) * inv_dx;
 }
 
-// Issue the global loads of one slab and its face halos (cells tid, tid + NT, ...) into registers.
-template <int KS>
+// Cells of a slab and its face halos gathered per thread by a workgroup of NTH threads.
+template <int KS, int NTH>
+constexpr int gather_npt() { return (Slab<KS>::NC + NTH - 1) / NTH; }
+
+// Issue the global loads of one slab and its face halos (cells tid, tid + NTH, ...) into registers.
+template <int KS, int NTH = Slab<KS>::NT>
 __device__ __forceinline__ void gather_issue(const Tables &T, const StageArgs &A, int b, int slab,
-                                             double (&u)[Slab<KS>::NPT][8]) {
+                                             double (&u)[gather_npt<KS, NTH>()][8]) {
     using SL = Slab<KS>;
+    constexpr int NPT = gather_npt<KS, NTH>();
     const DevBlock &B = T.blocks[b];
     const DevSim &S = T.sims[B.sim];
     const size_t vs = size_t(T.nb) * 512;
     const int tid = lane_tid();
 #pragma unroll
-    for (int m = 0; m < SL::NPT; ++m) {
-        const int c = tid + m * SL::NT;
+    for (int m = 0; m < NPT; ++m) {
+        const int c = tid + m * NTH;
         if (c >= SL::NC) break;
         int i, j, k;
         SL::decode(c, i, j, k);
@@ -808,7 +821,7 @@ __device__ __forceinline__ void neighbour_range(R (*sW)[Slab<KS>::NC], int tid, 
 // Powell source, stage update and write of the thread's own cell (threads below 64 KS own cell tid of
 // the slab), then the end-of-step bookkeeping: positivity check and the next time-step bound. With the
 // learned correction, `rng` (or the LDS primitives when it is null) gives the old neighbourhood range.
-template <int KS, typename R, bool POWELL, bool LEARN, typename Mask>
+template <int KS, typename R, bool POWELL, bool LEARN, typename Mask, int NT = Slab<KS>::NT>
 __device__ __forceinline__ void cell_update(const Tables &T, const StageArgs &A, int b, int slab, const double (&uin)[8],
                                             R (*sW)[Slab<KS>::NC], Mask sM, double (&rhs)[8], double divb,
                                             double inv_dx, double *red, int *redi, const double *rng = nullptr) {
@@ -904,8 +917,8 @@ __device__ __forceinline__ void cell_update(const Tables &T, const StageArgs &A,
                 if (A.want_lam) lam = cell_bound(w, inv_dx);
             }
         }
-        block_publish<SL::NT>(lam, A.count_faults ? nf : 0, red, redi, A.want_lam ? T.lam + B.sim : nullptr,
-                              A.faults);
+        block_publish<NT>(lam, A.count_faults ? nf : 0, red, redi, A.want_lam ? T.lam + B.sim : nullptr,
+                          A.faults);
     }
 }
 
@@ -1182,12 +1195,12 @@ __global__ void __launch_bounds__(64 * (KS + 1), (wp_waves_per_simd<KS, R>())) k
     __shared__ double red[KS + 1];
     __shared__ int redi[KS + 1];
 
-    const int nwork = T.nb * S_PER_BLOCK;
+    const int nwork = sched_count(T, A) * S_PER_BLOCK;
     const int wg = blockIdx.x, xcd = wg & 7, slot = wg >> 3;
     const int first = xcd_first(nwork, xcd), count = xcd_count(nwork, xcd);
     if constexpr (!PERSIST) {
         const int item = first + slot;
-        const int b = T.order[item / S_PER_BLOCK], slab = item % S_PER_BLOCK;
+        const int b = sched_block(T, A, item / S_PER_BLOCK), slab = item % S_PER_BLOCK;
         {
             double u[SL::NPT][8];
             gather_issue<KS>(T, A, b, slab, u);
@@ -1200,12 +1213,251 @@ __global__ void __launch_bounds__(64 * (KS + 1), (wp_waves_per_simd<KS, R>())) k
 #pragma nounroll
         for (int it = slot; it < count; it += step) {
             const int item = first + it;
-            const int b = T.order[item / S_PER_BLOCK], slab = item % S_PER_BLOCK;
+            const int b = sched_block(T, A, item / S_PER_BLOCK), slab = item % S_PER_BLOCK;
             wp_item<KS, R, FLUX, POWELL, LEARN>(T, A, b, slab, sW, sH, sMb, red, redi);
             __syncthreads();
             __builtin_amdgcn_sched_barrier(0);
         }
     }
+}
+
+// ------------------------------------------------------------------------------------------------
+// Block form of the stage kernel: one workgroup of eight wavefronts per 8x8x8 block clear of any body,
+// wavefront k owning cell layer k (lane = (i, j)). Each wavefront computes the low-side face of each of
+// its cells in x, y and z, as the plane form does, and, in one more pass with the direction chosen per
+// lane, its layer's eight faces at x = 8 and eight at y = 8 (each evaluated in the lane whose cell it
+// bounds) plus eight of the block's 64 faces at z = 8: every wavefront does four face passes and no
+// wavefront is set aside for the high faces. Flux differences enter each cell's sums as two multiply-adds
+// (low side, then high side). LDS holds exactly the block and its face halos (80 KiB in FP64): the z
+// fluxes travel through the x/y halo space and the top halo layer once those are dead, and the
+// end-of-step reduction reuses the bottom halo layers, so two workgroups (sixteen wavefronts) share a
+// CU (the plane form on 8x8x4 slabs: ten). Blocks near a body run on the plane form in a second launch.
+
+constexpr int BLK_NT = 512;
+
+// Convert the gathered conserved values of a block and its face halos to primitives in LDS.
+template <typename R>
+__device__ __forceinline__ void gather_store_blk(const double (&u)[gather_npt<8, BLK_NT>()][8], R (*sW)[Slab<8>::NC]) {
+    const int tid = lane_tid();
+#pragma unroll
+    for (int m = 0; m < gather_npt<8, BLK_NT>(); ++m) {
+        // 1,280 cells over 512 threads: a wavefront's cells are all valid or all past the end
+        const int c = tid + m * BLK_NT;
+        if (c >= Slab<8>::NC) break;
+        double w[8];
+        cons_to_prim(u[m], w);
+#pragma unroll
+        for (int v = 0; v < 8; ++v) sW[v][c] = R(w[v]);
+    }
+}
+
+// Rotate the vector components of a state into the frame of normal direction d (normal first, then the
+// other two in cyclic order), d chosen per lane.
+template <typename R>
+__device__ __forceinline__ void rotate_in(int d, R w[8]) {
+#pragma unroll
+    for (int base = 1; base <= 4; base += 3) {
+        const R x = w[base], y = w[base + 1], z = w[base + 2];
+        w[base] = d == 0 ? x : (d == 1 ? y : z);
+        w[base + 1] = d == 0 ? y : (d == 1 ? z : x);
+        w[base + 2] = d == 0 ? z : (d == 1 ? x : y);
+    }
+}
+
+// Flux through a face whose direction d (0, 1, 2) is chosen per lane, away from any body cell: the face
+// between the cells (i, j, k) - e_d and (i, j, k), block-local. The face states are reconstructed component
+// by component (the limiter acts on each component alone) and then rotated into the face-normal frame, so
+// one x-normal evaluation serves every direction; fr is the flux in that frame, bbar the face-averaged
+// normal field.
+template <typename R, int FLUX>
+__device__ __forceinline__ void face_flux_any(R (*sW)[Slab<8>::NC], int d, int i, int j, int k, R fr[8], R &bbar) {
+    using SL = Slab<8>;
+    int c[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int o = q - 2;
+        c[q] = SL::idx(i + (d == 0 ? o : 0), j + (d == 1 ? o : 0), k + (d == 2 ? o : 0));
+    }
+    R wl[8], wr[8];
+#pragma unroll
+    for (int v = 0; v < 8; ++v) {
+        const R a = sW[v][c[0]], b = sW[v][c[1]], cc = sW[v][c[2]], dd = sW[v][c[3]];
+        const R d0 = b - a, d1 = cc - b, d2 = dd - cc;
+        wl[v] = b + mc_half(d0, d1);
+        wr[v] = cc - mc_half(d1, d2);
+    }
+    rotate_in(d, wl);
+    rotate_in(d, wr);
+    num_flux<R, 0, FLUX>(wl, wr, fr);
+    bbar = R(0.5) * (wl[4] + wr[4]);
+}
+
+// Flux of a face of direction D from the rotated frame of face_flux_any back to x, y, z.
+template <int D, typename R>
+__device__ __forceinline__ void unrotate(const R fr[8], R f[8]) {
+    f[0] = fr[0];
+    f[7] = fr[7];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        f[1 + (D + a) % 3] = fr[1 + a];
+        f[4 + (D + a) % 3] = fr[4 + a];
+    }
+}
+
+// The value of the next lane (lane + 1) within each row of 16 lanes (DPP row shift; the last lane of a row
+// receives its own value).
+__device__ __forceinline__ int dpp_next(int x) { return __builtin_amdgcn_update_dpp(x, x, 0x101, 0xf, 0xf, false); }
+__device__ __forceinline__ float lane_next(float x) { return __int_as_float(dpp_next(__float_as_int(x))); }
+__device__ __forceinline__ double lane_next(double x) {
+    const long long v = __double_as_longlong(x);
+    const int lo = dpp_next(int(v)), hi = dpp_next(int(v >> 32));
+    return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+__device__ __forceinline__ double lane_read(double x, int l) {
+    const long long v = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_readlane(int(v), l), hi = __builtin_amdgcn_readlane(int(v >> 32), l);
+    return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+__device__ __forceinline__ float lane_read(float x, int l) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), l));
+}
+
+// The four face passes, the source and the update of one block whose primitives are in LDS.
+template <typename R, int FLUX, bool POWELL>
+__device__ __forceinline__ void blk_compute(const Tables &T, const StageArgs &A, int b, R (*sW)[Slab<8>::NC]) {
+    using SL = Slab<8>;
+    const DevBlock &B = T.blocks[b];
+    const DevSim &S = T.sims[B.sim];
+    const BitMask mk{nullptr};  // no body cells in these blocks: never read
+    const int tid = lane_tid();
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int l = tid & 63, ci = l & 7, cj = l >> 3;
+    const double inv_dx = double(1 << B.level) / S.dx0;
+    double rhs[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    double divb = 0.0;
+    R f[8], bb;
+
+    // x: the low-x face of each cell; its flux enters the cell and, from the next lane, the cell below
+    face_flux<8, R, 0, FLUX, false, false>(T, A, B, b, 0, sW, mk, ci, cj, w, f, bb);
+#pragma unroll
+    for (int v = 0; v < 8; ++v) {
+        const R g = lane_next(f[v]);
+        rhs[v] = fma(double(f[v]), inv_dx, rhs[v]);
+        if (ci < 7) rhs[v] = fma(-double(g), inv_dx, rhs[v]);
+    }
+    {
+        const R g = lane_next(bb);
+        divb = fma(-double(bb), inv_dx, divb);
+        if (ci < 7) divb = fma(double(g), inv_dx, divb);
+    }
+
+    // y: the low-y face of each cell; the cell below is eight lanes on
+    face_flux<8, R, 1, FLUX, false, false>(T, A, B, b, 0, sW, mk, ci, cj, w, f, bb);
+#pragma unroll
+    for (int v = 0; v < 8; ++v) {
+        const R g = __shfl_down(f[v], 8, 64);
+        rhs[v] = fma(double(f[v]), inv_dx, rhs[v]);
+        if (cj < 7) rhs[v] = fma(-double(g), inv_dx, rhs[v]);
+    }
+    {
+        const R g = __shfl_down(bb, 8, 64);
+        divb = fma(-double(bb), inv_dx, divb);
+        if (cj < 7) divb = fma(double(g), inv_dx, divb);
+    }
+
+    // high faces: lane (7, j) takes face x = 8 of row j, lane (i, 7) face y = 8 of column i (i < 7; lane
+    // (6, 6) takes column 7 for lane (7, 7)), lanes 0-6 and 8 eight faces z = 8 (row j = w of the top face
+    // layer); the other lanes repeat face x = 8 of row 0
+    R zf[8], zb;
+    {
+        int d = 0, fi = 8, fj = 0, fk = w;
+        if (ci == 7) { fj = cj; }
+        else if (cj == 7 || l == 54) { d = 1; fi = cj == 7 ? ci : 7; fj = 8; }
+        else if (l < 7 || l == 8) { d = 2; fi = l == 8 ? 7 : l; fj = w; fk = 8; }
+        R fr[8], bf;  // the flux in the face-normal frame
+        face_flux_any<R, FLUX>(sW, d, fi, fj, fk, fr, bf);
+        // the y = 8 face of column 7 moves from lane 54 to lane 63
+        R yr[8], yb;
+#pragma unroll
+        for (int v = 0; v < 8; ++v) yr[v] = lane_read(fr[v], 54);
+        yb = lane_read(bf, 54);
+        if (ci == 7) {
+            R fx[8];
+            unrotate<0>(fr, fx);
+#pragma unroll
+            for (int v = 0; v < 8; ++v) rhs[v] = fma(-double(fx[v]), inv_dx, rhs[v]);
+            divb = fma(double(bf), inv_dx, divb);
+            if (B.flags & BF_FC) record_fc<0>(T, B, 8, cj, w, fx);
+        }
+        if (cj == 7) {
+            R fy[8];
+            if (ci == 7) unrotate<1>(yr, fy);
+            else unrotate<1>(fr, fy);
+            const R by = ci == 7 ? yb : bf;
+#pragma unroll
+            for (int v = 0; v < 8; ++v) rhs[v] = fma(-double(fy[v]), inv_dx, rhs[v]);
+            divb = fma(double(by), inv_dx, divb);
+            if (B.flags & BF_FC) record_fc<1>(T, B, ci, 8, w, fy);
+        }
+        if (l < 7 || l == 8) {
+            unrotate<2>(fr, zf);
+            zb = bf;
+            if (B.flags & BF_FC) record_fc<2>(T, B, fi, w, 8, zf);
+        }
+    }
+    // past this barrier the x/y halos and the top halo layer (z = 9) are dead: the z fluxes of face layers
+    // 1-8 go to the x/y halo space of each variable (64 per layer), their normal field to the top layer
+    __syncthreads();
+    R *zbar = &sW[0][0] + SL::ZHI + 64;  // [face layer - 1] strided by NC, 64 lanes each
+    if (l < 7 || l == 8) {
+        const int q = 7 * 64 + w * 8 + (l == 8 ? 7 : l);
+#pragma unroll
+        for (int v = 0; v < 8; ++v) sW[v][SL::XH + q] = zf[v];
+        zbar[7 * SL::NC + w * 8 + (l == 8 ? 7 : l)] = zb;
+    }
+    face_flux<8, R, 2, FLUX, false, false>(T, A, B, b, 0, sW, mk, ci, cj, w, f, bb);
+#pragma unroll
+    for (int v = 0; v < 8; ++v) rhs[v] = fma(double(f[v]), inv_dx, rhs[v]);
+    divb = fma(-double(bb), inv_dx, divb);
+    if (w > 0) {
+#pragma unroll
+        for (int v = 0; v < 8; ++v) sW[v][SL::XH + (w - 1) * 64 + l] = f[v];
+        zbar[(w - 1) * SL::NC + l] = bb;
+    }
+    __syncthreads();
+    double uin[8];
+    {
+#pragma unroll
+        for (int v = 0; v < 8; ++v) rhs[v] = fma(-double(sW[v][SL::XH + w * 64 + l]), inv_dx, rhs[v]);
+        divb = fma(double(zbar[w * SL::NC + l]), inv_dx, divb);
+        const size_t vs = size_t(T.nb) * 512, off = size_t(b) * 512 + tid;
+#pragma unroll
+        for (int v = 0; v < 8; ++v) uin[v] = A.Uin[v * vs + off];
+    }
+    // the bottom halo layers are dead here: the end-of-step reduction uses them
+    double *red = reinterpret_cast<double *>(&sW[0][SL::ZLO]);
+    int *redi = reinterpret_cast<int *>(&sW[1][SL::ZLO]);
+    cell_update<8, R, POWELL, false, BitMask, BLK_NT>(T, A, b, 0, uin, sW, mk, rhs, divb, inv_dx, red, redi);
+}
+
+template <typename R>
+constexpr int blk_waves_per_simd() { return sizeof(R) == 8 ? 4 : 4; }
+
+template <typename R, int FLUX, bool POWELL>
+__global__ void __launch_bounds__(BLK_NT, (blk_waves_per_simd<R>())) k_stage_blk(Tables T, StageArgs A) {
+    using SL = Slab<8>;
+    static_assert(SL::NC - SL::XH >= 8 * 64, "z-flux exchange space");
+    static_assert(sizeof(R) * 2 * 64 >= sizeof(double) * 8 + sizeof(int) * 8, "reduction space");
+    __shared__ R sW[8][SL::NC];
+    const int wg = blockIdx.x, xcd = wg & 7, slot = wg >> 3;
+    const int b = sched_block(T, A, xcd_first(sched_count(T, A), xcd) + slot);
+    {
+        double u[gather_npt<8, BLK_NT>()][8];
+        gather_issue<8, BLK_NT>(T, A, b, 0, u);
+        gather_store_blk<R>(u, sW);
+    }
+    __syncthreads();
+    blk_compute<R, FLUX, POWELL>(T, A, b, sW);
 }
 
 // Per-face training data of a whole block (one workgroup of 576 threads = one face per thread and
@@ -1509,6 +1761,10 @@ int32_t hip_check(hipError_t e, const char *what) {
 
 int32_t launch_check(const char *what) { return hip_check(hipGetLastError(), what); }
 
+int32_t record_event(void *ev, hipStream_t s) {
+    return ev ? hip_check(hipEventRecord(reinterpret_cast<hipEvent_t>(ev), s), "event") : BMHD_OK;
+}
+
 bool ptr_ok(const void *p) { return p && (reinterpret_cast<uintptr_t>(p) & 7u) == 0; }
 
 // Launch shape of the stage kernel: work split (face per thread or wave per cell layer), tile depth (4
@@ -1520,7 +1776,8 @@ struct Shape {
 };
 
 template <int KS, typename R, int FLUX, bool POWELL>
-int32_t launch_stage_shape(const HostGrid &h, const StageArgs &a, int scheme, int persist_wgs, hipStream_t s) {
+int32_t launch_stage_shape(const HostGrid &h, const StageArgs &a, int scheme, int persist_wgs, void *ev0, void *ev1,
+                           hipStream_t s) {
     constexpr int nt = Slab<KS>::NT;
     const int items = h.nb * (8 / KS);
     int grid = items;
@@ -1528,6 +1785,22 @@ int32_t launch_stage_shape(const HostGrid &h, const StageArgs &a, int scheme, in
         grid = persist_wgs < items ? persist_wgs : items;
         grid = (grid + 7) & ~7;
     }
+    if (scheme == BMHD_SCHEME_BLOCK) {
+        // blocks clear of any body on the block form, then the blocks near a body on the plane form
+        const int nc = h.n_clear, nn = h.nb - h.n_clear;
+        StageArgs ac = a, an = a;
+        ac.sched = h.dev.order_split;
+        ac.n_sched = nc;
+        an.sched = h.dev.order_split + nc;
+        an.n_sched = nn;
+        // the events bracket the block form alone, the dominant kernel
+        if (nn) k_stage_wp<4, R, FLUX, POWELL, false><<<nn * 2, Slab<4>::NT, 0, s>>>(h.dev, an);
+        if (int32_t rc = record_event(ev0, s)) return rc;
+        if (nc) k_stage_blk<R, FLUX, POWELL><<<nc, BLK_NT, 0, s>>>(h.dev, ac);
+        if (int32_t rc = record_event(ev1, s)) return rc;
+        return launch_check("stage kernel");
+    }
+    if (int32_t rc = record_event(ev0, s)) return rc;
     if (scheme == BMHD_SCHEME_PLANE) {
         if (persist_wgs > 0) k_stage_wp<KS, R, FLUX, POWELL, true><<<grid, nt, 0, s>>>(h.dev, a);
         else k_stage_wp<KS, R, FLUX, POWELL, false><<<grid, nt, 0, s>>>(h.dev, a);
@@ -1535,40 +1808,47 @@ int32_t launch_stage_shape(const HostGrid &h, const StageArgs &a, int scheme, in
         if (persist_wgs > 0) k_stage<KS, R, FLUX, POWELL, true><<<grid, nt, 0, s>>>(h.dev, a);
         else k_stage<KS, R, FLUX, POWELL, false><<<grid, nt, 0, s>>>(h.dev, a);
     }
+    if (int32_t rc = record_event(ev1, s)) return rc;
     return launch_check("stage kernel");
 }
 
 template <int KS, typename R>
-int32_t launch_stage_prec(const HostGrid &h, const StageArgs &a, int flux, bool powell, const Shape &sh,
-                          hipStream_t s) {
+int32_t launch_stage_prec(const HostGrid &h, const StageArgs &a, int flux, bool powell, const Shape &sh, void *ev0,
+                          void *ev1, hipStream_t s) {
     const int sc = sh.scheme, pw = sh.persist_wgs;
     if (flux == BMHD_FLUX_RUSANOV) {
-        if (powell) return launch_stage_shape<KS, R, BMHD_FLUX_RUSANOV, true>(h, a, sc, pw, s);
-        return launch_stage_shape<KS, R, BMHD_FLUX_RUSANOV, false>(h, a, sc, pw, s);
+        if (powell) return launch_stage_shape<KS, R, BMHD_FLUX_RUSANOV, true>(h, a, sc, pw, ev0, ev1, s);
+        return launch_stage_shape<KS, R, BMHD_FLUX_RUSANOV, false>(h, a, sc, pw, ev0, ev1, s);
     }
-    if (powell) return launch_stage_shape<KS, R, BMHD_FLUX_HLLE, true>(h, a, sc, pw, s);
-    return launch_stage_shape<KS, R, BMHD_FLUX_HLLE, false>(h, a, sc, pw, s);
+    if (powell) return launch_stage_shape<KS, R, BMHD_FLUX_HLLE, true>(h, a, sc, pw, ev0, ev1, s);
+    return launch_stage_shape<KS, R, BMHD_FLUX_HLLE, false>(h, a, sc, pw, ev0, ev1, s);
 }
 
 Shape pick_shape(const bmhd_opts &o) {
     Shape sh;
-    // measured on the 256^3 magnetosphere: the wave-per-layer scheme on 8x8x4 slabs in both precisions
-    // (FP64: 1.79 / 2.11 ms per stage against 1.91 / 2.16 for the face scheme on full blocks; FP32 flux:
-    // 1.03 / 1.24 against 1.12 / 1.35 on 8x8x4 slabs). With the face scheme, full blocks for FP64.
-    sh.scheme = o.scheme == 0 ? BMHD_SCHEME_PLANE : o.scheme;
-    sh.ks = o.slab == 0 ? ((o.precision == BMHD_FP64 && sh.scheme == BMHD_SCHEME_FACE) ? 8 : 4) : o.slab;
+    // measured on the 256^3 magnetosphere: the block form in both precisions (FP64: 1.25 / 1.40 ms per
+    // stage against 1.74 / 2.07 for the plane form on 8x8x4 slabs and 1.91 / 2.16 for the face form on
+    // full blocks; FP32 flux: 0.94 / 1.14 against 1.04 / 1.26). A persistent grid or a tile of four
+    // layers asks for the plane form. With the face form, full blocks for FP64.
+    if (o.scheme == 0) sh.scheme = (o.persist_wgs > 0 || o.slab == 4) ? BMHD_SCHEME_PLANE : BMHD_SCHEME_BLOCK;
+    else sh.scheme = o.scheme;
+    sh.ks = o.slab == 0 ? ((o.precision == BMHD_FP64 && sh.scheme == BMHD_SCHEME_FACE) || sh.scheme == BMHD_SCHEME_BLOCK
+                               ? 8 : 4)
+                        : o.slab;
     sh.persist_wgs = o.persist_wgs;
     return sh;
 }
 
-int32_t launch_stage(const HostGrid &h, const StageArgs &a, const bmhd_opts &o, hipStream_t s) {
+// The stage kernel of the chosen shape; ev0 / ev1 (hipEvent_t, may be null) are recorded right before and
+// after the dominant kernel.
+int32_t launch_stage(const HostGrid &h, const StageArgs &a, const bmhd_opts &o, void *ev0, void *ev1, hipStream_t s) {
     const Shape sh = pick_shape(o);
     if (o.precision == BMHD_FP64) {
-        if (sh.ks == 4) return launch_stage_prec<4, double>(h, a, o.flux, o.powell, sh, s);
-        return launch_stage_prec<8, double>(h, a, o.flux, o.powell, sh, s);
+        if (sh.ks == 4) return launch_stage_prec<4, double>(h, a, o.flux, o.powell, sh, ev0, ev1, s);
+        return launch_stage_prec<8, double>(h, a, o.flux, o.powell, sh, ev0, ev1, s);
     }
-    if (sh.ks == 4) return launch_stage_prec<4, float>(h, a, o.flux, o.powell, sh, s);
-    return launch_stage_prec<8, float>(h, a, o.flux, o.powell, sh, s);
+    if (sh.ks == 4) return launch_stage_prec<4, float>(h, a, o.flux, o.powell, sh, ev0, ev1, s);
+    return launch_stage_prec<8, float>(h, a, o.flux, o.powell, sh, ev0, ev1, s);
 }
 
 template <typename R, int FLUX>
@@ -1592,8 +1872,10 @@ int32_t check_opts(const bmhd_opts &o) {
     if (o.flux != BMHD_FLUX_RUSANOV && o.flux != BMHD_FLUX_HLLE) return fail(BMHD_EINVAL, "unknown flux");
     if (o.precision != BMHD_FP64 && o.precision != BMHD_FP32_FLUX) return fail(BMHD_EINVAL, "unknown precision");
     if (o.slab != 0 && o.slab != 4 && o.slab != 8) return fail(BMHD_EINVAL, "slab must be 0, 4 or 8");
-    if (o.scheme != 0 && o.scheme != BMHD_SCHEME_FACE && o.scheme != BMHD_SCHEME_PLANE)
+    if (o.scheme != 0 && o.scheme != BMHD_SCHEME_FACE && o.scheme != BMHD_SCHEME_PLANE && o.scheme != BMHD_SCHEME_BLOCK)
         return fail(BMHD_EINVAL, "unknown scheme");
+    if (o.scheme == BMHD_SCHEME_BLOCK && (o.slab == 4 || o.persist_wgs != 0))
+        return fail(BMHD_EUNSUPPORTED, "the block scheme takes whole blocks, one workgroup each");
     if (o.persist_wgs < 0 || o.persist_wgs > (1 << 20)) return fail(BMHD_EINVAL, "persist_wgs out of range");
     if (o.recompute_dt && !(o.cfl > 0.0)) return fail(BMHD_EINVAL, "cfl must be positive");
     if (o.learned) {
@@ -1669,11 +1951,7 @@ int32_t enqueue_stage(const HostGrid &h, const bmhd_opts &o, int e, double *d_U0
         k_learn_fixup<<<h.nb, 512, 0, s>>>(h.dev, a, L.fallback_cells);
         return launch_check("learned fallback");
     }
-    if (ev0)
-        if (int32_t rc = hip_check(hipEventRecord(reinterpret_cast<hipEvent_t>(ev0), s), "event")) return rc;
-    if (int32_t rc = launch_stage(h, a, o, s)) return rc;
-    if (ev1)
-        if (int32_t rc = hip_check(hipEventRecord(reinterpret_cast<hipEvent_t>(ev1), s), "event")) return rc;
+    if (int32_t rc = launch_stage(h, a, o, ev0, ev1, s)) return rc;
     if (!h.fc_cells.empty()) {
         k_flux_correct<<<unsigned((h.fc_cells.size() + 255) / 256), 256, 0, s>>>(h.dev, a);
         if (int32_t rc = launch_check("flux correction")) return rc;
@@ -1873,6 +2151,7 @@ int32_t bmhd_grid_upload(bmhd_grid *g, void *d_work, size_t work_bytes, void *st
     t.sims = reinterpret_cast<const DevSim *>(base + h.off_sims);
     t.lut = reinterpret_cast<const int32_t *>(base + h.off_lut);
     t.order = reinterpret_cast<const int32_t *>(base + h.off_order);
+    t.order_split = reinterpret_cast<const int32_t *>(base + h.off_order_split);
     t.halo_items = reinterpret_cast<const int32_t *>(base + h.off_halo_items);
     t.fc_cells = reinterpret_cast<const DevFcCell *>(base + h.off_fc_cells);
     t.lam = reinterpret_cast<unsigned long long *>(base + h.off_lam);
@@ -1882,6 +2161,7 @@ int32_t bmhd_grid_upload(bmhd_grid *g, void *d_work, size_t work_bytes, void *st
     t.ns = h.ns;
     t.n_halo_items = int32_t(h.halo_items.size());
     t.n_fc_cells = int32_t(h.fc_cells.size());
+    t.n_clear = h.n_clear;
     return BMHD_OK;
 }
 
@@ -2018,7 +2298,7 @@ int32_t bmhd_autotune(const bmhd_grid *g, double *d_U0, double *d_U1, double *d_
             best->slab = sl;
             best->persist_wgs = pp * cus;
             if (h_ms)
-                for (int c = 0; c < 12; ++c) h_ms[c] = -1.0f;
+                for (int c = 0; c < BMHD_AUTOTUNE_SHAPES; ++c) h_ms[c] = -1.0f;
             return BMHD_OK;
         }
     }
@@ -2029,11 +2309,17 @@ int32_t bmhd_autotune(const bmhd_grid *g, double *d_U0, double *d_U1, double *d_
     float best_ms = 1e30f;
     int32_t rc = BMHD_OK;
     *best = *base;
-    for (int c = 0; c < 12 && rc == BMHD_OK; ++c) {
+    for (int c = 0; c < BMHD_AUTOTUNE_SHAPES && rc == BMHD_OK; ++c) {
         bmhd_opts o = *base;
-        o.scheme = c < 6 ? BMHD_SCHEME_FACE : BMHD_SCHEME_PLANE;
-        o.slab = shapes[c % 6][0];
-        o.persist_wgs = shapes[c % 6][1] * cus;
+        if (c < 12) {
+            o.scheme = c < 6 ? BMHD_SCHEME_FACE : BMHD_SCHEME_PLANE;
+            o.slab = shapes[c % 6][0];
+            o.persist_wgs = shapes[c % 6][1] * cus;
+        } else {  // the block form: whole blocks, one workgroup each
+            o.scheme = BMHD_SCHEME_BLOCK;
+            o.slab = 8;
+            o.persist_wgs = 0;
+        }
         o.events = nullptr;
         o.n_events = 0;
         rc = bmhd_advance(g, d_U0, d_U1, d_dt, 2, &o, nullptr, stream);  // warm-up

@@ -141,7 +141,7 @@ STAGE_CASES = {
 }
 
 
-@pytest.mark.parametrize("scheme", ["face", "plane"])
+@pytest.mark.parametrize("scheme", ["face", "plane", "block"])
 @pytest.mark.parametrize("case", list(STAGE_CASES))
 @pytest.mark.parametrize("n_stages", [1, 2, 6])
 def test_advance_parity(bd, oracle_mod, case, n_stages, scheme):
@@ -190,6 +190,34 @@ def test_plane_scheme_matches_face_scheme(bd, precision, slab):
     assert a[3] == 0 and b[3] == 0
     assert max(err.values()) <= (1e-13 if precision == "fp64" else 1e-5), err
     assert np.all(np.abs(a[2] - b[2]) <= 1e-14 * b[2])
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_flux"])
+@pytest.mark.parametrize("case", ["two_level_48", "magnetosphere_32", "periodic_1"])
+def test_block_scheme_matches_plane_scheme(bd, precision, case):
+    """The block form (blocks clear of a body; the others on the plane form) evaluates the same face
+    fluxes as the plane form; the cell sums take each flux as its own multiply-add, so the two differ in
+    the last places only."""
+    make, kw = STAGE_CASES[case]
+    wl = make()
+    kw = dict(kw, precision=precision)
+    a = gpu_run(bd, wl, wl.W, 4, scheme="block", **kw)
+    b = gpu_run(bd, wl, wl.W, 4, scheme="plane", slab=4, **kw)
+    err = group_err(a[0], b[0])
+    say("block vs plane", case, precision, err)
+    assert a[3] == 0 and b[3] == 0
+    assert max(err.values()) <= (1e-13 if precision == "fp64" else 1e-5), err
+    assert np.all(np.abs(a[2] - b[2]) <= 1e-14 * b[2])
+
+
+def test_block_scheme_is_deterministic_and_graph_replays_match(bd):
+    wl = wk.two_level_magnetosphere(48)
+    kw = dict(flux="hlle", powell=True, scheme="block")
+    a = gpu_run(bd, wl, wl.W, 6, **kw)
+    b = gpu_run(bd, wl, wl.W, 6, **kw)
+    c = gpu_run(bd, wl, wl.W, 6, use_graph=True, **kw)
+    for x in (b, c):
+        assert np.array_equal(a[0], x[0]) and np.array_equal(a[1], x[1]) and np.array_equal(a[2], x[2])
 
 
 def test_cp_alfven_ten_steps(bd, oracle_mod):
@@ -310,8 +338,8 @@ def test_autotune_picks_a_valid_shape(bd):
     dt = torch.zeros(len(wl.sims), dtype=torch.float64, device="cuda")
     best, ms = g.autotune(U0, U1, dt, n_steps=2, flux="rusanov", precision="fp32_flux")
     say("autotune", ms, best.scheme, best.slab, best.persist_wgs)
-    assert len(ms) == 12 and all(v > 0 for v in ms.values())
-    assert best.scheme in (1, 2) and best.slab in (4, 8) and best.persist_wgs >= 0
+    assert len(ms) == 13 and all(v > 0 for v in ms.values())
+    assert best.scheme in (1, 2, 3) and best.slab in (4, 8) and best.persist_wgs >= 0
     assert all(v > 0 for v in ms.values())
     assert min(ms.values()) == pytest.approx(ms[min(ms, key=ms.get)])
 
