@@ -870,14 +870,17 @@ __device__ __forceinline__ void cell_update(const Tables &T, const StageArgs &A,
             if (A.use_u0) {
                 const double a0 = A.alpha, a1 = 1.0 - A.alpha;
 #pragma unroll
-                for (int v = 0; v < 8; ++v) out[v] = a0 * A.U0[v * vs + off] + a1 * uin[v] + bdt * rhs[v];
+                for (int v = 0; v < 8; ++v)
+                    out[v] = a0 * __builtin_nontemporal_load(A.U0 + v * vs + off) + a1 * uin[v] + bdt * rhs[v];
             } else {
 #pragma unroll
                 for (int v = 0; v < 8; ++v) out[v] = uin[v] + bdt * rhs[v];
             }
         }
 #pragma unroll
-        for (int v = 0; v < 8; ++v) A.Uout[v * vs + off] = out[v];
+        // the stage result and U^n are streamed (stored / read once per stage): non-temporal, so that they
+        // do not push the neighbours' halo cells out of L2
+        for (int v = 0; v < 8; ++v) __builtin_nontemporal_store(out[v], A.Uout + v * vs + off);
         if constexpr (LEARN) {
             // reject the provisional state if it is not positive or leaves the widened range of the old
             // 7-point neighbourhood in density or pressure
@@ -1339,16 +1342,18 @@ __device__ __forceinline__ void blk_compute(const Tables &T, const StageArgs &A,
 
     // x: the low-x face of each cell; its flux enters the cell and, from the next lane, the cell below
     face_flux<8, R, 0, FLUX, false, false>(T, A, B, b, 0, sW, mk, ci, cj, w, f, bb);
+    // the next lane's flux enters with weight inv_dx, or 0 in the last column (its high face comes later)
+    const double wx = ci < 7 ? inv_dx : 0.0, wy = cj < 7 ? inv_dx : 0.0;
 #pragma unroll
     for (int v = 0; v < 8; ++v) {
         const R g = lane_next(f[v]);
         rhs[v] = fma(double(f[v]), inv_dx, rhs[v]);
-        if (ci < 7) rhs[v] = fma(-double(g), inv_dx, rhs[v]);
+        rhs[v] = fma(-double(g), wx, rhs[v]);
     }
     {
         const R g = lane_next(bb);
         divb = fma(-double(bb), inv_dx, divb);
-        if (ci < 7) divb = fma(double(g), inv_dx, divb);
+        divb = fma(double(g), wx, divb);
     }
 
     // y: the low-y face of each cell; the cell below is eight lanes on
@@ -1357,12 +1362,12 @@ __device__ __forceinline__ void blk_compute(const Tables &T, const StageArgs &A,
     for (int v = 0; v < 8; ++v) {
         const R g = __shfl_down(f[v], 8, 64);
         rhs[v] = fma(double(f[v]), inv_dx, rhs[v]);
-        if (cj < 7) rhs[v] = fma(-double(g), inv_dx, rhs[v]);
+        rhs[v] = fma(-double(g), wy, rhs[v]);
     }
     {
         const R g = __shfl_down(bb, 8, 64);
         divb = fma(-double(bb), inv_dx, divb);
-        if (cj < 7) divb = fma(double(g), inv_dx, divb);
+        divb = fma(double(g), wy, divb);
     }
 
     // high faces: lane (7, j) takes face x = 8 of row j, lane (i, 7) face y = 8 of column i (i < 7; lane
