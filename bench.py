@@ -79,9 +79,11 @@ def parse():
                    help="also run a plain 256 MiB device copy (scales the HBM byte counters of a profiler run)")
     p.add_argument("--precision", default="fp64", choices=["fp64", "fp32_flux"],
                    help="precision of the timed magnetosphere run (the metric is quoted for fp64)")
-    p.add_argument("--form", default="plain", choices=["plain", "batched", "learned"],
+    p.add_argument("--form", default="plain", choices=["plain", "batched", "learned", "two_level", "exchange"],
                    help="with --profile: run only this form (batched: the 64-simulation batch, graph-replayed; "
-                        "learned: the learned correction on the 128^3 grid)")
+                        "learned: the learned correction on the 128^3 grid; two_level: the two-level "
+                        "magnetosphere, FP64 and FP32 flux)")
+    p.add_argument("--two-level-steps", type=int, default=200, help="steps of the two-level form")
     return p.parse_args()
 
 
@@ -250,6 +252,100 @@ def bench_paper_fast_wave():
             "ratio_to_paper": cells * steps / t / (960000 * 500 / 5.76)}
 
 
+def bench_two_level(steps):
+    """The two-level magnetosphere (level-1 shell 3-10 body radii around the dipole: 7,456 blocks,
+    3,817,472 cells, 264 coarse-fine block faces), HLLE + Powell, FP64 and FP32 flux with FP64 update, each
+    from the initial state over `steps` steps; the FP32-flux result against the FP64 one. The stage
+    includes the level-change ghost fill (restriction, prolongation) and the flux correction."""
+    import torch
+    from paper_2501_06717_amd import binding, workloads as wk
+    wl = wk.two_level_magnetosphere(144)
+    g = binding.Grid.from_workload(wl).upload()
+    W = torch.from_numpy(wl.W).cuda()
+    out = {"workload": f"two-level magnetosphere: {wl.n_blocks} blocks, {wl.n_cells} cells, "
+                       f"{int(g.info.n_level_faces)} level-change block faces, HLLE + Powell, CFL 0.8",
+           "steps": steps}
+    res = {}
+    for precision in ("fp64", "fp32_flux"):
+        U0 = g.set_state(W)
+        U1 = torch.empty_like(U0)
+        dt = torch.zeros(1, dtype=torch.float64, device="cuda")
+        faults = torch.zeros(1, dtype=torch.int32, device="cuda")
+        g.advance(U0, U1, dt, 2, flux="hlle", powell=True, cfl=0.8, precision=precision)  # warm-up
+        U0 = g.set_state(W)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        g.advance(U0, U1, dt, 2 * steps, faults=faults, flux="hlle", powell=True, cfl=0.8, precision=precision)
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+        res[precision] = U0.cpu().numpy()
+        out[precision] = {"value": wl.n_cells * steps / t, "unit": "cell-updates/s", "wall_s": t,
+                          "faults": int(faults.item())}
+        del U0, U1
+        log(f"two-level {precision}: {wl.n_cells * steps / t:.3e} cell-updates/s over {steps} steps")
+    ref, got = res["fp64"], res["fp32_flux"]
+    out["fp32_flux"]["l1_rel_vs_fp64"] = float(np.abs(got - ref).sum() / np.abs(ref).sum())
+    out["fp32_flux"]["linf_rel_vs_fp64"] = {k: float(np.abs(got[v] - ref[v]).max() / np.abs(ref[v]).max())
+                                            for k, v in (("rho", [0]), ("mom", [1, 2, 3]), ("B", [4, 5, 6]),
+                                                         ("e", [7]))}
+    del g, W, res
+    torch.cuda.synchronize()
+    return out
+
+
+def bench_exchange(reps=20):
+    """The ghost exchange between processes (Algorithm 4) at one process's share of the 256^3
+    magnetosphere split into 2 x 2 x 2 processes of 128^3 cells (4,096 blocks each): the pack kernel of
+    process 0 (its messages to the 7 other processes: 3 faces, 3 edges, 1 corner of sub-cubes), the unpack
+    of the messages it receives (plus its local messages and boundary ghosts), with the transfers as device
+    copies between them. Per call: HIP events around each kernel launch, mean over `reps`."""
+    import torch
+    from paper_2501_06717_amd import binding, workloads as wk
+    wl = wk.magnetosphere(256)
+    ijk = np.asarray(wl.ijk).reshape(-1, 3)
+    rank = ((ijk[:, 0] // 16) + 2 * (ijk[:, 1] // 16) + 4 * (ijk[:, 2] // 16)).astype(np.int32)
+    g = binding.Grid.from_workload(wl).upload()
+    x = binding.Xchg(g, rank, 8).upload()
+    U = g.set_state(torch.from_numpy(wl.W).cuda())
+    views = [x.new_view(r) for r in range(8)]
+    for r in range(8):
+        x.interior(r, U, views[r])
+    sends = [torch.empty(x.send_len(1, s), dtype=torch.float64, device="cuda") for s in range(8)]
+    recvs = [torch.empty(x.recv_len(1, r), dtype=torch.float64, device="cuda") for r in range(8)]
+    for s in range(8):
+        x.pack(1, s, views[s], sends[s])
+    x.transfer(1, sends, recvs)
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    tp = tu = 0.0
+    for _ in range(reps):
+        ev[0].record()
+        x.pack(1, 0, views[0], sends[0])
+        ev[1].record()
+        ev[2].record()
+        x.unpack(1, 0, recvs[0], views[0])
+        ev[3].record()
+        torch.cuda.synchronize()
+        tp += ev[0].elapsed_time(ev[1]) * 1e-3 / reps
+        tu += ev[2].elapsed_time(ev[3]) * 1e-3 / reps
+    msgs = x.messages()
+    m0 = msgs[(msgs[:, 0] == 0) & (msgs[:, 1] != 0)]
+    r0 = msgs[(msgs[:, 1] == 0) & (msgs[:, 0] != 0)]
+    sent, recv = 8 * x.send_len(1, 0), 8 * x.recv_len(1, 0)
+    out = {"workload": "256^3 magnetosphere as 2 x 2 x 2 processes of 128^3 cells (4,096 blocks each); "
+                       "process 0's pass 1 (copies)",
+           "messages_sent": int(len(m0)), "messages_received": int(len(r0)),
+           "bytes_sent": sent, "bytes_received": recv,
+           "pack_us": tp * 1e6, "unpack_us": tu * 1e6,
+           "pack_GBs": sent / tp / 1e9, "unpack_GBs": recv / tu / 1e9,
+           "note": "unpack also copies process 0's local messages (every ghost face inside its sub-cube) and "
+                   "fills its outflow/inflow ghost cells"}
+    log(f"exchange: pack {tp * 1e6:.1f} us ({sent / 1e6:.1f} MB), unpack {tu * 1e6:.1f} us ({recv / 1e6:.1f} MB)")
+    del views, sends, recvs, U, x, g
+    torch.cuda.synchronize()
+    return out
+
+
 def accuracy_vs_oracle(binding, wl, R, steps):
     """L1 and per-group L-infinity error of the FP64 path and of the FP32-flux form against the oracle's
     result R after the same steps from the same state (the workload the benchmark times, full size)."""
@@ -287,7 +383,9 @@ def main():
 
     torch.cuda.set_device(0)
     if a.profile and a.form != "plain":
-        log(json.dumps(bench_batched(a.steps) if a.form == "batched" else bench_learned(a.steps)))
+        fn = {"batched": bench_batched, "learned": bench_learned, "two_level": bench_two_level,
+              "exchange": bench_exchange}[a.form]
+        log(json.dumps(fn(a.steps)))
         return
     wl = wk.magnetosphere(a.n, n_steps=a.steps)
     log(f"workload {wl.name}: {wl.n_blocks} blocks, {wl.n_cells} cells")
@@ -378,6 +476,8 @@ def main():
     if not (a.no_forms or a.profile) and fp64:
         del g, W
         out.setdefault("forms", {})
+        out["forms"]["two_level"] = bench_two_level(a.two_level_steps)
+        out["forms"]["exchange"] = bench_exchange()
         out["forms"]["batched"] = bench_batched(a.form_steps)
         out["forms"]["learned"] = bench_learned(a.form_steps)
         out["paper_context"] = {"fast_wave": bench_paper_fast_wave()}
@@ -398,6 +498,16 @@ def main():
         log(f"cpu oracle: {tc:.1f} s for {a.cpu_steps} step(s)")
         out["accuracy_vs_oracle"] = accuracy_vs_oracle(binding, wl, U0, a.cpu_steps)
         log(f"accuracy vs oracle: {json.dumps(out['accuracy_vs_oracle'])}")
+        if "two_level" in out.get("forms", {}):
+            # the two-level form after one step against the oracle doing the same step
+            tl = wk.two_level_magnetosphere(144)
+            ot = oracle.Grid.from_workload(tl)
+            R0 = ot.set_state(tl.W)
+            R1 = np.zeros_like(R0)
+            ot.advance(R0, R1, [0.0], 2, flux="hlle", powell=True, cfl=0.8)
+            out["forms"]["two_level"]["accuracy_vs_oracle"] = accuracy_vs_oracle(binding, tl, R0, 1)
+            del R0, R1
+            log("two-level accuracy vs oracle: " + json.dumps(out["forms"]["two_level"]["accuracy_vs_oracle"]))
         # one thread on a 64^3 cut of the same workload (the per-cell work is the same), for the GPU's
         # equivalent in host cores
         import ctypes

@@ -246,6 +246,67 @@ int32_t bmhd_autotune(const bmhd_grid *g, double *d_U0, double *d_U1, double *d_
                       int32_t n_steps, bmhd_opts *best, float *h_ms, void *stream);
 
 /* ---------------------------------------------------------------------------------------------
+ * Ghost-cell exchange between processes: the message passing of Sec. 4.2-4.4 (Algorithm 4; message types
+ * of Sec. 4.2: copy from an equal-level neighbour, restriction computed by the finer sender, prolongation
+ * computed by the coarser sender), at one GPU's shapes. Blocks are assigned to processes (rank[b]); process
+ * r keeps its blocks, in ascending global id (the local index), in a padded view
+ * d_view[8][n_local(r)][12][12][12] of conserved values with two ghost layers, like bmhd_fill_ghosts'
+ * view. Messages to other processes go through one buffer per (sender, receiver) pair and pass: each
+ * message is a header of n_C = 7 doubles (receiving block's local index, low corner i, j, k, high corner
+ * i, j, k of its receive box, inclusive, in the receiver's padded coordinates -2..9) followed by the box's
+ * cells, 8 values each (v fastest, then i, j, k). Its start offset is the previous message's start plus
+ * n_C plus the previous message's 8 * cells; the messages of one buffer follow the counting order
+ * (sending process's blocks in local order, each block's 26 directions with x fastest). Pass 1 carries
+ * copies and restrictions, pass 2 the prolongations (computed from the coarse sender's ghost cells after
+ * pass 1). Messages within one process are written straight into its view. Ghost cells outside the
+ * domain are filled by their own process (level-0 blocks after pass 1, level-1 blocks after pass 2).
+ * After both passes every process's view equals the matching blocks of bmhd_fill_ghosts' view bit for
+ * bit. The sequence per pass: bmhd_xchg_pack for every process, the transfers (any device copy, or a
+ * point-to-point transfer between GPUs), bmhd_xchg_unpack for every process. */
+typedef struct bmhd_xchg bmhd_xchg;
+
+/* Count the message maps of an assignment rank[n_blocks] (host, values in [0, n_ranks)) on the host
+ * (the paper rebuilds them only when the grid changes, Sec. 4.4): which messages each process sends and
+ * receives in each pass and their start offsets. The grid must outlive the handle. Errors: BMHD_EINVAL. */
+int32_t bmhd_xchg_create(const bmhd_grid *g, const int32_t *rank, int32_t n_ranks, bmhd_xchg **out);
+void bmhd_xchg_destroy(bmhd_xchg *x);
+
+/* h_nloc[n_ranks] (may be NULL): blocks per process. h_len[2][n_ranks][n_ranks] (may be NULL): doubles in
+ * the buffer from process s to process r in pass p + 1 (0 for s == r); a sender's send buffer holds its
+ * buffers to the receivers one after another in receiver order, a receiver's receive buffer the buffers
+ * from the senders in sender order. *work_bytes (may be NULL): the device workspace bmhd_xchg_upload
+ * needs. */
+int32_t bmhd_xchg_sizes(const bmhd_xchg *x, int32_t *h_nloc, int64_t *h_len, size_t *work_bytes);
+
+/* The message list in counting order, one row of 16 int64 per message: sending process, receiving
+ * process, pass, index among the messages of that (sender, receiver, pass), start offset, sending block,
+ * direction slot (direction * 4 + finer sub-block), receiving block, its local index, type (0 copy, 1
+ * restriction, 2 prolongation), box low corner (3), box high corner (3). With h_out NULL returns the
+ * number of rows; otherwise fills up to max_rows rows and returns their number (BMHD_ENOMEM when too
+ * small). Host only. */
+int64_t bmhd_xchg_messages(const bmhd_xchg *x, int64_t *h_out, int64_t max_rows);
+
+/* Copy the maps into the caller's device workspace (256-byte aligned, work_bytes from bmhd_xchg_sizes);
+ * it must stay allocated while the handle is used. Waits for the copy. The grid must be uploaded before
+ * the calls below. */
+int32_t bmhd_xchg_upload(bmhd_xchg *x, void *d_work, size_t work_bytes, void *stream);
+
+/* Process r's view with its blocks' interior cells from the global state d_U[8][n_blocks][512]. */
+int32_t bmhd_xchg_interior(const bmhd_xchg *x, int32_t r, const double *d_U, double *d_view, void *stream);
+
+/* Pass `pass` (1 or 2) on the sending side: every message process s sends to other processes, headers
+ * and values computed from s's view, into d_send (sum over r of h_len[pass-1][s][r] doubles). */
+int32_t bmhd_xchg_pack(const bmhd_xchg *x, int32_t pass, int32_t s, const double *d_view, double *d_send,
+                       void *stream);
+
+/* Pass `pass` on the receiving side: the messages in d_recv (sum over s of h_len[pass-1][s][r] doubles)
+ * placed into r's view by their headers, then r's messages between its own blocks, then its boundary
+ * ghost cells of the level this pass completes. A message whose header disagrees with the counted map (a
+ * damaged buffer) is skipped and counted into d_bad (int32[1], may be NULL). */
+int32_t bmhd_xchg_unpack(const bmhd_xchg *x, int32_t pass, int32_t r, const double *d_recv, double *d_view,
+                         int32_t *d_bad, void *stream);
+
+/* ---------------------------------------------------------------------------------------------
  * Learned flux correction: a multilayer perceptron 32 -> H -> H -> H -> 8 with SiLU activations
  * (hidden width H in {32, 64, 128}). This component is not in the paper: it corrects the plain flux
  * of a coarse grid toward that of a grid twice as fine. Parameters are one flat float32 vector W1[H][32], b1[H], W2[H][H], b2[H], W3[H][H], b3[H],

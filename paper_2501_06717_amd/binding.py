@@ -23,7 +23,9 @@ SCHEME = {"default": 0, "face": 1, "plane": 2, "block": 3}
 EXPORTS = ["bmhd_version", "bmhd_last_error", "bmhd_grid_create", "bmhd_grid_destroy", "bmhd_grid_info_get",
            "bmhd_grid_neighbors", "bmhd_grid_upload", "bmhd_set_state", "bmhd_fill_ghosts", "bmhd_remap",
            "bmhd_reduce_dt", "bmhd_advance", "bmhd_autotune", "bmhd_mlp_last_error", "bmhd_mlp_n_params", "bmhd_mlp_work_bytes",
-           "bmhd_mlp_forward", "bmhd_mlp_backward", "bmhd_mlp_backward_noalloc", "bmhd_mlp_adam", "bmhd_mlp_to_bf16", "bmhd_face_data"]
+           "bmhd_mlp_forward", "bmhd_mlp_backward", "bmhd_mlp_backward_noalloc", "bmhd_mlp_adam", "bmhd_mlp_to_bf16", "bmhd_face_data",
+           "bmhd_xchg_create", "bmhd_xchg_destroy", "bmhd_xchg_sizes", "bmhd_xchg_messages", "bmhd_xchg_upload",
+           "bmhd_xchg_interior", "bmhd_xchg_pack", "bmhd_xchg_unpack"]
 
 
 class SimDesc(ctypes.Structure):
@@ -118,6 +120,22 @@ def lib():
     L.bmhd_mlp_adam.restype = i32
     L.bmhd_mlp_to_bf16.argtypes = [vp, vp, ctypes.c_int64, vp]
     L.bmhd_mlp_to_bf16.restype = i32
+    L.bmhd_xchg_create.argtypes = [vp, P(i32), i32, P(vp)]
+    L.bmhd_xchg_create.restype = i32
+    L.bmhd_xchg_destroy.argtypes = [vp]
+    L.bmhd_xchg_destroy.restype = None
+    L.bmhd_xchg_sizes.argtypes = [vp, P(i32), P(ctypes.c_int64), P(ctypes.c_size_t)]
+    L.bmhd_xchg_sizes.restype = i32
+    L.bmhd_xchg_messages.argtypes = [vp, P(ctypes.c_int64), ctypes.c_int64]
+    L.bmhd_xchg_messages.restype = ctypes.c_int64
+    L.bmhd_xchg_upload.argtypes = [vp, vp, ctypes.c_size_t, vp]
+    L.bmhd_xchg_upload.restype = i32
+    L.bmhd_xchg_interior.argtypes = [vp, i32, vp, vp, vp]
+    L.bmhd_xchg_interior.restype = i32
+    L.bmhd_xchg_pack.argtypes = [vp, i32, i32, vp, vp, vp]
+    L.bmhd_xchg_pack.restype = i32
+    L.bmhd_xchg_unpack.argtypes = [vp, i32, i32, vp, vp, vp, vp]
+    L.bmhd_xchg_unpack.restype = i32
     _lib = L
     return L
 
@@ -355,6 +373,108 @@ class Grid:
         names = [f"{s}_slab{k}{p}" for s in ("face", "plane") for k in (4, 8) for p in ("", "_persist2", "_persist4")]
         names.append("block")
         return best, dict(zip(names, list(ms)))
+
+
+class Xchg:
+    """Ghost exchange between (virtual) processes for a block-to-process assignment: message maps built by
+    the library on the host, pack / unpack kernels on the device. Views and buffers are torch tensors."""
+
+    def __init__(self, grid: "Grid", rank, n_ranks):
+        L = lib()
+        self.grid = grid
+        self.rank = np.ascontiguousarray(rank, np.int32)
+        self.nr = int(n_ranks)
+        h = ctypes.c_void_p()
+        _check(L.bmhd_xchg_create(grid.h, self.rank.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), self.nr,
+                                  ctypes.byref(h)))
+        self.h = h
+        self.nloc = np.zeros(self.nr, np.int32)
+        self.len = np.zeros((2, self.nr, self.nr), np.int64)
+        wb = ctypes.c_size_t()
+        _check(L.bmhd_xchg_sizes(self.h, self.nloc.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                 self.len.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), ctypes.byref(wb)))
+        self.work_bytes = int(wb.value)
+        self.work = None
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        L = globals().get("_lib")
+        if h is not None and h.value and L is not None:
+            L.bmhd_xchg_destroy(h)
+            self.h = None
+
+    def messages(self) -> np.ndarray:
+        L = lib()
+        n = int(L.bmhd_xchg_messages(self.h, None, 0))
+        out = np.zeros((max(n, 1), 16), np.int64)
+        got = int(L.bmhd_xchg_messages(self.h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), n))
+        if got < 0:
+            _check(got)
+        return out[:n]
+
+    def upload(self, device="cuda", stream=None):
+        import torch
+        self.work = torch.empty(self.work_bytes + 256, dtype=torch.uint8, device=device)
+        aligned = (self.work.data_ptr() + 255) & ~255
+        _check(lib().bmhd_xchg_upload(self.h, ctypes.c_void_p(aligned), ctypes.c_size_t(self.work_bytes),
+                                      _stream_ptr(stream)))
+        return self
+
+    def new_view(self, r, device="cuda"):
+        import torch
+        return torch.zeros((8, int(self.nloc[r]), 12, 12, 12), dtype=torch.float64, device=device)
+
+    def send_len(self, p, s):
+        return int(self.len[p - 1, s].sum())
+
+    def recv_len(self, p, r):
+        return int(self.len[p - 1, :, r].sum())
+
+    def interior(self, r, U, view, stream=None):
+        import torch
+        _check(lib().bmhd_xchg_interior(self.h, int(r), _dev_ptr(U, torch.float64),
+                                        _dev_ptr(view, torch.float64) if view.numel() else None, _stream_ptr(stream)))
+
+    def pack(self, p, s, view, send, stream=None):
+        import torch
+        _check(lib().bmhd_xchg_pack(self.h, int(p), int(s), _dev_ptr(view, torch.float64) if view.numel() else None,
+                                    _dev_ptr(send, torch.float64) if send.numel() else None, _stream_ptr(stream)))
+
+    def unpack(self, p, r, recv, view, bad=None, stream=None):
+        import torch
+        _check(lib().bmhd_xchg_unpack(self.h, int(p), int(r), _dev_ptr(recv, torch.float64) if recv.numel() else None,
+                                      _dev_ptr(view, torch.float64) if view.numel() else None,
+                                      _dev_ptr(bad, torch.int32) if bad is not None else None,
+                                      _stream_ptr(stream)))
+
+    def transfer(self, p, sends, recvs):
+        """The point-to-point transfers of pass p, as device copies: the segment for r in s's send buffer
+        to the segment from s in r's receive buffer."""
+        for s in range(self.nr):
+            so = 0
+            for r in range(self.nr):
+                n = int(self.len[p - 1, s, r])
+                if n:
+                    ro = int(self.len[p - 1, :s, r].sum())
+                    recvs[r][ro:ro + n].copy_(sends[s][so:so + n])
+                so += n
+
+    def run(self, U, bad=None):
+        """Both passes of the exchange for every process: returns the views (bad: optional int32 device
+        counter of skipped messages)."""
+        import torch
+        views = [self.new_view(r, U.device) for r in range(self.nr)]
+        for r in range(self.nr):
+            self.interior(r, U, views[r])
+        for p in (1, 2):
+            sends = [torch.empty(self.send_len(p, s), dtype=torch.float64, device=U.device) for s in range(self.nr)]
+            recvs = [torch.empty(self.recv_len(p, r), dtype=torch.float64, device=U.device) for r in range(self.nr)]
+            for s in range(self.nr):
+                self.pack(p, s, views[s], sends[s])
+            self.transfer(p, sends, recvs)
+            for r in range(self.nr):
+                self.unpack(p, r, recvs[r], views[r], bad=bad)
+        return views
 
 
 # ------------------------------------------------------------------------------------------------

@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libbmhd.so")
-SOURCES = ["kernels.hip", "mlp.hip", "grid.cpp"]
+SOURCES = ["kernels.hip", "mlp.hip", "xchg.hip", "grid.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

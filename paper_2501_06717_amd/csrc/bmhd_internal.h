@@ -124,6 +124,9 @@ int32_t mlp_infer_bf16_inputs(const float *d_params, const uint16_t *d_params_bf
                               const uint16_t *d_x, float *d_y, void *stream, std::string &err);
 void prim_to_cons_host(const double *w, double *u);
 
+// Sets the message bmhd_last_error reports on this thread; returns code.
+int32_t set_last_error(int32_t code, const std::string &msg);
+
 }  // namespace bmhd
 
 struct bmhd_grid {

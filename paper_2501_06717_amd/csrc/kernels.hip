@@ -2090,6 +2090,10 @@ int32_t need_upload(const bmhd_grid *g) {
 }
 }  // namespace
 
+namespace bmhd {
+int32_t set_last_error(int32_t code, const std::string &msg) { return fail(code, msg); }
+}  // namespace bmhd
+
 extern "C" {
 
 int32_t bmhd_version(void) { return 100; }

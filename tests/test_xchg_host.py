@@ -1,0 +1,62 @@
+"""Host side of the ghost exchange between processes (Sec. 4.2-4.4, Algorithm 4), CPU only: the library
+counts the same message maps as the oracle (integer-equal rows: sender, receiver, pass, index, start
+offset with the n_C = 7 header, blocks, slot, type, receive box) for every grid shape and assignment of
+blocks to processes, and its buffer sizes are the counted ones."""
+import numpy as np
+import pytest
+
+from paper_2501_06717_amd import binding as bd
+from paper_2501_06717_amd import workloads as wk
+
+GRIDS = {
+    "periodic_2x2x2": lambda: wk.uniform_state((2, 2, 2)),
+    "one_block_periodic": lambda: wk.uniform_state((1, 1, 1)),
+    "odd_box_mixed_bc": lambda: wk.odd_box(),
+    "two_level_periodic": lambda: wk.two_level_box(),
+    "two_level_mixed_bc": lambda: wk.two_level_box(bc=(1, 2, 0, 0, 2, 1)),
+    "two_roots_one_refined": lambda: wk.two_level_box(nroot=(2, 1, 1), refine=((1, 0, 0),)),
+    "fast_wave_octant": lambda: wk.fast_wave((2, 2, 2), refine_octant=True),
+    "magnetosphere_cut": lambda: wk.magnetosphere_cut(32),
+}
+
+
+def ranks(wl, kind, seed=0):
+    nb = wl.n_blocks
+    if kind == "one":
+        return np.zeros(nb, np.int32), 1
+    if kind == "each":
+        return np.arange(nb, dtype=np.int32), nb
+    if kind == "halves":
+        return (np.arange(nb) * 2 // nb).astype(np.int32), 2
+    rng = np.random.default_rng(seed)
+    return rng.integers(0, 3, nb).astype(np.int32), 3
+
+
+@pytest.mark.parametrize("kind", ["one", "halves", "random3", "each"])
+@pytest.mark.parametrize("grid", list(GRIDS))
+def test_message_maps_equal_the_oracle(oracle_mod, grid, kind):
+    wl = GRIDS[grid]()
+    rank, n = ranks(wl, kind, seed=len(grid))
+    g = bd.Grid.from_workload(wl)
+    x = bd.Xchg(g, rank, n)
+    got = x.messages()
+    ref = oracle_mod.Grid.from_workload(wl).xchg_messages(rank, n)
+    assert got.shape == ref.shape and np.array_equal(got, ref), (got.shape, ref.shape)
+    # buffer lengths: the end of the last message of each (sender, receiver, pass)
+    for p in (1, 2):
+        for s in range(n):
+            for r in range(n):
+                rows = ref[(ref[:, 0] == s) & (ref[:, 1] == r) & (ref[:, 2] == p)]
+                want = 0 if (s == r or len(rows) == 0) else int(
+                    rows[-1, 4] + 7 + 8 * np.prod(rows[-1, 13:16] - rows[-1, 10:13] + 1))
+                assert x.len[p - 1, s, r] == want
+    assert x.nloc.sum() == wl.n_blocks and np.array_equal(x.nloc, np.bincount(rank, minlength=n))
+
+
+def test_bad_assignments_are_refused():
+    wl = wk.uniform_state((2, 2, 2))
+    g = bd.Grid.from_workload(wl)
+    with pytest.raises(bd.BmhdError):
+        bd.Xchg(g, np.full(wl.n_blocks, 2, np.int32), 2)
+    with pytest.raises(bd.BmhdError):
+        bd.Xchg(g, np.zeros(wl.n_blocks, np.int32), 0)
