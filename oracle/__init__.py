@@ -16,7 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB = os.path.join(HERE, "liboracle.so")
 SOURCES = ["oracle.c", "mlp.c"]
 
-FLUX = {"rusanov": 0, "hlle": 1}
+FLUX = {"rusanov": 0, "hlle": 1, "linde": 2}
 
 
 def build(verbose=False):

@@ -42,7 +42,7 @@
 
 enum { BC_PERIODIC = 0, BC_OUTFLOW = 1, BC_INFLOW = 2 };
 enum { REL_SAME = 0, REL_COARSER = 1, REL_FINER = 2, REL_OUTFLOW = -1, REL_INFLOW = -2 };
-enum { FLUX_RUSANOV = 0, FLUX_HLLE = 1 };
+enum { FLUX_RUSANOV = 0, FLUX_HLLE = 1, FLUX_LINDE = 2 };
 
 static const double GAM = 5.0 / 3.0;
 
@@ -57,7 +57,7 @@ typedef struct {
 } or_sim;
 
 typedef struct {
-    int32_t flux;      /* FLUX_RUSANOV or FLUX_HLLE */
+    int32_t flux;      /* FLUX_RUSANOV, FLUX_HLLE or FLUX_LINDE */
     int32_t powell;    /* 0 / 1 */
     int32_t n_table;   /* number of stages in the table (1 or 2) */
     int32_t recompute_dt;
@@ -146,7 +146,19 @@ double or_fast_speed(const double *w, int d)
 
 /* Numerical flux from primitive face states (reading: Rusanov with the larger of the two |u_n|+c_f;
  * HLLE with Davis-type min/max signal speeds; every component, B_n included, gets the same
- * dissipation). */
+ * dissipation).
+ *
+ * FLUX_LINDE, the flux the paper's fast-wave test names (Sec. 5.1) without printing it; reading, after
+ * T. Linde's two-state HLL solver (Int. J. Numer. Meth. Fluids 40, 2002), whose aim is that HLL's
+ * dissipation vanish on an isolated intermediate discontinuity: HLLE plus an anti-diffusion term for the
+ * entropy (contact) wave. Its density jump is delta = minmod(drho - dp / c^2, drho) with
+ * c^2 = gamma (p_L + p_R) / (rho_L + rho_R) (the part of the density jump no pressure change explains,
+ * never larger than the jump itself), its conserved jump dU_c = delta (1, u_bar, 0, 0, 0, |u_bar|^2 / 2)
+ * at the mean velocity u_bar, and the term replaces HLL's dissipation of that jump by upwinding at the
+ * contact speed lambda = u_bar_n clamped to [S_L, S_R]:
+ *   F = F_HLLE + K dU_c / (S_R - S_L),   K = -S_L S_R + S_L max(lambda, 0) + S_R min(lambda, 0) >= 0.
+ * An isolated contact (u, p, B continuous, rho jumping) gets the exact upwind flux, F_L for lambda >= 0
+ * and F_R otherwise; where S_L >= 0 or S_R <= 0 the flux is HLLE's (upwind). */
 void or_num_flux(const double *wl, const double *wr, int d, int kind, double *f)
 {
     double ul[8], ur[8], fl[8], fr[8];
@@ -167,8 +179,26 @@ void or_num_flux(const double *wl, const double *wr, int d, int kind, double *f)
         } else if (sr <= 0.0) {
             for (int v = 0; v < 8; v++) f[v] = fr[v];
         } else {
+            double duc[8] = {0, 0, 0, 0, 0, 0, 0, 0}, K = 0.0;
+            if (kind == FLUX_LINDE) {
+                double drho = wr[0] - wl[0], dp = wr[7] - wl[7];
+                double c2 = GAM * (wl[7] + wr[7]) / (wl[0] + wr[0]);
+                double t = drho - dp / c2, delta = 0.0;
+                if (t > 0.0 && drho > 0.0) delta = fmin(t, drho);
+                if (t < 0.0 && drho < 0.0) delta = fmax(t, drho);
+                double ub[3], ub2 = 0.0;
+                for (int a = 0; a < 3; a++) {
+                    ub[a] = 0.5 * (wl[1 + a] + wr[1 + a]);
+                    ub2 += ub[a] * ub[a];
+                }
+                double lam = fmin(fmax(ub[d], sl), sr);
+                K = -sl * sr + sl * fmax(lam, 0.0) + sr * fmin(lam, 0.0);
+                duc[0] = delta;
+                for (int a = 0; a < 3; a++) duc[1 + a] = delta * ub[a];
+                duc[7] = delta * 0.5 * ub2;
+            }
             for (int v = 0; v < 8; v++)
-                f[v] = (sr * fl[v] - sl * fr[v] + sl * sr * (ur[v] - ul[v])) / (sr - sl);
+                f[v] = (sr * fl[v] - sl * fr[v] + sl * sr * (ur[v] - ul[v]) + K * duc[v]) / (sr - sl);
         }
     }
 }

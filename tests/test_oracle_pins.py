@@ -110,8 +110,9 @@ def test_numerical_flux_consistency(oracle_mod, seed):
     for d in range(3):
         F = oracle_mod.phys_flux(W, d)
         assert np.array_equal(oracle_mod.num_flux(W, W, d, "rusanov"), F)
-        Fh = oracle_mod.num_flux(W, W, d, "hlle")
-        assert np.all(np.abs(Fh - F) <= 4 * np.spacing(np.maximum(np.abs(F), 1e-300)) + 1e-300), (Fh - F)
+        for kind in ("hlle", "linde"):
+            Fh = oracle_mod.num_flux(W, W, d, kind)
+            assert np.all(np.abs(Fh - F) <= 4 * np.spacing(np.maximum(np.abs(F), 1e-300)) + 1e-300), (kind, Fh - F)
 
 
 def test_hlle_upwinds_supersonic_states(oracle_mod):
@@ -133,13 +134,77 @@ def test_numerical_flux_mirror_symmetry(oracle_mod):
         WL = np.array([rng.uniform(0.5, 2), *rng.uniform(-1, 1, 3), *rng.uniform(-1, 1, 3), rng.uniform(0.3, 2)])
         WR = np.array([rng.uniform(0.5, 2), *rng.uniform(-1, 1, 3), *rng.uniform(-1, 1, 3), rng.uniform(0.3, 2)])
         flip = np.array([1, -1, 1, 1, -1, 1, 1, 1.0])
-        for kind in ("rusanov", "hlle"):
+        for kind in ("rusanov", "hlle", "linde"):
             F = oracle_mod.num_flux(WL, WR, 0, kind)
             Fm = oracle_mod.num_flux(WR * flip, WL * flip, 0, kind)
             # mass, transverse momentum, transverse B, energy fluxes change sign; normal momentum and
             # normal-B fluxes keep it
             parity = np.array([-1, 1, -1, -1, 1, -1, -1, -1.0])
             assert np.allclose(Fm, parity * F, rtol=1e-13, atol=1e-13)
+
+
+def _contact(rho_l, rho_r, u, p=0.7, B=(0.3, -0.2, 0.5)):
+    WL = np.array([rho_l, *u, *B, p], dtype=np.float64)
+    WR = np.array([rho_r, *u, *B, p], dtype=np.float64)
+    return WL, WR
+
+
+@pytest.mark.parametrize("d", [0, 1, 2])
+def test_linde_resolves_a_stationary_contact(oracle_mod, d):
+    """A density jump with u = 0 and uniform p and B is an exact steady solution (the flux is the same
+    on both sides). The Linde-type flux returns that flux: zero mass flux; HLLE's mass flux
+    S_L S_R drho / (S_R - S_L) smears the jump."""
+    WL, WR = _contact(1.0, 3.0, (0.0, 0.0, 0.0))
+    F = oracle_mod.phys_flux(WL, d)
+    assert np.array_equal(F, oracle_mod.phys_flux(WR, d))
+    Fl = oracle_mod.num_flux(WL, WR, d, "linde")
+    Fh = oracle_mod.num_flux(WL, WR, d, "hlle")
+    assert Fl[0] == 0.0
+    assert np.all(np.abs(Fl - F) <= 4 * np.spacing(np.maximum(np.abs(F), 1.0)))
+    assert abs(Fh[0]) > 0.1
+
+
+@pytest.mark.parametrize("un", [0.4, -0.3])
+def test_linde_upwinds_a_moving_contact(oracle_mod, un):
+    """A density jump carried by a uniform flow (u, p, B continuous) is an isolated contact moving at u_n:
+    the exact (upwind) flux is the left state's for u_n > 0 and the right state's for u_n < 0."""
+    WL, WR = _contact(0.5, 2.0, (un, 0.2, -0.1))
+    Fl = oracle_mod.num_flux(WL, WR, 0, "linde")
+    ref = oracle_mod.phys_flux(WL if un > 0 else WR, 0)
+    assert np.allclose(Fl, ref, rtol=1e-13, atol=1e-13), (Fl - ref)
+    assert not np.allclose(oracle_mod.num_flux(WL, WR, 0, "hlle"), ref, rtol=1e-6)
+
+
+def test_linde_adds_nothing_without_a_contact_jump(oracle_mod):
+    """Jumps whose density change is the one their pressure change explains (drho = dp / c^2, the
+    acoustic relation at the mean sound speed), or that carry no density jump at all, get HLLE's flux."""
+    g = 5.0 / 3.0
+    WL = np.array([1.0, 0.1, 0.2, -0.3, 0.4, 0.1, -0.2, 1.0])
+    WR = WL.copy()
+    WR[7] = 1.3
+    c2 = g * (WL[7] + WR[7]) / (WL[0] + WL[0])
+    WR[0] = WL[0] + 0.3 / c2                      # drho - dp / c^2 = 0 up to rounding
+    c2 = g * (WL[7] + WR[7]) / (WL[0] + WR[0])
+    WR[0] = WL[0] + 0.3 / c2
+    assert np.allclose(oracle_mod.num_flux(WL, WR, 0, "linde"), oracle_mod.num_flux(WL, WR, 0, "hlle"),
+                       rtol=1e-12, atol=1e-12)
+    WR2 = WL.copy()
+    WR2[4:7] = [0.6, -0.3, 0.1]                   # a magnetic jump, no density jump
+    assert np.array_equal(oracle_mod.num_flux(WL, WR2, 1, "linde"), oracle_mod.num_flux(WL, WR2, 1, "hlle"))
+
+
+def test_linde_keeps_a_stationary_contact_in_a_periodic_box(oracle_mod):
+    """Whole stages: a periodic box with a density slab (u = 0, uniform p and B) stays as it is to
+    round-off over eight steps with the Linde-type flux; HLLE diffuses the density across the jump."""
+    wl = wk.uniform_state((2, 1, 1), W0=(1.0, 0.0, 0.0, 0.0, 0.3, -0.2, 0.5, 0.7))
+    W = wl.W.copy()
+    W[0, 1] = 3.0                                  # the second block holds the dense slab
+    Ul, _, fl = _run(oracle_mod, wl, W, 8, flux="linde", powell=False)
+    Uh, _, fh = _run(oracle_mod, wl, W, 8, flux="hlle", powell=False)
+    U0 = oracle_mod.Grid.from_workload(wl).set_state(W)
+    assert fl == 0 and fh == 0
+    assert np.abs(Ul - U0).max() <= 1e-14 * np.abs(U0).max()
+    assert np.abs(Uh[0] - U0[0]).max() > 1e-2
 
 
 # ------------------------------------------------------------------------------------------------
@@ -362,7 +427,7 @@ def test_uniform_state_preserved_bitwise(oracle_mod, case):
     assert np.array_equal(U, ref)
 
 
-@pytest.mark.parametrize("flux", ["rusanov", "hlle"])
+@pytest.mark.parametrize("flux", ["rusanov", "hlle", "linde"])
 @pytest.mark.parametrize("two_level", [False, True])
 def test_conservation_periodic(oracle_mod, flux, two_level):
     wl = wk.two_level_box() if two_level else wk.uniform_state((2, 2, 2))
@@ -501,7 +566,7 @@ def _permute(wl, U):
     return out
 
 
-@pytest.mark.parametrize("flux,powell", [("rusanov", False), ("hlle", True)])
+@pytest.mark.parametrize("flux,powell", [("rusanov", False), ("hlle", True), ("linde", True)])
 def test_axis_permutation_symmetry(oracle_mod, flux, powell):
     wl = wk.uniform_state((2, 2, 2))
     W = wk.random_positive_state(wl, seed=21)
