@@ -45,6 +45,14 @@ extern "C" {
 
 #define BMHD_FLUX_RUSANOV 0
 #define BMHD_FLUX_HLLE 1
+#define BMHD_FLUX_LINDE 2 /* HLLE plus the anti-diffusion of the entropy (contact) wave: the flux the paper's
+                             fast-wave test names (Sec. 5.1), here after Linde's two-state HLL solver (whose
+                             aim is no HLL dissipation on an isolated intermediate discontinuity): the density
+                             jump no pressure change explains, delta = minmod(drho - dp / c^2, drho) with
+                             c^2 = gamma (p_L + p_R) / (rho_L + rho_R), carried at the mean velocity u_bar, is
+                             upwinded at lambda = u_bar_n clamped to [S_L, S_R]: F = F_HLLE + delta (S_L
+                             max(lambda, 0) + S_R min(lambda, 0) - S_L S_R) / (S_R - S_L) (1, u_bar, 0, 0, 0,
+                             |u_bar|^2 / 2). An isolated contact gets the exact upwind flux. */
 
 #define BMHD_FP64 0      /* every step in float64 */
 #define BMHD_FP32_FLUX 1 /* reconstruction and fluxes in float32; update, flux correction, dt in float64 */
@@ -107,7 +115,7 @@ typedef struct {
 } bmhd_learned;
 
 typedef struct {
-    int32_t flux;         /* BMHD_FLUX_* */
+    int32_t flux;         /* BMHD_FLUX_* (the learned correction takes RUSANOV or HLLE) */
     int32_t powell;       /* 1: Powell source terms (right-hand sides of Eqs. 2-4) */
     int32_t precision;    /* BMHD_FP64 or BMHD_FP32_FLUX */
     int32_t recompute_dt; /* 1: dt = CFL-limited global minimum per simulation, recomputed at the start
@@ -117,7 +125,8 @@ typedef struct {
     double beta[2];       /* Heun: alpha = {0, 0.5}, beta = {1, 0.5} */
     int32_t slab;         /* tile depth of the stage kernel: 0 = default, 4 or 8 cells along z */
     int32_t scheme;       /* work split of the stage kernel: 0 = default (BMHD_SCHEME_BLOCK, or
-                             BMHD_SCHEME_PLANE when slab is 4 or persist_wgs > 0); BMHD_SCHEME_FACE: one face per
+                             BMHD_SCHEME_PLANE when slab is 4, persist_wgs > 0 or the flux is
+                             BMHD_FLUX_LINDE); BMHD_SCHEME_FACE: one face per
                              thread and direction, fluxes exchanged through LDS; BMHD_SCHEME_PLANE: one
                              wave per cell layer of the tile plus one wave for the tile's high-side faces,
                              fluxes exchanged across lanes (less LDS, more workgroups per CU);

@@ -16,7 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libbmhd.so")
 
 BC_PERIODIC, BC_OUTFLOW, BC_INFLOW = 0, 1, 2
-FLUX = {"rusanov": 0, "hlle": 1}
+FLUX = {"rusanov": 0, "hlle": 1, "linde": 2}
 PRECISION = {"fp64": 0, "fp32_flux": 1}
 SCHEME = {"default": 0, "face": 1, "plane": 2, "block": 3}
 

@@ -154,6 +154,18 @@ __device__ __forceinline__ void face_side(const R w[8], R U[8], R F[8], R &un, R
 
 template <typename R, int D, int FLUX>
 __device__ __forceinline__ void num_flux(const R wl[8], const R wr[8], R f[8]) {
+    // Linde-type flux: the entropy wave's density jump (the part no pressure change explains, bounded by
+    // the jump) and the mean velocity, formed before the face states' fluxes so that only these four
+    // values stay live through them
+    R delta = R(0), ub[3] = {R(0), R(0), R(0)};
+    if constexpr (FLUX == BMHD_FLUX_LINDE) {
+        const R drho = wr[0] - wl[0], dp = wr[7] - wl[7];
+        const R c2 = R(GAMMA) * (wl[7] + wr[7]) * frcp1(wl[0] + wr[0]);
+        const R t = drho - dp * frcp1(c2);
+        delta = (t > R(0) && drho > R(0)) ? rmin(t, drho) : ((t < R(0) && drho < R(0)) ? rmax(t, drho) : R(0));
+#pragma unroll
+        for (int a = 0; a < 3; ++a) ub[a] = R(0.5) * (wl[1 + a] + wr[1 + a]);
+    }
     R UL[8], FL[8], UR[8], FR[8], unl, cl, unr, cr;
     face_side<R, D>(wl, UL, FL, unl, cl);
     face_side<R, D>(wr, UR, FR, unr, cr);
@@ -169,6 +181,17 @@ __device__ __forceinline__ void num_flux(const R wl[8], const R wr[8], R f[8]) {
         const R a = sr * inv, b = -sl * inv, c = sl * a;
 #pragma unroll
         for (int v = 0; v < 8; ++v) f[v] = fma(a, FL[v], fma(b, FR[v], c * (UR[v] - UL[v])));
+        if constexpr (FLUX == BMHD_FLUX_LINDE) {
+            // anti-diffusion of the entropy (contact) wave: its jump carried at the mean velocity,
+            // upwinded at the contact speed
+            const R lam = rmin(rmax(ub[D], sl), sr);
+            const R k = (sl * rmax(lam, R(0)) + sr * rmin(lam, R(0)) - sl * sr) * inv * delta;
+            f[0] += k;
+            f[1] += k * ub[0];
+            f[2] += k * ub[1];
+            f[3] += k * ub[2];
+            f[7] += k * (R(0.5) * (ub[0] * ub[0] + ub[1] * ub[1] + ub[2] * ub[2]));
+        }
     }
 }
 
@@ -1825,6 +1848,10 @@ int32_t launch_stage_prec(const HostGrid &h, const StageArgs &a, int flux, bool 
         if (powell) return launch_stage_shape<KS, R, BMHD_FLUX_RUSANOV, true>(h, a, sc, pw, ev0, ev1, s);
         return launch_stage_shape<KS, R, BMHD_FLUX_RUSANOV, false>(h, a, sc, pw, ev0, ev1, s);
     }
+    if (flux == BMHD_FLUX_LINDE) {
+        if (powell) return launch_stage_shape<KS, R, BMHD_FLUX_LINDE, true>(h, a, sc, pw, ev0, ev1, s);
+        return launch_stage_shape<KS, R, BMHD_FLUX_LINDE, false>(h, a, sc, pw, ev0, ev1, s);
+    }
     if (powell) return launch_stage_shape<KS, R, BMHD_FLUX_HLLE, true>(h, a, sc, pw, ev0, ev1, s);
     return launch_stage_shape<KS, R, BMHD_FLUX_HLLE, false>(h, a, sc, pw, ev0, ev1, s);
 }
@@ -1834,8 +1861,10 @@ Shape pick_shape(const bmhd_opts &o) {
     // measured on the 256^3 magnetosphere: the block form in both precisions (FP64: 1.25 / 1.40 ms per
     // stage against 1.74 / 2.07 for the plane form on 8x8x4 slabs and 1.91 / 2.16 for the face form on
     // full blocks; FP32 flux: 0.94 / 1.14 against 1.04 / 1.26). A persistent grid or a tile of four
-    // layers asks for the plane form. With the face form, full blocks for FP64.
-    if (o.scheme == 0) sh.scheme = (o.persist_wgs > 0 || o.slab == 4) ? BMHD_SCHEME_PLANE : BMHD_SCHEME_BLOCK;
+    // layers asks for the plane form, and so does the Linde-type flux (its block form does not fit 128
+    // registers: 4.46 against 3.98 ms per step on the same grid). With the face form, full blocks for FP64.
+    if (o.scheme == 0)
+        sh.scheme = (o.persist_wgs > 0 || o.slab == 4 || o.flux == BMHD_FLUX_LINDE) ? BMHD_SCHEME_PLANE : BMHD_SCHEME_BLOCK;
     else sh.scheme = o.scheme;
     sh.ks = o.slab == 0 ? ((o.precision == BMHD_FP64 && sh.scheme == BMHD_SCHEME_FACE) || sh.scheme == BMHD_SCHEME_BLOCK
                                ? 8 : 4)
@@ -1874,7 +1903,8 @@ int32_t launch_learn(const HostGrid &h, const StageArgs &a, const bmhd_opts &o, 
 }
 
 int32_t check_opts(const bmhd_opts &o) {
-    if (o.flux != BMHD_FLUX_RUSANOV && o.flux != BMHD_FLUX_HLLE) return fail(BMHD_EINVAL, "unknown flux");
+    if (o.flux != BMHD_FLUX_RUSANOV && o.flux != BMHD_FLUX_HLLE && o.flux != BMHD_FLUX_LINDE)
+        return fail(BMHD_EINVAL, "unknown flux");
     if (o.precision != BMHD_FP64 && o.precision != BMHD_FP32_FLUX) return fail(BMHD_EINVAL, "unknown precision");
     if (o.slab != 0 && o.slab != 4 && o.slab != 8) return fail(BMHD_EINVAL, "slab must be 0, 4 or 8");
     if (o.scheme != 0 && o.scheme != BMHD_SCHEME_FACE && o.scheme != BMHD_SCHEME_PLANE && o.scheme != BMHD_SCHEME_BLOCK)
@@ -1894,6 +1924,7 @@ int32_t check_opts(const bmhd_opts &o) {
         if (!(L.tau >= 0.0)) return fail(BMHD_EINVAL, "learned: tau must be >= 0");
         if (o.use_graph) return fail(BMHD_EUNSUPPORTED, "learned correction is not captured in graphs");
         if (o.local_dt) return fail(BMHD_EUNSUPPORTED, "learned correction with local time stepping");
+        if (o.flux == BMHD_FLUX_LINDE) return fail(BMHD_EUNSUPPORTED, "learned correction is added to the HLLE or Rusanov flux");
     }
     if (o.local_dt != 0 && o.local_dt != 1) return fail(BMHD_EINVAL, "local_dt must be 0 or 1");
     return BMHD_OK;

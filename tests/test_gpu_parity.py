@@ -138,6 +138,11 @@ STAGE_CASES = {
     "two_level_48": (lambda: wk.two_level_magnetosphere(48), dict(flux="hlle", powell=True)),
     # a body cell on the coarse side of a level face: flux correction must leave it alone
     "two_level_box_body": (lambda: wk.two_level_box(body=True), dict(flux="hlle", powell=True)),
+    # the Linde-type flux (contact anti-diffusion) on the paper's fast wave with a refined octant and on
+    # the magnetosphere cut (body, inflow, outflow)
+    "fast_wave_octant_linde": (lambda: wk.fast_wave((2, 2, 2), refine_octant=True), dict(flux="linde", powell=True)),
+    "magnetosphere_32_linde": (lambda: wk.magnetosphere_cut(32), dict(flux="linde", powell=True)),
+    "odd_box_linde": (lambda: wk.odd_box(), dict(flux="linde", powell=False)),
 }
 
 
