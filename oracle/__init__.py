@@ -76,6 +76,9 @@ def lib():
         L.or_prolong1.argtypes = [ctypes.c_double, dp, dp, ip]
         L.or_prolong1.restype = ctypes.c_double
         L.or_face_features.argtypes = [ctypes.c_void_p, dp, dp, dp]
+        L.or_block_indicator.argtypes = [ctypes.c_void_p, dp, dp]
+        L.or_adapt.argtypes = [ctypes.c_void_p, dp, ctypes.c_double, ctypes.c_double, ip, ip, ip, ctypes.c_long]
+        L.or_adapt.restype = ctypes.c_long
         L.or_advance_learned.argtypes = [ctypes.c_void_p, dp, dp, dp, ctypes.c_int, P(_Opts), dp, dp,
                                          ctypes.c_double, ctypes.c_double, P(ctypes.c_long), P(ctypes.c_long)]
         L.or_advance_learned.restype = ctypes.c_int
@@ -215,6 +218,23 @@ class Grid:
         if lib().or_remap(self.h, _dp(U), to.h, _dp(out)) != 0:
             raise ValueError("remap: the grids differ in their simulations or a block of `to` cannot be supplied")
         return out
+
+    def block_indicator(self, U):
+        """Refinement indicator per block (or_block_indicator)."""
+        U = np.ascontiguousarray(U, np.float64)
+        ind = np.empty(self.nb)
+        lib().or_block_indicator(self.h, _dp(U), _dp(ind))
+        return ind
+
+    def adapt(self, ind, r_refine, r_coarsen):
+        """The adapted block list (levels, ijk [n, 3], sims) for indicators ind (or_adapt)."""
+        ind = np.ascontiguousarray(ind, np.float64)
+        cap = 8 * self.nb + 8
+        lv, ijk, sim = np.empty(cap, np.int32), np.empty(3 * cap, np.int32), np.empty(cap, np.int32)
+        n = lib().or_adapt(self.h, _dp(ind), float(r_refine), float(r_coarsen), _ip(lv), _ip(ijk), _ip(sim), cap)
+        if n < 0:
+            raise RuntimeError("adapt: output too small")
+        return lv[:n].copy(), ijk[:3 * n].reshape(n, 3).copy(), sim[:n].copy()
 
     def advance(self, U0, U1, dt, n_stages, flux="rusanov", powell=False, cfl=0.8, recompute_dt=True,
                 alpha=(0.0, 0.5), beta=(1.0, 0.5), local_dt=False):

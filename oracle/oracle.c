@@ -847,6 +847,91 @@ void or_dt(const or_grid *g, const double *U, double cfl, double *dt)
     free(st);
 }
 
+/* ------------------------------------------------------------------------------------------------ */
+/* refinement criterion (the grid adapts between steps on the CPU, Sec. 2-3; the paper gives no       */
+/* criterion: reading)                                                                              */
+/*                                                                                                  */
+/* Per block: the largest normalised jump, over its cells and the three axes, of the density and of  */
+/* the squared field strength between the two face neighbours of a cell (ghost cells included):      */
+/*   ind = max over cells, axes d, q in {rho, |B|^2} of |q(c + e_d) - q(c - e_d)| / (q(c + e_d) +    */
+/*   q(c - e_d) + 1e-300).                                                                          */
+/* A level-0 root whose indicator reaches r_refine is refined into its 8 children; a refined root    */
+/* whose 8 children all stay below r_coarsen (< r_refine) is coarsened into it; other roots keep    */
+/* their blocks. The new block list runs over each simulation's roots with x fastest, a refined root  */
+/* listing its children with x fastest. Two levels only, so the result is always 2:1 balanced.       */
+
+void or_block_indicator(const or_grid *g, const double *U, double *ind)
+{
+    double *st = pad_alloc(g->nb);
+    pad_from_ext(g, U, st);
+    exchange_messages(g, st);
+    for (int b = 0; b < g->nb; b++) {
+        double m = 0.0;
+        for (int k = 0; k < NC; k++)
+            for (int j = 0; j < NC; j++)
+                for (int i = 0; i < NC; i++)
+                    for (int d = 0; d < 3; d++) {
+                        int p[3] = {i, j, k}, q[3] = {i, j, k};
+                        p[d] += 1;
+                        q[d] -= 1;
+                        const double *cp = pcell(st, b, p[0], p[1], p[2]), *cm = pcell(st, b, q[0], q[1], q[2]);
+                        double rp = cp[0], rm = cm[0];
+                        double bp = cp[4] * cp[4] + cp[5] * cp[5] + cp[6] * cp[6];
+                        double bm = cm[4] * cm[4] + cm[5] * cm[5] + cm[6] * cm[6];
+                        double jr = fabs(rp - rm) / (rp + rm + 1e-300);
+                        double jb = fabs(bp - bm) / (bp + bm + 1e-300);
+                        if (jr > m) m = jr;
+                        if (jb > m) m = jb;
+                    }
+        ind[b] = m;
+    }
+    free(st);
+}
+
+/* The adapted block list (levels, block indices, simulations) for indicators ind[nB]; returns the
+ * number of blocks, or -1 when out_cap is too small. */
+long or_adapt(const or_grid *g, const double *ind, double r_refine, double r_coarsen, int32_t *out_level,
+              int32_t *out_ijk, int32_t *out_sim, long out_cap)
+{
+    long n = 0;
+    for (int s = 0; s < g->ns; s++) {
+        const or_sim *sm = &g->sims[s];
+        for (long z = 0; z < sm->nroot[2]; z++)
+            for (long y = 0; y < sm->nroot[1]; y++)
+                for (long x = 0; x < sm->nroot[0]; x++) {
+                    long r[3] = {x, y, z};
+                    int root = lut_get(g, s, 0, r);
+                    int refine;
+                    if (root >= 0) {
+                        refine = ind[root] >= r_refine;
+                    } else {
+                        double m = 0.0;
+                        for (int q = 0; q < 8; q++) {
+                            long c[3] = {2 * x + (q & 1), 2 * y + ((q >> 1) & 1), 2 * z + (q >> 2)};
+                            double v = ind[lut_get(g, s, 1, c)];
+                            if (v > m) m = v;
+                        }
+                        refine = !(m < r_coarsen);
+                    }
+                    if (n + (refine ? 8 : 1) > out_cap) return -1;
+                    if (!refine) {
+                        out_level[n] = 0;
+                        for (int a = 0; a < 3; a++) out_ijk[3 * n + a] = (int32_t)r[a];
+                        out_sim[n++] = s;
+                    } else {
+                        for (int q = 0; q < 8; q++) {
+                            out_level[n] = 1;
+                            out_ijk[3 * n + 0] = (int32_t)(2 * x + (q & 1));
+                            out_ijk[3 * n + 1] = (int32_t)(2 * y + ((q >> 1) & 1));
+                            out_ijk[3 * n + 2] = (int32_t)(2 * z + (q >> 2));
+                            out_sim[n++] = s;
+                        }
+                    }
+                }
+    }
+    return n;
+}
+
 /* Move a state to another grid of the same simulations after a refinement change (Sec. 2: a block is
  * refined into its 8 children, or 8 children are coarsened into their parent; Sec. 3 does this on the CPU
  * between steps, then rebuilds the message maps). Every cell of `to` takes the value the ghost rules of
