@@ -215,6 +215,23 @@ int32_t bmhd_fill_ghosts(const bmhd_grid *g, const double *d_U, double *d_view, 
 int32_t bmhd_remap(const bmhd_grid *from, const double *d_U_from, const bmhd_grid *to, double *d_U_to,
                    void *stream);
 
+/* Refinement indicator per block into d_ind[n_blocks] (device): the largest normalised jump, over the
+ * block's cells and the three axes, of the density and of |B|^2 between a cell's two face neighbours
+ * (neighbours outside the block by the ghost rules of bmhd_fill_ghosts): |q+ - q-| / (q+ + q- + 1e-300).
+ * The paper adapts its grid between steps on the CPU (Sec. 2-3) without stating a criterion; this is the
+ * library's (bit-exact, no contraction). */
+int32_t bmhd_block_indicator(const bmhd_grid *g, const double *d_U, double *d_ind, void *stream);
+
+/* Host: the adapted block list for indicators h_ind[n_blocks] (host): a level-0 root whose indicator
+ * reaches r_refine becomes its 8 level-1 children, a refined root whose 8 children all stay below r_coarsen
+ * (<= r_refine) becomes one level-0 block, other roots keep their blocks (two levels, so the result is 2:1
+ * balanced). The list runs over each simulation's roots with x fastest, a refined root listing its
+ * children with x fastest: h_level[n], h_ijk[n][3], h_sim[n] (host, may be NULL to count only, else at
+ * least max_blocks long), *n_out = n. Feed it to bmhd_grid_create, bmhd_grid_upload and bmhd_remap.
+ * Errors: BMHD_EINVAL, BMHD_ENOMEM (max_blocks too small). */
+int32_t bmhd_adapt(const bmhd_grid *g, const double *h_ind, double r_refine, double r_coarsen, int32_t *h_level,
+                   int32_t *h_ijk, int32_t *h_sim, int32_t max_blocks, int32_t *n_out);
+
 /* d_dt[n_sims] = cfl * min over fluid cells of 1 / sum_d ((|u_d| + c_f,d) / dx) from d_U. */
 int32_t bmhd_reduce_dt(const bmhd_grid *g, const double *d_U, double cfl, double *d_dt, void *stream);
 

@@ -24,7 +24,7 @@ EXPORTS = ["bmhd_version", "bmhd_last_error", "bmhd_grid_create", "bmhd_grid_des
            "bmhd_grid_neighbors", "bmhd_grid_upload", "bmhd_set_state", "bmhd_fill_ghosts", "bmhd_remap",
            "bmhd_reduce_dt", "bmhd_advance", "bmhd_autotune", "bmhd_mlp_last_error", "bmhd_mlp_n_params", "bmhd_mlp_work_bytes",
            "bmhd_mlp_forward", "bmhd_mlp_backward", "bmhd_mlp_backward_noalloc", "bmhd_mlp_adam", "bmhd_mlp_to_bf16", "bmhd_face_data",
-           "bmhd_xchg_create", "bmhd_xchg_destroy", "bmhd_xchg_sizes", "bmhd_xchg_messages", "bmhd_xchg_upload",
+           "bmhd_block_indicator", "bmhd_adapt", "bmhd_xchg_create", "bmhd_xchg_destroy", "bmhd_xchg_sizes", "bmhd_xchg_messages", "bmhd_xchg_upload",
            "bmhd_xchg_interior", "bmhd_xchg_pack", "bmhd_xchg_unpack"]
 
 
@@ -120,6 +120,11 @@ def lib():
     L.bmhd_mlp_adam.restype = i32
     L.bmhd_mlp_to_bf16.argtypes = [vp, vp, ctypes.c_int64, vp]
     L.bmhd_mlp_to_bf16.restype = i32
+    L.bmhd_block_indicator.argtypes = [vp, vp, vp, vp]
+    L.bmhd_block_indicator.restype = i32
+    L.bmhd_adapt.argtypes = [vp, P(ctypes.c_double), ctypes.c_double, ctypes.c_double, P(i32), P(i32), P(i32), i32,
+                             P(i32)]
+    L.bmhd_adapt.restype = i32
     L.bmhd_xchg_create.argtypes = [vp, P(i32), i32, P(vp)]
     L.bmhd_xchg_create.restype = i32
     L.bmhd_xchg_destroy.argtypes = [vp]
@@ -209,6 +214,7 @@ class Grid:
         self.sim = np.ascontiguousarray(sim, np.int32)
         self.nb = int(self.level.shape[0])
         self.ns = len(sims)
+        self.sims = list(sims)
         arr = (SimDesc * self.ns)()
         for i, s in enumerate(sims):
             arr[i].nroot[:] = [int(v) for v in s.nroot]
@@ -288,6 +294,37 @@ class Grid:
         _check(lib().bmhd_remap(self.h, _dev_ptr(U, torch.float64), to.h, _dev_ptr(out, torch.float64),
                                 _stream_ptr(stream)))
         return out
+
+    def block_indicator(self, U, out=None, stream=None):
+        """Refinement indicator per block (device tensor [n_blocks])."""
+        import torch
+        if out is None:
+            out = torch.empty(self.nb, dtype=torch.float64, device=U.device)
+        _check(lib().bmhd_block_indicator(self.h, _dev_ptr(U, torch.float64), _dev_ptr(out, torch.float64),
+                                          _stream_ptr(stream)))
+        return out
+
+    def adapt_blocks(self, ind, r_refine, r_coarsen):
+        """The adapted block list (levels, ijk [n, 3], sims) for host indicators `ind`."""
+        ind = np.ascontiguousarray(ind, np.float64)
+        P = ctypes.POINTER
+        n = ctypes.c_int32()
+        _check(lib().bmhd_adapt(self.h, ind.ctypes.data_as(P(ctypes.c_double)), float(r_refine), float(r_coarsen),
+                                None, None, None, 0, ctypes.byref(n)))
+        cap = int(n.value)
+        lv, ijk, sim = np.empty(cap, np.int32), np.empty(3 * cap, np.int32), np.empty(cap, np.int32)
+        _check(lib().bmhd_adapt(self.h, ind.ctypes.data_as(P(ctypes.c_double)), float(r_refine), float(r_coarsen),
+                                lv.ctypes.data_as(P(ctypes.c_int32)), ijk.ctypes.data_as(P(ctypes.c_int32)),
+                                sim.ctypes.data_as(P(ctypes.c_int32)), cap, ctypes.byref(n)))
+        return lv, ijk.reshape(-1, 3), sim
+
+    def adapt(self, U, r_refine, r_coarsen, stream=None):
+        """One adaptation between steps: indicator on the device, new block list on the host, a new grid
+        (tables uploaded) and the state remapped onto it. Returns (new grid, new state)."""
+        ind = self.block_indicator(U, stream=stream).cpu().numpy()
+        lv, ijk, sim = self.adapt_blocks(ind, r_refine, r_coarsen)
+        new = Grid(lv, ijk, sim, self.sims).upload(device=U.device, stream=stream)
+        return new, self.remap(U, new, stream=stream)
 
     def reduce_dt(self, U, cfl, dt=None, stream=None):
         import torch

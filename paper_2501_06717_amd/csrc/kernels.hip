@@ -21,6 +21,7 @@
 // handed a contiguous run of the Morton-ordered block schedule and neighbouring blocks share an L2.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -398,6 +399,51 @@ __global__ void __launch_bounds__(512) k_remap(Tables F, const double *__restric
     const size_t vs = size_t(N.nb) * 512, off = size_t(b) * 512 + c;
 #pragma unroll
     for (int v = 0; v < 8; ++v) Un[v * vs + off] = u[v];
+}
+
+// Refinement indicator per block: the largest normalised jump, over its cells and the three axes, of the
+// density and of |B|^2 between a cell's two face neighbours (neighbours outside the block by the ghost
+// rules): |q+ - q-| / (q+ + q- + 1e-300). One workgroup per block, one thread per cell. No contraction: the
+// value equals the host-side reference bit for bit.
+__global__ void __launch_bounds__(512) k_block_indicator(Tables T, const double *__restrict__ U, double *__restrict__ ind) {
+#pragma clang fp contract(off)
+    __shared__ double red[8];
+    const int b = blockIdx.x, c = threadIdx.x;
+    const DevBlock &B = T.blocks[b];
+    const DevSim &S = T.sims[B.sim];
+    const size_t vs = size_t(T.nb) * 512;
+    const Cursor cur{&T, U, vs};
+    const int ii[3] = {c & 7, (c >> 3) & 7, c >> 6};
+    double m = 0.0;
+    for (int d = 0; d < 3; ++d) {
+        double q[2][8];
+        for (int side = 0; side < 2; ++side) {
+            int n[3] = {ii[0], ii[1], ii[2]};
+            n[d] += side ? 1 : -1;
+            if ((unsigned)n[d] < 8u) {
+                const size_t off = size_t(b) * 512 + (n[2] * 8 + n[1]) * 8 + n[0];
+                for (int v = 0; v < 8; ++v) q[side][v] = U[v * vs + off];
+            } else {
+                const long long G[3] = {(long long)B.ijk[0] * 8 + n[0], (long long)B.ijk[1] * 8 + n[1],
+                                        (long long)B.ijk[2] * 8 + n[2]};
+                ghost_cell(cur, S, B.level, G, q[side]);
+            }
+        }
+        const double rp = q[1][0], rm = q[0][0];
+        const double bp = q[1][4] * q[1][4] + q[1][5] * q[1][5] + q[1][6] * q[1][6];
+        const double bm = q[0][4] * q[0][4] + q[0][5] * q[0][5] + q[0][6] * q[0][6];
+        const double jr = fabs(rp - rm) / (rp + rm + 1e-300);
+        const double jb = fabs(bp - bm) / (bp + bm + 1e-300);
+        m = fmax(m, fmax(jr, jb));
+    }
+    for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o));
+    if ((c & 63) == 0) red[c >> 6] = m;
+    __syncthreads();
+    if (c == 0) {
+        double r = red[0];
+        for (int w = 1; w < 8; ++w) r = fmax(r, red[w]);
+        ind[b] = r;
+    }
 }
 
 __global__ void __launch_bounds__(128) k_halo_fill(Tables T, const double *__restrict__ U) {
@@ -2237,6 +2283,53 @@ int32_t bmhd_remap(const bmhd_grid *from, const double *d_U_from, const bmhd_gri
     if (t.nb == 0) return BMHD_OK;
     k_remap<<<t.nb, 512, 0, reinterpret_cast<hipStream_t>(stream)>>>(f.dev, d_U_from, t.dev, d_U_to);
     return launch_check("remap");
+}
+
+int32_t bmhd_block_indicator(const bmhd_grid *g, const double *d_U, double *d_ind, void *stream) {
+    if (int32_t rc = need_upload(g)) return rc;
+    if (!ptr_ok(d_U) || !ptr_ok(d_ind)) return fail(BMHD_EINVAL, "block_indicator: null or misaligned buffer");
+    if (g->h.nb == 0) return BMHD_OK;
+    k_block_indicator<<<g->h.nb, 512, 0, reinterpret_cast<hipStream_t>(stream)>>>(g->h.dev, d_U, d_ind);
+    return launch_check("block indicator");
+}
+
+int32_t bmhd_adapt(const bmhd_grid *g, const double *h_ind, double r_refine, double r_coarsen, int32_t *h_level,
+                   int32_t *h_ijk, int32_t *h_sim, int32_t max_blocks, int32_t *n_out) {
+    if (!g || !h_ind || !n_out || !(r_coarsen <= r_refine)) return fail(BMHD_EINVAL, "adapt: bad arguments");
+    const HostGrid &h = g->h;
+    int64_t n = 0;
+    for (int s = 0; s < h.ns; ++s) {
+        const DevSim &S = h.sims[s];
+        for (int64_t z = 0; z < S.nroot[2]; ++z)
+            for (int64_t y = 0; y < S.nroot[1]; ++y)
+                for (int64_t x = 0; x < S.nroot[0]; ++x) {
+                    const int32_t root = host_lut(h, s, 0, x, y, z);
+                    bool refine;
+                    if (root >= 0) {
+                        refine = h_ind[root] >= r_refine;
+                    } else {
+                        double m = 0.0;
+                        for (int q = 0; q < 8; ++q) {
+                            const int32_t c = host_lut(h, s, 1, 2 * x + (q & 1), 2 * y + ((q >> 1) & 1), 2 * z + (q >> 2));
+                            if (c < 0) return fail(BMHD_EINVAL, "adapt: a root is neither a block nor 8 children");
+                            m = std::max(m, h_ind[c]);
+                        }
+                        refine = !(m < r_coarsen);
+                    }
+                    const int add = refine ? 8 : 1;
+                    if (h_level && n + add > max_blocks) return fail(BMHD_ENOMEM, "adapt: output arrays too small");
+                    for (int q = 0; q < add; ++q, ++n) {
+                        if (!h_level) continue;
+                        h_level[n] = refine ? 1 : 0;
+                        h_ijk[3 * n + 0] = int32_t(refine ? 2 * x + (q & 1) : x);
+                        h_ijk[3 * n + 1] = int32_t(refine ? 2 * y + ((q >> 1) & 1) : y);
+                        h_ijk[3 * n + 2] = int32_t(refine ? 2 * z + (q >> 2) : z);
+                        h_sim[n] = s;
+                    }
+                }
+    }
+    *n_out = int32_t(n);
+    return BMHD_OK;
 }
 
 int32_t bmhd_reduce_dt(const bmhd_grid *g, const double *d_U, double cfl, double *d_dt, void *stream) {
