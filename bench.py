@@ -35,6 +35,7 @@ HBM_PEAK_GBS = 8000.0
 TRAFFIC = {
     ("face", 8): (1.722e9 + 1.074e9, 2.807e9 + 1.074e9),
     ("plane", 4): (2.019e9 + 1.074e9, 3.007e9 + 1.074e9),
+    ("block", 8): (2.336e9 + 1.073e9, 3.381e9 + 1.073e9),
 }
 
 
@@ -42,7 +43,7 @@ TRAFFIC = {
 # stages, SQ_INSTS_VALU x 64 / cells from a rocprofv3 counter run; the summary under profiles/), keyed
 # like TRAFFIC; the VALU issue peak is one wave64 instruction per CU per clock (4 SIMDs x 16 lanes):
 # 256 CUs x 2.4 GHz x 64 lanes
-VALU_PER_CELL_STAGE = {("plane", 4): 1917.0}
+VALU_PER_CELL_STAGE = {("plane", 4): 1917.0, ("block", 8): 2138.0}
 VALU_PEAK_LANE_OPS = 256 * 2.4e9 * 64
 
 
