@@ -96,8 +96,11 @@ typedef struct {
  * every face (primitives in the face-normal frame (rho, u_n, u_t1, u_t2, B_n, B_t1, B_t2, p), z-scored
  * with stats[0..63]) goes through the MLP; its output, de-normalised with stats[64..79] and rotated back,
  * is added to the face flux. Cells whose provisional state has rho <= 0 or p <= 0, or rho or p outside
- * [min - tau * range, max + tau * range] of their old 7-point neighbourhood, are flagged; every face of a
- * flagged cell falls back to the plain flux on both sides and the affected cells are recomputed once. */
+ * [min - tau * h, max + tau * h] of their old 7-point neighbourhood (FP64 values of the stage input),
+ * with h = max(max - min, floor_rel * max(|min|, |max|)), are flagged; every face of a flagged cell falls
+ * back to the plain flux on both sides and the affected cells are recomputed once. The flux scheme (the
+ * second-order scheme of Sec. 5.1 with HLLE or Rusanov) is the paper's; the correction is this library's
+ * own form. */
 typedef struct {
     int32_t hidden;              /* 32, 64 or 128 */
     int32_t mode;                /* 0: BF16 matrix cores, 1: FP32 reference, 2: no network: y_buf holds
@@ -112,6 +115,9 @@ typedef struct {
     uint8_t *flags;              /* device scratch [n_blocks * 512] */
     int32_t *fallback_cells;     /* device counter of flagged cells, incremented per stage (may be NULL) */
     double tau;                  /* tolerance of the neighbourhood bound (0.1) */
+    double floor_rel;            /* least neighbourhood range, relative to its largest magnitude (>= 0;
+                                    0: the range itself, which rejects any change where the old
+                                    neighbourhood is uniform) */
 } bmhd_learned;
 
 typedef struct {

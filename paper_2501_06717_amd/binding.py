@@ -44,7 +44,7 @@ class Learned(ctypes.Structure):
     _fields_ = [("hidden", ctypes.c_int32), ("mode", ctypes.c_int32), ("params", ctypes.c_void_p),
                 ("params_bf16", ctypes.c_void_p), ("stats", ctypes.c_void_p), ("x_buf", ctypes.c_void_p),
                 ("y_buf", ctypes.c_void_p), ("flags", ctypes.c_void_p), ("fallback_cells", ctypes.c_void_p),
-                ("tau", ctypes.c_double)]
+                ("tau", ctypes.c_double), ("floor_rel", ctypes.c_double)]
 
 
 class Opts(ctypes.Structure):
@@ -357,7 +357,7 @@ class Grid:
                                     _stream_ptr(stream)))
         return X, F
 
-    def learned(self, mlp, stats, mode="bf16", tau=0.1, fallback=None):
+    def learned(self, mlp, stats, mode="bf16", tau=0.1, fallback=None, floor_rel=0.0):
         """Scratch buffers and the options struct of the learned correction for this grid."""
         import torch
         nf = self.nb * 1728
@@ -377,9 +377,10 @@ class Grid:
         L.flags = self._lf.data_ptr()
         L.fallback_cells = fallback.data_ptr() if fallback is not None else None
         L.tau = float(tau)
+        L.floor_rel = float(floor_rel)
         return L
 
-    def given_corrections(self, y, stats, tau=0.1, fallback=None):
+    def given_corrections(self, y, stats, tau=0.1, fallback=None, floor_rel=0.0):
         """Options of the learned form with the normalised flux corrections y [n_blocks * 1728, 8] float32
         (face-normal frame, the face order of bmhd_face_data) given instead of a network's outputs."""
         import torch
@@ -396,6 +397,7 @@ class Grid:
         L.flags = self._lf.data_ptr()
         L.fallback_cells = fallback.data_ptr() if fallback is not None else None
         L.tau = float(tau)
+        L.floor_rel = float(floor_rel)
         return L
 
     def autotune(self, U0, U1, dt, n_steps=3, stream=None, **kw):

@@ -615,6 +615,7 @@ struct StageArgs {
     const float *lrn_stats;  // in_mean[32], in_std[32], out_mean[8], out_std[8]
     uint8_t *lrn_flags;      // per cell: provisional state rejected
     double tau;
+    double floor_rel;        // the neighbourhood range is at least floor_rel times its largest magnitude
     // work list of the launch: a part of the Morton schedule (block ids), or null for all of T.order
     const int32_t *sched;
     int32_t n_sched;
@@ -870,9 +871,10 @@ __device__ __forceinline__ void gather_store(const Tables &T, int b, int slab, c
 }
 
 // Range of density and pressure over the old 7-point neighbourhood of slab cell tid (learned
-// correction's acceptance test): rng = {rho min, rho max, p min, p max}.
-template <int KS, typename R>
-__device__ __forceinline__ void neighbour_range(R (*sW)[Slab<KS>::NC], int tid, double rng[4]) {
+// correction's acceptance test): rng = {rho min, rho max, p min, p max}, from the slab arrays `rho` and
+// `p` (the LDS primitives, or their FP64 copies in the FP32-flux form).
+template <int KS, typename V>
+__device__ __forceinline__ void neighbour_range(const V *rho, const V *p, int tid, double rng[4]) {
     using SL = Slab<KS>;
     const int i = tid & 7, j = (tid >> 3) & 7, kk = tid >> 6;
     const int nb7[7] = {SL::idx(i, j, kk), SL::idx(i - 1, j, kk), SL::idx(i + 1, j, kk), SL::idx(i, j - 1, kk),
@@ -880,11 +882,31 @@ __device__ __forceinline__ void neighbour_range(R (*sW)[Slab<KS>::NC], int tid, 
     double rlo = 1e300, rhi = -1e300, plo = 1e300, phi = -1e300;
 #pragma unroll
     for (int q = 0; q < 7; ++q) {
-        const double r0 = double(sW[0][nb7[q]]), p0 = double(sW[7][nb7[q]]);
+        const double r0 = double(rho[nb7[q]]), p0 = double(p[nb7[q]]);
         rlo = fmin(rlo, r0); rhi = fmax(rhi, r0);
         plo = fmin(plo, p0); phi = fmax(phi, p0);
     }
     rng[0] = rlo; rng[1] = rhi; rng[2] = plo; rng[3] = phi;
+}
+
+// Acceptance test of a provisional state under the learned correction: density r and pressure p positive
+// and each inside [lo - tau h, hi + tau h] of its old neighbourhood range nr, where h is the range widened
+// to at least floor_rel * max(|lo|, |hi|) (so that a uniform neighbourhood still admits a small change).
+// Evaluated without contraction: the decision is the one plain FP64 arithmetic takes.
+__device__ __forceinline__ bool learned_rejects(double r, double p, const double nr[4], double tau,
+                                                double floor_rel) {
+#pragma clang fp contract(off)
+    bool bad = !(r > 0.0) || !(p > 0.0);
+#pragma unroll
+    for (int m = 0; m < 2; ++m) {
+        const double lo = nr[2 * m], hi = nr[2 * m + 1], v = m ? p : r;
+        double h = hi - lo;
+        const double fh = floor_rel * fmax(fabs(lo), fabs(hi));
+        if (fh > h) h = fh;
+        const double band = tau * h;
+        bad = bad || v < lo - band || v > hi + band;
+    }
+    return bad;
 }
 
 // Powell source, stage update and write of the thread's own cell (threads below 64 KS own cell tid of
@@ -962,12 +984,9 @@ __device__ __forceinline__ void cell_update(const Tables &T, const StageArgs &A,
 #pragma unroll
                     for (int q = 0; q < 4; ++q) nr[q] = rng[q];
                 } else {
-                    neighbour_range<KS, R>(sW, tid, nr);
+                    neighbour_range<KS, R>(sW[0], sW[7], tid, nr);
                 }
-                const double rlo = nr[0], rhi = nr[1], plo = nr[2], phi = nr[3];
-                const double rr = A.tau * (rhi - rlo), pr = A.tau * (phi - plo);
-                bad = !(w[0] > 0.0) || !(w[7] > 0.0) || w[0] < rlo - rr || w[0] > rhi + rr || w[7] < plo - pr ||
-                      w[7] > phi + pr;
+                bad = learned_rejects(w[0], w[7], nr, A.tau, A.floor_rel);
             }
             A.lrn_flags[off] = bad ? 1 : 0;
         }
@@ -1090,10 +1109,10 @@ __global__ void __launch_bounds__(Slab<KS>::NT) k_stage(Tables T, StageArgs A) {
 // normal field). LDS per slab of four layers: 51.6 KB in FP64, small enough for three workgroups per CU.
 
 // Convert the gathered conserved values to primitives in LDS and set one body-mask bit per cell.
-template <int KS, typename R>
+template <int KS, typename R, bool RP = false>
 __device__ __forceinline__ void gather_store_bits(const Tables &T, int b, int slab,
                                                   const double (&u)[Slab<KS>::NPT][8], R (*sW)[Slab<KS>::NC],
-                                                  uint32_t *sMb) {
+                                                  uint32_t *sMb, double *rp = nullptr) {
     using SL = Slab<KS>;
     const DevBlock &B = T.blocks[b];
     const bool near_body = (B.flags & BF_NEAR_BODY) != 0;
@@ -1107,6 +1126,10 @@ __device__ __forceinline__ void gather_store_bits(const Tables &T, int b, int sl
         cons_to_prim(u[m], w);
 #pragma unroll
         for (int v = 0; v < 8; ++v) sW[v][c] = R(w[v]);
+        if constexpr (RP) {
+            rp[c] = w[0];
+            rp[SL::NC + c] = w[7];
+        }
         if (near_body) {
             int i, j, k;
             SL::decode(c, i, j, k);
@@ -1134,7 +1157,7 @@ __device__ __forceinline__ R lane_down(R x, int delta) { return __shfl_down(x, d
 template <int KS, typename R, int FLUX, bool POWELL, bool LEARN>
 __device__ __forceinline__ void wp_compute(const Tables &T, const StageArgs &A, int b, int slab,
                                            R (*sW)[Slab<KS>::NC], R (*sH)[8 * KS], const uint32_t *sMb, double *red,
-                                           int *redi) {
+                                           int *redi, const double *rp = nullptr) {
     using SL = Slab<KS>;
     constexpr int NE = 8 * KS;
     const DevBlock &B = T.blocks[b];
@@ -1149,10 +1172,15 @@ __device__ __forceinline__ void wp_compute(const Tables &T, const StageArgs &A, 
     double rhs[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     double divb = 0.0;
     R fl[8], fr[8], bb, bbr;
-    // learned correction: the old neighbourhood range, taken before the x/y halos are overwritten
+    // learned correction: the old neighbourhood range, taken before the x/y halos are overwritten (from the
+    // FP64 copies of density and pressure when the LDS primitives are FP32)
     double rng[4] = {0, 0, 0, 0};
-    if constexpr (LEARN)
-        if (cellw) neighbour_range<KS, R>(sW, tid, rng);
+    if constexpr (LEARN) {
+        if (cellw) {
+            if constexpr (sizeof(R) == 4) neighbour_range<KS, double>(rp, rp + SL::NC, tid, rng);
+            else neighbour_range<KS, R>(sW[0], sW[7], tid, rng);
+        }
+    }
 
     // x: low-x face of each cell; the last wave takes the faces at x = 8 of the slab's 8 KS rows
     if (cellw) {
@@ -1266,6 +1294,9 @@ __global__ void __launch_bounds__(64 * (KS + 1), (wp_waves_per_simd<KS, R>())) k
     __shared__ uint32_t sMb[SL::NC / 32];
     __shared__ double red[KS + 1];
     __shared__ int redi[KS + 1];
+    // learned FP32-flux form: FP64 density and pressure of the gathered cells, for the acceptance test
+    constexpr bool RP = LEARN && sizeof(R) == 4;
+    __shared__ double sRP[RP ? 2 * SL::NC : 1];
 
     const int nwork = sched_count(T, A) * S_PER_BLOCK;
     const int wg = blockIdx.x, xcd = wg & 7, slot = wg >> 3;
@@ -1276,11 +1307,12 @@ __global__ void __launch_bounds__(64 * (KS + 1), (wp_waves_per_simd<KS, R>())) k
         {
             double u[SL::NPT][8];
             gather_issue<KS>(T, A, b, slab, u);
-            gather_store_bits<KS, R>(T, b, slab, u, sW, sMb);
+            gather_store_bits<KS, R, RP>(T, b, slab, u, sW, sMb, sRP);
         }
         __syncthreads();
-        wp_compute<KS, R, FLUX, POWELL, LEARN>(T, A, b, slab, sW, sH, sMb, red, redi);
+        wp_compute<KS, R, FLUX, POWELL, LEARN>(T, A, b, slab, sW, sH, sMb, red, redi, sRP);
     } else {
+        static_assert(!LEARN, "the learned correction runs one workgroup per slab");
         const int step = int(gridDim.x >> 3);
 #pragma nounroll
         for (int it = slot; it < count; it += step) {
@@ -1968,6 +2000,7 @@ int32_t check_opts(const bmhd_opts &o) {
         if (L.mode == 0 && (reinterpret_cast<uintptr_t>(L.x_buf) & 15u))
             return fail(BMHD_EINVAL, "learned: x_buf must be 16-byte aligned");
         if (!(L.tau >= 0.0)) return fail(BMHD_EINVAL, "learned: tau must be >= 0");
+        if (!(L.floor_rel >= 0.0)) return fail(BMHD_EINVAL, "learned: floor_rel must be >= 0");
         if (o.use_graph) return fail(BMHD_EUNSUPPORTED, "learned correction is not captured in graphs");
         if (o.local_dt) return fail(BMHD_EUNSUPPORTED, "learned correction with local time stepping");
         if (o.flux == BMHD_FLUX_LINDE) return fail(BMHD_EUNSUPPORTED, "learned correction is added to the HLLE or Rusanov flux");
@@ -2007,6 +2040,7 @@ int32_t enqueue_stage(const HostGrid &h, const bmhd_opts &o, int e, double *d_U0
         a.lrn_stats = L.stats;
         a.lrn_flags = L.flags;
         a.tau = L.tau;
+        a.floor_rel = L.floor_rel;
         a.want_lam = 0;
         const int count = a.count_faults;
         a.count_faults = 0;

@@ -278,3 +278,63 @@ def test_learned_stage_matches_the_oracle(bd, oracle_mod, flux):
     assert 0.05 * 2 * wl.n_cells <= rflag <= 0.3 * 2 * wl.n_cells
     assert nflag == rflag
     assert max(err.values()) <= 1e-12, err
+
+
+@pytest.mark.parametrize("floor_rel", [0.0, 0.02])
+def test_range_floor_matches_the_oracle(bd, oracle_mod, floor_rel):
+    """The acceptance test's range floor against the oracle: density and pressure uniform, velocity and
+    field of random sign per cell (every old 7-point range is zero), corrections given per face. With no
+    floor every cell whose density or pressure changes at all is flagged; with the floor h = floor_rel *
+    max(|lo|, |hi|) only changes beyond tau * h are. Flag counts equal the oracle's and states agree to
+    1e-12 per variable group."""
+    base = wk.uniform_state((2, 2, 2))
+    wl = wk.with_state(base, wk.uniform_bound_state(base, seed=41, rho=1.1, p=0.7, u0=0.002, b0=0.002))
+    o = oracle_mod.Grid.from_workload(wl)
+    R0 = o.set_state(wl.W)
+    R1 = np.zeros_like(R0)
+    rng = np.random.default_rng(42)
+    y = (np.round(rng.normal(size=(wl.n_blocks * 1728, 8)) * 64.0) / 64.0).astype(np.float32)
+    ystats = np.zeros(16)
+    ystats[8:16] = 2.0 ** -8
+    rdt, rf, rflag = o.advance_learned(R0, R1, [0.0], 2, y.astype(np.float64), ystats, tau=0.1,
+                                       floor_rel=floor_rel, flux="hlle", powell=True)
+    g = bd.Grid.from_workload(wl).upload()
+    U0 = dev(o.set_state(wl.W))
+    U1 = torch.zeros_like(U0)
+    dt = torch.zeros(1, dtype=torch.float64, device="cuda")
+    fb = torch.zeros(1, dtype=torch.int32, device="cuda")
+    stats = torch.zeros(80)
+    stats[72:80] = torch.from_numpy(ystats[8:].astype(np.float32))
+    L = g.given_corrections(dev(y), stats, tau=0.1, fallback=fb, floor_rel=floor_rel)
+    g.advance(U0, U1, dt, 2, flux="hlle", powell=True, learned=L, scheme="plane", slab=4)
+    torch.cuda.synchronize()
+    err = _group_err(U0.cpu().numpy(), R0)
+    nflag = int(fb.item())
+    print("floor", floor_rel, "flagged", nflag, "oracle", rflag, "of", 2 * wl.n_cells, err, flush=True)
+    assert nflag == rflag
+    # (the oracle flags 7,369 and 2,765 of 8,192 cell-stages)
+    if floor_rel == 0.0:
+        assert rflag >= 0.8 * 2 * wl.n_cells
+    else:
+        assert 0.1 * 2 * wl.n_cells <= rflag <= 0.5 * 2 * wl.n_cells
+    assert max(err.values()) <= 1e-12, err
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_flux"])
+def test_unchanged_uniform_state_is_never_flagged(bd, precision):
+    """A uniform state whose density and pressure are not FP32 numbers (1.1, 0.7) stays exactly as it is
+    under zero corrections, in both precisions: the acceptance test compares it with the FP64 range of
+    its neighbourhood, so no cell is flagged even with no range floor."""
+    wl = wk.uniform_state((2, 2, 2), W0=(1.1, 0.1, -0.2, 0.3, 0.5, -0.4, 0.3, 0.7))
+    g = bd.Grid.from_workload(wl).upload()
+    U0 = g.set_state(dev(wl.W))
+    Uref = U0.clone()
+    U1 = torch.zeros_like(U0)
+    dt = torch.zeros(1, dtype=torch.float64, device="cuda")
+    fb = torch.zeros(1, dtype=torch.int32, device="cuda")
+    y = torch.zeros((wl.n_blocks * 1728, 8), dtype=torch.float32, device="cuda")
+    L = g.given_corrections(y, torch.zeros(80), tau=0.1, fallback=fb)
+    g.advance(U0, U1, dt, 2, flux="hlle", powell=True, learned=L, precision=precision)
+    torch.cuda.synchronize()
+    assert int(fb.item()) == 0
+    assert torch.equal(U0, Uref)
