@@ -79,10 +79,15 @@ def from_global(G, nb):
 
 def restrict(Uf, nbf):
     """Mean of the 8 fine cells of each coarse cell (conserved variables)."""
+    return restrict_by(Uf, nbf, 2)
+
+
+def restrict_by(Uf, nbf, k):
+    """Mean of the k^3 fine cells of each coarse cell (conserved variables); nbf^3 fine blocks of 8^3."""
     G = to_global(Uf, nbf)
-    n = G.shape[1] // 2
-    Gc = G.reshape(8, n, 2, n, 2, n, 2).mean(dim=(2, 4, 6))
-    return from_global(Gc, nbf // 2)
+    n = G.shape[1] // k
+    Gc = G.reshape(8, n, k, n, k, n, k).mean(dim=(2, 4, 6))
+    return from_global(Gc, nbf // k)
 
 
 def faces_global(F, nb, d, c):
@@ -141,6 +146,7 @@ class Config:
     hidden: int = 128
     epochs: int = 24
     strength: float = 0.25         # the correction applied is this fraction of the network's output
+    floor_rel: float = 0.01        # least neighbourhood range of the acceptance test, relative to its magnitude
     batch: int = 4096
     lr: float = 1e-3
     seed_train: int = 5
@@ -300,13 +306,13 @@ def train(bd, cfg: Config, X, T, log=print, init=None):
     return mlp, stats, hist
 
 
-def one_step_gain(bd, cfg: Config, mlp, stats, st, warm_steps=100):
-    """Local (one coarse step) error: from the restricted fine state after `warm_steps` fine steps, one
-    coarse step (dt = 2 fine dt) plain and learned against the fine run advanced two steps and restricted.
-    L1 of the change of state, per variable, relative to the fine change."""
+def developed_state(bd, st, n_fine, warm_steps=100):
+    """The fine run of solar-wind state `st` after `warm_steps` fine steps (HLLE + Powell, CFL 0.8) and its
+    restriction to the coarse grid: (fine grid, coarse grid, coarse workload, fine state, the fine dt of
+    that state, restricted coarse state). The flow has then left the uniform start."""
     import torch
-    nbf = cfg.n_fine // 8
-    fine, coarse = magnetosphere_pair(st, cfg.n_fine)
+    nbf = n_fine // 8
+    fine, coarse = magnetosphere_pair(st, n_fine)
     gf = bd.Grid.from_workload(fine).upload()
     gc = bd.Grid.from_workload(coarse).upload()
     Uf = gf.set_state(torch.from_numpy(fine.W).cuda())
@@ -314,17 +320,30 @@ def one_step_gain(bd, cfg: Config, mlp, stats, st, warm_steps=100):
     dtf = torch.zeros(1, dtype=torch.float64, device="cuda")
     gf.advance(Uf, U1, dtf, 2 * warm_steps, flux="hlle", powell=True, cfl=0.8)
     dtf = gf.reduce_dt(Uf, 0.8)
-    Uc0 = restrict(Uf, nbf)
+    return gf, gc, coarse, Uf, dtf, restrict(Uf, nbf)
+
+
+def one_step_gain(bd, cfg: Config, mlp, stats, st, warm_steps=100):
+    """Local (one coarse step) error: from the restricted fine state after `warm_steps` fine steps, one
+    coarse step (dt = 2 fine dt) plain and learned against the fine run advanced two steps and restricted.
+    L1 of the change of state, per variable, relative to the fine change; and the flagged share of the
+    learned step's cell-stages."""
+    import torch
+    nbf = cfg.n_fine // 8
+    gf, gc, coarse, Uf, dtf, Uc0 = developed_state(bd, st, cfg.n_fine, warm_steps)
+    U1 = torch.empty_like(Uf)
     gf.advance(Uf, U1, dtf, 4, flux="hlle", powell=True, recompute_dt=False)
     dref = restrict(Uf, nbf) - Uc0
     out = {}
-    for name, learned in (("plain", None), ("learned", gc.learned(mlp, stats))):
+    fb = torch.zeros(1, dtype=torch.int32, device="cuda")
+    for name, learned in (("plain", None), ("learned", gc.learned(mlp, stats, fallback=fb, floor_rel=cfg.floor_rel))):
         U = Uc0.clone()
         Ub = torch.empty_like(U)
         gc.advance(U, Ub, dtf * 2.0, 2, flux="hlle", powell=True, recompute_dt=False, learned=learned)
         d = U - Uc0
         out[name] = [float((d[v] - dref[v]).abs().sum() / dref[v].abs().sum()) for v in range(8)]
     out["gain"] = float(np.mean(out["plain"]) / max(np.mean(out["learned"]), 1e-300))
+    out["flagged_share"] = int(fb.item()) / (2.0 * coarse.n_cells)
     return out
 
 
@@ -347,15 +366,8 @@ def exact_target_one_step(bd, cfg: Config, st, warm_steps=100):
     the learned stage as its correction: the best a correction of this form can do from this state."""
     import torch
     nbf, nbc = cfg.n_fine // 8, cfg.n_fine // 16
-    fine, coarse = magnetosphere_pair(st, cfg.n_fine)
-    gf = bd.Grid.from_workload(fine).upload()
-    gc = bd.Grid.from_workload(coarse).upload()
-    Uf = gf.set_state(torch.from_numpy(fine.W).cuda())
+    gf, gc, coarse, Uf, dtf, Uc0 = developed_state(bd, st, cfg.n_fine, warm_steps)
     U1 = torch.empty_like(Uf)
-    dtf = torch.zeros(1, dtype=torch.float64, device="cuda")
-    gf.advance(Uf, U1, dtf, 2 * warm_steps, flux="hlle", powell=True, cfl=0.8)
-    dtf = gf.reduce_dt(Uf, 0.8)
-    Uc0 = restrict(Uf, nbf)
     _, Fc = gc.face_data(Uc0, flux="hlle", want_x=False)
     _, Ff = gf.face_data(Uf, flux="hlle", want_x=False)
     ys = []
@@ -399,7 +411,9 @@ def evaluate(bd, cfg: Config, mlp, stats, states, log=print):
         del U1
         dtc = dtf * 2.0
         res = {}
-        for name, learned in (("plain", None), ("learned", gc.learned(mlp, stats))):
+        fb = torch.zeros(1, dtype=torch.int32, device="cuda")
+        for name, learned in (("plain", None),
+                              ("learned", gc.learned(mlp, stats, fallback=fb, floor_rel=cfg.floor_rel))):
             U = Uc0.clone()
             Ub = torch.empty_like(U)
             dt = dtc.clone()
@@ -409,6 +423,7 @@ def evaluate(bd, cfg: Config, mlp, stats, states, log=print):
             torch.cuda.synchronize()
             l1 = [float((U[v] - ref[v]).abs().sum() / ref[v].abs().sum()) for v in range(8)]
             res[name] = {"l1_rel_mean": float(np.mean(l1)), "l1_rel": l1, "faults": int(faults.item())}
+        res["learned"]["flagged_share"] = int(fb.item()) / (float(cfg.fine_steps) * coarse.n_cells)  # per stage
         res["gain"] = res["plain"]["l1_rel_mean"] / max(res["learned"]["l1_rel_mean"], 1e-300)
         res["one_step"] = one_step_gain(bd, cfg, mlp, stats, st)
         res["one_step_exact_target"] = exact_target_one_step(bd, cfg, st)
@@ -416,6 +431,56 @@ def evaluate(bd, cfg: Config, mlp, stats, states, log=print):
             f"gain {res['gain']:.3f}; one-step gain {res['one_step']['gain']:.3f} (exact target: "
             f"{res['one_step_exact_target']['gain']:.3f})")
         out.append(res)
+    return out
+
+
+def equal_cost(bd, cfg: Config, mlp, stats, st, coarse_steps=100, n_ref=384):
+    """The learned coarse run beside a plain run on a finer grid of about the same cost. Plain and learned
+    at 128^3 and plain at 192^3 ((3/2)^4 = 5.06 times the plain 128^3 work per unit of simulated time)
+    advance from the n_ref^3 initial state restricted, to the time of `coarse_steps` coarse steps, with
+    the n_ref^3 run's CFL-0.8 step scaled by the cell size (the dt of every run is that run's CFL 0.8);
+    each is compared with the n_ref^3 run restricted to its grid. Returns per run: relative L1 error
+    (mean over the 8 conserved variables) and wall time."""
+    import time
+    import torch
+    ref_wl = wk.magnetosphere(n_ref, **st)
+    nbr = n_ref // 8
+    gr = bd.Grid.from_workload(ref_wl).upload()
+    Ur = gr.set_state(torch.from_numpy(ref_wl.W).cuda())
+    dtr = gr.reduce_dt(Ur, 0.8)
+    runs = {}
+    for name, n, learned in (("plain_128", 128, False), ("learned_128", 128, True), ("plain_192", 192, False)):
+        k = n_ref // n
+        assert k * n == n_ref
+        sim = wk.magnetosphere_sim(n, **st)
+        lv, ijk, sid = wk.uniform_blocks(sim.nroot)
+        wl = wk.Workload(f"coarse_{n}", lv, ijk, sid, [sim], None, flux="hlle", powell=True, cfl=0.8)
+        runs[name] = dict(n=n, k=k, learned=learned, grid=bd.Grid.from_workload(wl).upload(),
+                          U=restrict_by(Ur, nbr, k), steps=coarse_steps * (n_ref // 128) // k)
+    Ub = torch.empty_like(Ur)
+    gr.advance(Ur, Ub, dtr, 2 * coarse_steps * (n_ref // 128), flux="hlle", powell=True, recompute_dt=False)
+    del Ub
+    out = {}
+    for name, r in runs.items():
+        g, U = r["grid"], r["U"]
+        Ub = torch.empty_like(U)
+        fb = torch.zeros(1, dtype=torch.int32, device="cuda")
+        L = g.learned(mlp, stats, fallback=fb, floor_rel=cfg.floor_rel) if r["learned"] else None
+        dt = dtr * float(r["k"])
+        g.advance(U.clone(), Ub, dt, 2, flux="hlle", powell=True, recompute_dt=False, learned=L)  # warm-up
+        fb.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        g.advance(U, Ub, dt, 2 * r["steps"], flux="hlle", powell=True, recompute_dt=False, learned=L)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        ref = restrict_by(Ur, nbr, r["k"])
+        l1 = [float((U[v] - ref[v]).abs().sum() / ref[v].abs().sum()) for v in range(8)]
+        out[name] = {"cells": r["n"] ** 3, "steps": r["steps"], "wall_s": wall, "l1_rel_mean": float(np.mean(l1))}
+        if r["learned"]:
+            out[name]["flagged_share"] = int(fb.item()) / (2.0 * r["steps"] * r["n"] ** 3)
+        del Ub
+    out["reference"] = f"{n_ref}^3 FP64 run restricted, same time"
     return out
 
 
