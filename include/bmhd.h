@@ -183,16 +183,23 @@ const char *bmhd_last_error(void);
 int32_t bmhd_grid_create(const bmhd_grid_desc *desc, bmhd_grid **out);
 void bmhd_grid_destroy(bmhd_grid *g);
 
+/* Sizes of the tables bmhd_grid_create built (the grid information of Sec. 2 that the message passing of
+ * Sec. 4.2 and 4.4 looks up per block and direction), and the device workspace they need. Host only.
+ * Errors: BMHD_EINVAL for a null argument. */
 int32_t bmhd_grid_info_get(const bmhd_grid *g, bmhd_grid_info *info);
 
-/* Neighbour table into host memory h_out[n_blocks][26][5]: {relation, id0, id1, id2, id3} for the 26
+/* The relation to the neighbour in each direction, the lookup Sec. 4.2 makes per block and direction
+ * (same, finer or coarser resolution, or a domain boundary), as a neighbour table in host memory
+ * h_out[n_blocks][26][5] (caller-owned): {relation, id0, id1, id2, id3} for the 26
  * directions (dx, dy, dz) in {-1,0,1}^3 \ {0}, enumerated with dx fastest. SAME/COARSER: id0 is the
  * neighbour. FINER: the finer blocks that touch the block, ordered x fastest over the free
  * sub-positions. OUTFLOW/INFLOW: the direction leaves the domain through a non-periodic face (the
  * first such axis in x, y, z order decides). Unused ids are -1. */
 int32_t bmhd_grid_neighbors(const bmhd_grid *g, int32_t *h_out);
 
-/* Copy the tables into the caller's device workspace d_work (work_bytes from bmhd_grid_info_get,
+/* Send the tables built on the CPU to the GPU (Sec. 4.4 fills its maps on the CPU and sends them; Sec. 3.1
+ * keeps everything the time loop reads resident on the GPU). Copies the tables into the caller's device
+ * workspace d_work (work_bytes from bmhd_grid_info_get,
  * 256-byte aligned) on `stream`. The grid keeps d_work as a borrowed pointer: it must stay allocated
  * while the grid is used, and upload must be repeated if it moves. The host tables are read again
  * by the copy only until the stream reaches it (the call waits for the copy before returning). */
@@ -238,7 +245,10 @@ int32_t bmhd_block_indicator(const bmhd_grid *g, const double *d_U, double *d_in
 int32_t bmhd_adapt(const bmhd_grid *g, const double *h_ind, double r_refine, double r_coarsen, int32_t *h_level,
                    int32_t *h_ijk, int32_t *h_sim, int32_t max_blocks, int32_t *n_out);
 
-/* d_dt[n_sims] = cfl * min over fluid cells of 1 / sum_d ((|u_d| + c_f,d) / dx) from d_U. */
+/* The CFL-limited time step (Sec. 5.1 runs at CFL 0.8, Sec. 5.2 at 0.6 and 0.85), reduced on the GPU so
+ * that steps advance without a transfer to the host (Sec. 3.1): d_dt[n_sims] (device) = cfl * min over
+ * fluid cells of 1 / sum_d ((|u_d| + c_f,d) / dx) from d_U (device, [8][n_blocks][8][8][8]), c_f,d the
+ * fast magnetosonic speed along axis d. Errors: BMHD_EINVAL (null pointer, grid not uploaded, cfl <= 0). */
 int32_t bmhd_reduce_dt(const bmhd_grid *g, const double *d_U, double cfl, double *d_dt, void *stream);
 
 /* Advance n_stages stages of the two-stage scheme (Algorithm 2's block sweep, repeated). Stage s uses

@@ -302,45 +302,58 @@ __global__ void __launch_bounds__(64 * NW) k_mlp_infer(const float *__restrict__
 // ------------------------------------------------------------------------------------------------
 // generic product for the backward pass: C[M x N] = A[M x K] B[K x N] (+ C when ACC), element (m, k)
 // of A at A[m * am + k * ak], element (k, n) of B at B[k * bk + n * bn]; rows/cols/k beyond the sizes
-// read as 0. One wave per 16 x 16 tile of C.
+// read as 0. One workgroup of four waves per 32 x 32 tile of C, each wave one 16 x 16 quarter. For every
+// 32-wide slice of K the workgroup stages the A and B tiles in LDS, loading along whichever axis of each
+// operand is contiguous in memory (so a wave's loads are coalesced whatever the transposition), and each
+// wave then forms its quarter from LDS: one MFMA per slice, or (FP32 reference mode) one FMA chain per
+// output in ascending k.
+constexpr int GT = 32;  // tile edge and K slice of k_gemm
 
 template <bool MFMA, bool ACC>
 __global__ void __launch_bounds__(256) k_gemm(int M, int N, int K, const float *__restrict__ A, long am, long ak,
                                               const float *__restrict__ B, long bk, long bn, float *__restrict__ C,
                                               long ldc) {
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, q = lane >> 4, r = lane & 15;
-    const int tiles_n = (N + 15) / 16;
-    const int t = blockIdx.x * 4 + wave;
-    const int tm = t / tiles_n, tn = t % tiles_n;
-    if (tm * 16 >= M) return;
+    __shared__ float sA[GT][GT + 1];  // [m][k]
+    __shared__ float sB[GT][GT + 1];  // [k][n]
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, q = lane >> 4, r = lane & 15;
+    const int tiles_n = (N + GT - 1) / GT;
+    const int m0 = int(blockIdx.x) / tiles_n * GT, n0 = int(blockIdx.x) % tiles_n * GT;
+    const int wm = (wave >> 1) * 16, wn = (wave & 1) * 16;
+    const bool a_k_fast = ak == 1, b_n_fast = bn == 1;
     f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-    const int mrow = tm * 16 + r, ncol = tn * 16 + r;
-    if constexpr (MFMA) {
-        for (int k0 = 0; k0 < K; k0 += 32) {
+    for (int k0 = 0; k0 < K; k0 += GT) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int fast = tid & 31, slow = (tid >> 5) + 8 * i;
+            const int ta = a_k_fast ? slow : fast, ka = a_k_fast ? fast : slow;  // A tile row m, column k
+            const int gm = m0 + ta, gka = k0 + ka;
+            sA[ta][ka] = (gm < M && gka < K) ? A[gm * am + gka * ak] : 0.0f;
+            const int tb = b_n_fast ? fast : slow, kb = b_n_fast ? slow : fast;  // B tile column n, row k
+            const int gn = n0 + tb, gkb = k0 + kb;
+            sB[kb][tb] = (gn < N && gkb < K) ? B[gkb * bk + gn * bn] : 0.0f;
+        }
+        __syncthreads();
+        if constexpr (MFMA) {
             bf16x8 av, bv;
 #pragma unroll
             for (int j = 0; j < 8; ++j) {
-                const int k = k0 + 8 * q + j;
-                av[j] = __bf16((mrow < M && k < K) ? A[mrow * am + k * ak] : 0.0f);
-                bv[j] = __bf16((ncol < N && k < K) ? B[k * bk + ncol * bn] : 0.0f);
+                av[j] = __bf16(sA[wm + r][8 * q + j]);
+                bv[j] = __bf16(sB[8 * q + j][wn + r]);
             }
             acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc, 0, 0, 0);
-        }
-    } else {
+        } else {
+            const int kend = K - k0 < GT ? K - k0 : GT;
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int m = tm * 16 + 4 * q + i;
-            float s = 0.f;
-            if (m < M && ncol < N)
-                for (int k = 0; k < K; ++k) s = fmaf(A[m * am + k * ak], B[k * bk + ncol * bn], s);
-            acc[i] = s;
+            for (int i = 0; i < 4; ++i)
+                for (int kk = 0; kk < kend; ++kk) acc[i] = fmaf(sA[wm + 4 * q + i][kk], sB[kk][wn + r], acc[i]);
         }
+        __syncthreads();
     }
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-        const int m = tm * 16 + 4 * q + i;
-        if (m < M && ncol < N) {
-            float *c = C + m * ldc + ncol;
+        const int m = m0 + wm + 4 * q + i, n = n0 + wn + r;
+        if (m < M && n < N) {
+            float *c = C + m * ldc + n;
             *c = ACC ? *c + acc[i] : acc[i];
         }
     }
@@ -368,13 +381,26 @@ __global__ void k_silu(long count, const float *__restrict__ Z, float *__restric
     if (i < count) A[i] = silu(Z[i]);
 }
 
-// column sums of G[n][cols] into out[cols] (one thread per column, fixed order: deterministic)
-__global__ void k_colsum(int n, int cols, const float *__restrict__ G, float *__restrict__ out) {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= cols) return;
+// column sums of G[n][cols] into out[cols]: one workgroup of 1,024 threads per 64 columns; thread (c, p)
+// sums the rows p, p + 16, ... of column c in ascending order (a wave reads 64 neighbouring columns of
+// one row), then the 16 partial sums of a column are added pairwise in LDS (fixed tree: deterministic)
+constexpr int CS_PHASES = 16;
+
+__global__ void __launch_bounds__(1024) k_colsum(int n, int cols, const float *__restrict__ G, float *__restrict__ out) {
+    __shared__ float part[CS_PHASES][64];
+    const int tx = threadIdx.x & 63, p = threadIdx.x >> 6;
+    const int c = blockIdx.x * 64 + tx;
     float s = 0.f;
-    for (int i = 0; i < n; ++i) s += G[size_t(i) * cols + c];
-    out[c] = s;
+    if (c < cols)
+        for (int i = p; i < n; i += CS_PHASES) s += G[size_t(i) * cols + c];
+    part[p][tx] = s;
+    __syncthreads();
+#pragma unroll
+    for (int h = CS_PHASES / 2; h > 0; h >>= 1) {
+        if (p < h) part[p][tx] += part[p + h][tx];
+        __syncthreads();
+    }
+    if (p == 0 && c < cols) out[c] = part[0][tx];
 }
 
 // Adam on the FP32 master vector; refreshes the BF16 copy
@@ -428,9 +454,10 @@ unsigned blocks_for(long n, int t) { return unsigned((n + t - 1) / t); }
 template <bool MFMA>
 void gemm(int M, int N, int K, const float *A, long am, long ak, const float *B, long bk, long bn, float *C, long ldc,
           bool acc, hipStream_t s) {
-    const long tiles = long((M + 15) / 16) * ((N + 15) / 16);
-    if (acc) k_gemm<MFMA, true><<<blocks_for(tiles, 4), 256, 0, s>>>(M, N, K, A, am, ak, B, bk, bn, C, ldc);
-    else k_gemm<MFMA, false><<<blocks_for(tiles, 4), 256, 0, s>>>(M, N, K, A, am, ak, B, bk, bn, C, ldc);
+    const unsigned tiles = unsigned((M + GT - 1) / GT) * unsigned((N + GT - 1) / GT);
+    if (tiles == 0) return;
+    if (acc) k_gemm<MFMA, true><<<tiles, 256, 0, s>>>(M, N, K, A, am, ak, B, bk, bn, C, ldc);
+    else k_gemm<MFMA, false><<<tiles, 256, 0, s>>>(M, N, K, A, am, ak, B, bk, bn, C, ldc);
 }
 
 // BF16 inference: persistent, one workgroup per CU
@@ -504,7 +531,7 @@ int32_t backward_impl(const float *d_params, int32_t hidden, int32_t n, const fl
     float *A3 = bufB;
     k_silu<<<blocks_for(long(n) * H, 256), 256, 0, s>>>(long(n) * H, d_save + size_t(2) * n * H, A3);
     G(8, H, n, dY, 1, 8, A3, H, 1, d_grad + V.off_w[3], H);
-    k_colsum<<<1, 64, 0, s>>>(n, 8, dY, d_grad + V.off_b[3]);
+    k_colsum<<<1, 1024, 0, s>>>(n, 8, dY, d_grad + V.off_b[3]);
     float *dA = bufA, *other = bufB;
     G(n, H, 8, dY, 8, 1, d_params + V.off_w[3], H, 1, dA, H);
     // hidden layers 3, 2, 1 (index l = 2, 1, 0)
@@ -520,7 +547,7 @@ int32_t backward_impl(const float *d_params, int32_t hidden, int32_t n, const fl
         } else {
             G(H, nin, n, dZ, 1, H, d_x, MLP_IN, 1, d_grad + V.off_w[l], nin);
         }
-        k_colsum<<<blocks_for(H, 64), 64, 0, s>>>(n, H, dZ, d_grad + V.off_b[l]);
+        k_colsum<<<blocks_for(H, 64), 1024, 0, s>>>(n, H, dZ, d_grad + V.off_b[l]);
         if (l > 0) {
             // dA_{l-1}[n][i] = sum_o dZ[n][o] W_l[o][i], into the buffer the inputs no longer need
             G(n, nin, H, dZ, H, 1, d_params + V.off_w[l], nin, 1, other, nin);

@@ -58,7 +58,7 @@ def test_inference_kernel_equals_training_forward(bd, oracle_mod, H, n):
     assert _rel(y_inf[sel], ref) <= BF16_BOUND
 
 
-@pytest.mark.parametrize("H,n", [(32, 50), (128, 96)])
+@pytest.mark.parametrize("H,n", [(32, 50), (128, 96), (64, 1000)])
 @pytest.mark.parametrize("mode", ["fp32", "bf16"])
 def test_gradients_match_oracle(bd, oracle_mod, H, n, mode):
     p, x, t = _setup(oracle_mod, H, n, 2)
