@@ -360,7 +360,34 @@ def bench_exchange(reps=20):
            "note": "unpack also copies process 0's local messages (every ghost face inside its sub-cube) and "
                    "fills its outflow/inflow ghost cells"}
     log(f"exchange: pack {tp * 1e6:.1f} us ({sent / 1e6:.1f} MB), unpack {tu * 1e6:.1f} us ({recv / 1e6:.1f} MB)")
-    del views, sends, recvs, U, x, g
+    del views, sends, recvs
+    # whole steps with the eight processes advanced separately from their exchanged views (every process's
+    # exchange and stage run one after another on this one GPU), beside the single-process step on the
+    # same grid with the same per-step dt; the first step of each warms up
+    steps = 3
+    walls = {}
+    for name in ("sharded", "single"):
+        U = g.set_state(torch.from_numpy(wl.W).cuda())
+        U1 = torch.empty_like(U)
+        for k in range(steps + 1):
+            if k == 1:
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+            if name == "sharded":
+                x.advance(U, U1, 1, cfl=0.8, flux="hlle", powell=True)
+            else:
+                dt = g.reduce_dt(U, 0.8)
+                g.advance(U, U1, dt, 2, recompute_dt=False, flux="hlle", powell=True)
+        torch.cuda.synchronize()
+        walls[name] = (time.perf_counter() - t0) / steps
+        del U, U1
+    out["sharded_step_ms"] = walls["sharded"] * 1e3
+    out["single_step_ms"] = walls["single"] * 1e3
+    out["sharded_note"] = ("each process's stage reads every ghost cell from its padded view, which the exchange "
+                           "fills completely (interior copy, local and received messages, boundary cells); on one "
+                           "GPU the eight processes run one after another")
+    log(f"exchange: sharded step {walls['sharded'] * 1e3:.2f} ms, single-process step {walls['single'] * 1e3:.2f} ms")
+    del x, g
     torch.cuda.synchronize()
     return out
 

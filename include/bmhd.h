@@ -348,6 +348,26 @@ int32_t bmhd_xchg_pack(const bmhd_xchg *x, int32_t pass, int32_t s, const double
 int32_t bmhd_xchg_unpack(const bmhd_xchg *x, int32_t pass, int32_t r, const double *d_recv, double *d_view,
                          int32_t *d_bad, void *stream);
 
+/* One stage of the two-stage scheme (Algorithm 2's block sweep; stage in {0, 1} picks alpha/beta of the
+ * options' table) for process r's blocks, every ghost cell read from r's padded view d_view after both
+ * exchange passes (Sec. 4.4: each process then updates its own blocks). d_Uin, d_U0 and d_Uout are the
+ * grid's [8][n_blocks][8][8][8] states, of which only r's blocks are read (d_Uin's own cells, d_U0's
+ * own cells in the second stage) and written (d_Uout); dt is given per simulation (d_dt, the minimum over
+ * every process: bmhd_reduce_dt stands in for that reduction on one GPU); positivity faults of the second
+ * stage go to d_faults (may be NULL). Blocks clear of a body run on the block form, the others on the
+ * plane form (all on the plane form with BMHD_FLUX_LINDE); the scheme, slab and graph options are not
+ * used. Faces on a level change record their fluxes for bmhd_xchg_flux_correct, which runs after every
+ * process's stage (the fine side's records are in the one device's memory here; between GPUs they would
+ * travel like the ghost messages). Errors: BMHD_EINVAL; BMHD_EUNSUPPORTED with a learned correction,
+ * local time stepping or a persistent grid. */
+int32_t bmhd_xchg_stage(const bmhd_xchg *x, int32_t r, int32_t stage, const double *d_view, const double *d_U0,
+                        const double *d_Uin, double *d_Uout, const double *d_dt, const bmhd_opts *o,
+                        int32_t *d_faults, void *stream);
+/* The flux corrections of process r's coarse cells next to a finer block after that stage (the coarse
+ * face flux replaced by the mean of the fine ones), as bmhd_advance applies them. */
+int32_t bmhd_xchg_flux_correct(const bmhd_xchg *x, int32_t r, int32_t stage, double *d_Uout, const double *d_dt,
+                               const bmhd_opts *o, int32_t *d_faults, void *stream);
+
 /* ---------------------------------------------------------------------------------------------
  * Learned flux correction: a multilayer perceptron 32 -> H -> H -> H -> 8 with SiLU activations
  * (hidden width H in {32, 64, 128}). This component is not in the paper: it corrects the plain flux

@@ -25,7 +25,7 @@ EXPORTS = ["bmhd_version", "bmhd_last_error", "bmhd_grid_create", "bmhd_grid_des
            "bmhd_reduce_dt", "bmhd_advance", "bmhd_autotune", "bmhd_mlp_last_error", "bmhd_mlp_n_params", "bmhd_mlp_work_bytes",
            "bmhd_mlp_forward", "bmhd_mlp_backward", "bmhd_mlp_backward_noalloc", "bmhd_mlp_adam", "bmhd_mlp_to_bf16", "bmhd_face_data",
            "bmhd_block_indicator", "bmhd_adapt", "bmhd_xchg_create", "bmhd_xchg_destroy", "bmhd_xchg_sizes", "bmhd_xchg_messages", "bmhd_xchg_upload",
-           "bmhd_xchg_interior", "bmhd_xchg_pack", "bmhd_xchg_unpack"]
+           "bmhd_xchg_interior", "bmhd_xchg_pack", "bmhd_xchg_unpack", "bmhd_xchg_stage", "bmhd_xchg_flux_correct"]
 
 
 class SimDesc(ctypes.Structure):
@@ -141,6 +141,10 @@ def lib():
     L.bmhd_xchg_pack.restype = i32
     L.bmhd_xchg_unpack.argtypes = [vp, i32, i32, vp, vp, vp, vp]
     L.bmhd_xchg_unpack.restype = i32
+    L.bmhd_xchg_stage.argtypes = [vp, i32, i32, vp, vp, vp, vp, vp, P(Opts), vp, vp]
+    L.bmhd_xchg_stage.restype = i32
+    L.bmhd_xchg_flux_correct.argtypes = [vp, i32, i32, vp, vp, P(Opts), vp, vp]
+    L.bmhd_xchg_flux_correct.restype = i32
     _lib = L
     return L
 
@@ -502,7 +506,9 @@ class Xchg:
         """Both passes of the exchange for every process: returns the views (bad: optional int32 device
         counter of skipped messages)."""
         import torch
-        views = [self.new_view(r, U.device) for r in range(self.nr)]
+        # every cell of a view is written below (interior, 26 directions of ghost cells): no clearing
+        views = [torch.empty((8, int(self.nloc[r]), 12, 12, 12), dtype=torch.float64, device=U.device)
+                 for r in range(self.nr)]
         for r in range(self.nr):
             self.interior(r, U, views[r])
         for p in (1, 2):
@@ -514,6 +520,40 @@ class Xchg:
             for r in range(self.nr):
                 self.unpack(p, r, recvs[r], views[r], bad=bad)
         return views
+
+    def stage(self, r, e, view, U0, Uin, Uout, dt, opts: Optional[Opts] = None, faults=None, stream=None, **kw):
+        """Stage e (0 or 1) of process r's blocks, ghost cells from its exchanged view."""
+        import torch
+        o = opts if opts is not None else make_opts(**kw)
+        fp = _dev_ptr(faults, torch.int32) if faults is not None else ctypes.c_void_p(0)
+        _check(lib().bmhd_xchg_stage(self.h, int(r), int(e), _dev_ptr(view, torch.float64) if view.numel() else None,
+                                     _dev_ptr(U0, torch.float64), _dev_ptr(Uin, torch.float64),
+                                     _dev_ptr(Uout, torch.float64), _dev_ptr(dt, torch.float64), ctypes.byref(o), fp,
+                                     _stream_ptr(stream)))
+
+    def flux_correct(self, r, e, Uout, dt, opts: Optional[Opts] = None, faults=None, stream=None, **kw):
+        import torch
+        o = opts if opts is not None else make_opts(**kw)
+        fp = _dev_ptr(faults, torch.int32) if faults is not None else ctypes.c_void_p(0)
+        _check(lib().bmhd_xchg_flux_correct(self.h, int(r), int(e), _dev_ptr(Uout, torch.float64),
+                                            _dev_ptr(dt, torch.float64), ctypes.byref(o), fp, _stream_ptr(stream)))
+
+    def advance(self, U0, U1, n_steps, cfl=0.8, faults=None, **kw):
+        """n_steps steps of the two-stage scheme with the processes' blocks advanced separately: per stage,
+        both exchange passes into every process's view, each process's stage from its view, then the flux
+        corrections. dt per step: the CFL minimum over all blocks (bmhd_reduce_dt, the stand-in for the
+        reduction over processes). Returns the last step's dt."""
+        o = make_opts(recompute_dt=False, cfl=cfl, **kw)
+        dt = None
+        for _ in range(n_steps):
+            dt = self.grid.reduce_dt(U0, cfl)
+            for e, (Uin, Uout) in enumerate(((U0, U1), (U1, U0))):
+                views = self.run(Uin)
+                for r in range(self.nr):
+                    self.stage(r, e, views[r], U0, Uin, Uout, dt, opts=o, faults=faults)
+                for r in range(self.nr):
+                    self.flux_correct(r, e, Uout, dt, opts=o, faults=faults)
+        return dt
 
 
 # ------------------------------------------------------------------------------------------------

@@ -124,6 +124,26 @@ int32_t mlp_infer_bf16_inputs(const float *d_params, const uint16_t *d_params_bf
                               const uint16_t *d_x, float *d_y, void *stream, std::string &err);
 void prim_to_cons_host(const double *w, double *u);
 
+// A subset of a grid's blocks (one process's) whose ghost cells come from a padded view filled by the
+// ghost exchange between processes. All pointers are device pointers into the exchange's workspace or
+// the caller's view.
+struct ViewStage {
+    const double *view;          // [8][n_local][12][12][12]
+    const int32_t *view_local;   // [nb]: each block's index in its process's view
+    int64_t view_vs;             // n_local * 1728
+    const int32_t *split;        // the subset's blocks, those clear of any body first
+    int32_t n_clear, n_total;
+    const DevFcCell *fc_cells;   // the subset's coarse cells that take flux corrections
+    int32_t n_fc;
+};
+
+// One stage of the two-stage scheme (stage e in {0, 1} of o's table) for the subset, and its flux
+// corrections (to be enqueued after every process's stage kernels, which record the face fluxes).
+int32_t stage_from_view(const HostGrid &h, const ViewStage &v, int e, const double *U0, const double *Uin,
+                        double *Uout, const double *dt, const bmhd_opts &o, int32_t *faults, void *stream);
+int32_t flux_correct_subset(const HostGrid &h, const ViewStage &v, int e, double *Uout, const double *dt,
+                            const bmhd_opts &o, int32_t *faults, void *stream);
+
 // Sets the message bmhd_last_error reports on this thread; returns code.
 int32_t set_last_error(int32_t code, const std::string &msg);
 

@@ -619,6 +619,15 @@ struct StageArgs {
     // work list of the launch: a part of the Morton schedule (block ids), or null for all of T.order
     const int32_t *sched;
     int32_t n_sched;
+    // ghost cells from a padded view [8][n][12][12][12] (one process's blocks after the exchange between
+    // processes) instead of the neighbours' interiors, the boundary rules and the halo buffer: view_local[b]
+    // is block b's index in the view, view_vs its variable stride; null: the usual gather
+    const double *view;
+    const int32_t *view_local;
+    int64_t view_vs;
+    // the coarse cells k_flux_correct takes: a list of n_fc_list cells, or null for all of T.fc_cells
+    const DevFcCell *fc_list;
+    int32_t n_fc_list;
 };
 
 __device__ __forceinline__ int sched_count(const Tables &T, const StageArgs &A) { return A.sched ? A.n_sched : T.nb; }
@@ -795,7 +804,7 @@ template <int KS, int NTH>
 constexpr int gather_npt() { return (Slab<KS>::NC + NTH - 1) / NTH; }
 
 // Issue the global loads of one slab and its face halos (cells tid, tid + NTH, ...) into registers.
-template <int KS, int NTH = Slab<KS>::NT>
+template <int KS, int NTH = Slab<KS>::NT, bool VIEW = false>
 __device__ __forceinline__ void gather_issue(const Tables &T, const StageArgs &A, int b, int slab,
                                              double (&u)[gather_npt<KS, NTH>()][8]) {
     using SL = Slab<KS>;
@@ -804,6 +813,21 @@ __device__ __forceinline__ void gather_issue(const Tables &T, const StageArgs &A
     const DevSim &S = T.sims[B.sim];
     const size_t vs = size_t(T.nb) * 512;
     const int tid = lane_tid();
+    if constexpr (VIEW) {
+        // every ghost cell is in the view, whatever its origin (copy, restriction, prolongation, boundary)
+        const double *base = A.view + size_t(A.view_local[b]) * 1728;
+#pragma unroll
+        for (int m = 0; m < NPT; ++m) {
+            const int c = tid + m * NTH;
+            if (c >= SL::NC) break;
+            int i, j, k;
+            SL::decode(c, i, j, k);
+            const double *p = base + ((slab * KS + k + 2) * 12 + (j + 2)) * 12 + (i + 2);
+#pragma unroll
+            for (int v = 0; v < 8; ++v) u[m][v] = p[v * A.view_vs];
+        }
+        return;
+    }
 #pragma unroll
     for (int m = 0; m < NPT; ++m) {
         const int c = tid + m * NTH;
@@ -1283,7 +1307,7 @@ __device__ __noinline__ void wp_item(const Tables &T, const StageArgs &A, int b,
 template <int KS, typename R>
 constexpr int wp_waves_per_simd() { return (KS == 8 && sizeof(R) == 8) ? 3 : 4; }
 
-template <int KS, typename R, int FLUX, bool POWELL, bool PERSIST, bool LEARN = false>
+template <int KS, typename R, int FLUX, bool POWELL, bool PERSIST, bool LEARN = false, bool VIEW = false>
 __global__ void __launch_bounds__(64 * (KS + 1), (wp_waves_per_simd<KS, R>())) k_stage_wp(Tables T, StageArgs A) {
     using SL = Slab<KS>;
     static_assert(SL::NT == 64 * (KS + 1), "one wave per cell layer plus one");
@@ -1306,13 +1330,13 @@ __global__ void __launch_bounds__(64 * (KS + 1), (wp_waves_per_simd<KS, R>())) k
         const int b = sched_block(T, A, item / S_PER_BLOCK), slab = item % S_PER_BLOCK;
         {
             double u[SL::NPT][8];
-            gather_issue<KS>(T, A, b, slab, u);
+            gather_issue<KS, SL::NT, VIEW>(T, A, b, slab, u);
             gather_store_bits<KS, R, RP>(T, b, slab, u, sW, sMb, sRP);
         }
         __syncthreads();
         wp_compute<KS, R, FLUX, POWELL, LEARN>(T, A, b, slab, sW, sH, sMb, red, redi, sRP);
     } else {
-        static_assert(!LEARN, "the learned correction runs one workgroup per slab");
+        static_assert(!LEARN && !VIEW, "the learned correction and the view gather run one workgroup per slab");
         const int step = int(gridDim.x >> 3);
 #pragma nounroll
         for (int it = slot; it < count; it += step) {
@@ -1549,7 +1573,7 @@ __device__ __forceinline__ void blk_compute(const Tables &T, const StageArgs &A,
 template <typename R>
 constexpr int blk_waves_per_simd() { return sizeof(R) == 8 ? 4 : 4; }
 
-template <typename R, int FLUX, bool POWELL>
+template <typename R, int FLUX, bool POWELL, bool VIEW = false>
 __global__ void __launch_bounds__(BLK_NT, (blk_waves_per_simd<R>())) k_stage_blk(Tables T, StageArgs A) {
     using SL = Slab<8>;
     static_assert(SL::NC - SL::XH >= 8 * 64, "z-flux exchange space");
@@ -1559,7 +1583,7 @@ __global__ void __launch_bounds__(BLK_NT, (blk_waves_per_simd<R>())) k_stage_blk
     const int b = sched_block(T, A, xcd_first(sched_count(T, A), xcd) + slot);
     {
         double u[gather_npt<8, BLK_NT>()][8];
-        gather_issue<8, BLK_NT>(T, A, b, 0, u);
+        gather_issue<8, BLK_NT, VIEW>(T, A, b, 0, u);
         gather_store_blk<R>(u, sW);
     }
     __syncthreads();
@@ -1790,19 +1814,21 @@ __global__ void __launch_bounds__(256) k_flux_correct(Tables T, StageArgs A) {
     __shared__ double red[4];
     __shared__ int redi[4];
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    const DevFcCell *cells = A.fc_list ? A.fc_list : T.fc_cells;
+    const int ncells = A.fc_list ? A.n_fc_list : T.n_fc_cells;
     double lam = 0.0;
     int nf = 0;
     int sim = 0;
     bool body = false;
-    if (e < T.n_fc_cells) {
-        const DevFcCell C = T.fc_cells[e];
+    if (e < ncells) {
+        const DevFcCell C = cells[e];
         const DevBlock &B = T.blocks[C.block];
         const DevSim &S = T.sims[B.sim];
         sim = B.sim;
         body = (B.flags & BF_NEAR_BODY) && in_body(S, B.level, B.ijk, C.cell & 7, (C.cell >> 3) & 7, C.cell >> 6);
     }
-    if (e < T.n_fc_cells && !body) {
-        const DevFcCell C = T.fc_cells[e];
+    if (e < ncells && !body) {
+        const DevFcCell C = cells[e];
         const DevBlock &B = T.blocks[C.block];
         const DevSim &S = T.sims[B.sim];
         const size_t vs = size_t(T.nb) * 512, off = size_t(C.block) * 512 + C.cell;
@@ -1834,7 +1860,7 @@ __global__ void __launch_bounds__(256) k_flux_correct(Tables T, StageArgs A) {
     }
     if (A.want_lam) {
         // a grid may mix simulations inside one workgroup here: publish per thread (few cells)
-        if (e < T.n_fc_cells && !body) publish_max(T.lam + sim, lam);
+        if (e < ncells && !body) publish_max(T.lam + sim, lam);
     }
     if (A.count_faults) block_publish<256>(0.0, nf, red, redi, nullptr, A.faults);
 }
@@ -2007,6 +2033,93 @@ int32_t check_opts(const bmhd_opts &o) {
     }
     if (o.local_dt != 0 && o.local_dt != 1) return fail(BMHD_EINVAL, "local_dt must be 0 or 1");
     return BMHD_OK;
+}
+
+// One stage for a subset of blocks whose ghost cells come from a padded view (one process after the
+// ghost exchange between processes): the block form for the subset's blocks clear of a body and the plane
+// form for the others (the plane form for all of them with the Linde-type flux, as in bmhd_advance). No
+// level-change halos (the view holds every ghost cell), no flux correction (flux_correct_subset, once the
+// stage has run for every process) and no next-dt bound.
+template <typename R, int FLUX, bool POWELL>
+int32_t launch_view_stage(const HostGrid &h, const StageArgs &a, const ViewStage &v, hipStream_t s) {
+    StageArgs ac = a, an = a;
+    if constexpr (FLUX == BMHD_FLUX_LINDE) {
+        an.sched = v.split;
+        an.n_sched = v.n_total;
+        if (v.n_total) k_stage_wp<4, R, FLUX, POWELL, false, false, true><<<v.n_total * 2, Slab<4>::NT, 0, s>>>(h.dev, an);
+        return launch_check("stage kernel");
+    } else {
+        const int nn = v.n_total - v.n_clear;
+        ac.sched = v.split;
+        ac.n_sched = v.n_clear;
+        an.sched = v.split + v.n_clear;
+        an.n_sched = nn;
+        if (nn) k_stage_wp<4, R, FLUX, POWELL, false, false, true><<<nn * 2, Slab<4>::NT, 0, s>>>(h.dev, an);
+        if (v.n_clear) k_stage_blk<R, FLUX, POWELL, true><<<v.n_clear, BLK_NT, 0, s>>>(h.dev, ac);
+        return launch_check("stage kernel");
+    }
+}
+
+template <typename R, int FLUX>
+int32_t launch_view_stage_p(const HostGrid &h, const StageArgs &a, const ViewStage &v, bool powell, hipStream_t s) {
+    return powell ? launch_view_stage<R, FLUX, true>(h, a, v, s) : launch_view_stage<R, FLUX, false>(h, a, v, s);
+}
+
+template <typename R>
+int32_t launch_view_stage_f(const HostGrid &h, const StageArgs &a, const ViewStage &v, const bmhd_opts &o, hipStream_t s) {
+    if (o.flux == BMHD_FLUX_RUSANOV) return launch_view_stage_p<R, BMHD_FLUX_RUSANOV>(h, a, v, o.powell, s);
+    if (o.flux == BMHD_FLUX_LINDE) return launch_view_stage_p<R, BMHD_FLUX_LINDE>(h, a, v, o.powell, s);
+    return launch_view_stage_p<R, BMHD_FLUX_HLLE>(h, a, v, o.powell, s);
+}
+
+int32_t check_view_stage(const HostGrid &h, int e, const bmhd_opts &o) {
+    if (!h.d_work) return fail(BMHD_EINVAL, "grid not uploaded (call bmhd_grid_upload first)");
+    if (e != 0 && e != 1) return fail(BMHD_EINVAL, "stage must be 0 or 1");
+    if (int32_t rc = check_opts(o)) return rc;
+    if (o.learned || o.local_dt || o.persist_wgs)
+        return fail(BMHD_EUNSUPPORTED, "the stage from an exchanged view takes no learned correction, local time "
+                                       "stepping or persistent grid");
+    return BMHD_OK;
+}
+
+int32_t stage_from_view_impl(const HostGrid &h, const ViewStage &v, int e, const double *U0, const double *Uin,
+                             double *Uout, const double *dt, const bmhd_opts &o, int32_t *faults, void *stream) {
+    if (int32_t rc = check_view_stage(h, e, o)) return rc;
+    if (v.n_total == 0) return BMHD_OK;
+    StageArgs a;
+    std::memset(&a, 0, sizeof a);
+    a.Uin = Uin;
+    a.U0 = U0;
+    a.Uout = Uout;
+    a.dt = const_cast<double *>(dt);  // read only: no local stepping here
+    a.faults = faults;
+    a.alpha = o.alpha[e];
+    a.beta = o.beta[e];
+    a.use_u0 = o.alpha[e] != 0.0 ? 1 : 0;
+    a.count_faults = (e == 1 && faults) ? 1 : 0;
+    a.view = v.view;
+    a.view_local = v.view_local;
+    a.view_vs = v.view_vs;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    if (o.precision == BMHD_FP64) return launch_view_stage_f<double>(h, a, v, o, s);
+    return launch_view_stage_f<float>(h, a, v, o, s);
+}
+
+int32_t flux_correct_subset_impl(const HostGrid &h, const ViewStage &v, int e, double *Uout, const double *dt,
+                                 const bmhd_opts &o, int32_t *faults, void *stream) {
+    if (int32_t rc = check_view_stage(h, e, o)) return rc;
+    if (v.n_fc == 0) return BMHD_OK;
+    StageArgs a;
+    std::memset(&a, 0, sizeof a);
+    a.Uout = Uout;
+    a.dt = const_cast<double *>(dt);
+    a.faults = faults;
+    a.beta = o.beta[e];
+    a.count_faults = (e == 1 && faults) ? 1 : 0;
+    a.fc_list = v.fc_cells;
+    a.n_fc_list = v.n_fc;
+    k_flux_correct<<<unsigned((v.n_fc + 255) / 256), 256, 0, reinterpret_cast<hipStream_t>(stream)>>>(h.dev, a);
+    return launch_check("flux correction");
 }
 
 // One stage: level-change halos, the stage kernel (optionally bracketed by events), flux correction.
@@ -2203,6 +2316,14 @@ int32_t need_upload(const bmhd_grid *g) {
 
 namespace bmhd {
 int32_t set_last_error(int32_t code, const std::string &msg) { return fail(code, msg); }
+int32_t stage_from_view(const HostGrid &h, const ViewStage &v, int e, const double *U0, const double *Uin,
+                        double *Uout, const double *dt, const bmhd_opts &o, int32_t *faults, void *stream) {
+    return stage_from_view_impl(h, v, e, U0, Uin, Uout, dt, o, faults, stream);
+}
+int32_t flux_correct_subset(const HostGrid &h, const ViewStage &v, int e, double *Uout, const double *dt,
+                            const bmhd_opts &o, int32_t *faults, void *stream) {
+    return flux_correct_subset_impl(h, v, e, Uout, dt, o, faults, stream);
+}
 }  // namespace bmhd
 
 extern "C" {

@@ -69,9 +69,15 @@ struct bmhd_xchg {
     std::vector<int64_t> bnd_first[2];                               // are filled after it, per process
     std::vector<int32_t> blocks_local;                               // global ids in local order per process
     std::vector<int64_t> blocks_first;                               // [nr + 1]
+    // for the stage from a process's view: its blocks clear of any body first (n_clear of them), then the
+    // blocks near a body (ranges as blocks_first); its coarse cells taking flux corrections
+    std::vector<int32_t> split, n_clear;
+    std::vector<bmhd::DevFcCell> fc;
+    std::vector<int64_t> fc_first;                                   // [nr + 1]
     std::vector<std::vector<int64_t>> table;                         // or_xchg_messages-style rows
     size_t work_bytes = 0;
     size_t off_msgs[2][3] = {}, off_grp[2][3] = {}, off_bnd[2] = {}, off_blocks = 0;
+    size_t off_split = 0, off_local = 0, off_fc = 0;
     void *d_work = nullptr;
 };
 
@@ -430,6 +436,21 @@ int32_t need_xchg(const bmhd_xchg *x, int32_t pass, int32_t r) {
 
 bool aligned8(const void *p) { return p && (reinterpret_cast<uintptr_t>(p) & 7u) == 0; }
 
+// Process r's blocks and coarse flux-correction cells in the uploaded workspace, ghost cells from d_view.
+ViewStage view_stage(const bmhd_xchg *x, int r, const double *d_view) {
+    const unsigned char *base = static_cast<const unsigned char *>(x->d_work);
+    ViewStage v{};
+    v.view = d_view;
+    v.view_local = reinterpret_cast<const int32_t *>(base + x->off_local);
+    v.view_vs = int64_t(x->nloc[r]) * 1728;
+    v.split = reinterpret_cast<const int32_t *>(base + x->off_split) + x->blocks_first[r];
+    v.n_clear = x->n_clear[r];
+    v.n_total = x->nloc[r];
+    v.fc_cells = reinterpret_cast<const DevFcCell *>(base + x->off_fc) + x->fc_first[r];
+    v.n_fc = int32_t(x->fc_first[r + 1] - x->fc_first[r]);
+    return v;
+}
+
 }  // namespace
 
 extern "C" {
@@ -450,6 +471,23 @@ int32_t bmhd_xchg_create(const bmhd_grid *g, const int32_t *rank, int32_t n_rank
     for (int r = 0; r < n_ranks; ++r) x->blocks_first[r + 1] = x->blocks_first[r] + x->nloc[r];
     x->blocks_local.assign(size_t(h.nb), 0);
     for (int b = 0; b < h.nb; ++b) x->blocks_local[size_t(x->blocks_first[rank[b]] + x->local[b])] = b;
+    x->split.reserve(size_t(h.nb));
+    x->n_clear.assign(size_t(n_ranks), 0);
+    for (int r = 0; r < n_ranks; ++r) {
+        for (int near = 0; near < 2; ++near)
+            for (int64_t q = x->blocks_first[r]; q < x->blocks_first[r + 1]; ++q) {
+                const int b = x->blocks_local[size_t(q)];
+                if (((h.blocks[b].flags & BF_NEAR_BODY) != 0) != (near != 0)) continue;
+                x->split.push_back(b);
+                if (!near) x->n_clear[r]++;
+            }
+    }
+    x->fc_first.assign(size_t(n_ranks) + 1, 0);
+    for (int r = 0; r < n_ranks; ++r) {
+        for (const DevFcCell &c : h.fc_cells)
+            if (rank[c.block] == r) x->fc.push_back(c);
+        x->fc_first[r + 1] = int64_t(x->fc.size());
+    }
 
     std::vector<std::vector<Msg>> per_block(size_t(h.nb));
     for (int b = 0; b < h.nb; ++b) per_block[b] = block_messages(h, b);
@@ -590,6 +628,12 @@ int32_t bmhd_xchg_create(const bmhd_grid *g, const int32_t *rank, int32_t n_rank
     }
     x->off_blocks = off;
     off = align256(off + sizeof(int32_t) * std::max<size_t>(1, x->blocks_local.size()));
+    x->off_split = off;
+    off = align256(off + sizeof(int32_t) * std::max<size_t>(1, x->split.size()));
+    x->off_local = off;
+    off = align256(off + sizeof(int32_t) * std::max<size_t>(1, x->local.size()));
+    x->off_fc = off;
+    off = align256(off + sizeof(DevFcCell) * std::max<size_t>(1, x->fc.size()));
     x->work_bytes = off;
     *out = x;
     return BMHD_OK;
@@ -638,6 +682,9 @@ int32_t bmhd_xchg_upload(bmhd_xchg *x, void *d_work, size_t work_bytes, void *st
         put(x->off_bnd[p], bl.data(), sizeof(int32_t) * bl.size());
     }
     put(x->off_blocks, x->blocks_local.data(), sizeof(int32_t) * x->blocks_local.size());
+    put(x->off_split, x->split.data(), sizeof(int32_t) * x->split.size());
+    put(x->off_local, x->local.data(), sizeof(int32_t) * x->local.size());
+    put(x->off_fc, x->fc.data(), sizeof(DevFcCell) * x->fc.size());
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     if (int32_t rc = hip_ok(hipMemcpyAsync(d_work, blob.data(), x->work_bytes, hipMemcpyHostToDevice, s), "xchg upload"))
         return rc;
@@ -701,6 +748,28 @@ int32_t bmhd_xchg_unpack(const bmhd_xchg *x, int32_t pass, int32_t r, const doub
         k_xchg_bounds<<<unsigned(bn), 256, 0, st>>>(x->grid->h.dev, bl + bf, bl + nb_all + bf, d_view, vs);
     }
     return hip_ok(hipGetLastError(), "xchg unpack");
+}
+
+int32_t bmhd_xchg_stage(const bmhd_xchg *x, int32_t r, int32_t stage, const double *d_view, const double *d_U0,
+                        const double *d_Uin, double *d_Uout, const double *d_dt, const bmhd_opts *o,
+                        int32_t *d_faults, void *stream) {
+    if (int32_t rc = need_xchg(x, 1, r)) return rc;
+    if (!o) return set_last_error(BMHD_EINVAL, "xchg_stage: null options");
+    if (x->nloc[r] == 0) return BMHD_OK;  // no blocks, nothing to advance
+    if (!aligned8(d_view) || !aligned8(d_U0) || !aligned8(d_Uin) || !aligned8(d_Uout) || !aligned8(d_dt))
+        return set_last_error(BMHD_EINVAL, "xchg_stage: null or misaligned buffer");
+    const ViewStage v = view_stage(x, r, d_view);
+    return stage_from_view(x->grid->h, v, stage, d_U0, d_Uin, d_Uout, d_dt, *o, d_faults, stream);
+}
+
+int32_t bmhd_xchg_flux_correct(const bmhd_xchg *x, int32_t r, int32_t stage, double *d_Uout, const double *d_dt,
+                               const bmhd_opts *o, int32_t *d_faults, void *stream) {
+    if (int32_t rc = need_xchg(x, 1, r)) return rc;
+    if (!o) return set_last_error(BMHD_EINVAL, "xchg_flux_correct: null options");
+    if (x->fc_first[r + 1] == x->fc_first[r]) return BMHD_OK;
+    if (!aligned8(d_Uout) || !aligned8(d_dt)) return set_last_error(BMHD_EINVAL, "xchg_flux_correct: null or misaligned buffer");
+    const ViewStage v = view_stage(x, r, nullptr);
+    return flux_correct_subset(x->grid->h, v, stage, d_Uout, d_dt, *o, d_faults, stream);
 }
 
 }  // extern "C"

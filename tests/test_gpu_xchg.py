@@ -120,3 +120,85 @@ def test_damaged_header_is_skipped_and_counted(bd):
     lb, lo, hi = int(recvs[0][0].item()) - 1, recvs[0][1:4].long().cpu().numpy() + 2, recvs[0][4:7].long().cpu().numpy() + 2
     box = (slice(None), lb, slice(lo[2], hi[2] + 1), slice(lo[1], hi[1] + 1), slice(lo[0], hi[0] + 1))
     assert torch.equal(views[0][box], before[box])
+
+
+SHARDED = {
+    "magnetosphere_cut_hlle_powell": (lambda: wk.magnetosphere_cut(32), dict(flux="hlle", powell=True)),
+    "two_level_box_body_hlle_powell": (lambda: wk.two_level_box(body=True), dict(flux="hlle", powell=True)),
+    "two_level_mixed_bc_rusanov_fp32": (lambda: wk.two_level_box(bc=(1, 2, 0, 0, 2, 1)),
+                                        dict(flux="rusanov", precision="fp32_flux")),
+    "fast_wave_octant_linde_powell": (lambda: wk.fast_wave((2, 2, 2), refine_octant=True),
+                                      dict(flux="linde", powell=True)),
+}
+
+
+def single_process_steps(g, U, n_steps, faults, **kw):
+    """The reference: bmhd_advance step by step with the same per-step dt (CFL 0.8 minimum)."""
+    U1 = torch.empty_like(U)
+    for _ in range(n_steps):
+        dt = g.reduce_dt(U, 0.8)
+        g.advance(U, U1, dt, 2, recompute_dt=False, faults=faults, **kw)
+
+
+@pytest.mark.parametrize("kind", ["halves", "random3", "each"])
+@pytest.mark.parametrize("case", list(SHARDED))
+def test_sharded_steps_equal_single_process(bd, case, kind):
+    """Two steps with every process advancing only its own blocks from its exchanged view (both passes,
+    then each process's stage, then the flux corrections) equal bmhd_advance bit for bit: the same stage
+    kernels read the same ghost values, whether they come from the neighbours' interiors and the
+    level-change halos or from messages."""
+    make, kw = SHARDED[case]
+    wl = make()
+    if kind == "each" and wl.n_blocks > 64:
+        pytest.skip("one process per block: small grids only")
+    rank, n = ranks(wl, kind, seed=len(case))
+    print("sharded", case, kind, n, "processes", wl.n_blocks, "blocks", flush=True)
+    g = bd.Grid.from_workload(wl).upload()
+    x = bd.Xchg(g, rank, n).upload()
+    W = torch.from_numpy(wk.random_positive_state(wl, seed=7) if case.startswith("two_level") else wl.W).cuda()
+    R = g.set_state(W)
+    fa = torch.zeros(1, dtype=torch.int32, device="cuda")
+    single_process_steps(g, R, 2, fa, **kw)
+    U = g.set_state(W)
+    U1 = torch.empty_like(U)
+    fb = torch.zeros(1, dtype=torch.int32, device="cuda")
+    x.advance(U, U1, 2, cfl=0.8, faults=fb, **kw)
+    torch.cuda.synchronize()
+    assert int(fa.item()) == int(fb.item()) == 0
+    assert torch.equal(U, R), (case, kind, float((U - R).abs().max()))
+
+
+def test_sharded_step_of_eight_128_cubed_processes(bd):
+    """One step of the 256^3 magnetosphere as 2 x 2 x 2 processes of 128^3 cells equals the single-process
+    step bit for bit."""
+    wl = wk.magnetosphere(256)
+    ijk = np.asarray(wl.ijk).reshape(-1, 3)
+    rank = ((ijk[:, 0] // 16) + 2 * (ijk[:, 1] // 16) + 4 * (ijk[:, 2] // 16)).astype(np.int32)
+    g = bd.Grid.from_workload(wl).upload()
+    x = bd.Xchg(g, rank, 8).upload()
+    W = torch.from_numpy(wl.W).cuda()
+    R = g.set_state(W)
+    fa = torch.zeros(1, dtype=torch.int32, device="cuda")
+    single_process_steps(g, R, 1, fa, flux="hlle", powell=True)
+    U = g.set_state(W)
+    U1 = torch.empty_like(U)
+    fb = torch.zeros(1, dtype=torch.int32, device="cuda")
+    x.advance(U, U1, 1, cfl=0.8, faults=fb, flux="hlle", powell=True)
+    torch.cuda.synchronize()
+    assert int(fa.item()) == int(fb.item()) == 0
+    assert torch.equal(U, R)
+
+
+def test_sharded_stage_refuses_what_it_does_not_take(bd):
+    wl = wk.uniform_state((2, 2, 2))
+    g = bd.Grid.from_workload(wl).upload()
+    x = bd.Xchg(g, np.zeros(wl.n_blocks, np.int32), 1).upload()
+    U = g.set_state(torch.from_numpy(wl.W).cuda())
+    view = x.run(U)[0]
+    dt = g.reduce_dt(U, 0.8)
+    with pytest.raises(bd.BmhdError):
+        x.stage(0, 2, view, U, U, torch.empty_like(U), dt)
+    with pytest.raises(bd.BmhdError):
+        x.stage(0, 0, view, U, U, torch.empty_like(U), dt, local_dt=True)
+    with pytest.raises(bd.BmhdError):
+        x.stage(0, 0, view, U, U, torch.empty_like(U), dt, persist_wgs=256)
