@@ -335,3 +335,60 @@ def mlp_loss_grad(params, H, x, t):
 def mlp_adam(p, m, v, g, lr, t, b1=0.9, b2=0.999, eps=1e-8):
     """In place on float64 arrays p, m, v."""
     lib().mlp_adam(_dp(p), _dp(m), _dp(v), _dp(np.ascontiguousarray(g, np.float64)), p.size, lr, b1, b2, eps, int(t))
+
+
+# ------------------------------------------------------------------------------------------------
+# training targets of the learned flux correction (the library's own form, not the paper's)
+
+def _face_slot(d, x, y, z):
+    """Index of face (x, y, z) of direction d in a block's face-data layout (576 faces per direction)."""
+    return ((z * 8 + y) * 9 + x) if d == 0 else (((z * 9 + y) * 8 + x) if d == 1 else ((z * 8 + y) * 8 + x))
+
+
+def _face_coords(d, f):
+    """Face coordinates (x, y, z) of slot f of direction d (the coordinate along d in 0..8)."""
+    if d == 0:
+        return f % 9, (f // 9) % 8, f // 72
+    if d == 1:
+        return f % 8, (f // 8) % 9, f // 72
+    return f % 8, (f // 8) % 8, f // 64
+
+
+def face_targets(Ff, fine_ijk, Fc, coarse_ijk):
+    """For every face of a level-0 grid (blocks coarse_ijk), the mean of the 4 faces of the fine grid (the
+    same domain refined once: blocks fine_ijk at level 1) covering it, minus the coarse face value, per
+    component. Ff [n_fine * 1728, 8] and Fc [n_coarse * 1728, 8] are float32 face data in the layout
+    [block][direction][576 faces][8]; the result is float32 in the coarse layout.
+
+    In global fine coordinates the coarse face at position a along its normal d (block ic) is the fine
+    face plane 16 ic + 2 a, and a coarse tangential position t covers the fine rows 16 ic + 2 t and + 1.
+    A fine face at normal position P belongs to the fine block P // 8 at local position P % 8, except a
+    coarse block's high face (a = 8), which is read as local position 8 of the fine block below it, so that
+    every fine face read lies in one of the coarse block's children. The mean is taken in float64 as
+    ((f00 + f10) + (f01 + f11)) / 4 with the first tangential axis (x before y before z) fastest, the
+    difference rounded to float32 once."""
+    Ff = np.asarray(Ff, np.float32).reshape(-1, 3, 576, 8).astype(np.float64)
+    Fc = np.asarray(Fc, np.float32).reshape(-1, 3, 576, 8).astype(np.float64)
+    coarse_ijk = np.asarray(coarse_ijk).reshape(-1, 3)
+    where = {tuple(int(v) for v in ijk): b for b, ijk in enumerate(np.asarray(fine_ijk).reshape(-1, 3))}
+    out = np.empty(Fc.shape, np.float32)
+    for d in range(3):
+        t1, t2 = [a for a in range(3) if a != d]
+        for f in range(576):
+            q = _face_coords(d, f)
+            for c in range(coarse_ijk.shape[0]):
+                parts = []
+                for e2 in (0, 1):
+                    for e1 in (0, 1):
+                        g = [16 * int(coarse_ijk[c, a]) + 2 * q[a] for a in range(3)]
+                        g[t1] += e1
+                        g[t2] += e2
+                        n = [g[a] // 8 for a in range(3)]
+                        loc = [g[a] % 8 for a in range(3)]
+                        if q[d] == 8:
+                            n[d] -= 1
+                            loc[d] = 8
+                        parts.append(Ff[where[tuple(n)], d, _face_slot(d, *loc)])
+                mean = ((parts[0] + parts[1]) + (parts[2] + parts[3])) * 0.25
+                out[c, d, f] = (mean - Fc[c, d, f]).astype(np.float32)
+    return out.reshape(-1, 8)
