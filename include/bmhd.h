@@ -228,6 +228,17 @@ int32_t bmhd_fill_ghosts(const bmhd_grid *g, const double *d_U, double *d_view, 
 int32_t bmhd_remap(const bmhd_grid *from, const double *d_U_from, const bmhd_grid *to, double *d_U_to,
                    void *stream);
 
+/* Training targets of the learned flux correction (this library's own form, not the paper's): for every
+ * face of the level-0 grid `coarse`, the mean of the 4 face fluxes of `fine` (the same simulations with
+ * every root refined once, all blocks level 1) that cover it minus the coarse face flux, per component:
+ * d_T[coarse n_blocks * 1728][8] from d_Ff[fine n_blocks * 1728][8] and d_Fc[coarse n_blocks * 1728][8]
+ * (float32 device buffers in the layout and face-normal frame of bmhd_face_data). The 4 fine faces are
+ * averaged pairwise, ((f00 + f10) + (f01 + f11)) / 4 with the first tangential index fastest, in float64
+ * without contraction, then rounded. Coarse blocks are restricted from the fine grid by bmhd_remap.
+ * Errors: BMHD_EINVAL (grids not uploaded or not in that relation, null buffers). */
+int32_t bmhd_face_targets(const bmhd_grid *fine, const float *d_Ff, const bmhd_grid *coarse, const float *d_Fc,
+                          float *d_T, void *stream);
+
 /* Refinement indicator per block into d_ind[n_blocks] (device): the largest normalised jump, over the
  * block's cells and the three axes, of the density and of |B|^2 between a cell's two face neighbours
  * (neighbours outside the block by the ghost rules of bmhd_fill_ghosts): |q+ - q-| / (q+ + q- + 1e-300).

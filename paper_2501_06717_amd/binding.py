@@ -25,7 +25,8 @@ EXPORTS = ["bmhd_version", "bmhd_last_error", "bmhd_grid_create", "bmhd_grid_des
            "bmhd_reduce_dt", "bmhd_advance", "bmhd_autotune", "bmhd_mlp_last_error", "bmhd_mlp_n_params", "bmhd_mlp_work_bytes",
            "bmhd_mlp_forward", "bmhd_mlp_backward", "bmhd_mlp_backward_noalloc", "bmhd_mlp_adam", "bmhd_mlp_to_bf16", "bmhd_face_data",
            "bmhd_block_indicator", "bmhd_adapt", "bmhd_xchg_create", "bmhd_xchg_destroy", "bmhd_xchg_sizes", "bmhd_xchg_messages", "bmhd_xchg_upload",
-           "bmhd_xchg_interior", "bmhd_xchg_pack", "bmhd_xchg_unpack", "bmhd_xchg_stage", "bmhd_xchg_flux_correct"]
+           "bmhd_xchg_interior", "bmhd_xchg_pack", "bmhd_xchg_unpack", "bmhd_xchg_stage", "bmhd_xchg_flux_correct",
+           "bmhd_face_targets"]
 
 
 class SimDesc(ctypes.Structure):
@@ -141,6 +142,8 @@ def lib():
     L.bmhd_xchg_pack.restype = i32
     L.bmhd_xchg_unpack.argtypes = [vp, i32, i32, vp, vp, vp, vp]
     L.bmhd_xchg_unpack.restype = i32
+    L.bmhd_face_targets.argtypes = [vp, vp, vp, vp, vp, vp]
+    L.bmhd_face_targets.restype = i32
     L.bmhd_xchg_stage.argtypes = [vp, i32, i32, vp, vp, vp, vp, vp, P(Opts), vp, vp]
     L.bmhd_xchg_stage.restype = i32
     L.bmhd_xchg_flux_correct.argtypes = [vp, i32, i32, vp, vp, P(Opts), vp, vp]
@@ -297,6 +300,16 @@ class Grid:
             out = torch.empty((8, to.nb, 8, 8, 8), dtype=torch.float64, device=U.device)
         _check(lib().bmhd_remap(self.h, _dev_ptr(U, torch.float64), to.h, _dev_ptr(out, torch.float64),
                                 _stream_ptr(stream)))
+        return out
+
+    def face_targets(self, Ff, coarse, Fc, out=None, stream=None):
+        """Flux-correction targets of grid `coarse`'s faces from this grid (the same simulations refined
+        everywhere): mean of the 4 fine face fluxes minus the coarse one, [coarse.nb * 1728, 8] float32."""
+        import torch
+        if out is None:
+            out = torch.empty((coarse.nb * 1728, 8), dtype=torch.float32, device=Ff.device)
+        _check(lib().bmhd_face_targets(self.h, _dev_ptr(Ff, torch.float32), coarse.h, _dev_ptr(Fc, torch.float32),
+                                       _dev_ptr(out, torch.float32), _stream_ptr(stream)))
         return out
 
     def block_indicator(self, U, out=None, stream=None):

@@ -1590,6 +1590,58 @@ __global__ void __launch_bounds__(BLK_NT, (blk_waves_per_simd<R>())) k_stage_blk
     blk_compute<R, FLUX, POWELL>(T, A, b, sW);
 }
 
+// Flux-correction target of every face of a level-0 grid C from the same simulations refined everywhere
+// (grid F, every block level 1): the mean of the 4 fine face fluxes covering the coarse face minus the
+// coarse face flux, per component, with the face-data layout of both grids ([block][3][576][8], face-
+// normal frame). The 4 fine faces lie in one child of the coarse block: along the face normal the coarse
+// position a (0..8) is the fine position 2a, across it the coarse position t the fine positions 2t and
+// 2t + 1; their mean is taken pairwise ((f00 + f10) + (f01 + f11)) / 4 with the first tangential index
+// fastest, in FP64 without contraction, and rounded to FP32. One workgroup per coarse block, one thread per
+// face of each direction.
+__global__ void __launch_bounds__(576) k_face_targets(Tables F, const float *__restrict__ Ff, Tables C,
+                                                      const float *__restrict__ Fc, float *__restrict__ Tout) {
+#pragma clang fp contract(off)
+    const int c = blockIdx.x, f = threadIdx.x;
+    const DevBlock &B = C.blocks[c];
+    const DevSim &S = F.sims[B.sim];
+#pragma unroll
+    for (int D = 0; D < 3; ++D) {
+        int q[3];  // coarse face coordinates (x, y, z), the one along D in 0..8
+        if (D == 0) { q[0] = f % 9; q[1] = (f / 9) & 7; q[2] = f / 72; }
+        else if (D == 1) { q[0] = f & 7; q[1] = (f >> 3) % 9; q[2] = f / 72; }
+        else { q[0] = f & 7; q[1] = (f >> 3) & 7; q[2] = f >> 6; }
+        const int a1 = D == 0 ? 1 : 0, a2 = D == 2 ? 1 : 2;  // tangential axes, the first one fastest
+        int child[3], fq[3];
+        {
+            const int g = 2 * q[D];
+            child[D] = g >= 8 ? 1 : 0;
+            fq[D] = g - 8 * child[D];
+        }
+        child[a1] = q[a1] >> 2;
+        fq[a1] = 2 * q[a1] - 8 * child[a1];
+        child[a2] = q[a2] >> 2;
+        fq[a2] = 2 * q[a2] - 8 * child[a2];
+        const int32_t fb = lut_at(F, S, 1, 2LL * B.ijk[0] + child[0], 2LL * B.ijk[1] + child[1],
+                                  2LL * B.ijk[2] + child[2]);
+        const float *src[4];
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            int p[3] = {fq[0], fq[1], fq[2]};
+            p[a1] += m & 1;
+            p[a2] += m >> 1;
+            const int idx = D == 0 ? face_index<0>(p[0], p[1], p[2])
+                                   : (D == 1 ? face_index<1>(p[0], p[1], p[2]) : face_index<2>(p[0], p[1], p[2]));
+            src[m] = Ff + ((size_t(fb) * 3 + D) * 576 + idx) * 8;
+        }
+        const size_t o = ((size_t(c) * 3 + D) * 576 + f) * 8;
+#pragma unroll
+        for (int v = 0; v < 8; ++v) {
+            const double mean = ((double(src[0][v]) + double(src[1][v])) + (double(src[2][v]) + double(src[3][v]))) * 0.25;
+            Tout[o + v] = float(mean - double(Fc[o + v]));
+        }
+    }
+}
+
 // Per-face training data of a whole block (one workgroup of 576 threads = one face per thread and
 // direction): stencil features in the face-normal frame (optionally z-scored) and the plain flux in the
 // face-normal frame, FP64 arithmetic.
@@ -2438,6 +2490,26 @@ int32_t bmhd_remap(const bmhd_grid *from, const double *d_U_from, const bmhd_gri
     if (t.nb == 0) return BMHD_OK;
     k_remap<<<t.nb, 512, 0, reinterpret_cast<hipStream_t>(stream)>>>(f.dev, d_U_from, t.dev, d_U_to);
     return launch_check("remap");
+}
+
+int32_t bmhd_face_targets(const bmhd_grid *fine, const float *d_Ff, const bmhd_grid *coarse, const float *d_Fc,
+                          float *d_T, void *stream) {
+    if (int32_t rc = need_upload(fine)) return rc;
+    if (int32_t rc = need_upload(coarse)) return rc;
+    if (!d_Ff || !d_Fc || !d_T) return fail(BMHD_EINVAL, "face_targets: null buffer");
+    const HostGrid &f = fine->h, &c = coarse->h;
+    if (!remap_compatible(f, c)) return fail(BMHD_EINVAL, "face_targets: the grids differ in their simulations");
+    if (f.nb != 8 * c.nb) return fail(BMHD_EINVAL, "face_targets: the fine grid must be the coarse grid refined everywhere");
+    for (int b = 0; b < c.nb; ++b) {
+        if (c.level[b] != 0) return fail(BMHD_EINVAL, "face_targets: the coarse grid must be all level 0");
+        for (int q = 0; q < 8; ++q)
+            if (host_lut(f, c.sim[b], 1, 2LL * c.ijk[3 * b] + (q & 1), 2LL * c.ijk[3 * b + 1] + ((q >> 1) & 1),
+                         2LL * c.ijk[3 * b + 2] + (q >> 2)) < 0)
+                return fail(BMHD_EINVAL, "face_targets: a coarse block lacks its 8 level-1 children in the fine grid");
+    }
+    if (c.nb == 0) return BMHD_OK;
+    k_face_targets<<<c.nb, 576, 0, reinterpret_cast<hipStream_t>(stream)>>>(f.dev, d_Ff, c.dev, d_Fc, d_T);
+    return launch_check("face targets");
 }
 
 int32_t bmhd_block_indicator(const bmhd_grid *g, const double *d_U, double *d_ind, void *stream) {

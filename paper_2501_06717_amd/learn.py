@@ -2,7 +2,8 @@
 
 The network corrects the plain HLLE flux of a coarse grid (128^3 cells, dx = 2) toward the flux a grid
 twice as fine would put through the same face. Training data come from plain FP64 runs on the fine
-grid (256^3, dx = 1) of solar-wind states drawn at random:
+grid (256^3, dx = 1: the coarse grid's simulation with every root refined once) of solar-wind states
+drawn at random:
 
 * every `snap_every` fine steps, the fine state is restricted to the coarse grid (mean of the 8 fine
   cells); the target of a coarse face is the mean of the 4 fine face fluxes covering it minus the plain
@@ -18,9 +19,9 @@ Evaluation on held-out states: coarse plain and coarse learned runs against the 
 many steps and over one step; the one-step test also runs with the exact target of that state given as
 the correction (no network), the bound for any correction of this form.
 
-Training and inference run in the library's kernels (BF16 matrix cores, FP32 master weights, Adam).
-Data preparation (restriction, face averaging, sampling, statistics) uses torch tensor operations on
-the GPU.
+Training and inference run in the library's kernels (BF16 matrix cores, FP32 master weights, Adam), and
+so do restriction (bmhd_remap) and the face targets (bmhd_face_targets); sampling and statistics use torch
+tensor operations on the GPU.
 """
 from __future__ import annotations
 
@@ -52,13 +53,42 @@ def solar_wind_states(n, seed):
 
 
 def magnetosphere_pair(state, n_fine=256, M=7.9e4):
-    """Fine (n_fine^3, dx = 1) and coarse (n_fine/2)^3 (dx = 2) workloads of one solar-wind state."""
-    fine = wk.magnetosphere(n_fine, M=M, **state)
-    sim_c = wk.magnetosphere_sim(n_fine // 2, **state)
-    lv, ijk, sid = wk.uniform_blocks(sim_c.nroot)
-    coarse = wk.Workload(f"coarse_{n_fine // 2}", lv, ijk, sid, [sim_c], wk.magnetosphere_state(sim_c, lv, ijk, M),
+    """Fine and coarse workloads of one solar-wind state: the coarse grid (n_fine/2)^3, dx = 2, level-0
+    blocks; the fine grid the same simulation with every root refined once (all blocks level 1, dx = 1),
+    so that bmhd_remap restricts fine states onto the coarse grid and bmhd_face_targets pairs the faces."""
+    sim = wk.magnetosphere_sim(n_fine // 2, **state)
+    lv, ijk, sid = wk.uniform_blocks(sim.nroot)
+    coarse = wk.Workload(f"coarse_{n_fine // 2}", lv, ijk, sid, [sim], wk.magnetosphere_state(sim, lv, ijk, M),
                          flux="hlle", powell=True, cfl=0.8)
+    lvf, ijkf, sidf = wk.two_level_blocks(sim.nroot, np.ones(sim.nroot[::-1], bool))
+    fine = wk.Workload(f"fine_{n_fine}", lvf, ijkf, sidf, [sim], wk.magnetosphere_state(sim, lvf, ijkf, M),
+                       flux="hlle", powell=True, cfl=0.8)
     return fine, coarse
+
+
+def low_faces(nb, d):
+    """Rows of the per-block face layout (bmhd_face_data: [block][3][576]) of direction d whose position
+    along d is 0..7: every face of the grid once (faces on the domain's high side excepted)."""
+    import torch
+    f = torch.arange(576)
+    a = (f % 9) if d == 0 else (((f >> 3) % 9) if d == 1 else (f >> 6))
+    sel = f[a < 8]
+    return (torch.arange(nb).reshape(-1, 1) * 1728 + d * 576 + sel.reshape(1, -1)).reshape(-1)
+
+
+def face_pairs(nb, d):
+    """Row pairs (low face, high face) of every cell along direction d in the per-block face layout."""
+    import torch
+    k, j, i = torch.meshgrid(torch.arange(8), torch.arange(8), torch.arange(8), indexing="ij")
+    i, j, k = i.reshape(-1), j.reshape(-1), k.reshape(-1)   # cell (i, j, k) = (x, y, z)
+    if d == 0:
+        lo, hi = (k * 8 + j) * 9 + i, (k * 8 + j) * 9 + i + 1
+    elif d == 1:
+        lo, hi = (k * 9 + j) * 8 + i, (k * 9 + j + 1) * 8 + i
+    else:
+        lo, hi = (k * 8 + j) * 8 + i, ((k + 1) * 8 + j) * 8 + i
+    base = torch.arange(nb).reshape(-1, 1) * 1728 + d * 576
+    return (base + lo.reshape(1, -1)).reshape(-1), (base + hi.reshape(1, -1)).reshape(-1)
 
 
 # --------------------------------------------------------------------------------------------------
@@ -77,55 +107,14 @@ def from_global(G, nb):
     return t.permute(0, 1, 3, 5, 2, 4, 6).reshape(v, nb ** 3, 8, 8, 8).contiguous()
 
 
-def restrict(Uf, nbf):
-    """Mean of the 8 fine cells of each coarse cell (conserved variables)."""
-    return restrict_by(Uf, nbf, 2)
-
-
 def restrict_by(Uf, nbf, k):
-    """Mean of the k^3 fine cells of each coarse cell (conserved variables); nbf^3 fine blocks of 8^3."""
+    """Mean of the k^3 fine cells of each coarse cell (conserved variables); nbf^3 fine blocks of 8^3 in
+    i-fastest order. Used where no remap applies: the equal-cost comparison restricts a 384^3 uniform run
+    by 3 and by 2."""
     G = to_global(Uf, nbf)
     n = G.shape[1] // k
     Gc = G.reshape(8, n, k, n, k, n, k).mean(dim=(2, 4, 6))
     return from_global(Gc, nbf // k)
-
-
-def faces_global(F, nb, d, c):
-    """Per-block face data [nb^3 * 3 * 576, c] -> global faces of direction d: [c, Nz', Ny', Nx'] with
-    N + 1 positions along d."""
-    import torch
-    N = nb * 8
-    t = F.reshape(nb, nb, nb, 3, 576, c)[:, :, :, d]        # (bz, by, bx, f, c)
-    if d == 0:
-        t = t.reshape(nb, nb, nb, 8, 8, 9, c)               # (bz, by, bx, z, y, x)
-        body = t[..., :8, :].permute(6, 0, 3, 1, 4, 2, 5).reshape(c, N, N, N)
-        last = t[:, :, -1, :, :, 8, :].permute(4, 0, 2, 1, 3).reshape(c, N, N, 1)
-        return torch.cat([body, last], dim=3)
-    if d == 1:
-        t = t.reshape(nb, nb, nb, 8, 9, 8, c)
-        body = t[:, :, :, :, :8].permute(6, 0, 3, 1, 4, 2, 5).reshape(c, N, N, N)
-        last = t[:, -1, :, :, 8, :, :].permute(4, 0, 2, 1, 3).reshape(c, N, 1, N)
-        return torch.cat([body, last], dim=2)
-    t = t.reshape(nb, nb, nb, 9, 8, 8, c)
-    body = t[:, :, :, :8].permute(6, 0, 3, 1, 4, 2, 5).reshape(c, N, N, N)
-    last = t[-1, :, :, 8].permute(4, 0, 2, 1, 3).reshape(c, 1, N, N)
-    return torch.cat([body, last], dim=1)
-
-
-def coarse_face_mean(Ff, d):
-    """Mean of the 4 fine faces covering each coarse face: fine global faces [c, ...] of direction d."""
-    c = Ff.shape[0]
-    if d == 0:
-        t = Ff[:, :, :, ::2]
-        nz, ny, nx = t.shape[1] // 2, t.shape[2] // 2, t.shape[3]
-        return t.reshape(c, nz, 2, ny, 2, nx).mean(dim=(2, 4))
-    if d == 1:
-        t = Ff[:, :, ::2, :]
-        nz, ny, nx = t.shape[1] // 2, t.shape[2], t.shape[3] // 2
-        return t.reshape(c, nz, 2, ny, nx, 2).mean(dim=(2, 5))
-    t = Ff[:, ::2, :, :]
-    nz, ny, nx = t.shape[1], t.shape[2] // 2, t.shape[3] // 2
-    return t.reshape(c, nz, ny, 2, nx, 2).mean(dim=(3, 5))
 
 
 # --------------------------------------------------------------------------------------------------
@@ -136,9 +125,9 @@ class Config:
     n_fine: int = 256
     train_states: int = 32
     heldout_states: int = 2
-    fine_steps: int = 200
+    fine_steps: int = 400
     snap_every: int = 20
-    samples_per_dir: int = 16384
+    samples_per_dir: int = 8192
     top_frac: float = 0.0          # share of each snapshot's samples drawn from the top decile of |target|
     pair: float = 0.0              # > 0: samples are the two faces of a coarse cell along each direction, and
                                    # this weight goes to the error of their difference (what the cell update
@@ -157,67 +146,57 @@ def fine_dt(g, U, cfl=0.8):
     return g.reduce_dt(U, cfl)
 
 
-def snapshot_data(bd, gf, gc, Uf, nbf, gen):
-    """(X, T) samples of one fine snapshot: coarse stencil features and flux corrections."""
-    import torch
-    Uc = restrict(Uf, nbf)
+def snapshot_targets(gf, gc, Uf):
+    """Coarse stencil features Xc [nbc * 1728, 32] and flux-correction targets T [nbc * 1728, 8] of one
+    fine snapshot (the fine state restricted by bmhd_remap; targets by bmhd_face_targets)."""
+    Uc = gf.remap(Uf, gc)
     Xc, Fc = gc.face_data(Uc, flux="hlle")
     _, Ff = gf.face_data(Uf, flux="hlle", want_x=False)
-    nbc = nbf // 2
+    T = gf.face_targets(Ff, gc, Fc)
+    del Ff, Fc, Uc
+    return Xc, T
+
+
+def sample(n, mag, gen):
+    """Indices 0..n-1: `samples` of them, a share `top_frac` from the top decile of `mag`, the rest
+    uniform."""
+    import torch
+    kt = int(round(gen["samples"] * gen["top_frac"]))
+    ku = gen["samples"] - kt
+    top = torch.topk(mag, max(n // 10, kt)).indices
+    pick_top = top[torch.randint(0, top.numel(), (kt,), generator=gen["g"], device=top.device)]
+    pick_uni = torch.randint(0, n, (ku,), generator=gen["g"], device=top.device)
+    return torch.cat([pick_uni, pick_top])
+
+
+def snapshot_data(bd, gf, gc, Uf, gen):
+    """(X, T) samples of one fine snapshot: coarse stencil features and flux corrections."""
+    import torch
+    Xc, T = snapshot_targets(gf, gc, Uf)
     xs, ts = [], []
     for d in range(3):
-        Fg = faces_global(Ff, nbf, d, 8)
-        target = coarse_face_mean(Fg, d) - faces_global(Fc, nbc, d, 8)
-        Xg = faces_global(Xc, nbc, d, 32)
-        T = target.reshape(8, -1).t()
-        X = Xg.reshape(32, -1).t()
-        n = T.shape[0]
-        kt = int(round(gen["samples"] * gen["top_frac"]))
-        ku = gen["samples"] - kt
-        mag = (T / (T.std(dim=0) + 1e-30)).norm(dim=1)
-        top = torch.topk(mag, max(n // 10, kt)).indices
-        pick_top = top[torch.randint(0, top.numel(), (kt,), generator=gen["g"], device=top.device)]
-        pick_uni = torch.randint(0, n, (ku,), generator=gen["g"], device=top.device)
-        idx = torch.cat([pick_uni, pick_top])
-        xs.append(X[idx])
-        ts.append(T[idx])
-        del Fg, target, Xg
+        rows = low_faces(gc.nb, d).to(T.device)
+        Td, Xd = T[rows], Xc[rows]
+        idx = sample(Td.shape[0], (Td / (Td.std(dim=0) + 1e-30)).norm(dim=1), gen)
+        xs.append(Xd[idx])
+        ts.append(Td[idx])
     return torch.cat(xs), torch.cat(ts)
 
 
-def snapshot_pairs(bd, gf, gc, Uf, nbf, gen):
+def snapshot_pairs(bd, gf, gc, Uf, gen):
     """Samples of one fine snapshot as face pairs: the low and high face of a coarse cell along each
-    direction, X [n, 2, 32] (coarse stencil features) and T [n, 2, 8] (flux corrections). Half of them are
-    uniform, `top_frac` from the top decile of the difference of the two corrections."""
+    direction, X [n, 2, 32] (coarse stencil features) and T [n, 2, 8] (flux corrections). A share
+    `top_frac` comes from the top decile of the difference of the two corrections, the rest is uniform."""
     import torch
-    Uc = restrict(Uf, nbf)
-    Xc, Fc = gc.face_data(Uc, flux="hlle")
-    _, Ff = gf.face_data(Uf, flux="hlle", want_x=False)
-    nbc = nbf // 2
+    Xc, T = snapshot_targets(gf, gc, Uf)
     xs, ts = [], []
     for d in range(3):
-        Fg = faces_global(Ff, nbf, d, 8)
-        target = coarse_face_mean(Fg, d) - faces_global(Fc, nbc, d, 8)
-        Xg = faces_global(Xc, nbc, d, 32)
-        ax = 3 - d                                   # global face arrays are [c, z, y, x]
-        lo = [slice(None)] * 4
-        hi = [slice(None)] * 4
-        lo[ax] = slice(0, -1)
-        hi[ax] = slice(1, None)
-        Ta, Tb = target[tuple(lo)].reshape(8, -1).t(), target[tuple(hi)].reshape(8, -1).t()
-        Xa, Xb = Xg[tuple(lo)].reshape(32, -1).t(), Xg[tuple(hi)].reshape(32, -1).t()
-        n = Ta.shape[0]
-        kt = int(round(gen["samples"] * gen["top_frac"]))
-        ku = gen["samples"] - kt
+        lo, hi = (r.to(T.device) for r in face_pairs(gc.nb, d))
+        Ta, Tb, Xa, Xb = T[lo], T[hi], Xc[lo], Xc[hi]
         dT = Tb - Ta
-        mag = (dT / (dT.std(dim=0) + 1e-30)).norm(dim=1)
-        top = torch.topk(mag, max(n // 10, kt)).indices
-        pick_top = top[torch.randint(0, top.numel(), (kt,), generator=gen["g"], device=top.device)]
-        pick_uni = torch.randint(0, n, (ku,), generator=gen["g"], device=top.device)
-        idx = torch.cat([pick_uni, pick_top])
+        idx = sample(Ta.shape[0], (dT / (dT.std(dim=0) + 1e-30)).norm(dim=1), gen)
         xs.append(torch.stack([Xa[idx], Xb[idx]], dim=1))
         ts.append(torch.stack([Ta[idx], Tb[idx]], dim=1))
-        del Fg, target, Xg
     return torch.cat(xs), torch.cat(ts)
 
 
@@ -227,7 +206,6 @@ def generate(bd, cfg: Config, states, log=print):
     gen = {"g": torch.Generator(device="cuda"), "samples": cfg.samples_per_dir, "top_frac": cfg.top_frac}
     gen["g"].manual_seed(cfg.seed_train)
     X, T = [], []
-    nbf = cfg.n_fine // 8
     for si, st in enumerate(states):
         fine, coarse = magnetosphere_pair(st, cfg.n_fine)
         gf = bd.Grid.from_workload(fine).upload()
@@ -238,7 +216,7 @@ def generate(bd, cfg: Config, states, log=print):
         t0 = time.time()
         for s0 in range(0, cfg.fine_steps, cfg.snap_every):
             gf.advance(U0, U1, dt, 2 * cfg.snap_every, flux="hlle", powell=True, cfl=0.8)
-            x, t = (snapshot_pairs if cfg.pair > 0 else snapshot_data)(bd, gf, gc, U0, nbf, gen)
+            x, t = (snapshot_pairs if cfg.pair > 0 else snapshot_data)(bd, gf, gc, U0, gen)
             X.append(x)
             T.append(t)
         torch.cuda.synchronize()
@@ -311,7 +289,6 @@ def developed_state(bd, st, n_fine, warm_steps=100):
     restriction to the coarse grid: (fine grid, coarse grid, coarse workload, fine state, the fine dt of
     that state, restricted coarse state). The flow has then left the uniform start."""
     import torch
-    nbf = n_fine // 8
     fine, coarse = magnetosphere_pair(st, n_fine)
     gf = bd.Grid.from_workload(fine).upload()
     gc = bd.Grid.from_workload(coarse).upload()
@@ -320,7 +297,7 @@ def developed_state(bd, st, n_fine, warm_steps=100):
     dtf = torch.zeros(1, dtype=torch.float64, device="cuda")
     gf.advance(Uf, U1, dtf, 2 * warm_steps, flux="hlle", powell=True, cfl=0.8)
     dtf = gf.reduce_dt(Uf, 0.8)
-    return gf, gc, coarse, Uf, dtf, restrict(Uf, nbf)
+    return gf, gc, coarse, Uf, dtf, gf.remap(Uf, gc)
 
 
 def one_step_gain(bd, cfg: Config, mlp, stats, st, warm_steps=100):
@@ -329,11 +306,10 @@ def one_step_gain(bd, cfg: Config, mlp, stats, st, warm_steps=100):
     L1 of the change of state, per variable, relative to the fine change; and the flagged share of the
     learned step's cell-stages."""
     import torch
-    nbf = cfg.n_fine // 8
     gf, gc, coarse, Uf, dtf, Uc0 = developed_state(bd, st, cfg.n_fine, warm_steps)
     U1 = torch.empty_like(Uf)
     gf.advance(Uf, U1, dtf, 4, flux="hlle", powell=True, recompute_dt=False)
-    dref = restrict(Uf, nbf) - Uc0
+    dref = gf.remap(Uf, gc) - Uc0
     out = {}
     fb = torch.zeros(1, dtype=torch.int32, device="cuda")
     for name, learned in (("plain", None), ("learned", gc.learned(mlp, stats, fallback=fb, floor_rel=cfg.floor_rel))):
@@ -347,37 +323,18 @@ def one_step_gain(bd, cfg: Config, mlp, stats, st, warm_steps=100):
     return out
 
 
-def faces_to_blocks(G, nb, d):
-    """Inverse of faces_global: global faces of direction d [c, ...] -> per-block faces [nb^3, 576, c] in
-    the face order of bmhd_face_data."""
-    import torch
-    ar = lambda n: torch.arange(n, device=G.device)
-    bz, by, bx = torch.meshgrid(ar(nb), ar(nb), ar(nb), indexing="ij")
-    dims = {0: (8, 8, 9), 1: (8, 9, 8), 2: (9, 8, 8)}[d]
-    z, y, x = torch.meshgrid(ar(dims[0]), ar(dims[1]), ar(dims[2]), indexing="ij")
-    Z = bz.reshape(-1, 1) * 8 + z.reshape(1, -1)
-    Y = by.reshape(-1, 1) * 8 + y.reshape(1, -1)
-    X = bx.reshape(-1, 1) * 8 + x.reshape(1, -1)
-    return G[:, Z, Y, X].permute(1, 2, 0)
-
-
 def exact_target_one_step(bd, cfg: Config, st, warm_steps=100):
     """The one_step_gain test with the exact a-priori target (from the fine state, not a network) given to
     the learned stage as its correction: the best a correction of this form can do from this state."""
     import torch
-    nbf, nbc = cfg.n_fine // 8, cfg.n_fine // 16
     gf, gc, coarse, Uf, dtf, Uc0 = developed_state(bd, st, cfg.n_fine, warm_steps)
     U1 = torch.empty_like(Uf)
     _, Fc = gc.face_data(Uc0, flux="hlle", want_x=False)
     _, Ff = gf.face_data(Uf, flux="hlle", want_x=False)
-    ys = []
-    for d in range(3):
-        T = coarse_face_mean(faces_global(Ff, nbf, d, 8), d) - faces_global(Fc, nbc, d, 8)
-        ys.append(faces_to_blocks(T, nbc, d))
-    y = torch.stack(ys, dim=1).reshape(-1, 8).float().contiguous()
-    del Ff, Fc, ys
+    y = gf.face_targets(Ff, gc, Fc)
+    del Ff, Fc
     gf.advance(Uf, U1, dtf, 4, flux="hlle", powell=True, recompute_dt=False)
-    dref = restrict(Uf, nbf) - Uc0
+    dref = gf.remap(Uf, gc) - Uc0
     stats = torch.zeros(80)
     stats[32:64] = 1.0
     stats[72:80] = 1.0
@@ -397,17 +354,16 @@ def evaluate(bd, cfg: Config, mlp, stats, states, log=print):
     """Coarse plain vs coarse learned against the fine run restricted, at the same time."""
     import torch
     out = []
-    nbf = cfg.n_fine // 8
     for st in states:
         fine, coarse = magnetosphere_pair(st, cfg.n_fine)
         gf = bd.Grid.from_workload(fine).upload()
         gc = bd.Grid.from_workload(coarse).upload()
         Uf = gf.set_state(torch.from_numpy(fine.W).cuda())
         dtf = gf.reduce_dt(Uf, 0.8)
-        Uc0 = restrict(Uf, nbf)
+        Uc0 = gf.remap(Uf, gc)
         U1 = torch.empty_like(Uf)
         gf.advance(Uf, U1, dtf, 2 * cfg.fine_steps, flux="hlle", powell=True, recompute_dt=False)
-        ref = restrict(Uf, nbf)
+        ref = gf.remap(Uf, gc)
         del U1
         dtc = dtf * 2.0
         res = {}
@@ -514,11 +470,11 @@ def main():
     ap.add_argument("--n-fine", type=int, default=256)
     ap.add_argument("--train-states", type=int, default=32)
     ap.add_argument("--heldout-states", type=int, default=2)
-    ap.add_argument("--fine-steps", type=int, default=200)
+    ap.add_argument("--fine-steps", type=int, default=400)
     ap.add_argument("--epochs", type=int, default=24)
     ap.add_argument("--strength", type=float, default=0.25,
                     help="fraction of the network's correction applied (folded into the output statistics)")
-    ap.add_argument("--samples", type=int, default=16384)
+    ap.add_argument("--samples", type=int, default=8192)
     ap.add_argument("--top-frac", type=float, default=0.0)
     ap.add_argument("--pair", type=float, default=0.0,
                     help="train on face pairs with this weight on the error of the pair's difference")

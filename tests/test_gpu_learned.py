@@ -338,3 +338,44 @@ def test_unchanged_uniform_state_is_never_flagged(bd, precision):
     torch.cuda.synchronize()
     assert int(fb.item()) == 0
     assert torch.equal(U0, Uref)
+
+
+@pytest.mark.parametrize("nroot", [(2, 1, 1), (2, 2, 2)])
+def test_face_targets_match_the_oracle(bd, oracle_mod, nroot):
+    """bmhd_face_targets against the oracle bit for bit: on random face data (every fine face read from
+    the right block and slot), and on the face fluxes of a state on the refined grid and of its
+    restriction by bmhd_remap."""
+    sim_wl = wk.magnetosphere_cut(8 * nroot[0]) if nroot == (2, 2, 2) else wk.uniform_state(nroot)
+    sim = sim_wl.sims[0]
+    lv, ijk, sid = wk.uniform_blocks(sim.nroot)
+    coarse = wk.Workload("coarse", lv, ijk, sid, [sim], wk._empty_W(len(lv)))
+    lvf, ijkf, sidf = wk.two_level_blocks(sim.nroot, np.ones(sim.nroot[::-1], bool))
+    fine = wk.Workload("fine", lvf, ijkf, sidf, [sim], wk._empty_W(len(lvf)))
+    fine = wk.with_state(fine, wk.random_positive_state(fine, seed=9))
+    gf = bd.Grid.from_workload(fine).upload()
+    gc = bd.Grid.from_workload(coarse).upload()
+    rng = np.random.default_rng(10)
+    Ff = rng.normal(size=(fine.n_blocks * 1728, 8)).astype(np.float32)
+    Fc = rng.normal(size=(coarse.n_blocks * 1728, 8)).astype(np.float32)
+    got = gf.face_targets(dev(Ff), gc, dev(Fc)).cpu().numpy()
+    ref = oracle_mod.face_targets(Ff, ijkf, Fc, ijk)
+    assert np.array_equal(got, ref)
+    Uf = gf.set_state(dev(fine.W))
+    Uc = gf.remap(Uf, gc)
+    _, Ffd = gf.face_data(Uf, flux="hlle", want_x=False)
+    _, Fcd = gc.face_data(Uc, flux="hlle", want_x=False)
+    got = gf.face_targets(Ffd, gc, Fcd).cpu().numpy()
+    ref = oracle_mod.face_targets(Ffd.cpu().numpy(), ijkf, Fcd.cpu().numpy(), ijk)
+    assert np.array_equal(got, ref)
+
+
+def test_face_targets_refuse_unrelated_grids(bd):
+    base = wk.uniform_state((2, 1, 1))
+    g2 = bd.Grid.from_workload(base).upload()
+    two = wk.two_level_box(nroot=(2, 1, 1), refine=((1, 0, 0),))
+    g3 = bd.Grid.from_workload(two).upload()
+    F = torch.zeros((max(base.n_blocks, two.n_blocks) * 1728, 8), dtype=torch.float32, device="cuda")
+    with pytest.raises(bd.BmhdError):
+        g3.face_targets(F, g2, F)        # not every root refined
+    with pytest.raises(bd.BmhdError):
+        g2.face_targets(F, g3, F)        # the coarse grid has level-1 blocks

@@ -27,54 +27,44 @@ def per_block_faces(nb, fn):
     return torch.from_numpy(out.reshape(-1, 1))
 
 
-def test_global_roundtrip_and_restriction():
+def test_global_roundtrip_and_restriction_by_k():
     nb = 2
     U = torch.arange(8 * nb ** 3 * 512, dtype=torch.float64).reshape(8, nb ** 3, 8, 8, 8)
     G = learn.to_global(U, nb)
     assert torch.equal(learn.from_global(G, nb), U)
     # block 1 is bx = 1: its cell (k, j, i) is global (z=k, y=j, x=8+i)
     assert G[3, 2, 5, 8 + 4] == U[3, 1, 2, 5, 4]
-    R = learn.restrict(U, nb)
+    R = learn.restrict_by(U, nb, 2)
     Gr = learn.to_global(R, 1)
     assert torch.isclose(Gr[0, 1, 2, 3], G[0, 2:4, 4:6, 6:8].mean())
 
 
 @pytest.mark.parametrize("d", [0, 1, 2])
-def test_faces_global_and_coarse_mean(d):
+def test_low_faces_cover_each_face_once(d):
+    """Per-block faces of direction d at positions 0..7 along d: 512 per block, and together with the
+    domain's high-side faces every global face position exactly once."""
     nb = 2
-    fn = lambda dd, X, Y, Z: 1000.0 * dd + X + 100.0 * Y + 10000.0 * Z
-    F = per_block_faces(nb, fn)
-    Fg = learn.faces_global(F, nb, d, 1)
+    F = per_block_faces(nb, lambda dd, X, Y, Z: X + 100.0 * Y + 10000.0 * Z).reshape(-1)
+    rows = learn.low_faces(nb ** 3, d)
+    assert rows.numel() == nb ** 3 * 512
+    vals = F[rows].numpy()
+    assert len(np.unique(vals)) == len(vals)
     N = 8 * nb
-    shape = [N, N, N]
-    shape[2 - d] += 1
-    assert tuple(Fg.shape[1:]) == tuple(shape)
-    Z, Y, X = np.meshgrid(np.arange(shape[0]), np.arange(shape[1]), np.arange(shape[2]), indexing="ij")
-    assert np.array_equal(Fg[0].numpy(), fn(d, X, Y, Z))
-    # coarse face (Zc, Yc, Xc) averages fine faces at twice the position along d, 2x2 across
-    M = learn.coarse_face_mean(Fg, d)[0].numpy()
-    c = [5, 3, 6]          # x, y, z of a coarse face
-    f = [2 * v for v in c]
-    acc = 0.0
-    for a in range(2):
-        for b in range(2):
-            g = list(f)
-            t = [ax for ax in range(3) if ax != d]
-            g[t[0]] += a
-            g[t[1]] += b
-            acc += fn(d, g[0], g[1], g[2])
-    assert M[c[2], c[1], c[0]] == acc / 4
+    pos = [np.arange(N)] * 3
+    X, Y, Z = np.meshgrid(*pos, indexing="ij")
+    assert set(vals.tolist()) == set((X + 100.0 * Y + 10000.0 * Z).reshape(-1).tolist())
 
 
 @pytest.mark.parametrize("d", [0, 1, 2])
-def test_faces_to_blocks_inverts_faces_global(d):
-    """Per-block faces -> global faces -> per-block faces is the identity (faces shared by two blocks
-    carry the same value in both)."""
+def test_face_pairs_are_the_two_faces_of_a_cell(d):
     nb = 2
-    F = per_block_faces(nb, lambda dd, X, Y, Z: 1000.0 * dd + X + 20.0 * Y + 400.0 * Z)
-    G = learn.faces_global(F, nb, d, 1)
-    back = learn.faces_to_blocks(G, nb, d)
-    assert torch.equal(back, F.reshape(nb ** 3, 3, 576, 1)[:, d])
+    fn = lambda dd, X, Y, Z: X + 100.0 * Y + 10000.0 * Z
+    F = per_block_faces(nb, fn).reshape(-1)
+    lo, hi = learn.face_pairs(nb ** 3, d)
+    assert lo.numel() == hi.numel() == nb ** 3 * 512
+    step = [1.0, 100.0, 10000.0][d]
+    assert torch.equal(F[hi] - F[lo], torch.full((lo.numel(),), step, dtype=F.dtype))
+    assert len(np.unique(F[lo].numpy())) == lo.numel()
 
 
 def test_strength_scales_only_the_output_statistics():
