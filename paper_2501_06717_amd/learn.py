@@ -125,9 +125,10 @@ class Config:
     n_fine: int = 256
     train_states: int = 32
     heldout_states: int = 2
-    fine_steps: int = 400
+    fine_steps: int = 200          # fine steps per training state (a snapshot every snap_every)
+    eval_fine_steps: int = 400     # evaluation horizon in fine steps (the coarse runs take half as many)
     snap_every: int = 20
-    samples_per_dir: int = 8192
+    samples_per_dir: int = 16384
     top_frac: float = 0.0          # share of each snapshot's samples drawn from the top decile of |target|
     pair: float = 0.0              # > 0: samples are the two faces of a coarse cell along each direction, and
                                    # this weight goes to the error of their difference (what the cell update
@@ -362,7 +363,7 @@ def evaluate(bd, cfg: Config, mlp, stats, states, log=print):
         dtf = gf.reduce_dt(Uf, 0.8)
         Uc0 = gf.remap(Uf, gc)
         U1 = torch.empty_like(Uf)
-        gf.advance(Uf, U1, dtf, 2 * cfg.fine_steps, flux="hlle", powell=True, recompute_dt=False)
+        gf.advance(Uf, U1, dtf, 2 * cfg.eval_fine_steps, flux="hlle", powell=True, recompute_dt=False)
         ref = gf.remap(Uf, gc)
         del U1
         dtc = dtf * 2.0
@@ -374,12 +375,12 @@ def evaluate(bd, cfg: Config, mlp, stats, states, log=print):
             Ub = torch.empty_like(U)
             dt = dtc.clone()
             faults = torch.zeros(1, dtype=torch.int32, device="cuda")
-            gc.advance(U, Ub, dt, cfg.fine_steps, flux="hlle", powell=True, recompute_dt=False, learned=learned,
+            gc.advance(U, Ub, dt, cfg.eval_fine_steps, flux="hlle", powell=True, recompute_dt=False, learned=learned,
                        faults=faults)
             torch.cuda.synchronize()
             l1 = [float((U[v] - ref[v]).abs().sum() / ref[v].abs().sum()) for v in range(8)]
             res[name] = {"l1_rel_mean": float(np.mean(l1)), "l1_rel": l1, "faults": int(faults.item())}
-        res["learned"]["flagged_share"] = int(fb.item()) / (float(cfg.fine_steps) * coarse.n_cells)  # per stage
+        res["learned"]["flagged_share"] = int(fb.item()) / (float(cfg.eval_fine_steps) * coarse.n_cells)  # per stage
         res["gain"] = res["plain"]["l1_rel_mean"] / max(res["learned"]["l1_rel_mean"], 1e-300)
         res["one_step"] = one_step_gain(bd, cfg, mlp, stats, st)
         res["one_step_exact_target"] = exact_target_one_step(bd, cfg, st)
@@ -470,23 +471,25 @@ def main():
     ap.add_argument("--n-fine", type=int, default=256)
     ap.add_argument("--train-states", type=int, default=32)
     ap.add_argument("--heldout-states", type=int, default=2)
-    ap.add_argument("--fine-steps", type=int, default=400)
+    ap.add_argument("--fine-steps", type=int, default=200, help="fine steps per training state")
+    ap.add_argument("--eval-fine-steps", type=int, default=400, help="evaluation horizon in fine steps")
     ap.add_argument("--epochs", type=int, default=24)
     ap.add_argument("--strength", type=float, default=0.25,
                     help="fraction of the network's correction applied (folded into the output statistics)")
-    ap.add_argument("--samples", type=int, default=8192)
+    ap.add_argument("--samples", type=int, default=16384)
     ap.add_argument("--top-frac", type=float, default=0.0)
     ap.add_argument("--pair", type=float, default=0.0,
                     help="train on face pairs with this weight on the error of the pair's difference")
     ap.add_argument("--out", default=None)
     ap.add_argument("--init", default=None, help="start from the parameters of a saved network")
     ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--seed", type=int, default=5, help="seed of the training states, sampling and initial weights")
     a = ap.parse_args()
     import torch
     from . import binding as bd
     cfg = Config(n_fine=a.n_fine, train_states=a.train_states, heldout_states=a.heldout_states,
-                 fine_steps=a.fine_steps, epochs=a.epochs, samples_per_dir=a.samples, top_frac=a.top_frac,
-                 pair=a.pair, strength=a.strength, lr=a.lr)
+                 fine_steps=a.fine_steps, eval_fine_steps=a.eval_fine_steps, epochs=a.epochs, samples_per_dir=a.samples, top_frac=a.top_frac,
+                 pair=a.pair, strength=a.strength, lr=a.lr, seed_train=a.seed)
     log = lambda *m: print(*m, file=sys.stderr, flush=True)
     t0 = time.time()
     X, T = generate(bd, cfg, solar_wind_states(cfg.train_states, cfg.seed_train), log)
