@@ -163,7 +163,7 @@ def bench_learned(steps, floor_rel=None):
     beside the plain FP64 path on the same grid. Both are timed from the developed state the one-step
     gain uses (the 256^3 run after 100 steps, restricted), with the share of flagged cell-stages of the
     timed window; then what the learned form gains over the plain path on that held-out solar-wind state
-    against the restricted 256^3 run (100 coarse steps from the start, and one step), and the equal-cost
+    against the restricted 256^3 run (200 coarse steps from the start, and one step), and the equal-cost
     comparison with a plain 192^3 run against a 384^3 reference."""
     import torch
     from paper_2501_06717_amd import binding, learn
@@ -197,7 +197,7 @@ def bench_learned(steps, floor_rel=None):
             "weights": "trained (paper_2501_06717_amd/trained/flux_mlp_h128.npz, strength %.2f)" % meta["strength"],
             "accuracy": {"state": state, "reference": "256^3 FP64 run restricted to 128^3, same time",
                          "l1_rel_plain": ev["plain"]["l1_rel_mean"], "l1_rel_learned": ev["learned"]["l1_rel_mean"],
-                         "gain_100_steps": ev["gain"], "flagged_share_100_steps": ev["learned"]["flagged_share"],
+                         "gain_200_steps": ev["gain"], "flagged_share_200_steps": ev["learned"]["flagged_share"],
                          "gain_one_step": ev["one_step"]["gain"],
                          "flagged_share_one_step": ev["one_step"]["flagged_share"],
                          "gain_one_step_exact_target": ev["one_step_exact_target"]["gain"]},

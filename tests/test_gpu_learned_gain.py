@@ -1,7 +1,7 @@
 """What the trained flux-correction network gains over the plain method (GPU): the network shipped with
 the package (trained by `python -m paper_2501_06717_amd.learn` on 32 solar-wind states, written to
 paper_2501_06717_amd/trained/) on held-out solar-wind states it never saw, against the fine 256^3 FP64
-run restricted to 128^3: 100 coarse steps of the learned path against 100 of the plain path, one coarse
+run restricted to 128^3: 200 coarse steps of the learned path against 200 of the plain path, one coarse
 step likewise, and one step with the exact a-priori target (the bound for a correction of this form)."""
 import os
 
@@ -35,6 +35,6 @@ def test_trained_network_gains_over_the_plain_path(bd, seed):
         assert e["learned"]["faults"] == 0 and e["plain"]["faults"] == 0
         # the exact target improves one step several-fold: the comparison itself is sound
         assert e["one_step_exact_target"]["gain"] > 3.0
-    # the network improves on the plain path locally and over 100 steps
+    # the network improves on the plain path locally and over 200 coarse steps
     assert min(e["one_step"]["gain"] for e in ev) > 1.0
     assert np.mean([e["gain"] for e in ev]) > 1.0
