@@ -276,18 +276,27 @@ class Grid:
         _check(lib().bmhd_grid_upload(self.h, ctypes.c_void_p(aligned), ctypes.c_size_t(n), _stream_ptr(stream)))
         return self
 
+    def _need(self, t, n, what):
+        """Size check before a pointer crosses the boundary (the library cannot see tensor sizes)."""
+        if t.numel() != n:
+            raise BmhdError(f"{what} holds {t.numel()} values; this grid needs {n}")
+
     def set_state(self, W, U=None, stream=None):
         import torch
+        self._need(W, 8 * self.nb * 512, "W")
         if U is None:
             U = torch.empty_like(W)
+        self._need(U, 8 * self.nb * 512, "U")
         _check(lib().bmhd_set_state(self.h, _dev_ptr(W, torch.float64), _dev_ptr(U, torch.float64),
                                     _stream_ptr(stream)))
         return U
 
     def fill_ghosts(self, U, view=None, stream=None):
         import torch
+        self._need(U, 8 * self.nb * 512, "U")
         if view is None:
             view = torch.empty((8, self.nb, 12, 12, 12), dtype=torch.float64, device=U.device)
+        self._need(view, 8 * self.nb * 1728, "view")
         _check(lib().bmhd_fill_ghosts(self.h, _dev_ptr(U, torch.float64), _dev_ptr(view, torch.float64),
                                       _stream_ptr(stream)))
         return view
@@ -296,8 +305,10 @@ class Grid:
         """The state U of this grid moved onto grid `to` (same simulations; blocks refined or coarsened):
         copy, prolongation or restriction per cell, on the device."""
         import torch
+        self._need(U, 8 * self.nb * 512, "U")
         if out is None:
             out = torch.empty((8, to.nb, 8, 8, 8), dtype=torch.float64, device=U.device)
+        to._need(out, 8 * to.nb * 512, "out")
         _check(lib().bmhd_remap(self.h, _dev_ptr(U, torch.float64), to.h, _dev_ptr(out, torch.float64),
                                 _stream_ptr(stream)))
         return out
@@ -306,8 +317,12 @@ class Grid:
         """Flux-correction targets of grid `coarse`'s faces from this grid (the same simulations refined
         everywhere): mean of the 4 fine face fluxes minus the coarse one, [coarse.nb * 1728, 8] float32."""
         import torch
+        if tuple(Ff.shape) != (self.nb * 1728, 8) or tuple(Fc.shape) != (coarse.nb * 1728, 8):
+            raise BmhdError("face data must be [n_blocks * 1728, 8] of the fine and the coarse grid")
         if out is None:
             out = torch.empty((coarse.nb * 1728, 8), dtype=torch.float32, device=Ff.device)
+        if tuple(out.shape) != (coarse.nb * 1728, 8):
+            raise BmhdError("targets must be [coarse n_blocks * 1728, 8]")
         _check(lib().bmhd_face_targets(self.h, _dev_ptr(Ff, torch.float32), coarse.h, _dev_ptr(Fc, torch.float32),
                                        _dev_ptr(out, torch.float32), _stream_ptr(stream)))
         return out
@@ -315,8 +330,10 @@ class Grid:
     def block_indicator(self, U, out=None, stream=None):
         """Refinement indicator per block (device tensor [n_blocks])."""
         import torch
+        self._need(U, 8 * self.nb * 512, "U")
         if out is None:
             out = torch.empty(self.nb, dtype=torch.float64, device=U.device)
+        self._need(out, self.nb, "indicator")
         _check(lib().bmhd_block_indicator(self.h, _dev_ptr(U, torch.float64), _dev_ptr(out, torch.float64),
                                           _stream_ptr(stream)))
         return out
@@ -324,6 +341,8 @@ class Grid:
     def adapt_blocks(self, ind, r_refine, r_coarsen):
         """The adapted block list (levels, ijk [n, 3], sims) for host indicators `ind`."""
         ind = np.ascontiguousarray(ind, np.float64)
+        if ind.size != self.nb:
+            raise BmhdError(f"one indicator per block: {ind.size} given, {self.nb} blocks")
         P = ctypes.POINTER
         n = ctypes.c_int32()
         _check(lib().bmhd_adapt(self.h, ind.ctypes.data_as(P(ctypes.c_double)), float(r_refine), float(r_coarsen),
@@ -345,8 +364,11 @@ class Grid:
 
     def reduce_dt(self, U, cfl, dt=None, stream=None):
         import torch
+        self._need(U, 8 * self.nb * 512, "U")
         if dt is None:
             dt = torch.empty(self.ns, dtype=torch.float64, device=U.device)
+        if dt.numel() < self.ns:
+            raise BmhdError("dt needs one value per simulation")
         _check(lib().bmhd_reduce_dt(self.h, _dev_ptr(U, torch.float64), float(cfl), _dev_ptr(dt, torch.float64),
                                     _stream_ptr(stream)))
         return dt
@@ -354,6 +376,8 @@ class Grid:
     def advance(self, U0, U1, dt, n_stages, opts: Optional[Opts] = None, faults=None, stream=None, **kw):
         import torch
         o = opts if opts is not None else make_opts(**kw)
+        self._need(U0, 8 * self.nb * 512, "U0")
+        self._need(U1, 8 * self.nb * 512, "U1")
         need = self.nb * 512 if o.local_dt else self.ns
         if dt.numel() < need:
             raise BmhdError(f"dt holds {dt.numel()} values; this grid and local_dt={o.local_dt} need {need}")
@@ -365,6 +389,9 @@ class Grid:
     def face_data(self, U, flux="hlle", stats=None, want_x=True, want_f=True, stream=None):
         """Per-face stencil features [nB*1728][32] and plain fluxes [nB*1728][8] (face-normal frame)."""
         import torch
+        self._need(U, 8 * self.nb * 512, "U")
+        if stats is not None and stats.numel() < 64:
+            raise BmhdError("stats needs the 32 input means and 32 deviations")
         nf = self.nb * 1728
         X = torch.empty((nf, 32), dtype=torch.float32, device=U.device) if want_x else None
         F = torch.empty((nf, 8), dtype=torch.float32, device=U.device) if want_f else None
@@ -382,6 +409,8 @@ class Grid:
         self._lx = torch.empty((nf, 32), dtype=torch.float32, device=dev)
         self._ly = torch.empty((nf, 8), dtype=torch.float32, device=dev)
         self._lf = torch.zeros(self.nb * 512, dtype=torch.uint8, device=dev)
+        if stats.numel() != 80:
+            raise BmhdError("stats must hold the 80 normalisation values")
         self._lstats = stats.to(dev, torch.float32).contiguous()
         L = Learned()
         L.hidden = mlp.H
@@ -420,7 +449,11 @@ class Grid:
     def autotune(self, U0, U1, dt, n_steps=3, stream=None, **kw):
         """Time the stage kernel's launch shapes on (scratch) buffers; returns (best Opts, {shape: ms})."""
         import torch
+        self._need(U0, 8 * self.nb * 512, "U0")
+        self._need(U1, 8 * self.nb * 512, "U1")
         base = make_opts(**kw)
+        if dt.numel() < self.ns:
+            raise BmhdError("dt needs one value per simulation")
         best = Opts()
         ms = (ctypes.c_float * 13)()
         _check(lib().bmhd_autotune(self.h, _dev_ptr(U0, torch.float64), _dev_ptr(U1, torch.float64),
@@ -486,18 +519,31 @@ class Xchg:
     def recv_len(self, p, r):
         return int(self.len[p - 1, :, r].sum())
 
+    def _need_view(self, r, view):
+        if tuple(view.shape) != (8, int(self.nloc[r]), 12, 12, 12):
+            raise BmhdError("the view must be [8][blocks of the process][12][12][12]")
+
     def interior(self, r, U, view, stream=None):
         import torch
+        if tuple(U.shape) != (8, self.grid.nb, 8, 8, 8):
+            raise BmhdError("the state must be [8][n_blocks][8][8][8]")
+        self._need_view(r, view)
         _check(lib().bmhd_xchg_interior(self.h, int(r), _dev_ptr(U, torch.float64),
                                         _dev_ptr(view, torch.float64) if view.numel() else None, _stream_ptr(stream)))
 
     def pack(self, p, s, view, send, stream=None):
         import torch
+        self._need_view(s, view)
+        if send.numel() < self.send_len(p, s):
+            raise BmhdError("send buffer too small")
         _check(lib().bmhd_xchg_pack(self.h, int(p), int(s), _dev_ptr(view, torch.float64) if view.numel() else None,
                                     _dev_ptr(send, torch.float64) if send.numel() else None, _stream_ptr(stream)))
 
     def unpack(self, p, r, recv, view, bad=None, stream=None):
         import torch
+        self._need_view(r, view)
+        if recv.numel() < self.recv_len(p, r):
+            raise BmhdError("receive buffer too small")
         _check(lib().bmhd_xchg_unpack(self.h, int(p), int(r), _dev_ptr(recv, torch.float64) if recv.numel() else None,
                                       _dev_ptr(view, torch.float64) if view.numel() else None,
                                       _dev_ptr(bad, torch.int32) if bad is not None else None,
@@ -538,6 +584,12 @@ class Xchg:
         """Stage e (0 or 1) of process r's blocks, ghost cells from its exchanged view."""
         import torch
         o = opts if opts is not None else make_opts(**kw)
+        state = (8, self.grid.nb, 8, 8, 8)
+        if any(tuple(t.shape) != state for t in (U0, Uin, Uout)):
+            raise BmhdError(f"states must be {state}")
+        self._need_view(r, view)
+        if dt.numel() < self.grid.ns:
+            raise BmhdError("dt needs one value per simulation")
         fp = _dev_ptr(faults, torch.int32) if faults is not None else ctypes.c_void_p(0)
         _check(lib().bmhd_xchg_stage(self.h, int(r), int(e), _dev_ptr(view, torch.float64) if view.numel() else None,
                                      _dev_ptr(U0, torch.float64), _dev_ptr(Uin, torch.float64),
@@ -547,6 +599,8 @@ class Xchg:
     def flux_correct(self, r, e, Uout, dt, opts: Optional[Opts] = None, faults=None, stream=None, **kw):
         import torch
         o = opts if opts is not None else make_opts(**kw)
+        if tuple(Uout.shape) != (8, self.grid.nb, 8, 8, 8) or dt.numel() < self.grid.ns:
+            raise BmhdError("state or dt of the wrong size")
         fp = _dev_ptr(faults, torch.int32) if faults is not None else ctypes.c_void_p(0)
         _check(lib().bmhd_xchg_flux_correct(self.h, int(r), int(e), _dev_ptr(Uout, torch.float64),
                                             _dev_ptr(dt, torch.float64), ctypes.byref(o), fp, _stream_ptr(stream)))
