@@ -322,6 +322,13 @@ typedef struct bmhd_xchg bmhd_xchg;
  * (the paper rebuilds them only when the grid changes, Sec. 4.4): which messages each process sends and
  * receives in each pass and their start offsets. The grid must outlive the handle. Errors: BMHD_EINVAL. */
 int32_t bmhd_xchg_create(const bmhd_grid *g, const int32_t *rank, int32_t n_ranks, bmhd_xchg **out);
+/* The same message maps for the sharded stage (bmhd_xchg_stage, Sec. 4.4's step on each process): the
+ * views then hold only the ghost cells the stage reads from them (faces whose neighbour is on another
+ * process or level) and what the packs of those messages read. Messages between blocks of one process
+ * are limited to restrictions, prolongations and the pass-1 ghost cells of blocks that send
+ * prolongations; bmhd_xchg_interior copies only the blocks that send; boundary cells are filled only
+ * for blocks that send prolongations. Message list and buffer sizes equal bmhd_xchg_create's. */
+int32_t bmhd_xchg_create_for_stage(const bmhd_grid *g, const int32_t *rank, int32_t n_ranks, bmhd_xchg **out);
 void bmhd_xchg_destroy(bmhd_xchg *x);
 
 /* h_nloc[n_ranks] (may be NULL): blocks per process. h_len[2][n_ranks][n_ranks] (may be NULL): doubles in
@@ -360,8 +367,9 @@ int32_t bmhd_xchg_unpack(const bmhd_xchg *x, int32_t pass, int32_t r, const doub
                          int32_t *d_bad, void *stream);
 
 /* One stage of the two-stage scheme (Algorithm 2's block sweep; stage in {0, 1} picks alpha/beta of the
- * options' table) for process r's blocks, every ghost cell read from r's padded view d_view after both
- * exchange passes (Sec. 4.4: each process then updates its own blocks). d_Uin, d_U0 and d_Uout are the
+ * options' table) for process r's blocks after both exchange passes (Sec. 4.4: each process then updates
+ * its own blocks): ghost cells of faces whose neighbour is on another process or level are read from r's
+ * padded view d_view, those of same-process neighbours and domain boundaries in place. d_Uin, d_U0 and d_Uout are the
  * grid's [8][n_blocks][8][8][8] states, of which only r's blocks are read (d_Uin's own cells, d_U0's
  * own cells in the second stage) and written (d_Uout); dt is given per simulation (d_dt, the minimum over
  * every process: bmhd_reduce_dt stands in for that reduction on one GPU); positivity faults of the second

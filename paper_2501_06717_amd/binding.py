@@ -26,7 +26,7 @@ EXPORTS = ["bmhd_version", "bmhd_last_error", "bmhd_grid_create", "bmhd_grid_des
            "bmhd_mlp_forward", "bmhd_mlp_backward", "bmhd_mlp_backward_noalloc", "bmhd_mlp_adam", "bmhd_mlp_to_bf16", "bmhd_face_data",
            "bmhd_block_indicator", "bmhd_adapt", "bmhd_xchg_create", "bmhd_xchg_destroy", "bmhd_xchg_sizes", "bmhd_xchg_messages", "bmhd_xchg_upload",
            "bmhd_xchg_interior", "bmhd_xchg_pack", "bmhd_xchg_unpack", "bmhd_xchg_stage", "bmhd_xchg_flux_correct",
-           "bmhd_face_targets"]
+           "bmhd_face_targets", "bmhd_xchg_create_for_stage"]
 
 
 class SimDesc(ctypes.Structure):
@@ -142,6 +142,8 @@ def lib():
     L.bmhd_xchg_pack.restype = i32
     L.bmhd_xchg_unpack.argtypes = [vp, i32, i32, vp, vp, vp, vp]
     L.bmhd_xchg_unpack.restype = i32
+    L.bmhd_xchg_create_for_stage.argtypes = L.bmhd_xchg_create.argtypes
+    L.bmhd_xchg_create_for_stage.restype = i32
     L.bmhd_face_targets.argtypes = [vp, vp, vp, vp, vp, vp]
     L.bmhd_face_targets.restype = i32
     L.bmhd_xchg_stage.argtypes = [vp, i32, i32, vp, vp, vp, vp, vp, P(Opts), vp, vp]
@@ -468,14 +470,18 @@ class Xchg:
     """Ghost exchange between (virtual) processes for a block-to-process assignment: message maps built by
     the library on the host, pack / unpack kernels on the device. Views and buffers are torch tensors."""
 
-    def __init__(self, grid: "Grid", rank, n_ranks):
+    def __init__(self, grid: "Grid", rank, n_ranks, for_stage=False):
+        """for_stage: maps for the sharded stage (views hold only what the stage and the packs read)."""
         L = lib()
         self.grid = grid
         self.rank = np.ascontiguousarray(rank, np.int32)
+        if self.rank.size != grid.nb:
+            raise BmhdError("one process index per block")
         self.nr = int(n_ranks)
+        self.for_stage = bool(for_stage)
         h = ctypes.c_void_p()
-        _check(L.bmhd_xchg_create(grid.h, self.rank.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), self.nr,
-                                  ctypes.byref(h)))
+        create = L.bmhd_xchg_create_for_stage if for_stage else L.bmhd_xchg_create
+        _check(create(grid.h, self.rank.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), self.nr, ctypes.byref(h)))
         self.h = h
         self.nloc = np.zeros(self.nr, np.int32)
         self.len = np.zeros((2, self.nr, self.nr), np.int64)
@@ -565,7 +571,8 @@ class Xchg:
         """Both passes of the exchange for every process: returns the views (bad: optional int32 device
         counter of skipped messages)."""
         import torch
-        # every cell of a view is written below (interior, 26 directions of ghost cells): no clearing
+        # complete views: every cell is written below (interior, 26 directions of ghost cells), no clearing;
+        # stage-mode views hold only what the stage reads from them
         views = [torch.empty((8, int(self.nloc[r]), 12, 12, 12), dtype=torch.float64, device=U.device)
                  for r in range(self.nr)]
         for r in range(self.nr):

@@ -130,6 +130,8 @@ void prim_to_cons_host(const double *w, double *u);
 struct ViewStage {
     const double *view;          // [8][n_local][12][12][12]
     const int32_t *view_local;   // [nb]: each block's index in its process's view
+    const int32_t *view_faces;   // [nb]: bit f set where face f's ghost cells come from the view (a neighbour
+                                 // on another process or level); the others are read in place
     int64_t view_vs;             // n_local * 1728
     const int32_t *split;        // the subset's blocks, those clear of any body first
     int32_t n_clear, n_total;

@@ -624,6 +624,7 @@ struct StageArgs {
     // is block b's index in the view, view_vs its variable stride; null: the usual gather
     const double *view;
     const int32_t *view_local;
+    const int32_t *view_faces;  // per block: bit f, face f's ghost cells from the view (others in place)
     int64_t view_vs;
     // the coarse cells k_flux_correct takes: a list of n_fc_list cells, or null for all of T.fc_cells
     const DevFcCell *fc_list;
@@ -813,21 +814,10 @@ __device__ __forceinline__ void gather_issue(const Tables &T, const StageArgs &A
     const DevSim &S = T.sims[B.sim];
     const size_t vs = size_t(T.nb) * 512;
     const int tid = lane_tid();
-    if constexpr (VIEW) {
-        // every ghost cell is in the view, whatever its origin (copy, restriction, prolongation, boundary)
-        const double *base = A.view + size_t(A.view_local[b]) * 1728;
-#pragma unroll
-        for (int m = 0; m < NPT; ++m) {
-            const int c = tid + m * NTH;
-            if (c >= SL::NC) break;
-            int i, j, k;
-            SL::decode(c, i, j, k);
-            const double *p = base + ((slab * KS + k + 2) * 12 + (j + 2)) * 12 + (i + 2);
-#pragma unroll
-            for (int v = 0; v < 8; ++v) u[m][v] = p[v * A.view_vs];
-        }
-        return;
-    }
+    // view gather: the ghost cells of faces whose neighbour is on another process or level come from the
+    // process's padded view (received messages, restrictions, prolongations); the rest is read in place
+    const int vfaces = VIEW ? A.view_faces[b] : 0;
+    const double *vbase = VIEW ? A.view + size_t(A.view_local[b]) * 1728 : nullptr;
 #pragma unroll
     for (int m = 0; m < NPT; ++m) {
         const int c = tid + m * NTH;
@@ -842,7 +832,10 @@ __device__ __forceinline__ void gather_issue(const Tables &T, const StageArgs &A
         const int rel = fd < 0 ? b : B.face[fd];
         const double *p;
         size_t stride;
-        if (rel >= 0 || rel == FACE_OUTFLOW) {
+        if (VIEW && fd >= 0 && ((vfaces >> fd) & 1)) {
+            p = vbase + ((z + 2) * 12 + (j + 2)) * 12 + (i + 2);
+            stride = size_t(A.view_vs);
+        } else if (rel >= 0 || rel == FACE_OUTFLOW) {
             int src = b, ii = i, jj = j, zz = z;
             if (rel >= 0) {
                 src = rel;
@@ -2151,6 +2144,7 @@ int32_t stage_from_view_impl(const HostGrid &h, const ViewStage &v, int e, const
     a.count_faults = (e == 1 && faults) ? 1 : 0;
     a.view = v.view;
     a.view_local = v.view_local;
+    a.view_faces = v.view_faces;
     a.view_vs = v.view_vs;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     if (o.precision == BMHD_FP64) return launch_view_stage_f<double>(h, a, v, o, s);

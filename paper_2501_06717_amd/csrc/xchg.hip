@@ -74,10 +74,16 @@ struct bmhd_xchg {
     std::vector<int32_t> split, n_clear;
     std::vector<bmhd::DevFcCell> fc;
     std::vector<int64_t> fc_first;                                   // [nr + 1]
+    // stage mode (bmhd_xchg_create_for_stage): the views hold only what the stage reads from them and
+    // what the packs of those messages read; the interior copies cover only the blocks that send
+    bool stage_mode = false;
+    std::vector<int32_t> view_faces;                                 // [nb]: bit f, face f's ghosts from the view
+    std::vector<int32_t> int_blocks;                                 // blocks whose interior is copied, per process
+    std::vector<int64_t> int_first;                                  // [nr + 1]
     std::vector<std::vector<int64_t>> table;                         // or_xchg_messages-style rows
     size_t work_bytes = 0;
     size_t off_msgs[2][3] = {}, off_grp[2][3] = {}, off_bnd[2] = {}, off_blocks = 0;
-    size_t off_split = 0, off_local = 0, off_fc = 0;
+    size_t off_split = 0, off_local = 0, off_fc = 0, off_vfaces = 0, off_int = 0;
     void *d_work = nullptr;
 };
 
@@ -404,9 +410,10 @@ __global__ void __launch_bounds__(256) k_xchg_bounds(Tables T, const int32_t *__
 }
 
 // A process's view with its blocks' interior cells from the global state.
-__global__ void __launch_bounds__(512) k_xchg_interior(const int32_t *__restrict__ blocks, const double *__restrict__ U,
+__global__ void __launch_bounds__(512) k_xchg_interior(const int32_t *__restrict__ blocks,
+                                                       const int32_t *__restrict__ local, const double *__restrict__ U,
                                                        size_t us, double *__restrict__ view, size_t vs) {
-    const int lb = blockIdx.x, b = blocks[lb], c = threadIdx.x;
+    const int b = blocks[blockIdx.x], lb = local[b], c = threadIdx.x;
     const int i = c & 7, j = (c >> 3) & 7, k = c >> 6;
     const size_t dst = size_t(lb) * 1728 + ((k + 2) * 12 + (j + 2)) * 12 + (i + 2);
 #pragma unroll
@@ -442,6 +449,7 @@ ViewStage view_stage(const bmhd_xchg *x, int r, const double *d_view) {
     ViewStage v{};
     v.view = d_view;
     v.view_local = reinterpret_cast<const int32_t *>(base + x->off_local);
+    v.view_faces = reinterpret_cast<const int32_t *>(base + x->off_vfaces);
     v.view_vs = int64_t(x->nloc[r]) * 1728;
     v.split = reinterpret_cast<const int32_t *>(base + x->off_split) + x->blocks_first[r];
     v.n_clear = x->n_clear[r];
@@ -453,15 +461,34 @@ ViewStage view_stage(const bmhd_xchg *x, int r, const double *d_view) {
 
 }  // namespace
 
+namespace bmhd {
+namespace {
+int32_t xchg_create(const bmhd_grid *g, const int32_t *rank, int32_t n_ranks, bool stage_mode, bmhd_xchg **out);
+}  // namespace
+}  // namespace bmhd
+
 extern "C" {
 
 int32_t bmhd_xchg_create(const bmhd_grid *g, const int32_t *rank, int32_t n_ranks, bmhd_xchg **out) {
+    return xchg_create(g, rank, n_ranks, false, out);
+}
+
+int32_t bmhd_xchg_create_for_stage(const bmhd_grid *g, const int32_t *rank, int32_t n_ranks, bmhd_xchg **out) {
+    return xchg_create(g, rank, n_ranks, true, out);
+}
+
+}  // extern "C"
+
+namespace bmhd {
+namespace {
+int32_t xchg_create(const bmhd_grid *g, const int32_t *rank, int32_t n_ranks, bool stage_mode, bmhd_xchg **out) {
     if (!g || !rank || !out || n_ranks < 1) return set_last_error(BMHD_EINVAL, "xchg_create: bad arguments");
     const HostGrid &h = g->h;
     for (int b = 0; b < h.nb; ++b)
         if (rank[b] < 0 || rank[b] >= n_ranks) return set_last_error(BMHD_EINVAL, "xchg_create: rank out of range");
     bmhd_xchg *x = new bmhd_xchg;
     x->grid = g;
+    x->stage_mode = stage_mode;
     x->nr = n_ranks;
     x->rank.assign(rank, rank + h.nb);
     x->local.assign(size_t(h.nb), 0);
@@ -492,6 +519,22 @@ int32_t bmhd_xchg_create(const bmhd_grid *g, const int32_t *rank, int32_t n_rank
     std::vector<std::vector<Msg>> per_block(size_t(h.nb));
     for (int b = 0; b < h.nb; ++b) per_block[b] = block_messages(h, b);
     const int nr = n_ranks;
+    // faces whose ghost cells the stage reads from the view: a neighbour on another process or on another
+    // level (same-process neighbours and domain boundaries are read in place)
+    x->view_faces.assign(size_t(h.nb), 0);
+    for (int b = 0; b < h.nb; ++b)
+        for (int f = 0; f < 6; ++f) {
+            const int32_t rel = h.blocks[b].face[f];
+            if (rel == FACE_LEVEL || (rel >= 0 && rank[rel] != rank[b])) x->view_faces[b] |= 1 << f;
+        }
+    // in stage mode a message between blocks of one process is needed only where the stage or a
+    // prolongation reads it: restrictions and prolongations, and every pass-1 ghost cell of a block that
+    // sends prolongations (its slopes reach into them)
+    std::vector<char> psend(size_t(h.nb), 0), sends(size_t(h.nb), 0);
+    for (int b = 0; b < h.nb; ++b)
+        for (const Msg &m : per_block[b])
+            if (m.type == MSG_PROLONG) psend[b] = 1;
+    auto kept_local = [&](const Msg &m) { return !stage_mode || m.type != MSG_COPY || psend[m.receiver]; };
     for (int p = 0; p < 2; ++p) {
         const int pass = p + 1;
         x->len[p].assign(size_t(nr) * nr, 0);
@@ -523,8 +566,13 @@ int32_t bmhd_xchg_create(const bmhd_grid *g, const int32_t *rank, int32_t n_rank
                         std::vector<int64_t> row = {sp, rp, pass, im, start, b, m.slot, m.receiver, x->local[m.receiver],
                                                     m.type, m.lo[0], m.lo[1], m.lo[2], m.hi[0], m.hi[1], m.hi[2]};
                         x->table.push_back(row);
-                        if (rp == sp) locv[sp].push_back(d);
-                        else incoming[rp][sp].push_back(d);
+                        if (rp != sp) {
+                            incoming[rp][sp].push_back(d);
+                            sends[b] = 1;
+                        } else if (kept_local(m)) {
+                            locv[sp].push_back(d);
+                            sends[b] = 1;
+                        }
                         start += XCHG_NC + 8 * int64_t(d.ncell);
                         ++im;
                     }
@@ -595,6 +643,7 @@ int32_t bmhd_xchg_create(const bmhd_grid *g, const int32_t *rank, int32_t n_rank
             for (int64_t q = x->blocks_first[rp]; q < x->blocks_first[rp + 1]; ++q) {
                 const int b = x->blocks_local[size_t(q)];
                 if (h.level[b] != p) continue;
+                if (stage_mode && !psend[b]) continue;
                 const bmhd_sim_desc &sd = h.sdesc[h.sim[b]];
                 bool edge = false;
                 for (int a = 0; a < 3; ++a) {
@@ -606,6 +655,15 @@ int32_t bmhd_xchg_create(const bmhd_grid *g, const int32_t *rank, int32_t n_rank
             }
             x->bnd_first[p][rp + 1] = int64_t(x->bnd_blocks[p].size());
         }
+    }
+    // blocks whose interior the views need: all of them for complete views, else the senders
+    x->int_first.assign(size_t(nr) + 1, 0);
+    for (int r = 0; r < nr; ++r) {
+        for (int64_t q = x->blocks_first[r]; q < x->blocks_first[r + 1]; ++q) {
+            const int b = x->blocks_local[size_t(q)];
+            if (!stage_mode || sends[b]) x->int_blocks.push_back(b);
+        }
+        x->int_first[r + 1] = int64_t(x->int_blocks.size());
     }
     // the message list in the counting order: sending process, pass, receiving process
     std::stable_sort(x->table.begin(), x->table.end(), [](const std::vector<int64_t> &a, const std::vector<int64_t> &b) {
@@ -634,10 +692,18 @@ int32_t bmhd_xchg_create(const bmhd_grid *g, const int32_t *rank, int32_t n_rank
     off = align256(off + sizeof(int32_t) * std::max<size_t>(1, x->local.size()));
     x->off_fc = off;
     off = align256(off + sizeof(DevFcCell) * std::max<size_t>(1, x->fc.size()));
+    x->off_vfaces = off;
+    off = align256(off + sizeof(int32_t) * std::max<size_t>(1, x->view_faces.size()));
+    x->off_int = off;
+    off = align256(off + sizeof(int32_t) * std::max<size_t>(1, x->int_blocks.size()));
     x->work_bytes = off;
     *out = x;
     return BMHD_OK;
 }
+}  // namespace
+}  // namespace bmhd
+
+extern "C" {
 
 void bmhd_xchg_destroy(bmhd_xchg *x) { delete x; }
 
@@ -685,6 +751,8 @@ int32_t bmhd_xchg_upload(bmhd_xchg *x, void *d_work, size_t work_bytes, void *st
     put(x->off_split, x->split.data(), sizeof(int32_t) * x->split.size());
     put(x->off_local, x->local.data(), sizeof(int32_t) * x->local.size());
     put(x->off_fc, x->fc.data(), sizeof(DevFcCell) * x->fc.size());
+    put(x->off_vfaces, x->view_faces.data(), sizeof(int32_t) * x->view_faces.size());
+    put(x->off_int, x->int_blocks.data(), sizeof(int32_t) * x->int_blocks.size());
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     if (int32_t rc = hip_ok(hipMemcpyAsync(d_work, blob.data(), x->work_bytes, hipMemcpyHostToDevice, s), "xchg upload"))
         return rc;
@@ -698,10 +766,13 @@ int32_t bmhd_xchg_interior(const bmhd_xchg *x, int32_t r, const double *d_U, dou
     const int n = x->nloc[r];
     if (n == 0) return BMHD_OK;  // a process without blocks has an empty view
     if (!aligned8(d_U) || !aligned8(d_view)) return set_last_error(BMHD_EINVAL, "xchg_interior: null or misaligned buffer");
-    const auto *blocks = reinterpret_cast<const int32_t *>(static_cast<const unsigned char *>(x->d_work) + x->off_blocks) +
-                         x->blocks_first[r];
-    k_xchg_interior<<<n, 512, 0, reinterpret_cast<hipStream_t>(stream)>>>(
-        blocks, d_U, size_t(x->grid->h.nb) * 512, d_view, size_t(n) * 1728);
+    const int64_t ni = x->int_first[r + 1] - x->int_first[r];
+    if (ni == 0) return BMHD_OK;
+    const unsigned char *base = static_cast<const unsigned char *>(x->d_work);
+    const auto *blocks = reinterpret_cast<const int32_t *>(base + x->off_int) + x->int_first[r];
+    const auto *local = reinterpret_cast<const int32_t *>(base + x->off_local);
+    k_xchg_interior<<<unsigned(ni), 512, 0, reinterpret_cast<hipStream_t>(stream)>>>(
+        blocks, local, d_U, size_t(x->grid->h.nb) * 512, d_view, size_t(n) * 1728);
     return hip_ok(hipGetLastError(), "xchg interior");
 }
 

@@ -140,21 +140,24 @@ def single_process_steps(g, U, n_steps, faults, **kw):
         g.advance(U, U1, dt, 2, recompute_dt=False, faults=faults, **kw)
 
 
+@pytest.mark.parametrize("for_stage", [False, True])
 @pytest.mark.parametrize("kind", ["halves", "random3", "each"])
 @pytest.mark.parametrize("case", list(SHARDED))
-def test_sharded_steps_equal_single_process(bd, case, kind):
-    """Two steps with every process advancing only its own blocks from its exchanged view (both passes,
-    then each process's stage, then the flux corrections) equal bmhd_advance bit for bit: the same stage
+def test_sharded_steps_equal_single_process(bd, case, kind, for_stage):
+    """Two steps with every process advancing only its own blocks (both exchange passes, then each
+    process's stage reading the ghost cells of faces with a neighbour on another process or level from its
+    view and the rest in place, then the flux corrections) equal bmhd_advance bit for bit: the same stage
     kernels read the same ghost values, whether they come from the neighbours' interiors and the
-    level-change halos or from messages."""
+    level-change halos or from messages. With complete views and with the stage-mode maps, whose views
+    hold only what the stage and the packs read."""
     make, kw = SHARDED[case]
     wl = make()
     if kind == "each" and wl.n_blocks > 64:
         pytest.skip("one process per block: small grids only")
     rank, n = ranks(wl, kind, seed=len(case))
-    print("sharded", case, kind, n, "processes", wl.n_blocks, "blocks", flush=True)
+    print("sharded", case, kind, for_stage, n, "processes", wl.n_blocks, "blocks", flush=True)
     g = bd.Grid.from_workload(wl).upload()
-    x = bd.Xchg(g, rank, n).upload()
+    x = bd.Xchg(g, rank, n, for_stage=for_stage).upload()
     W = torch.from_numpy(wk.random_positive_state(wl, seed=7) if case.startswith("two_level") else wl.W).cuda()
     R = g.set_state(W)
     fa = torch.zeros(1, dtype=torch.int32, device="cuda")
@@ -169,13 +172,13 @@ def test_sharded_steps_equal_single_process(bd, case, kind):
 
 
 def test_sharded_step_of_eight_128_cubed_processes(bd):
-    """One step of the 256^3 magnetosphere as 2 x 2 x 2 processes of 128^3 cells equals the single-process
-    step bit for bit."""
+    """One step of the 256^3 magnetosphere as 2 x 2 x 2 processes of 128^3 cells (stage-mode maps) equals
+    the single-process step bit for bit."""
     wl = wk.magnetosphere(256)
     ijk = np.asarray(wl.ijk).reshape(-1, 3)
     rank = ((ijk[:, 0] // 16) + 2 * (ijk[:, 1] // 16) + 4 * (ijk[:, 2] // 16)).astype(np.int32)
     g = bd.Grid.from_workload(wl).upload()
-    x = bd.Xchg(g, rank, 8).upload()
+    x = bd.Xchg(g, rank, 8, for_stage=True).upload()
     W = torch.from_numpy(wl.W).cuda()
     R = g.set_state(W)
     fa = torch.zeros(1, dtype=torch.int32, device="cuda")
