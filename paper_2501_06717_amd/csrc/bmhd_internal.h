@@ -37,7 +37,9 @@ struct DevBlock {
     int32_t fc_role;       // bit f: this block is the coarse side of face f's record
     int32_t fc_quad[6];    // fine side: quadrant (q1 + 2 q2) of the coarse face this block covers
     int32_t fc_skip;       // bit f: cells on face f are finished by the flux-correction kernel
-    int32_t pad[5];
+    int32_t hb_pos[3];     // per direction d: index of the block's high face plane among those with no
+                           // neighbour across them (learned correction's compact face layout), else -1
+    int32_t pad[2];
 };
 static_assert(sizeof(DevBlock) == 128, "DevBlock layout");
 
@@ -100,6 +102,7 @@ struct HostGrid {
     std::vector<int32_t> order;
     std::vector<int32_t> order_split;
     int32_t n_clear = 0;
+    int32_t n_hb = 0;           // high face planes with no neighbour across them (see DevBlock::hb_pos)
     std::vector<int32_t> halo_items;
     std::vector<DevFcCell> fc_cells;
     int32_t n_halo_slots = 0, n_fc_rec = 0;

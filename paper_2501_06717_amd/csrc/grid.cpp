@@ -346,6 +346,12 @@ int32_t build_grid(const bmhd_grid_desc *d, HostGrid &g, std::string &err) {
     for (int32_t b : g.order)
         if (g.blocks[b].flags & BF_NEAR_BODY) g.order_split.push_back(b);
 
+    // high face planes with no neighbour across them, numbered block by block (x, y, z)
+    g.n_hb = 0;
+    for (int b = 0; b < g.nb; ++b)
+        for (int d = 0; d < 3; ++d)
+            g.blocks[b].hb_pos[d] = g.blocks[b].face[2 * d + 1] < 0 ? g.n_hb++ : -1;
+
     // workspace layout
     size_t off = 0;
     g.off_blocks = off; off = align256(off + sizeof(DevBlock) * g.blocks.size());

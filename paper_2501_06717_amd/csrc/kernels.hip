@@ -614,6 +614,7 @@ struct StageArgs {
     const float *lrn_y;      // MLP outputs per face, normalised, face-normal frame
     const float *lrn_stats;  // in_mean[32], in_std[32], out_mean[8], out_std[8]
     uint8_t *lrn_flags;      // per cell: provisional state rejected
+    int lrn_compact;         // lrn_y in the compact face layout (each face once) rather than bmhd_face_data's
     double tau;
     double floor_rel;        // the neighbourhood range is at least floor_rel times its largest magnitude
     // work list of the launch: a part of the Morton schedule (block ids), or null for all of T.order
@@ -640,6 +641,27 @@ __device__ __forceinline__ int sched_block(const Tables &T, const StageArgs &A, 
 template <int D>
 __device__ __forceinline__ int face_index(int i, int j, int z) {
     return D == 0 ? (z * 8 + j) * 9 + i : (D == 1 ? (z * 9 + j) * 8 + i : (z * 8 + j) * 8 + i);
+}
+
+// Normalised learned correction of face (i, j, z) of direction D of block b (the face between cells
+// (i, j, z) - e_D and (i, j, z), its coordinate along D in 0..8). In bmhd_face_data's layout every block
+// holds its 576 faces per direction; in the compact layout of the network path every face is held once:
+// [n_blocks][3][512] low faces (coordinate 0..7 along D, index (z 8 + j) 8 + i), then 64 faces per high
+// face plane with no neighbour across it (DevBlock::hb_pos, index t2 8 + t1 over the two other axes in x,
+// y, z order), so that a block's high face is its neighbour's low face.
+template <int D>
+__device__ __forceinline__ const float *lrn_y_at(const Tables &T, const StageArgs &A, int b, int i, int j, int z) {
+    if (!A.lrn_compact) return A.lrn_y + ((size_t(b) * 3 + D) * 576 + face_index<D>(i, j, z)) * 8;
+    const int a = D == 0 ? i : (D == 1 ? j : z);
+    if (a < 8) return A.lrn_y + (size_t(b) * 1536 + D * 512 + (z * 8 + j) * 8 + i) * 8;
+    const DevBlock &B = T.blocks[b];
+    const int nbr = B.face[2 * D + 1];
+    if (nbr >= 0) {
+        const int i0 = D == 0 ? 0 : i, j0 = D == 1 ? 0 : j, z0 = D == 2 ? 0 : z;
+        return A.lrn_y + (size_t(nbr) * 1536 + D * 512 + (z0 * 8 + j0) * 8 + i0) * 8;
+    }
+    const int t1 = D == 0 ? j : i, t2 = D == 2 ? j : z;
+    return A.lrn_y + (size_t(T.nb) * 1536 + size_t(B.hb_pos[D]) * 64 + t2 * 8 + t1) * 8;
 }
 
 // learned flux increment of one face, de-normalised and rotated from the face-normal frame to x, y, z
@@ -750,9 +772,8 @@ __device__ __forceinline__ void face_flux(const Tables &T, const StageArgs &A, c
     if constexpr (LEARN) {
         // faces next to a body cell keep the plain (reflecting) flux
         if (!(m1 || m2)) {
-            const int fb = face_index<D>(i, j, slab * KS + k);
             R dF[8];
-            learned_increment<R, D>(A.lrn_y + (size_t(b) * 3 + D) * 4608 + size_t(fb) * 8, A.lrn_stats, dF);
+            learned_increment<R, D>(lrn_y_at<D>(T, A, b, i, j, slab * KS + k), A.lrn_stats, dF);
 #pragma unroll
             for (int v = 0; v < 8; ++v) fl[v] += dF[v];
         }
@@ -1723,8 +1744,8 @@ __global__ void __launch_bounds__(Slab<8>::NT) k_face_data(Tables T, StageArgs A
     }
 }
 
-// Z-scored stencil features of every face of a block for the learned correction's inference: the
-// layout of bmhd_face_data's X, FP32 primitives in LDS (40 KB per block, so several blocks per CU); each
+// Z-scored stencil features of the faces of a block for the learned correction's inference, in the
+// compact face layout (see lrn_y_at), FP32 primitives in LDS (40 KB per block, so several blocks per CU); each
 // thread takes one stencil cell of a face at a time (8 features), so a wavefront's stores cover
 // contiguous memory. TX = __bf16 stores the features rounded as the BF16 network consumes them (half
 // the bytes); TX = float keeps them for the FP32 network.
@@ -1744,20 +1765,31 @@ __global__ void __launch_bounds__(Slab<8>::NT) k_face_features(Tables T, StageAr
     gather_issue<8>(T, A, b, 0, u);
     gather_store<8, float>(T, b, 0, u, sW, sM);
     __syncthreads();
-    // task t = 4 f + q: stencil cell q of face f, so consecutive lanes write consecutive 32-byte pieces
+    // task t = 4 f + q: stencil cell q of face f of the compact layout (each face once: the block's low
+    // faces, then its high face planes with no neighbour across them), so consecutive lanes write
+    // consecutive 32-byte pieces
+    const DevBlock &B = T.blocks[b];
     const int tid = lane_tid();
 #pragma unroll
     for (int D = 0; D < 3; ++D) {
-        TX *base = X + (size_t(b) * 3 + D) * 576 * 32;
-#pragma unroll
-        for (int m = 0; m < 4; ++m) {
-            const int t = tid + m * SL::NT, f = t >> 2, q = t & 3;
-            int i, j, k;
-            if (D == 0) { i = f % 9; j = (f / 9) & 7; k = f / 72; }
-            else if (D == 1) { i = f & 7; j = (f >> 3) % 9; k = f / 72; }
-            else { i = f & 7; j = (f >> 3) & 7; k = f >> 6; }
+        const bool hb = B.hb_pos[D] >= 0;
+        const int ntask = hb ? 4 * (512 + 64) : 4 * 512;
+        for (int t = tid; t < ntask; t += SL::NT) {
+            const int f = t >> 2, q = t & 3;
+            int p[3];  // face coordinates (x, y, z), the one along D in 0..8
+            size_t row;
+            if (f < 512) {
+                p[0] = f & 7; p[1] = (f >> 3) & 7; p[2] = f >> 6;
+                row = size_t(b) * 1536 + D * 512 + f;
+            } else {
+                const int h = f - 512, t1 = h & 7, t2 = h >> 3;
+                p[D] = 8;
+                p[D == 0 ? 1 : 0] = t1;
+                p[D == 2 ? 1 : 2] = t2;
+                row = size_t(T.nb) * 1536 + size_t(B.hb_pos[D]) * 64 + h;
+            }
             const int o = q - 2;
-            const int c = D == 0 ? SL::idx(i + o, j, k) : (D == 1 ? SL::idx(i, j + o, k) : SL::idx(i, j, k + o));
+            const int c = D == 0 ? SL::idx(p[0] + o, p[1], p[2]) : (D == 1 ? SL::idx(p[0], p[1] + o, p[2]) : SL::idx(p[0], p[1], p[2] + o));
             float x[8];
             x[0] = sW[0][c];
             x[7] = sW[7][c];
@@ -1768,14 +1800,15 @@ __global__ void __launch_bounds__(Slab<8>::NT) k_face_features(Tables T, StageAr
             }
 #pragma unroll
             for (int v = 0; v < 8; ++v) x[v] = (x[v] - sMean[q * 8 + v]) * sInv[q * 8 + v];
+            TX *dst = X + row * 32 + q * 8;
             if constexpr (std::is_same<TX, __bf16>::value) {
                 typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8_t;
-                bf16x8_t h;
+                bf16x8_t hv;
 #pragma unroll
-                for (int v = 0; v < 8; ++v) h[v] = __bf16(x[v]);
-                *reinterpret_cast<bf16x8_t *>(base + size_t(t) * 8) = h;
+                for (int v = 0; v < 8; ++v) hv[v] = __bf16(x[v]);
+                *reinterpret_cast<bf16x8_t *>(dst) = hv;
             } else {
-                float4 *out = reinterpret_cast<float4 *>(base + size_t(t) * 8);
+                float4 *out = reinterpret_cast<float4 *>(dst);
                 out[0] = make_float4(x[0], x[1], x[2], x[3]);
                 out[1] = make_float4(x[4], x[5], x[6], x[7]);
             }
@@ -1822,9 +1855,8 @@ __global__ void __launch_bounds__(512) k_learn_fixup(Tables T, StageArgs A, int3
             if (nbody || !(self || other)) continue;
             int fi[3] = {ii[0], ii[1], ii[2]};
             fi[a] += side;  // face index along a: the cell's own index (minus face) or one more (plus face)
-            const int fb = a == 0 ? face_index<0>(fi[0], fi[1], fi[2])
-                                  : (a == 1 ? face_index<1>(fi[0], fi[1], fi[2]) : face_index<2>(fi[0], fi[1], fi[2]));
-            const float *y = A.lrn_y + (size_t(b) * 3 + a) * 4608 + size_t(fb) * 8;
+            const float *y = a == 0 ? lrn_y_at<0>(T, A, b, fi[0], fi[1], fi[2])
+                                    : (a == 1 ? lrn_y_at<1>(T, A, b, fi[0], fi[1], fi[2]) : lrn_y_at<2>(T, A, b, fi[0], fi[1], fi[2]));
             double dF[8];
             if (a == 0) learned_increment<double, 0>(y, A.lrn_stats, dF);
             else if (a == 1) learned_increment<double, 1>(y, A.lrn_stats, dF);
@@ -2203,17 +2235,21 @@ int32_t enqueue_stage(const HostGrid &h, const bmhd_opts &o, int e, double *d_U0
         a.want_lam = 0;
         const int count = a.count_faults;
         a.count_faults = 0;
+        // the network path evaluates every face once (compact layout); given corrections (mode 2) come in
+        // bmhd_face_data's layout
+        a.lrn_compact = L.mode != 2 ? 1 : 0;
+        const int nrows = h.nb * 1536 + h.n_hb * 64;
         if (L.mode == 0) {  // BF16 network: features stored in BF16 in the first half of x_buf
             uint16_t *xb = reinterpret_cast<uint16_t *>(L.x_buf);
             k_face_features<__bf16><<<h.nb, Slab<8>::NT, 0, s>>>(h.dev, a, L.stats, reinterpret_cast<__bf16 *>(xb));
             if (int32_t rc = launch_check("face features")) return rc;
             std::string err;
-            if (int32_t rc = mlp_infer_bf16_inputs(L.params, L.params_bf16, L.hidden, h.nb * 1728, xb, L.y_buf, s, err))
+            if (int32_t rc = mlp_infer_bf16_inputs(L.params, L.params_bf16, L.hidden, nrows, xb, L.y_buf, s, err))
                 return fail(rc, err);
         } else if (L.mode == 1) {  // FP32 network; mode 2: y_buf is given
             k_face_features<float><<<h.nb, Slab<8>::NT, 0, s>>>(h.dev, a, L.stats, L.x_buf);
             if (int32_t rc = launch_check("face features")) return rc;
-            if (int32_t rc = bmhd_mlp_forward(L.params, L.params_bf16, L.hidden, h.nb * 1728, L.x_buf, L.y_buf,
+            if (int32_t rc = bmhd_mlp_forward(L.params, L.params_bf16, L.hidden, nrows, L.x_buf, L.y_buf,
                                               nullptr, L.mode, s))
                 return fail(rc, bmhd_mlp_last_error());
         }

@@ -26,6 +26,53 @@ def face_index(d, i, j, z):
     return ((z * 8 + j) * 9 + i) if d == 0 else (((z * 9 + j) * 8 + i) if d == 1 else ((z * 8 + j) * 8 + i))
 
 
+def compact_rows(wl):
+    """Row of every face of bmhd_face_data's layout in the network path's compact layout (each face once:
+    per block and direction the 512 faces at positions 0..7 along it, (z 8 + j) 8 + i; then 64 faces per
+    high face plane with no neighbour across it, numbered block by block and direction by direction,
+    t2 8 + t1 over the other two axes), for single-level grids of one simulation."""
+    sim = wl.sims[0]
+    ijk = np.asarray(wl.ijk).reshape(-1, 3)
+    index = {tuple(int(v) for v in q): b for b, q in enumerate(ijk)}
+    nb = len(ijk)
+    nbr = np.full((nb, 3), -1, np.int64)
+    for b in range(nb):
+        for d in range(3):
+            q = [int(v) for v in ijk[b]]
+            q[d] += 1
+            if q[d] >= sim.nroot[d]:
+                if sim.bc[2 * d + 1] != 0:
+                    continue
+                q[d] = 0
+            nbr[b, d] = index[tuple(q)]
+    hb = np.full((nb, 3), -1, np.int64)
+    n = 0
+    for b in range(nb):
+        for d in range(3):
+            if nbr[b, d] < 0:
+                hb[b, d] = n
+                n += 1
+    rows = np.empty((nb, 3, 576), np.int64)
+    for b in range(nb):
+        for d in range(3):
+            for f in range(576):
+                if d == 0:
+                    p = [f % 9, (f // 9) % 8, f // 72]
+                elif d == 1:
+                    p = [f % 8, (f // 8) % 9, f // 72]
+                else:
+                    p = [f % 8, (f // 8) % 8, f // 64]
+                if p[d] < 8:
+                    rows[b, d, f] = b * 1536 + d * 512 + (p[2] * 8 + p[1]) * 8 + p[0]
+                elif nbr[b, d] >= 0:
+                    p[d] = 0
+                    rows[b, d, f] = nbr[b, d] * 1536 + d * 512 + (p[2] * 8 + p[1]) * 8 + p[0]
+                else:
+                    t = [p[a] for a in range(3) if a != d]
+                    rows[b, d, f] = nb * 1536 + hb[b, d] * 64 + t[1] * 8 + t[0]
+    return torch.from_numpy(rows.reshape(-1))
+
+
 def test_face_fluxes_reproduce_the_stage(bd):
     """One forward-Euler stage equals U + dt * (-sum_d (F_d+ - F_d-) / dx) built from bmhd_face_data's
     fluxes (rotated back from the face-normal frame)."""
@@ -140,9 +187,11 @@ def test_learned_stage_adds_the_network_increment(bd):
     Ua, U1a = U0.clone(), torch.zeros_like(U0)
     g.advance(Ua, U1a, dt, 1, learned=L, **kw)
     torch.cuda.synchronize()
-    # the BF16 network's stage keeps its features in BF16, in the first half of the scratch buffer
-    nf = wl.n_blocks * 1728
-    X_in = g._lx.view(-1)[: nf * 16].view(torch.bfloat16).view(nf, 32).float()
+    # the BF16 network's stage keeps its features in BF16, in the first half of the scratch buffer, each
+    # face once (the compact layout); spread back to bmhd_face_data's layout
+    rows = compact_rows(wl).cuda()
+    nc = int(rows.max()) + 1
+    X_in = g._lx.view(-1)[: nc * 16].view(torch.bfloat16).view(nc, 32).float()[rows]
     Xref, _ = g.face_data(U0, flux="hlle", stats=stats.cuda(), want_f=False)
     assert int(fb.item()) == 0
     # equal up to the rounding to BF16 (one BF16 unit where the FP32 values differ in the last places)
@@ -195,7 +244,7 @@ def test_given_corrections_equal_the_network_path(bd):
     Ua, U1a = U0.clone(), torch.zeros_like(U0)
     g.advance(Ua, U1a, dt, 1, learned=g.learned(mlp, stats), **kw)
     torch.cuda.synchronize()
-    y = g._ly.clone()
+    y = g._ly[compact_rows(wl).cuda()].contiguous()   # the network's outputs in bmhd_face_data's layout
     Ub, U1b = U0.clone(), torch.zeros_like(U0)
     g.advance(Ub, U1b, dt, 1, learned=g.given_corrections(y, stats), **kw)
     torch.cuda.synchronize()
