@@ -109,9 +109,13 @@ typedef struct {
     const float *params;         /* device [n_params] float32 */
     const uint16_t *params_bf16; /* device [n_params] bfloat16 copy */
     const float *stats;          /* device: in_mean[32], in_std[32], out_mean[8], out_std[8] */
-    float *x_buf;                /* device scratch [n_blocks * 1728][32] float32; mode 0 stores the
-                                    features as bfloat16 in its first half and needs 16-byte alignment */
-    float *y_buf;                /* device scratch [n_blocks * 1728][8] */
+    float *x_buf;                /* device scratch [n_blocks * 1728][32] float32; modes 0 and 1 store
+                                    the features of every face once (the block's faces at positions 0..7
+                                    along their normal, then the high face planes with no neighbour
+                                    across them), mode 0 as bfloat16 in its first half (16-byte aligned) */
+    float *y_buf;                /* device [n_blocks * 1728][8]: mode 2: the given corrections in
+                                    bmhd_face_data's layout; modes 0 and 1: scratch (the network's
+                                    outputs in the layout of x_buf) */
     uint8_t *flags;              /* device scratch [n_blocks * 512] */
     int32_t *fallback_cells;     /* device counter of flagged cells, incremented per stage (may be NULL) */
     double tau;                  /* tolerance of the neighbourhood bound (0.1) */
