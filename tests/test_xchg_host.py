@@ -60,3 +60,26 @@ def test_bad_assignments_are_refused():
         bd.Xchg(g, np.full(wl.n_blocks, 2, np.int32), 2)
     with pytest.raises(bd.BmhdError):
         bd.Xchg(g, np.zeros(wl.n_blocks, np.int32), 0)
+
+
+@pytest.mark.parametrize("kind", ["halves", "random3", "each"])
+@pytest.mark.parametrize("grid", ["two_level_mixed_bc", "fast_wave_octant", "magnetosphere_cut"])
+def test_stage_maps_send_the_same_messages(grid, kind):
+    """The maps for the sharded stage send exactly the messages of the complete-view maps (the same rows,
+    buffer sizes and block counts); only what each process fills locally differs."""
+    wl = GRIDS[grid]()
+    rank, n = ranks(wl, kind, seed=len(grid))
+    g = bd.Grid.from_workload(wl)
+    full = bd.Xchg(g, rank, n)
+    stage = bd.Xchg(g, rank, n, for_stage=True)
+    assert np.array_equal(full.messages(), stage.messages())
+    assert np.array_equal(full.len, stage.len) and np.array_equal(full.nloc, stage.nloc)
+
+
+def test_rank_list_must_cover_every_block():
+    wl = wk.uniform_state((2, 1, 1))
+    g = bd.Grid.from_workload(wl)
+    with pytest.raises(bd.BmhdError):
+        bd.Xchg(g, np.zeros(1, np.int32), 1)
+    with pytest.raises(bd.BmhdError):
+        bd.Xchg(g, np.array([0, 2], np.int32), 2)
