@@ -223,7 +223,7 @@ __device__ __forceinline__ double minmod_pair(double a, double b) {
 
 // The value of cell (i, j, k) of message m's receive box (receiver's padded coordinates) from the sending
 // block's padded cells, by the ghost rules of bmhd_fill_ghosts.
-__device__ __noinline__ void message_value(const Tables &T, const DevMsg &m, const XView &S, int i, int j, int k,
+__device__ __forceinline__ void message_value(const Tables &T, const DevMsg &m, const XView &S, int i, int j, int k,
                                            double out[8]) {
 #pragma clang fp contract(off)
     const DevBlock &B = T.blocks[m.sender];
