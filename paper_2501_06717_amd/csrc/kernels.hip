@@ -257,16 +257,22 @@ __device__ __forceinline__ bool apply_bounds(const DevSim &S, int l, long long G
     return true;
 }
 
-__device__ __forceinline__ bool leaf_cell(const Cursor &c, const DevSim &S, int l, const long long G[3], double out[8]) {
+// The helpers below produce NV consecutive variables v0 .. v0 + NV - 1 of a cell (all eight by default; the
+// level-change halo fill asks for four, so that two threads share a cell's loads).
+template <int NV = 8>
+__device__ __forceinline__ bool leaf_cell(const Cursor &c, const DevSim &S, int l, const long long G[3], double out[NV],
+                                          int v0 = 0) {
     const int32_t b = lut_at(*c.T, S, l, G[0] >> 3, G[1] >> 3, G[2] >> 3);
     if (b < 0) return false;
     const size_t off = size_t(b) * 512 + size_t(((G[2] & 7) * 8 + (G[1] & 7)) * 8 + (G[0] & 7));
 #pragma unroll
-    for (int v = 0; v < 8; ++v) out[v] = c.U[v * c.vs + off];
+    for (int v = 0; v < NV; ++v) out[v] = c.U[(v0 + v) * c.vs + off];
     return true;
 }
 
-__device__ __forceinline__ bool restricted_cell(const Cursor &c, const DevSim &S, const long long G[3], double out[8]) {
+template <int NV = 8>
+__device__ __forceinline__ bool restricted_cell(const Cursor &c, const DevSim &S, const long long G[3], double out[NV],
+                                                int v0 = 0) {
 #pragma clang fp contract(off)
     size_t off[8];
     for (int q = 0; q < 8; ++q) {
@@ -276,8 +282,8 @@ __device__ __forceinline__ bool restricted_cell(const Cursor &c, const DevSim &S
         off[q] = size_t(b) * 512 + size_t(((F[2] & 7) * 8 + (F[1] & 7)) * 8 + (F[0] & 7));
     }
 #pragma unroll
-    for (int v = 0; v < 8; ++v) {
-        const double *u = c.U + v * c.vs;
+    for (int v = 0; v < NV; ++v) {
+        const double *u = c.U + (v0 + v) * c.vs;
         const double s = ((u[off[0]] + u[off[1]]) + (u[off[2]] + u[off[3]])) +
                          ((u[off[4]] + u[off[5]]) + (u[off[6]] + u[off[7]]));
         out[v] = s * 0.125;
@@ -286,14 +292,15 @@ __device__ __forceinline__ bool restricted_cell(const Cursor &c, const DevSim &S
 }
 
 // level-0 value with boundary rule, from a level-0 leaf or restricted from level 1
-__device__ __forceinline__ void coarse_cell(const Cursor &c, const DevSim &S, long long G[3], double out[8]) {
+template <int NV = 8>
+__device__ __forceinline__ void coarse_cell(const Cursor &c, const DevSim &S, long long G[3], double out[NV], int v0 = 0) {
     if (!apply_bounds(S, 0, G)) {
 #pragma unroll
-        for (int v = 0; v < 8; ++v) out[v] = S.inflow_U[v];
+        for (int v = 0; v < NV; ++v) out[v] = S.inflow_U[v0 + v];
         return;
     }
-    if (leaf_cell(c, S, 0, G, out)) return;
-    restricted_cell(c, S, G, out);
+    if (leaf_cell<NV>(c, S, 0, G, out, v0)) return;
+    restricted_cell<NV>(c, S, G, out, v0);
 }
 
 __device__ __forceinline__ double minmod2(double a, double b) {
@@ -303,39 +310,41 @@ __device__ __forceinline__ double minmod2(double a, double b) {
 // any cell of a level-l grid, at a global index that may lie outside the domain. The ghost-rule helpers are
 // inlined into their kernels: out of line, their arrays went through scratch memory and the call held 210
 // registers (the level-change halo fill ran 19 % slower in FP64 two-level steps, 23 % with FP32 fluxes)
-__device__ __forceinline__ void ghost_cell(const Cursor &c, const DevSim &S, int l, const long long G0[3], double out[8]) {
+template <int NV = 8>
+__device__ __forceinline__ void ghost_cell(const Cursor &c, const DevSim &S, int l, const long long G0[3], double out[NV],
+                                           int v0 = 0) {
 #pragma clang fp contract(off)
     long long G[3] = {G0[0], G0[1], G0[2]};
     if (!apply_bounds(S, l, G)) {
 #pragma unroll
-        for (int v = 0; v < 8; ++v) out[v] = S.inflow_U[v];
+        for (int v = 0; v < NV; ++v) out[v] = S.inflow_U[v0 + v];
         return;
     }
-    if (leaf_cell(c, S, l, G, out)) return;
+    if (leaf_cell<NV>(c, S, l, G, out, v0)) return;
     if (l == 0) {
-        restricted_cell(c, S, G, out);
+        restricted_cell<NV>(c, S, G, out, v0);
         return;
     }
     // prolongation from coarse cell C = G / 2
     long long C[3] = {G[0] >> 1, G[1] >> 1, G[2] >> 1};
-    double uc[8];
-    leaf_cell(c, S, 0, C, uc);
-    double acc[8];
+    double uc[NV];
+    leaf_cell<NV>(c, S, 0, C, uc, v0);
+    double acc[NV];
 #pragma unroll
-    for (int v = 0; v < 8; ++v) acc[v] = uc[v];
+    for (int v = 0; v < NV; ++v) acc[v] = uc[v];
     for (int d = 0; d < 3; ++d) {
         long long Cm[3] = {C[0], C[1], C[2]}, Cp[3] = {C[0], C[1], C[2]};
         Cm[d] -= 1;
         Cp[d] += 1;
-        double um[8], up[8];
-        coarse_cell(c, S, Cm, um);
-        coarse_cell(c, S, Cp, up);
+        double um[NV], up[NV];
+        coarse_cell<NV>(c, S, Cm, um, v0);
+        coarse_cell<NV>(c, S, Cp, up, v0);
         const double s = (G[d] & 1) ? 0.25 : -0.25;
 #pragma unroll
-        for (int v = 0; v < 8; ++v) acc[v] = acc[v] + s * minmod2(uc[v] - um[v], up[v] - uc[v]);
+        for (int v = 0; v < NV; ++v) acc[v] = acc[v] + s * minmod2(uc[v] - um[v], up[v] - uc[v]);
     }
 #pragma unroll
-    for (int v = 0; v < 8; ++v) out[v] = acc[v];
+    for (int v = 0; v < NV; ++v) out[v] = acc[v];
 }
 
 // ------------------------------------------------------------------------------------------------
@@ -382,7 +391,6 @@ __global__ void __launch_bounds__(256) k_fill_view(Tables T, const double *__res
     }
 }
 
-// ghost layers of one level-change face: item = (block << 3) | face; 128 threads = 2 layers x 64
 // State remap after a refinement change: every cell of the new grid N takes the value that the ghost rules
 // of the old grid F give at its level and global index -- the leaf's own value (block unchanged), the
 // prolongation of a fine ghost cell (block refined from a level-0 parent) or the restriction of the 8
@@ -448,12 +456,16 @@ __global__ void __launch_bounds__(512) k_block_indicator(Tables T, const double 
     }
 }
 
-__global__ void __launch_bounds__(128) k_halo_fill(Tables T, const double *__restrict__ U) {
+// Ghost layers of one level-change face: item = (block << 3) | face; 256 threads = 2 halves of the
+// variables x 2 layers x 64 cells. Two threads per cell repeat its index work and each loads four variables:
+// on the two-level magnetosphere 1-2 % faster per step than one thread per cell (too few wavefronts to hide
+// the chains of dependent loads) and than four or eight threads per cell (the repeated index work dominates).
+__global__ void __launch_bounds__(256) k_halo_fill(Tables T, const double *__restrict__ U) {
     const int32_t item = T.halo_items[blockIdx.x];
     const int b = item >> 3, f = item & 7;
     const DevBlock &B = T.blocks[b];
     const DevSim &S = T.sims[B.sim];
-    const int t = threadIdx.x, layer = t >> 6, t1 = t & 7, t2 = (t >> 3) & 7;
+    const int t = threadIdx.x, v = (t >> 7) * 4, cell = t & 127, layer = cell >> 6, t1 = cell & 7, t2 = (cell >> 3) & 7;
     const int a = f >> 1, side = f & 1;
     const int a1 = a == 0 ? 1 : 0, a2 = a == 2 ? 1 : 2;
     int idx[3];
@@ -463,11 +475,11 @@ __global__ void __launch_bounds__(128) k_halo_fill(Tables T, const double *__res
     const long long G[3] = {(long long)B.ijk[0] * 8 + idx[0], (long long)B.ijk[1] * 8 + idx[1],
                             (long long)B.ijk[2] * 8 + idx[2]};
     Cursor cur{&T, U, size_t(T.nb) * 512};
-    double out[8];
-    ghost_cell(cur, S, B.level, G, out);
-    double *h = T.halo + size_t(B.halo_slot) * HALO_SLOT + size_t(f) * HALO_FACE + layer * 64 + t2 * 8 + t1;
+    double out[4];
+    ghost_cell<4>(cur, S, B.level, G, out, v);
 #pragma unroll
-    for (int v = 0; v < 8; ++v) h[v * 128] = out[v];
+    for (int q = 0; q < 4; ++q)
+        T.halo[size_t(B.halo_slot) * HALO_SLOT + size_t(f) * HALO_FACE + (v + q) * 128 + layer * 64 + t2 * 8 + t1] = out[q];
 }
 
 // ------------------------------------------------------------------------------------------------
@@ -2212,7 +2224,7 @@ int32_t enqueue_stage(const HostGrid &h, const bmhd_opts &o, int e, double *d_U0
                       int32_t *d_faults, bool want_lam, void *ev0, void *ev1, hipStream_t s) {
     const double *in = e ? d_U1 : d_U0;
     double *out = e ? d_U0 : d_U1;
-    if (!h.halo_items.empty()) k_halo_fill<<<unsigned(h.halo_items.size()), 128, 0, s>>>(h.dev, in);
+    if (!h.halo_items.empty()) k_halo_fill<<<unsigned(h.halo_items.size()), 256, 0, s>>>(h.dev, in);
     StageArgs a;
     std::memset(&a, 0, sizeof a);
     a.Uin = in;
