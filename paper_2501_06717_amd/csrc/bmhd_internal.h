@@ -117,6 +117,9 @@ struct HostGrid {
     // cached HIP graph of one step (opaque hipGraph_t / hipGraphExec_t / hipStream_t) and its key
     void *graph = nullptr, *graph_exec = nullptr, *capture_stream = nullptr;
     std::vector<unsigned char> graph_key;
+    // side stream (default priority) and fork / join events (hipStream_t / hipEvent_t) on which the
+    // blocks near a body run beside the block form's launch; created on first use
+    mutable void *side_stream = nullptr, *fork_event = nullptr, *join_event = nullptr;
 };
 
 int32_t build_grid(const bmhd_grid_desc *d, HostGrid &g, std::string &err);

@@ -1971,6 +1971,9 @@ bmhd_grid::~bmhd_grid() {
     if (h.graph_exec) (void)hipGraphExecDestroy(reinterpret_cast<hipGraphExec_t>(h.graph_exec));
     if (h.graph) (void)hipGraphDestroy(reinterpret_cast<hipGraph_t>(h.graph));
     if (h.capture_stream) (void)hipStreamDestroy(reinterpret_cast<hipStream_t>(h.capture_stream));
+    if (h.fork_event) (void)hipEventDestroy(reinterpret_cast<hipEvent_t>(h.fork_event));
+    if (h.join_event) (void)hipEventDestroy(reinterpret_cast<hipEvent_t>(h.join_event));
+    if (h.side_stream) (void)hipStreamDestroy(reinterpret_cast<hipStream_t>(h.side_stream));
 }
 
 namespace {
@@ -1993,6 +1996,39 @@ int32_t record_event(void *ev, hipStream_t s) {
 }
 
 bool ptr_ok(const void *p) { return p && (reinterpret_cast<uintptr_t>(p) & 7u) == 0; }
+
+// The side stream for work that may run beside the next launch on s: the grid's side stream, made to wait
+// for everything enqueued on s so far, or s itself while s is being captured into a graph (the launches
+// then stay in order on s). join_side makes s wait for what was enqueued on the side stream.
+int32_t fork_side(const HostGrid &h, hipStream_t s, hipStream_t &side) {
+    side = s;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (int32_t rc = hip_check(hipStreamIsCapturing(s, &cs), "capture status")) return rc;
+    if (cs != hipStreamCaptureStatusNone) return BMHD_OK;
+    if (!h.side_stream) {
+        hipStream_t ss;
+        hipEvent_t e0, e1;
+        if (int32_t rc = hip_check(hipStreamCreateWithFlags(&ss, hipStreamNonBlocking), "side stream")) return rc;
+        h.side_stream = ss;
+        if (int32_t rc = hip_check(hipEventCreateWithFlags(&e0, hipEventDisableTiming), "fork event")) return rc;
+        h.fork_event = e0;
+        if (int32_t rc = hip_check(hipEventCreateWithFlags(&e1, hipEventDisableTiming), "join event")) return rc;
+        h.join_event = e1;
+    }
+    hipStream_t ss = reinterpret_cast<hipStream_t>(h.side_stream);
+    hipEvent_t e0 = reinterpret_cast<hipEvent_t>(h.fork_event);
+    if (int32_t rc = hip_check(hipEventRecord(e0, s), "fork")) return rc;
+    if (int32_t rc = hip_check(hipStreamWaitEvent(ss, e0, 0), "fork wait")) return rc;
+    side = ss;
+    return BMHD_OK;
+}
+
+int32_t join_side(const HostGrid &h, hipStream_t s, hipStream_t side) {
+    if (side == s) return BMHD_OK;
+    hipEvent_t e1 = reinterpret_cast<hipEvent_t>(h.join_event);
+    if (int32_t rc = hip_check(hipEventRecord(e1, side), "join")) return rc;
+    return hip_check(hipStreamWaitEvent(s, e1, 0), "join wait");
+}
 
 // Launch shape of the stage kernel: work split (face per thread or wave per cell layer), tile depth (4
 // or 8 cells) and persistent grid size (0: one workgroup per slab).
@@ -2020,12 +2056,21 @@ int32_t launch_stage_shape(const HostGrid &h, const StageArgs &a, int scheme, in
         ac.n_sched = nc;
         an.sched = h.dev.order_split + nc;
         an.n_sched = nn;
-        // the events bracket the block form alone, the dominant kernel
-        if (nn) k_stage_wp<4, R, FLUX, POWELL, false><<<nn * 2, Slab<4>::NT, 0, s>>>(h.dev, an);
+        // the blocks near a body (a few workgroups) run on a side stream beside the block form's launch,
+        // which would otherwise wait for them with most of the chip idle; the two write disjoint blocks of
+        // the output. The events bracket the block form alone, the dominant kernel.
+        hipStream_t side = s;
+        if (nn) {
+            if (nc)
+                if (int32_t rc = fork_side(h, s, side)) return rc;
+            k_stage_wp<4, R, FLUX, POWELL, false><<<nn * 2, Slab<4>::NT, 0, side>>>(h.dev, an);
+            if (int32_t rc = launch_check("stage kernel (blocks near a body)")) return rc;
+        }
         if (int32_t rc = record_event(ev0, s)) return rc;
         if (nc) k_stage_blk<R, FLUX, POWELL><<<nc, BLK_NT, 0, s>>>(h.dev, ac);
         if (int32_t rc = record_event(ev1, s)) return rc;
-        return launch_check("stage kernel");
+        if (int32_t rc = launch_check("stage kernel")) return rc;
+        return join_side(h, s, side);
     }
     if (int32_t rc = record_event(ev0, s)) return rc;
     if (scheme == BMHD_SCHEME_PLANE) {
