@@ -12,7 +12,11 @@
  *   - Every device pointer is memory the caller owns (PyTorch tensors in the Python binding). The
  *     library never allocates device memory. Pointers must be 8-byte aligned; d_work 256-byte aligned.
  *   - `stream` is a hipStream_t passed as void*; NULL means the default stream. Every call that takes
- *     a stream only enqueues work on it and returns; nothing is synchronised.
+ *     a stream only enqueues work on it and returns; nothing is synchronised. bmhd_advance may run part
+ *     of a stage (the blocks near a body) on a side stream that the grid owns, made to wait for
+ *     `stream` by an event and joined back into `stream` by another before the call returns, so all of
+ *     its work is ordered on `stream` as if it ran there (while `stream` is being captured into a
+ *     graph, everything stays on `stream`).
  *   - State arrays are variable-major, U[8][n_blocks][8][8][8] (k, j, i with i fastest), float64.
  *     Conserved order: rho, rho*ux, rho*uy, rho*uz, Bx, By, Bz, e (total energy, Eq. 5, mu0 = 1).
  *     Primitive order: rho, ux, uy, uz, Bx, By, Bz, p. gamma = 5/3.
