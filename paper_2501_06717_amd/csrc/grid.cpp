@@ -337,11 +337,16 @@ int32_t build_grid(const bmhd_grid_desc *d, HostGrid &g, std::string &err) {
         return key[x] < key[y];
     });
 
-    // the same schedule with the blocks clear of any body first (the block form of the stage kernel takes
-    // those; blocks near a body go to the plane form)
+    // the same schedule split for the stage kernel: the blocks clear of any body and of level changes,
+    // then the clear blocks with a face on another level (they read the halo buffer, so they wait for the
+    // level-change halo fill while the others run), both on the block form; then the blocks near a body
+    // (plane form)
     g.order_split.clear();
     for (int32_t b : g.order)
-        if (!(g.blocks[b].flags & BF_NEAR_BODY)) g.order_split.push_back(b);
+        if (!(g.blocks[b].flags & (BF_NEAR_BODY | BF_LEVEL))) g.order_split.push_back(b);
+    g.n_clear_plain = int32_t(g.order_split.size());
+    for (int32_t b : g.order)
+        if (!(g.blocks[b].flags & BF_NEAR_BODY) && (g.blocks[b].flags & BF_LEVEL)) g.order_split.push_back(b);
     g.n_clear = int32_t(g.order_split.size());
     for (int32_t b : g.order)
         if (g.blocks[b].flags & BF_NEAR_BODY) g.order_split.push_back(b);

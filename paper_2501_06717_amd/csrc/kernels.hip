@@ -2040,7 +2040,7 @@ struct Shape {
 
 template <int KS, typename R, int FLUX, bool POWELL>
 int32_t launch_stage_shape(const HostGrid &h, const StageArgs &a, int scheme, int persist_wgs, void *ev0, void *ev1,
-                           hipStream_t s) {
+                           hipStream_t s, const double *halo_in) {
     constexpr int nt = Slab<KS>::NT;
     const int items = h.nb * (8 / KS);
     int grid = items;
@@ -2049,28 +2049,46 @@ int32_t launch_stage_shape(const HostGrid &h, const StageArgs &a, int scheme, in
         grid = (grid + 7) & ~7;
     }
     if (scheme == BMHD_SCHEME_BLOCK) {
-        // blocks clear of any body on the block form, then the blocks near a body on the plane form
-        const int nc = h.n_clear, nn = h.nb - h.n_clear;
-        StageArgs ac = a, an = a;
-        ac.sched = h.dev.order_split;
-        ac.n_sched = nc;
+        // Blocks clear of any body and of level changes on the block form (the dominant launch), blocks
+        // clear of any body with a face on another level on the block form once the level-change halo
+        // fill (halo_in: its input; null when the caller has enqueued it already) is done, blocks near a
+        // body on the plane form. The second group needs the halo fill, the third is a few workgroups:
+        // both go, after the halo fill, to a side stream beside the first launch, which would otherwise
+        // wait for them with most of the chip idle. The launches write disjoint blocks of the output. The
+        // events bracket the first launch alone.
+        const int np = h.n_clear_plain, nc = h.n_clear, nl = nc - np, nn = h.nb - nc;
+        StageArgs ap = a, al = a, an = a;
+        ap.sched = h.dev.order_split;
+        ap.n_sched = np;
+        al.sched = h.dev.order_split + np;
+        al.n_sched = nl;
         an.sched = h.dev.order_split + nc;
         an.n_sched = nn;
-        // the blocks near a body (a few workgroups) run on a side stream beside the block form's launch,
-        // which would otherwise wait for them with most of the chip idle; the two write disjoint blocks of
-        // the output. The events bracket the block form alone, the dominant kernel.
+        const bool halo = halo_in && !h.halo_items.empty();
         hipStream_t side = s;
+        if (np && (halo || nl || nn))
+            if (int32_t rc = fork_side(h, s, side)) return rc;
+        if (halo) {
+            k_halo_fill<<<unsigned(h.halo_items.size()), 256, 0, side>>>(h.dev, halo_in);
+            if (int32_t rc = launch_check("level-change halo fill")) return rc;
+        }
         if (nn) {
-            if (nc)
-                if (int32_t rc = fork_side(h, s, side)) return rc;
             k_stage_wp<4, R, FLUX, POWELL, false><<<nn * 2, Slab<4>::NT, 0, side>>>(h.dev, an);
             if (int32_t rc = launch_check("stage kernel (blocks near a body)")) return rc;
         }
+        if (nl) {
+            k_stage_blk<R, FLUX, POWELL><<<nl, BLK_NT, 0, side>>>(h.dev, al);
+            if (int32_t rc = launch_check("stage kernel (blocks at a level change)")) return rc;
+        }
         if (int32_t rc = record_event(ev0, s)) return rc;
-        if (nc) k_stage_blk<R, FLUX, POWELL><<<nc, BLK_NT, 0, s>>>(h.dev, ac);
+        if (np) k_stage_blk<R, FLUX, POWELL><<<np, BLK_NT, 0, s>>>(h.dev, ap);
         if (int32_t rc = record_event(ev1, s)) return rc;
         if (int32_t rc = launch_check("stage kernel")) return rc;
         return join_side(h, s, side);
+    }
+    if (halo_in && !h.halo_items.empty()) {
+        k_halo_fill<<<unsigned(h.halo_items.size()), 256, 0, s>>>(h.dev, halo_in);
+        if (int32_t rc = launch_check("level-change halo fill")) return rc;
     }
     if (int32_t rc = record_event(ev0, s)) return rc;
     if (scheme == BMHD_SCHEME_PLANE) {
@@ -2086,18 +2104,18 @@ int32_t launch_stage_shape(const HostGrid &h, const StageArgs &a, int scheme, in
 
 template <int KS, typename R>
 int32_t launch_stage_prec(const HostGrid &h, const StageArgs &a, int flux, bool powell, const Shape &sh, void *ev0,
-                          void *ev1, hipStream_t s) {
+                          void *ev1, hipStream_t s, const double *halo_in) {
     const int sc = sh.scheme, pw = sh.persist_wgs;
     if (flux == BMHD_FLUX_RUSANOV) {
-        if (powell) return launch_stage_shape<KS, R, BMHD_FLUX_RUSANOV, true>(h, a, sc, pw, ev0, ev1, s);
-        return launch_stage_shape<KS, R, BMHD_FLUX_RUSANOV, false>(h, a, sc, pw, ev0, ev1, s);
+        if (powell) return launch_stage_shape<KS, R, BMHD_FLUX_RUSANOV, true>(h, a, sc, pw, ev0, ev1, s, halo_in);
+        return launch_stage_shape<KS, R, BMHD_FLUX_RUSANOV, false>(h, a, sc, pw, ev0, ev1, s, halo_in);
     }
     if (flux == BMHD_FLUX_LINDE) {
-        if (powell) return launch_stage_shape<KS, R, BMHD_FLUX_LINDE, true>(h, a, sc, pw, ev0, ev1, s);
-        return launch_stage_shape<KS, R, BMHD_FLUX_LINDE, false>(h, a, sc, pw, ev0, ev1, s);
+        if (powell) return launch_stage_shape<KS, R, BMHD_FLUX_LINDE, true>(h, a, sc, pw, ev0, ev1, s, halo_in);
+        return launch_stage_shape<KS, R, BMHD_FLUX_LINDE, false>(h, a, sc, pw, ev0, ev1, s, halo_in);
     }
-    if (powell) return launch_stage_shape<KS, R, BMHD_FLUX_HLLE, true>(h, a, sc, pw, ev0, ev1, s);
-    return launch_stage_shape<KS, R, BMHD_FLUX_HLLE, false>(h, a, sc, pw, ev0, ev1, s);
+    if (powell) return launch_stage_shape<KS, R, BMHD_FLUX_HLLE, true>(h, a, sc, pw, ev0, ev1, s, halo_in);
+    return launch_stage_shape<KS, R, BMHD_FLUX_HLLE, false>(h, a, sc, pw, ev0, ev1, s, halo_in);
 }
 
 Shape pick_shape(const bmhd_opts &o) {
@@ -2119,14 +2137,17 @@ Shape pick_shape(const bmhd_opts &o) {
 
 // The stage kernel of the chosen shape; ev0 / ev1 (hipEvent_t, may be null) are recorded right before and
 // after the dominant kernel.
-int32_t launch_stage(const HostGrid &h, const StageArgs &a, const bmhd_opts &o, void *ev0, void *ev1, hipStream_t s) {
+// The stage kernels of one stage; halo_in, when not null, is the input of the level-change halo fill, which
+// the launches then enqueue themselves ahead of the blocks that read it.
+int32_t launch_stage(const HostGrid &h, const StageArgs &a, const bmhd_opts &o, void *ev0, void *ev1, hipStream_t s,
+                     const double *halo_in) {
     const Shape sh = pick_shape(o);
     if (o.precision == BMHD_FP64) {
-        if (sh.ks == 4) return launch_stage_prec<4, double>(h, a, o.flux, o.powell, sh, ev0, ev1, s);
-        return launch_stage_prec<8, double>(h, a, o.flux, o.powell, sh, ev0, ev1, s);
+        if (sh.ks == 4) return launch_stage_prec<4, double>(h, a, o.flux, o.powell, sh, ev0, ev1, s, halo_in);
+        return launch_stage_prec<8, double>(h, a, o.flux, o.powell, sh, ev0, ev1, s, halo_in);
     }
-    if (sh.ks == 4) return launch_stage_prec<4, float>(h, a, o.flux, o.powell, sh, ev0, ev1, s);
-    return launch_stage_prec<8, float>(h, a, o.flux, o.powell, sh, ev0, ev1, s);
+    if (sh.ks == 4) return launch_stage_prec<4, float>(h, a, o.flux, o.powell, sh, ev0, ev1, s, halo_in);
+    return launch_stage_prec<8, float>(h, a, o.flux, o.powell, sh, ev0, ev1, s, halo_in);
 }
 
 template <typename R, int FLUX>
@@ -2269,7 +2290,9 @@ int32_t enqueue_stage(const HostGrid &h, const bmhd_opts &o, int e, double *d_U0
                       int32_t *d_faults, bool want_lam, void *ev0, void *ev1, hipStream_t s) {
     const double *in = e ? d_U1 : d_U0;
     double *out = e ? d_U0 : d_U1;
-    if (!h.halo_items.empty()) k_halo_fill<<<unsigned(h.halo_items.size()), 256, 0, s>>>(h.dev, in);
+    // the plain stage enqueues the level-change halo fill with its launches (beside the blocks that do not
+    // read it); the learned form fills it first
+    if (!h.halo_items.empty() && o.learned) k_halo_fill<<<unsigned(h.halo_items.size()), 256, 0, s>>>(h.dev, in);
     StageArgs a;
     std::memset(&a, 0, sizeof a);
     a.Uin = in;
@@ -2325,7 +2348,7 @@ int32_t enqueue_stage(const HostGrid &h, const bmhd_opts &o, int e, double *d_U0
         k_learn_fixup<<<h.nb, 512, 0, s>>>(h.dev, a, L.fallback_cells);
         return launch_check("learned fallback");
     }
-    if (int32_t rc = launch_stage(h, a, o, ev0, ev1, s)) return rc;
+    if (int32_t rc = launch_stage(h, a, o, ev0, ev1, s, in)) return rc;
     if (!h.fc_cells.empty()) {
         k_flux_correct<<<unsigned((h.fc_cells.size() + 255) / 256), 256, 0, s>>>(h.dev, a);
         if (int32_t rc = launch_check("flux correction")) return rc;
