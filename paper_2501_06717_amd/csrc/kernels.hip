@@ -1848,12 +1848,10 @@ __global__ void __launch_bounds__(512) k_learn_fixup(Tables T, StageArgs A, int3
     const bool near_body = (B.flags & BF_NEAR_BODY) != 0;
     const bool body = near_body && in_body(S, B.level, B.ijk, ii[0], ii[1], ii[2]);
     const bool self = A.lrn_flags[off] != 0;
-    double u[8];
-#pragma unroll
-    for (int v = 0; v < 8; ++v) u[v] = A.Uout[v * vs + off];
-    bool changed = false;
+    // faces whose learned increment the cell gives back: those with a flagged cell on either side and no
+    // body cell across them (almost always none, and the cell's state is then read only to count faults)
+    unsigned undo = 0;
     if (!body) {
-        const double bdt = A.beta * A.dt[B.sim], inv_dx = double(1 << B.level) / S.dx0;
 #pragma unroll
         for (int fd = 0; fd < 6; ++fd) {
             const int a = fd >> 1, side = fd & 1;
@@ -1870,7 +1868,20 @@ __global__ void __launch_bounds__(512) k_learn_fixup(Tables T, StageArgs A, int3
                 other = A.lrn_flags[size_t(nblk) * 512 + (nn[2] * 8 + nn[1]) * 8 + nn[0]] != 0;
                 nbody = (NB.flags & BF_NEAR_BODY) && in_body(S, NB.level, NB.ijk, nn[0], nn[1], nn[2]);
             }
-            if (nbody || !(self || other)) continue;
+            if (!nbody && (self || other)) undo |= 1u << fd;
+        }
+    }
+    double u[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    if (undo || (A.count_faults && !body)) {
+#pragma unroll
+        for (int v = 0; v < 8; ++v) u[v] = A.Uout[v * vs + off];
+    }
+    if (undo) {
+        const double bdt = A.beta * A.dt[B.sim], inv_dx = double(1 << B.level) / S.dx0;
+#pragma unroll
+        for (int fd = 0; fd < 6; ++fd) {
+            if (!((undo >> fd) & 1)) continue;
+            const int a = fd >> 1, side = fd & 1;
             int fi[3] = {ii[0], ii[1], ii[2]};
             fi[a] += side;  // face index along a: the cell's own index (minus face) or one more (plus face)
             const float *y = a == 0 ? lrn_y_at<0>(T, A, b, fi[0], fi[1], fi[2])
@@ -1882,12 +1893,9 @@ __global__ void __launch_bounds__(512) k_learn_fixup(Tables T, StageArgs A, int3
             const double sg = side ? 1.0 : -1.0;
 #pragma unroll
             for (int v = 0; v < 8; ++v) u[v] += bdt * sg * dF[v] * inv_dx;
-            changed = true;
         }
-        if (changed) {
 #pragma unroll
-            for (int v = 0; v < 8; ++v) A.Uout[v * vs + off] = u[v];
-        }
+        for (int v = 0; v < 8; ++v) A.Uout[v * vs + off] = u[v];
     }
     int nf = 0;
     if (A.count_faults && !body) {
