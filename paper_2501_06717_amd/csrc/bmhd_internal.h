@@ -102,7 +102,9 @@ struct HostGrid {
     std::vector<int32_t> order;
     std::vector<int32_t> order_split;
     int32_t n_clear = 0;        // blocks clear of any body (the first n_clear of order_split)
-    int32_t n_clear_plain = 0;  // of those, the ones with no face on another level (the first of them)
+    int32_t n_clear_plain = 0;  // of those, the ones launched at once (with split_level: the ones with no
+                                // face on another level, which come first; else all of them)
+    bool split_level = false;   // the clear blocks at a level change are launched after the halo fill
     int32_t n_hb = 0;           // high face planes with no neighbour across them (see DevBlock::hb_pos)
     std::vector<int32_t> halo_items;
     std::vector<DevFcCell> fc_cells;

@@ -337,16 +337,26 @@ int32_t build_grid(const bmhd_grid_desc *d, HostGrid &g, std::string &err) {
         return key[x] < key[y];
     });
 
-    // the same schedule split for the stage kernel: the blocks clear of any body and of level changes,
-    // then the clear blocks with a face on another level (they read the halo buffer, so they wait for the
-    // level-change halo fill while the others run), both on the block form; then the blocks near a body
-    // (plane form)
+    // the same schedule split for the stage kernel: the blocks clear of any body (block form), then the
+    // blocks near a body (plane form). Where the clear blocks with a face on another level are at most a
+    // fifth of the clear blocks, they go after the others (n_clear_plain of them), so that the others can
+    // run while the level-change halo fill, which only the former read, is under way; with a larger share
+    // (the paper's fast-wave grid: a third) the two partial launches lose more than that saves, and the
+    // clear blocks keep their order.
+    std::vector<int32_t> plain, level;
+    for (int32_t b : g.order)
+        if (!(g.blocks[b].flags & BF_NEAR_BODY)) ((g.blocks[b].flags & BF_LEVEL) ? level : plain).push_back(b);
+    g.split_level = !level.empty() && plain.size() >= 4 * level.size();
     g.order_split.clear();
-    for (int32_t b : g.order)
-        if (!(g.blocks[b].flags & (BF_NEAR_BODY | BF_LEVEL))) g.order_split.push_back(b);
-    g.n_clear_plain = int32_t(g.order_split.size());
-    for (int32_t b : g.order)
-        if (!(g.blocks[b].flags & BF_NEAR_BODY) && (g.blocks[b].flags & BF_LEVEL)) g.order_split.push_back(b);
+    if (g.split_level) {
+        g.order_split = plain;
+        g.order_split.insert(g.order_split.end(), level.begin(), level.end());
+        g.n_clear_plain = int32_t(plain.size());
+    } else {
+        for (int32_t b : g.order)
+            if (!(g.blocks[b].flags & BF_NEAR_BODY)) g.order_split.push_back(b);
+        g.n_clear_plain = int32_t(g.order_split.size());
+    }
     g.n_clear = int32_t(g.order_split.size());
     for (int32_t b : g.order)
         if (g.blocks[b].flags & BF_NEAR_BODY) g.order_split.push_back(b);

@@ -2057,12 +2057,12 @@ int32_t launch_stage_shape(const HostGrid &h, const StageArgs &a, int scheme, in
         grid = (grid + 7) & ~7;
     }
     if (scheme == BMHD_SCHEME_BLOCK) {
-        // Blocks clear of any body and of level changes on the block form (the dominant launch), blocks
-        // clear of any body with a face on another level on the block form once the level-change halo
-        // fill (halo_in: its input; null when the caller has enqueued it already) is done, blocks near a
-        // body on the plane form. The second group needs the halo fill, the third is a few workgroups:
-        // both go, after the halo fill, to a side stream beside the first launch, which would otherwise
-        // wait for them with most of the chip idle. The launches write disjoint blocks of the output. The
+        // Blocks clear of any body on the block form (the dominant launch) and blocks near a body on the
+        // plane form; with split_level, the clear blocks with a face on another level are launched apart
+        // once the level-change halo fill (halo_in: its input; null when the caller has enqueued it
+        // already) is done, and the others at once. The launches that wait for the halo fill, and the few
+        // workgroups near a body, go to a side stream beside the first launch, which would otherwise wait
+        // for them with most of the chip idle. The launches write disjoint blocks of the output. The
         // events bracket the first launch alone.
         const int np = h.n_clear_plain, nc = h.n_clear, nl = nc - np, nn = h.nb - nc;
         StageArgs ap = a, al = a, an = a;
@@ -2073,10 +2073,14 @@ int32_t launch_stage_shape(const HostGrid &h, const StageArgs &a, int scheme, in
         an.sched = h.dev.order_split + nc;
         an.n_sched = nn;
         const bool halo = halo_in && !h.halo_items.empty();
+        if (halo && !h.split_level) {  // every clear block may read the halo buffer: fill it first
+            k_halo_fill<<<unsigned(h.halo_items.size()), 256, 0, s>>>(h.dev, halo_in);
+            if (int32_t rc = launch_check("level-change halo fill")) return rc;
+        }
         hipStream_t side = s;
-        if (np && (halo || nl || nn))
+        if (np && ((halo && h.split_level) || nl || nn))
             if (int32_t rc = fork_side(h, s, side)) return rc;
-        if (halo) {
+        if (halo && h.split_level) {
             k_halo_fill<<<unsigned(h.halo_items.size()), 256, 0, side>>>(h.dev, halo_in);
             if (int32_t rc = launch_check("level-change halo fill")) return rc;
         }
