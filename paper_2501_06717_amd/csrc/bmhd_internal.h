@@ -121,7 +121,8 @@ struct HostGrid {
     void *graph = nullptr, *graph_exec = nullptr, *capture_stream = nullptr;
     std::vector<unsigned char> graph_key;
     // side stream (default priority) and fork / join events (hipStream_t / hipEvent_t) on which the
-    // blocks near a body run beside the block form's launch; created on first use
+    // blocks near a body, and with split_level the halo fill and the blocks that read it, run beside the
+    // block form's main launch; created on first use
     mutable void *side_stream = nullptr, *fork_event = nullptr, *join_event = nullptr;
 };
 

@@ -2013,14 +2013,19 @@ int32_t fork_side(const HostGrid &h, hipStream_t s, hipStream_t &side) {
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
     if (int32_t rc = hip_check(hipStreamIsCapturing(s, &cs), "capture status")) return rc;
     if (cs != hipStreamCaptureStatusNone) return BMHD_OK;
-    if (!h.side_stream) {
-        hipStream_t ss;
-        hipEvent_t e0, e1;
-        if (int32_t rc = hip_check(hipStreamCreateWithFlags(&ss, hipStreamNonBlocking), "side stream")) return rc;
+    if (!h.side_stream) {  // all three or none
+        hipStream_t ss = nullptr;
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        int32_t rc = hip_check(hipStreamCreateWithFlags(&ss, hipStreamNonBlocking), "side stream");
+        if (!rc) rc = hip_check(hipEventCreateWithFlags(&e0, hipEventDisableTiming), "fork event");
+        if (!rc) rc = hip_check(hipEventCreateWithFlags(&e1, hipEventDisableTiming), "join event");
+        if (rc) {
+            if (e0) (void)hipEventDestroy(e0);
+            if (ss) (void)hipStreamDestroy(ss);
+            return rc;
+        }
         h.side_stream = ss;
-        if (int32_t rc = hip_check(hipEventCreateWithFlags(&e0, hipEventDisableTiming), "fork event")) return rc;
         h.fork_event = e0;
-        if (int32_t rc = hip_check(hipEventCreateWithFlags(&e1, hipEventDisableTiming), "join event")) return rc;
         h.join_event = e1;
     }
     hipStream_t ss = reinterpret_cast<hipStream_t>(h.side_stream);
