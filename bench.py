@@ -154,7 +154,9 @@ def bench_batched(steps):
     log(f"batched: {len(wl.sims)} simulations, {cells} cells, {t * 1e3:.2f} ms for {steps} steps, shape {shape}")
     return {"value": cells * steps / t, "unit": "cell-updates/s", "workload": f"{len(wl.sims)} simulations, "
             f"{wl.n_blocks} blocks, {cells} cells, Rusanov, FP32 flux / FP64 state", "steps": steps,
-            "ms_per_step": t * 1e3 / steps, "shape": shape, "autotune_ms": ms, "graph": True}
+            "ms_per_step": t * 1e3 / steps, "shape": shape, "autotune_ms": ms, "graph": True,
+            # algorithmic bytes (320 B per cell-update) over the whole graph-replayed step, against 8 TB/s
+            "hbm_frac_of_step": cells * steps * (BYTES_STAGE[0] + BYTES_STAGE[1]) / t / (HBM_PEAK_GBS * 1e9)}
 
 
 def bench_learned(steps, floor_rel=None):
@@ -510,8 +512,15 @@ def main():
         l1 = float(np.abs(got - ref).sum() / np.abs(ref).sum())
         linf = {k: float(np.abs(got[v] - ref[v]).max() / np.abs(ref[v]).max())
                 for k, v in (("rho", [0]), ("mom", [1, 2, 3]), ("B", [4, 5, 6]), ("e", [7]))}
+        t1_32, t2_32 = float(np.mean(st32[0])), float(np.mean(st32[1]))
+        ach32 = cells * (BYTES_STAGE[0] + BYTES_STAGE[1]) / (t1_32 + t2_32) / 1e9
         out["forms"] = {"fp32_flux": {"value": cells * steps / wall32, "unit": "cell-updates/s",
-                                      "stage_us": [float(np.mean(st32[0])) * 1e6, float(np.mean(st32[1])) * 1e6],
+                                      "stage_us": [t1_32 * 1e6, t2_32 * 1e6],
+                                      "roofline": {"bound": "hbm", "achieved": ach32, "peak": HBM_PEAK_GBS,
+                                                   "unit": "GB/s", "frac": ach32 / HBM_PEAK_GBS,
+                                                   "kernel": "k_stage_blk<float, HLLE, Powell> (both stages)"
+                                                   if resolve_shape(a.scheme, a.slab, "fp32_flux", a.persist)[0]
+                                                   == "block" else "stage kernel (both stages)"},
                                       "l1_rel_vs_fp64": l1, "linf_rel_vs_fp64": linf, "faults": f32,
                                       "error_reference": "the FP64 GPU path on the same steps (itself within "
                                                          "1e-12 of the CPU oracle)"}}
