@@ -23,6 +23,7 @@
 namespace bmhd {
 
 typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
+typedef __attribute__((__vector_size__(4 * sizeof(__bf16)))) __bf16 bf16x4;
 typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4;
 
 constexpr int MLP_IN = 32;
@@ -150,15 +151,16 @@ __global__ void __launch_bounds__(256) k_mlp_forward(const float *__restrict__ P
 // ------------------------------------------------------------------------------------------------
 // inference (BF16 products, no saved pre-activations): a persistent grid of one workgroup per CU keeps
 // every BF16 weight in LDS (rows padded by 8 elements against bank conflicts; the 8-row output layer
-// padded to 16 zero rows) and each wave streams tiles of 16 samples through the four layers, its
-// activations in a private LDS tile. For H = 128: 84.2 KB of weights + 16 x 4.4 KB of activations.
+// padded to 16 zero rows; 84.2 KB for H = 128) and each wave streams tiles of 16 samples through the four
+// layers with the activations in registers (each layer's products become the next layer's operands by
+// lane swaps, chunk_operand below).
 
-// per workgroup: four wavefronts per SIMD (122 VGPRs allow four), one 16-sample tile each per iteration.
-// Measured per launch on the 128^3 learned stage, before the bias moved into the accumulators (now
-// 0.91 ms): sixteen wavefronts 0.98 ms, twelve 1.04 ms; with FP32 inputs, two tiles per wavefront with
-// eight wavefronts 1.18 ms against 1.15 ms for one tile with twelve.
-constexpr int MLP_INFER_WAVES = 16;
-constexpr int MLP_INFER_TILES = 1;
+// per workgroup: three wavefronts per SIMD (162 VGPRs), two 16-sample tiles each per iteration, so that
+// each weight fragment read from LDS feeds two products. Measured per launch on the 128^3 learned stage:
+// activations through a private LDS tile per wave, one tile, sixteen wavefronts 0.81 ms; activations in
+// registers, one tile, sixteen wavefronts (103 VGPRs) 0.76 ms; two tiles, twelve wavefronts 0.75 ms.
+constexpr int MLP_INFER_WAVES = 12;
+constexpr int MLP_INFER_TILES = 2;
 
 template <int H>
 struct InferLds {
@@ -169,14 +171,27 @@ struct InferLds {
     static constexpr int W3 = W2 + H * LH;
     static constexpr int W4 = W3 + H * LH;
     static constexpr int NWE = W4 + 16 * LH;
-    static constexpr int LA = (H > MLP_IN ? H : MLP_IN) + 8;  // activation row
 };
 
-// make this wave's LDS writes visible to its other lanes before they read them
-__device__ __forceinline__ void wave_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+// The 32-wide input chunk c of the next layer as an MFMA B operand (lane (q, r): act[sample r][32c + 8q ..
+// 32c + 8q + 7]) from this layer's products, where lane (q, r) holds outputs 16 nt + 4q .. + 3 of sample r:
+// lo = its four (BF16) of nt = 2c, hi = its four of nt = 2c + 1. Lane row q (16 lanes) needs the pieces of
+// rows 2(q mod 2) and 2(q mod 2) + 1 of nt = 2c + q / 2; one 32-lane and one 16-lane swap per dword move
+// them there, in registers (gfx950 lane swaps: the first exchanges a's upper half with b's lower half,
+// the second a's odd rows with b's even rows).
+__device__ __forceinline__ bf16x8 chunk_operand(bf16x4 lo, bf16x4 hi) {
+    typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
+    typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+    const u32x2 a = __builtin_bit_cast(u32x2, lo), b = __builtin_bit_cast(u32x2, hi);
+    u32x4 t;
+#pragma unroll
+    for (int d = 0; d < 2; ++d) {
+        const auto h = __builtin_amdgcn_permlane32_swap(a[d], b[d], false, false);
+        const auto w = __builtin_amdgcn_permlane16_swap(h[0], h[1], false, false);
+        t[d] = w[0];      // outputs 8q .. 8q + 3 of the chunk
+        t[2 + d] = w[1];  // outputs 8q + 4 .. 8q + 7
+    }
+    return __builtin_bit_cast(bf16x8, t);
 }
 
 // X holds FP32 inputs (rounded to BF16 here) or inputs already rounded to BF16 by their producer.
@@ -184,10 +199,8 @@ template <int H, int NW, int TP, typename TX>
 __global__ void __launch_bounds__(64 * NW) k_mlp_infer(const float *__restrict__ P, const __bf16 *__restrict__ Pb,
                                                        int n, const TX *__restrict__ X, float *__restrict__ Y) {
     using Z = InferLds<H>;
-    constexpr int NT = H / 16;
-    typedef __attribute__((__vector_size__(4 * sizeof(__bf16)))) __bf16 bf16x4;
+    constexpr int NT = H / 16, NC = H / 32;
     __shared__ __attribute__((aligned(16))) __bf16 sw[Z::NWE];
-    __shared__ __attribute__((aligned(16))) __bf16 sa[NW][TP][16 * Z::LA];
     __shared__ float sb[3 * H + 16];
     const MlpView V = mlp_view(H);
     // stage the weights (16-byte moves) and biases
@@ -207,24 +220,27 @@ __global__ void __launch_bounds__(64 * NW) k_mlp_infer(const float *__restrict__
     }
     __syncthreads();
     // Products are formed transposed, D[out][sample] = W x act^T: the weight tile is the A operand (lane
-    // holds W[o][8q .. 8q+7]), the activation tile the B operand (lane holds act[sample r][8q .. 8q+7]),
-    // so lane (q, r) ends with outputs 4q .. 4q+3 of sample r: four neighbouring activations, written
-    // back with one 8-byte store. A wavefront carries TP tiles of 16 samples at once, so each weight
-    // fragment read from LDS feeds TP products.
+    // holds W[o][8q .. 8q+7]), the activation chunk the B operand (lane holds act[sample r][8q .. 8q+7]),
+    // so lane (q, r) ends with outputs 4q .. 4q+3 of sample r, which chunk_operand turns into the next
+    // layer's B operands without leaving registers. A wavefront carries TP tiles of 16 samples at once, so
+    // each weight fragment read from LDS feeds TP products.
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, q = lane >> 4, r = lane & 15;
     const int ntiles = (n + 15) / 16;
     for (int t0 = (blockIdx.x * NW + wave) * TP; t0 < ntiles; t0 += gridDim.x * NW * TP) {
+        // the biases are read from LDS in each tile, where they are used: hoisted out of the loop they
+        // would hold 100 registers (no instruction is emitted for this)
+        asm volatile("" ::: "memory");
+        bf16x8 act[TP][NC];  // this layer's input chunks (the first layer's 32 inputs: chunk 0)
 #pragma unroll
         for (int p = 0; p < TP; ++p) {
-            // input tile: lane -> sample lane / 4, inputs 8 (lane % 4) .. +7
-            const int s0 = (t0 + p) * 16, m = lane >> 2, k = (lane & 3) * 8;
+            const int smp = (t0 + p) * 16 + r;
             bf16x8 v;
-            if (s0 + m < n) {
+            if (smp < n) {
                 if constexpr (std::is_same<TX, __bf16>::value) {
-                    v = *reinterpret_cast<const bf16x8 *>(X + size_t(s0 + m) * MLP_IN + k);
+                    v = *reinterpret_cast<const bf16x8 *>(X + size_t(smp) * MLP_IN + 8 * q);
                 } else {
-                    const float4 x0 = *reinterpret_cast<const float4 *>(X + size_t(s0 + m) * MLP_IN + k);
-                    const float4 x1 = *reinterpret_cast<const float4 *>(X + size_t(s0 + m) * MLP_IN + k + 4);
+                    const float4 x0 = *reinterpret_cast<const float4 *>(X + size_t(smp) * MLP_IN + 8 * q);
+                    const float4 x1 = *reinterpret_cast<const float4 *>(X + size_t(smp) * MLP_IN + 8 * q + 4);
                     v[0] = __bf16(x0.x); v[1] = __bf16(x0.y); v[2] = __bf16(x0.z); v[3] = __bf16(x0.w);
                     v[4] = __bf16(x1.x); v[5] = __bf16(x1.y); v[6] = __bf16(x1.z); v[7] = __bf16(x1.w);
                 }
@@ -232,13 +248,12 @@ __global__ void __launch_bounds__(64 * NW) k_mlp_infer(const float *__restrict__
 #pragma unroll
                 for (int j = 0; j < 8; ++j) v[j] = __bf16(0.0f);
             }
-            *reinterpret_cast<bf16x8 *>(sa[wave][p] + m * Z::LA + k) = v;
+            act[p][0] = v;
         }
-        wave_sync();
-        f32x4 acc[TP][NT];
 #pragma unroll
         for (int l = 0; l < 3; ++l) {
-            const int nin = l == 0 ? MLP_IN : H, ld = l == 0 ? Z::L1 : Z::LH, wb = l == 0 ? Z::W1 : (l == 1 ? Z::W2 : Z::W3);
+            const int nc = l == 0 ? MLP_IN / 32 : NC, ld = l == 0 ? Z::L1 : Z::LH, wb = l == 0 ? Z::W1 : (l == 1 ? Z::W2 : Z::W3);
+            f32x4 acc[TP][NT];
             // the products accumulate onto the bias (no separate add in the epilogue)
 #pragma unroll
             for (int nt = 0; nt < NT; ++nt) {
@@ -246,31 +261,28 @@ __global__ void __launch_bounds__(64 * NW) k_mlp_infer(const float *__restrict__
 #pragma unroll
                 for (int p = 0; p < TP; ++p) acc[p][nt] = f32x4{bias.x, bias.y, bias.z, bias.w};
             }
-            for (int k0 = 0; k0 < nin; k0 += 32) {
-                bf16x8 bv[TP];
 #pragma unroll
-                for (int p = 0; p < TP; ++p) bv[p] = *reinterpret_cast<const bf16x8 *>(sa[wave][p] + r * Z::LA + k0 + 8 * q);
+            for (int c = 0; c < nc; ++c) {
 #pragma unroll
                 for (int nt = 0; nt < NT; ++nt) {
-                    const bf16x8 av = *reinterpret_cast<const bf16x8 *>(sw + wb + (16 * nt + r) * ld + k0 + 8 * q);
+                    const bf16x8 av = *reinterpret_cast<const bf16x8 *>(sw + wb + (16 * nt + r) * ld + 32 * c + 8 * q);
 #pragma unroll
                     for (int p = 0; p < TP; ++p)
-                        acc[p][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv[p], acc[p][nt], 0, 0, 0);
+                        acc[p][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, act[p][c], acc[p][nt], 0, 0, 0);
                 }
             }
-            wave_sync();  // every lane has read this layer's input
 #pragma unroll
             for (int p = 0; p < TP; ++p)
 #pragma unroll
-                for (int nt = 0; nt < NT; ++nt) {
-                    bf16x4 o;
-                    o[0] = __bf16(silu(acc[p][nt][0]));
-                    o[1] = __bf16(silu(acc[p][nt][1]));
-                    o[2] = __bf16(silu(acc[p][nt][2]));
-                    o[3] = __bf16(silu(acc[p][nt][3]));
-                    *reinterpret_cast<bf16x4 *>(sa[wave][p] + r * Z::LA + 16 * nt + 4 * q) = o;
+                for (int c = 0; c < NC; ++c) {
+                    bf16x4 lo, hi;
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        lo[i] = __bf16(silu(acc[p][2 * c][i]));
+                        hi[i] = __bf16(silu(acc[p][2 * c + 1][i]));
+                    }
+                    act[p][c] = chunk_operand(lo, hi);
                 }
-            wave_sync();
         }
         f32x4 out[TP];
         {
@@ -279,13 +291,11 @@ __global__ void __launch_bounds__(64 * NW) k_mlp_infer(const float *__restrict__
 #pragma unroll
             for (int p = 0; p < TP; ++p) out[p] = f32x4{bias.x, bias.y, bias.z, bias.w};
         }
-        for (int k0 = 0; k0 < H; k0 += 32) {
-            const bf16x8 av = *reinterpret_cast<const bf16x8 *>(sw + Z::W4 + r * Z::LH + k0 + 8 * q);
 #pragma unroll
-            for (int p = 0; p < TP; ++p) {
-                const bf16x8 bv = *reinterpret_cast<const bf16x8 *>(sa[wave][p] + r * Z::LA + k0 + 8 * q);
-                out[p] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, out[p], 0, 0, 0);
-            }
+        for (int c = 0; c < NC; ++c) {
+            const bf16x8 av = *reinterpret_cast<const bf16x8 *>(sw + Z::W4 + r * Z::LH + 32 * c + 8 * q);
+#pragma unroll
+            for (int p = 0; p < TP; ++p) out[p] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, act[p][c], out[p], 0, 0, 0);
         }
 #pragma unroll
         for (int p = 0; p < TP; ++p) {
@@ -295,7 +305,6 @@ __global__ void __launch_bounds__(64 * NW) k_mlp_infer(const float *__restrict__
                 *reinterpret_cast<float4 *>(Y + size_t(s0 + r) * MLP_OUT + 4 * q) = y;
             }
         }
-        wave_sync();  // the next tiles overwrite these activations
     }
 }
 
