@@ -158,7 +158,8 @@ __global__ void __launch_bounds__(256) k_mlp_forward(const float *__restrict__ P
 // per workgroup: three wavefronts per SIMD (162 VGPRs), two 16-sample tiles each per iteration, so that
 // each weight fragment read from LDS feeds two products. Measured per launch on the 128^3 learned stage:
 // activations through a private LDS tile per wave, one tile, sixteen wavefronts 0.81 ms; activations in
-// registers, one tile, sixteen wavefronts (103 VGPRs) 0.76 ms; two tiles, twelve wavefronts 0.75 ms.
+// registers, one tile, sixteen wavefronts (103 VGPRs) 0.76 ms; two tiles, twelve wavefronts 0.75 ms;
+// two tiles, sixteen wavefronts (128 VGPRs, 112 bytes of spills) 0.87 ms.
 constexpr int MLP_INFER_WAVES = 12;
 constexpr int MLP_INFER_TILES = 2;
 
